@@ -1,0 +1,198 @@
+/*
+ * ism.h -- C-ABI of libism.so: image-source-method room impulse responses on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper, section II.A, synthetic dataset generation): for a
+ * shoebox room with walls at x = 0, Lx, y = 0, Ly, z = 0, Lz, every image of
+ * the source (image method of Allen and Berkley) is found, its distance d to
+ * each microphone, its damping = product over the walls it was reflected by of
+ * that wall's pressure reflection coefficient, times 1/(4 pi d), and its delay
+ * d*fs/c, split into an integer part n0 = floor(tau + 1/2) and a fraction
+ * f = tau - n0.  A fractional-delay filter centred on tau is added into the
+ * RIR at samples n0-K .. n0+K.  The filter here is the Hann-windowed sinc
+ * h(t) = sinc(t) * (1 + cos(pi t / (K+1))) / 2, K = (fd_taps - 1) / 2 (the
+ * paper's own filter is a 7th-order Lagrange interpolator; the windowed sinc
+ * is the filter of the workloads this library serves).  Taps outside
+ * [0, rir_len) are dropped.  Image n,l,q in Z, u,v,w in {0,1} sits at
+ * ((1-2u) sx + 2n Lx, (1-2v) sy + 2l Ly, (1-2w) sz + 2q Lz) and is damped by
+ * beta[0]^|n-u| beta[1]^|n| beta[2]^|l-v| beta[3]^|l| beta[4]^|q-w| beta[5]^|q|
+ * (beta order: x0, xL, y0, yL, z0, zL).
+ *
+ * Image sets:
+ *   max_order >= 0, ISM_ORDER_INDEX_L1:    |n| + |l| + |q| <= max_order
+ *   max_order >= 0, ISM_ORDER_REFLECTIONS: |2n-u| + |2l-v| + |2q-w| <= max_order
+ *   max_order <  0: every image whose taps reach [0, rir_len) (the paper keeps
+ *                   every reflection arriving within the reverberation time).
+ *
+ * Conventions for every entry point:
+ *   - Host pointers (room geometry, microphone positions, room tables) are read
+ *     before the call returns; the caller may free them afterwards.
+ *   - Device pointers (out, rirs, src, z) must stay valid until the work queued
+ *     on `stream` has finished.  The caller owns them.  `out` is overwritten in
+ *     full, zeros included.
+ *   - Work is queued asynchronously on `stream` (a hipStream_t; NULL means the
+ *     default stream).  Calls return once the work is queued.
+ *   - Errors are return codes; nothing throws or aborts.  Arguments are
+ *     validated before any device work is queued, so a failed call leaves
+ *     `out` untouched.  ism_last_error() gives a one-line description.
+ *   - Summation order is fixed by the data: the same inputs give bitwise the
+ *     same outputs, alone or batched with other rooms.
+ *   - A handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef ISM_H
+#define ISM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ISM_VERSION 100
+
+typedef struct ism_handle ism_handle;
+typedef void *ism_stream; /* hipStream_t */
+
+enum ism_status {
+    ISM_OK = 0,
+    ISM_EINVAL = -1,  /* malformed argument: taps even or < 1 or > 255, rir_len < 1, n_mics < 1,
+                         fs/c/L not finite and > 0, beta outside [0,1], NULL pointer, bad enum */
+    ISM_EDOMAIN = -2, /* geometry outside the model: source not strictly inside the room,
+                         microphone outside [0, L], or microphone at the source position */
+    ISM_ENOMEM = -3,  /* device or pinned host allocation failed, or a size limit was exceeded */
+    ISM_EDEVICE = -4, /* a HIP runtime call failed (text in ism_last_error) */
+    ISM_EBUSY = -5    /* serving engine: no capacity for the request right now */
+};
+
+enum ism_order_mode { ISM_ORDER_INDEX_L1 = 0, ISM_ORDER_REFLECTIONS = 1 };
+
+/*
+ * Arithmetic of the tap evaluation.  In every mode the image positions,
+ * distances, delays and the integer/fractional delay split are computed in
+ * FP64 (except ISM_PREC_FP32_SPLIT).
+ *   ISM_PREC_FP32_COMP   FP32 tap evaluation, FP32 partial sums folded into a
+ *                        compensated (Neumaier) FP32 pair per output sample.
+ *   ISM_PREC_FP16_LUT    the windowed sinc read from an FP16 table (64 steps
+ *                        per sample, linear interpolation), FP32 accumulation.
+ *   ISM_PREC_FP32_SPLIT  ablation: distance and delay split in FP32.
+ *   ISM_PREC_FP32_PLAIN  ablation: FP32 taps, plain FP32 accumulation.
+ */
+enum ism_precision {
+    ISM_PREC_FP32_COMP = 0,
+    ISM_PREC_FP16_LUT = 1,
+    ISM_PREC_FP32_SPLIT = 2,
+    ISM_PREC_FP32_PLAIN = 3
+};
+
+/* One room of a batch.  Microphones of room i are mics[mic_offset .. mic_offset+n_mics);
+ * the RIR of its m-th microphone is out[out_offset + m*rir_len .. + rir_len). */
+typedef struct ism_room {
+    double L[3];
+    double beta[6];
+    double src[3];
+    int32_t mic_offset;
+    int32_t n_mics;
+    int32_t max_order;
+    int32_t rir_len;
+    int64_t out_offset;
+} ism_room;
+
+/* Create a handle bound to the current HIP device; the handle owns its device
+ * work buffers, pinned staging buffers and tuning state.  *h is NULL on error. */
+int ism_create(ism_handle **h);
+/* Waits for the handle's queued work, then releases everything it owns. */
+void ism_destroy(ism_handle *h);
+/* Static text for a status code. */
+const char *ism_strerror(int status);
+/* Text of the last error on this handle ("" if none); valid until the next call. */
+const char *ism_last_error(const ism_handle *h);
+int ism_version(void);
+
+/*
+ * One room, M microphones (section II.A).
+ *   L[3], beta[6], src[3]: host, room geometry (m) and reflection coefficients.
+ *   mics: host, M x 3 positions (m), row-major.
+ *   fs (Hz), c (m/s): sample rate and speed of sound.
+ *   max_order, order_mode: image set (see above).
+ *   rir_len: samples per RIR; fd_taps: odd filter length 2K+1 (<= 255).
+ *   precision: ism_precision.
+ *   out: device, M x rir_len floats, row-major, fully overwritten.
+ */
+int ism_rir(ism_handle *h, const double L[3], const double beta[6], const double src[3],
+            int M, const double *mics, double fs, double c, int max_order, int order_mode,
+            int rir_len, int fd_taps, int precision, float *out, ism_stream stream);
+
+/*
+ * Many rooms in one launch (the batched form of ism_rir): every (room, mic,
+ * output segment) of the batch is one work item of a single persistent launch.
+ *   rooms: host, n_rooms entries; mics: host, positions referenced by the rooms.
+ *   out: device; room i writes out[out_offset + m*rir_len + n].
+ * Results are bitwise equal to calling ism_rir room by room.
+ */
+int ism_rir_batch(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics,
+                  double fs, double c, int fd_taps, int order_mode, int precision, float *out,
+                  ism_stream stream);
+
+/*
+ * Counts of the work a batch implies, computed on the host without device work:
+ * work items (room, mic, segment), and upper-bound estimates of images and taps.
+ * Any output pointer may be NULL.
+ */
+int ism_batch_plan_stats(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics,
+                         double fs, double c, int fd_taps, int64_t *n_items,
+                         double *est_records, double *est_taps);
+
+/*
+ * Work counters of the last ism_rir / ism_rir_batch call on this handle: counts[0]
+ * = taps that landed in the outputs (one per image, microphone and output sample
+ * of its filter inside [0, rir_len)), counts[1] = image records processed (an
+ * image near a segment boundary is processed once per segment it reaches),
+ * counts[2] = candidate images evaluated.  Waits for that call to finish.
+ */
+int ism_last_counts(ism_handle *h, int64_t counts[3]);
+
+/*
+ * Tuning of the segment kernel: seg_len = output samples per work item
+ * (multiple of 64, 64..2048), fold = rounds of FP32 partial sums between
+ * compensated folds (>= 1), graphs = capture each batch launch sequence in a
+ * hipGraph and replay it (1) or launch directly (0).  A value of 0 for seg_len
+ * or fold, or -1 for graphs, keeps the current setting.  Settings apply to
+ * later calls on this handle.
+ */
+int ism_set_tuning(ism_handle *h, int seg_len, int fold, int graphs);
+int ism_get_tuning(const ism_handle *h, int *seg_len, int *fold, int *graphs);
+
+/*
+ * Autotuner: times the batch with each candidate segment length (64-multiples
+ * from the candidate list, or the built-in list if n_cand == 0) on `stream`,
+ * keeps the fastest in the handle, and returns it in *best_seg_len (may be NULL).
+ * out receives the batch result of the last candidate.  Synchronises `stream`.
+ */
+int ism_autotune(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics,
+                 double fs, double c, int fd_taps, int order_mode, int precision, float *out,
+                 ism_stream stream, const int *cand, int n_cand, int *best_seg_len);
+
+/*
+ * Source convolution and sensor noise for a batch of rooms (paper section III.A:
+ * the RIRs are convolved with source signals; Gaussian noise at a drawn SNR is
+ * added to the multichannel result).
+ *   rirs: device FP32; room r, mic m: rirs[rir_offset[r] + m*rir_len[r] + j].
+ *   rir_offset, rir_len: host arrays of n_rooms entries.
+ *   src: device FP32, n_rooms x src_len; out: device FP32, n_rooms x M x out_len.
+ *   y[r][m][n] = sum_{j <= min(n, rir_len-1)} h[r][m][j] * x[r][n-j], n < out_len.
+ *   snr_db: host, n_rooms entries, or NULL for no noise.  z: device FP32
+ *   n_rooms x M x out_len standard normal deviates (required if snr_db != NULL):
+ *   y += sigma_r * z, sigma_r^2 = mean over m,n of y^2 * 10^(-snr_db[r]/10).
+ *   use_mfma: 1 = block-Toeplitz GEMM on MFMA, BF16 inputs, FP32 accumulation;
+ *             0 = FP32 direct convolution on the vector units.
+ */
+int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float *rirs,
+                       const int64_t *rir_offset, const int32_t *rir_len, const float *src,
+                       int src_len, int out_len, const float *snr_db, const float *z,
+                       int use_mfma, float *out, ism_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISM_H */

@@ -1,0 +1,516 @@
+// Host side of libism.so: argument validation (the ingest step), the work plan
+// of a batch (one item per room x microphone x output segment, ordered
+// longest-first), staging of the plan through pinned memory, and the launch
+// sequence (prologue + persistent segment kernel), optionally captured once in a
+// hipGraph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ism.h"
+#include "ism_host.h"
+#include "ism_internal.h"
+
+using namespace ism;
+
+namespace ism {
+struct KernelEntry { hipError_t (*fn)(const LaunchDev *, int, int, hipStream_t); const void *sym; };
+KernelEntry select_segment_kernel(int K, int variant);
+hipError_t launch_prologue(const LaunchDev *P, int n_rooms, hipStream_t st);
+}  // namespace ism
+
+// ------------------------------------------------------------------ handle
+void ism_set_error(ism_handle *h, const char *fmt, ...)
+{
+    if (!h) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    h->last_error = buf;
+}
+
+int ism_hip_fail(ism_handle *h, hipError_t e, const char *what)
+{
+    ism_set_error(h, "%s: %s", what, hipGetErrorString(e));
+    return ISM_EDEVICE;
+}
+
+static void free_slot(Slot &s)
+{
+    if (s.gexec) hipGraphExecDestroy(s.gexec);
+    if (s.graph) hipGraphDestroy(s.graph);
+    if (s.event) hipEventDestroy(s.event);
+    if (s.host) hipHostFree(s.host);
+    if (s.dev) hipFree(s.dev);
+    s = Slot();
+}
+
+extern "C" int ism_create(ism_handle **out)
+{
+    if (!out) return ISM_EINVAL;
+    *out = nullptr;
+    ism_handle *h = new (std::nothrow) ism_handle();
+    if (!h) return ISM_ENOMEM;
+    // Without a HIP device the handle still validates and plans; device work
+    // then fails with ISM_EDEVICE.
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1 || hipGetDevice(&h->device) != hipSuccess) {
+        h->device = -1;
+        h->n_cu = 0;
+    } else {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, h->device) != hipSuccess) { delete h; return ISM_EDEVICE; }
+        h->n_cu = prop.multiProcessorCount;
+        h->lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
+    }
+    *out = h;
+    return ISM_OK;
+}
+
+extern "C" void ism_destroy(ism_handle *h)
+{
+    if (!h) return;
+    for (auto &s : h->slots) {
+        if (s.event && s.used) hipEventSynchronize(s.event);
+        free_slot(s);
+    }
+    ism_conv_release(h);
+    ism_serve_release(h);
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    delete h;
+}
+
+extern "C" const char *ism_strerror(int st)
+{
+    switch (st) {
+    case ISM_OK: return "ok";
+    case ISM_EINVAL: return "invalid argument";
+    case ISM_EDOMAIN: return "geometry outside the model";
+    case ISM_ENOMEM: return "out of memory or size limit";
+    case ISM_EDEVICE: return "HIP runtime error";
+    case ISM_EBUSY: return "busy";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *ism_last_error(const ism_handle *h) { return h ? h->last_error.c_str() : ""; }
+extern "C" int ism_version(void) { return ISM_VERSION; }
+
+extern "C" int ism_set_tuning(ism_handle *h, int seg_len, int fold, int graphs)
+{
+    if (!h) return ISM_EINVAL;
+    if (seg_len != 0 && (seg_len < 64 || seg_len > kSegMaxLimit || seg_len % 64 != 0)) {
+        ism_set_error(h, "seg_len must be a multiple of 64 in [64, %d]", kSegMaxLimit);
+        return ISM_EINVAL;
+    }
+    if (fold < 0) { ism_set_error(h, "fold must be >= 0"); return ISM_EINVAL; }
+    if (graphs < -1 || graphs > 1) { ism_set_error(h, "graphs must be -1, 0 or 1"); return ISM_EINVAL; }
+    if (seg_len) h->seg_len = seg_len;
+    if (fold) h->fold = fold;
+    if (graphs >= 0) h->graphs = graphs;
+    return ISM_OK;
+}
+
+extern "C" int ism_get_tuning(const ism_handle *h, int *seg_len, int *fold, int *graphs)
+{
+    if (!h) return ISM_EINVAL;
+    if (seg_len) *seg_len = h->seg_len;
+    if (fold) *fold = h->fold;
+    if (graphs) *graphs = h->graphs;
+    return ISM_OK;
+}
+
+// ------------------------------------------------------------------ validation
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int ism_validate_common(ism_handle *h, double fs, double c, int fd_taps, int order_mode, int precision)
+{
+    if (!finite_pos(fs)) { ism_set_error(h, "fs must be finite and > 0"); return ISM_EINVAL; }
+    if (!finite_pos(c)) { ism_set_error(h, "c must be finite and > 0"); return ISM_EINVAL; }
+    if (fd_taps < 1 || fd_taps % 2 == 0 || fd_taps > 2 * kKMax + 1) {
+        ism_set_error(h, "fd_taps must be odd and in [1, %d]", 2 * kKMax + 1);
+        return ISM_EINVAL;
+    }
+    if (order_mode != ISM_ORDER_INDEX_L1 && order_mode != ISM_ORDER_REFLECTIONS) {
+        ism_set_error(h, "order_mode must be ISM_ORDER_INDEX_L1 or ISM_ORDER_REFLECTIONS");
+        return ISM_EINVAL;
+    }
+    if (precision < ISM_PREC_FP32_COMP || precision > ISM_PREC_FP32_PLAIN) {
+        ism_set_error(h, "unknown precision %d", precision);
+        return ISM_EINVAL;
+    }
+    return ISM_OK;
+}
+
+int ism_validate_room(ism_handle *h, int idx, const ism_room &r, const double *mics)
+{
+    for (int a = 0; a < 3; ++a)
+        if (!finite_pos(r.L[a])) { ism_set_error(h, "room %d: L must be finite and > 0", idx); return ISM_EINVAL; }
+    for (int w = 0; w < 6; ++w)
+        if (!std::isfinite(r.beta[w]) || r.beta[w] < 0.0 || r.beta[w] > 1.0) {
+            ism_set_error(h, "room %d: beta[%d] must be in [0, 1]", idx, w);
+            return ISM_EINVAL;
+        }
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(r.src[a])) { ism_set_error(h, "room %d: source not finite", idx); return ISM_EINVAL; }
+    if (r.n_mics < 1) { ism_set_error(h, "room %d: n_mics must be >= 1", idx); return ISM_EINVAL; }
+    if (r.mic_offset < 0) { ism_set_error(h, "room %d: mic_offset < 0", idx); return ISM_EINVAL; }
+    if (r.rir_len < 1 || r.rir_len > (1 << 27)) {
+        ism_set_error(h, "room %d: rir_len must be in [1, 2^27]", idx);
+        return ISM_EINVAL;
+    }
+    if (r.out_offset < 0) { ism_set_error(h, "room %d: out_offset < 0", idx); return ISM_EINVAL; }
+    if (r.max_order > 100000) { ism_set_error(h, "room %d: max_order too large", idx); return ISM_EINVAL; }
+    for (int a = 0; a < 3; ++a)
+        if (!(r.src[a] > 0.0 && r.src[a] < r.L[a])) {
+            ism_set_error(h, "room %d: source must be strictly inside the room", idx);
+            return ISM_EDOMAIN;
+        }
+    for (int m = 0; m < r.n_mics; ++m) {
+        const double *p = mics + 3 * ((int64_t)r.mic_offset + m);
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(p[a])) { ism_set_error(h, "room %d mic %d: not finite", idx, m); return ISM_EINVAL; }
+            if (p[a] < 0.0 || p[a] > r.L[a]) {
+                ism_set_error(h, "room %d mic %d: outside the room", idx, m);
+                return ISM_EDOMAIN;
+            }
+            d2 += (p[a] - r.src[a]) * (p[a] - r.src[a]);
+        }
+        if (d2 == 0.0) { ism_set_error(h, "room %d mic %d: at the source position", idx, m); return ISM_EDOMAIN; }
+    }
+    return ISM_OK;
+}
+
+// ------------------------------------------------------------------ plan
+// Largest wall exponent any image of the room can need, with margin.
+static int pow_stride_for(const ism_room &r, double fs, double c, int K)
+{
+    double Lmin = std::min(r.L[0], std::min(r.L[1], r.L[2]));
+    long e;
+    if (r.max_order >= 0) e = (long)r.max_order + 4;
+    else {
+        double dmax = ((double)r.rir_len - 1.0 + K + 0.5) * c / fs;
+        e = (long)std::ceil(dmax / (2.0 * Lmin)) + 4;
+    }
+    return (int)std::min<long>(e + 1, 1L << 22);
+}
+
+// Expected tap count of an output segment (ordering key only).
+static double item_cost(const ism_room &r, double fs, double c, int K, int s0, int s1)
+{
+    const double V = r.L[0] * r.L[1] * r.L[2];
+    const double lo = std::max(0.0, (s0 - K - 0.5) * c / fs), hi = (s1 - 1 + K + 0.5) * c / fs;
+    double recs = 4.0 * M_PI / (3.0 * V) * (hi * hi * hi - lo * lo * lo);
+    const double cols = 4.0 * hi * hi / (r.L[0] * r.L[1]) + 1.0;
+    return recs * (2.0 * K + 1.0) + 30.0 * cols + 1.0;
+}
+
+int ism_build_plan(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics, double fs,
+                   double c, int fd_taps, int seg_len, Plan &plan)
+{
+    const int K = (fd_taps - 1) / 2;
+    plan.rooms.resize(n_rooms);
+    plan.items.clear();
+    plan.seg_max = 0;
+    plan.n_mics_total = 0;
+    plan.est_taps = 0.0;
+    plan.est_records = 0.0;
+    int64_t pow_total = 0;
+    std::vector<float> cost;
+    for (int i = 0; i < n_rooms; ++i) {
+        const ism_room &r = rooms[i];
+        RoomDev &d = plan.rooms[i];
+        std::memcpy(d.L, r.L, sizeof d.L);
+        std::memcpy(d.beta, r.beta, sizeof d.beta);
+        std::memcpy(d.src, r.src, sizeof d.src);
+        d.rir_len = r.rir_len;
+        d.max_order = r.max_order < 0 ? -1 : r.max_order;
+        d.n_mics = r.n_mics;
+        d.mic_offset = r.mic_offset;
+        d.out_offset = r.out_offset;
+        d.pow_stride = pow_stride_for(r, fs, c, K);
+        if (pow_total + 6LL * d.pow_stride > (1LL << 30)) {
+            ism_set_error(h, "wall-power tables exceed the size limit");
+            return ISM_ENOMEM;
+        }
+        d.pow_offset = (int32_t)pow_total;
+        pow_total += 6LL * d.pow_stride;
+        plan.n_mics_total = std::max<int64_t>(plan.n_mics_total, (int64_t)r.mic_offset + r.n_mics);
+        for (int m = 0; m < r.n_mics; ++m) {
+            for (int s0 = 0; s0 < r.rir_len; s0 += seg_len) {
+                const int s1 = std::min(s0 + seg_len, r.rir_len);
+                ItemDev it{i, r.mic_offset + m, s0, s1};
+                plan.items.push_back(it);
+                const double cst = item_cost(r, fs, c, K, s0, s1);
+                cost.push_back((float)cst);
+                plan.est_taps += (cst - 1.0) > 0 ? cst : 0.0;
+                plan.seg_max = std::max(plan.seg_max, s1 - s0);
+            }
+        }
+    }
+    if (plan.items.size() > (size_t)INT32_MAX / 2) {
+        ism_set_error(h, "too many work items");
+        return ISM_ENOMEM;
+    }
+    plan.est_records = plan.est_taps / (2.0 * K + 1.0);
+    plan.pow_total = pow_total;
+    // longest-first order: counting sort on a log2 cost key (1/16 octave buckets)
+    const int NB = 64 * 16;
+    std::vector<int> bucket(plan.items.size());
+    std::vector<int64_t> hist(NB + 1, 0);
+    for (size_t i = 0; i < plan.items.size(); ++i) {
+        int b = (int)std::floor(std::log2(std::max(1.0f, cost[i])) * 16.0);
+        b = std::min(std::max(b, 0), NB - 1);
+        bucket[i] = NB - 1 - b;
+        hist[bucket[i] + 1]++;
+    }
+    for (int b = 0; b < NB; ++b) hist[b + 1] += hist[b];
+    std::vector<ItemDev> sorted(plan.items.size());
+    for (size_t i = 0; i < plan.items.size(); ++i) sorted[hist[bucket[i]]++] = plan.items[i];
+    plan.items.swap(sorted);
+    return ISM_OK;
+}
+
+extern "C" int ism_batch_plan_stats(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics,
+                                    double fs, double c, int fd_taps, int64_t *n_items,
+                                    double *est_records, double *est_taps)
+{
+    if (!h || !rooms || !mics || n_rooms < 0) return ISM_EINVAL;
+    int st = ism_validate_common(h, fs, c, fd_taps, 0, 0);
+    if (st) return st;
+    for (int i = 0; i < n_rooms; ++i)
+        if ((st = ism_validate_room(h, i, rooms[i], mics))) return st;
+    Plan plan;
+    if ((st = ism_build_plan(h, n_rooms, rooms, mics, fs, c, fd_taps, h->seg_len, plan))) return st;
+    if (n_items) *n_items = (int64_t)plan.items.size();
+    if (est_records) *est_records = plan.est_records;
+    if (est_taps) *est_taps = plan.est_taps;
+    return ISM_OK;
+}
+
+// ------------------------------------------------------------------ staging + launch
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+static int ensure_slot(ism_handle *h, Slot &s, size_t bytes)
+{
+    if (s.cap >= bytes) return ISM_OK;
+    if (s.event && s.used) hipEventSynchronize(s.event);
+    free_slot(s);
+    size_t cap = std::max<size_t>(bytes + bytes / 4, 1 << 20);
+    hipError_t e = hipHostMalloc(&s.host, cap, hipHostMallocDefault);
+    if (e != hipSuccess) { s.host = nullptr; ism_set_error(h, "pinned allocation of %zu bytes failed", cap); return ISM_ENOMEM; }
+    e = hipMalloc(&s.dev, cap);
+    if (e != hipSuccess) { s.dev = nullptr; ism_set_error(h, "device allocation of %zu bytes failed", cap); return ISM_ENOMEM; }
+    e = hipEventCreateWithFlags(&s.event, hipEventDisableTiming);
+    if (e != hipSuccess) return ism_hip_fail(h, e, "hipEventCreate");
+    s.cap = cap;
+    return ISM_OK;
+}
+
+int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs, double c, int fd_taps,
+                 int order_mode, int precision, float *out, hipStream_t stream, double *t_ms)
+{
+    const int K = (fd_taps - 1) / 2;
+    const int n_items = (int)plan.items.size();
+    const int n_rooms = (int)plan.rooms.size();
+    if (n_items == 0) return ISM_OK;
+    if (h->device < 0) { ism_set_error(h, "no HIP device"); return ISM_EDEVICE; }
+    const int variant = precision == ISM_PREC_FP16_LUT ? VAR_LUT : VAR_FP32;
+    KernelEntry ke = select_segment_kernel(K, variant);
+    const int lds = seg_lds_bytes(plan.seg_max, K, variant);
+    if (lds > 160 * 1024) { ism_set_error(h, "segment needs %d bytes of LDS", lds); return ISM_ENOMEM; }
+
+    // layout: header | rooms | mics | items | counter | pow tables
+    size_t off_rooms = align_up(sizeof(LaunchDev), 256);
+    size_t off_mics = align_up(off_rooms + sizeof(RoomDev) * n_rooms, 256);
+    size_t off_items = align_up(off_mics + sizeof(double) * 3 * plan.n_mics_total, 256);
+    size_t off_cnt = align_up(off_items + sizeof(ItemDev) * n_items, 256);
+    size_t off_pow = align_up(off_cnt + 256, 256);  // counter at +0, stats at +64
+    size_t total = off_pow + sizeof(double) * (size_t)plan.pow_total;
+    size_t upload = off_cnt;
+
+    Slot &s = h->slots[h->next_slot];
+    h->next_slot ^= 1;
+    int st = ensure_slot(h, s, total);
+    if (st) return st;
+    if (s.used) {
+        hipError_t e = hipEventSynchronize(s.event);
+        if (e != hipSuccess) return ism_hip_fail(h, e, "hipEventSynchronize");
+    }
+    char *hb = (char *)s.host, *db = (char *)s.dev;
+    LaunchDev L{};
+    L.fs = fs;
+    L.c = c;
+    L.rooms = (const RoomDev *)(db + off_rooms);
+    L.mics = (const double *)(db + off_mics);
+    L.items = (const ItemDev *)(db + off_items);
+    L.counter = (uint32_t *)(db + off_cnt);
+    L.stats = (unsigned long long *)(db + off_cnt + 64);
+    L.pow_tab = (double *)(db + off_pow);
+    L.out = out;
+    L.n_rooms = n_rooms;
+    L.n_items = n_items;
+    L.K = K;
+    L.order_mode = order_mode;
+    L.fold = precision == ISM_PREC_FP32_PLAIN ? 0 : h->fold;
+    L.split32 = precision == ISM_PREC_FP32_SPLIT ? 1 : 0;
+    L.seg_max = plan.seg_max;
+    std::memcpy(hb, &L, sizeof L);
+    std::memcpy(hb + off_rooms, plan.rooms.data(), sizeof(RoomDev) * n_rooms);
+    std::memcpy(hb + off_mics, mics, sizeof(double) * 3 * plan.n_mics_total);
+    std::memcpy(hb + off_items, plan.items.data(), sizeof(ItemDev) * n_items);
+
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ke.sym, 64, lds);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    const int grid = (int)std::min<int64_t>(n_items, (int64_t)per_cu * h->n_cu);
+    const LaunchDev *Pd = (const LaunchDev *)db;
+
+    auto enqueue = [&](hipStream_t q) -> hipError_t {
+        hipError_t r = hipMemcpyAsync(db, hb, upload, hipMemcpyHostToDevice, q);
+        if (r != hipSuccess) return r;
+        r = launch_prologue(Pd, n_rooms, q);
+        if (r != hipSuccess) return r;
+        return ke.fn(Pd, grid, lds, q);
+    };
+
+    if (h->graphs) {
+        GraphKey key{(const void *)ke.fn, upload, grid, lds, n_rooms};
+        if (!s.gexec || !(s.key == key)) {
+            if (s.gexec) { hipGraphExecDestroy(s.gexec); s.gexec = nullptr; }
+            if (s.graph) { hipGraphDestroy(s.graph); s.graph = nullptr; }
+            // capture on the handle's own stream (the caller's may be the legacy
+            // default stream, which cannot be captured); replay on the caller's
+            if (!h->cap_stream) {
+                e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+                if (e != hipSuccess) { h->cap_stream = nullptr; return ism_hip_fail(h, e, "hipStreamCreate"); }
+            }
+            e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return ism_hip_fail(h, e, "hipStreamBeginCapture");
+            hipError_t e2 = enqueue(h->cap_stream);
+            e = hipStreamEndCapture(h->cap_stream, &s.graph);
+            if (e2 != hipSuccess) return ism_hip_fail(h, e2, "capture of the batch launch");
+            if (e != hipSuccess) return ism_hip_fail(h, e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&s.gexec, s.graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) { s.gexec = nullptr; return ism_hip_fail(h, e, "hipGraphInstantiate"); }
+            s.key = key;
+        }
+        e = hipGraphLaunch(s.gexec, stream);
+        if (e != hipSuccess) return ism_hip_fail(h, e, "hipGraphLaunch");
+    } else {
+        e = enqueue(stream);
+        if (e != hipSuccess) return ism_hip_fail(h, e, "segment launch");
+    }
+    e = hipEventRecord(s.event, stream);
+    if (e != hipSuccess) return ism_hip_fail(h, e, "hipEventRecord");
+    s.used = true;
+    h->last_slot = &s;
+    h->last_stats = db + off_cnt + 64;
+    (void)t_ms;
+    return ISM_OK;
+}
+
+extern "C" int ism_last_counts(ism_handle *h, int64_t counts[3])
+{
+    if (!h || !counts) return ISM_EINVAL;
+    counts[0] = counts[1] = counts[2] = 0;
+    if (!h->last_slot || !h->last_stats) return ISM_OK;
+    hipError_t e = hipEventSynchronize(h->last_slot->event);
+    if (e != hipSuccess) return ism_hip_fail(h, e, "hipEventSynchronize");
+    unsigned long long v[3];
+    e = hipMemcpy(v, h->last_stats, sizeof v, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return ism_hip_fail(h, e, "hipMemcpy of the work counters");
+    for (int i = 0; i < 3; ++i) counts[i] = (int64_t)v[i];
+    return ISM_OK;
+}
+
+extern "C" int ism_rir_batch(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics,
+                             double fs, double c, int fd_taps, int order_mode, int precision, float *out,
+                             ism_stream stream)
+{
+    if (!h) return ISM_EINVAL;
+    h->last_error.clear();
+    if (n_rooms < 0 || (n_rooms > 0 && (!rooms || !mics || !out))) {
+        ism_set_error(h, "NULL argument or negative room count");
+        return ISM_EINVAL;
+    }
+    int st = ism_validate_common(h, fs, c, fd_taps, order_mode, precision);
+    if (st) return st;
+    for (int i = 0; i < n_rooms; ++i)
+        if ((st = ism_validate_room(h, i, rooms[i], mics))) return st;
+    if (n_rooms == 0) return ISM_OK;
+    Plan &plan = h->plan;
+    if ((st = ism_build_plan(h, n_rooms, rooms, mics, fs, c, fd_taps, h->seg_len, plan))) return st;
+    return ism_run_plan(h, plan, mics, fs, c, fd_taps, order_mode, precision, out, (hipStream_t)stream, nullptr);
+}
+
+extern "C" int ism_rir(ism_handle *h, const double L[3], const double beta[6], const double src[3], int M,
+                       const double *mics, double fs, double c, int max_order, int order_mode, int rir_len,
+                       int fd_taps, int precision, float *out, ism_stream stream)
+{
+    if (!h) return ISM_EINVAL;
+    if (!L || !beta || !src || !mics || !out) {
+        ism_set_error(h, "NULL argument");
+        return ISM_EINVAL;
+    }
+    ism_room r;
+    std::memcpy(r.L, L, sizeof r.L);
+    std::memcpy(r.beta, beta, sizeof r.beta);
+    std::memcpy(r.src, src, sizeof r.src);
+    r.mic_offset = 0;
+    r.n_mics = M;
+    r.max_order = max_order;
+    r.rir_len = rir_len;
+    r.out_offset = 0;
+    return ism_rir_batch(h, 1, &r, mics, fs, c, fd_taps, order_mode, precision, out, stream);
+}
+
+// ------------------------------------------------------------------ autotuner
+extern "C" int ism_autotune(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics, double fs,
+                            double c, int fd_taps, int order_mode, int precision, float *out, ism_stream stream,
+                            const int *cand, int n_cand, int *best_seg_len)
+{
+    if (!h) return ISM_EINVAL;
+    static const int kDefault[] = {256, 512, 1024, 2048};
+    std::vector<int> cands;
+    if (cand && n_cand > 0) cands.assign(cand, cand + n_cand);
+    else cands.assign(kDefault, kDefault + 4);
+    hipStream_t q = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        ism_set_error(h, "hipEventCreate failed");
+        return ISM_EDEVICE;
+    }
+    const int saved = h->seg_len;
+    int best = saved;
+    float best_ms = 1e30f;
+    int st = ISM_OK;
+    for (int sl : cands) {
+        if (sl < 64 || sl > kSegMaxLimit || sl % 64) continue;
+        h->seg_len = sl;
+        // warm-up (graph capture, caches), then one timed run
+        if ((st = ism_rir_batch(h, n_rooms, rooms, mics, fs, c, fd_taps, order_mode, precision, out, stream))) break;
+        hipEventRecord(e0, q);
+        if ((st = ism_rir_batch(h, n_rooms, rooms, mics, fs, c, fd_taps, order_mode, precision, out, stream))) break;
+        hipEventRecord(e1, q);
+        if (hipEventSynchronize(e1) != hipSuccess) { st = ISM_EDEVICE; break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) { best_ms = ms; best = sl; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    h->seg_len = st == ISM_OK ? best : saved;
+    if (best_seg_len) *best_seg_len = h->seg_len;
+    return st;
+}

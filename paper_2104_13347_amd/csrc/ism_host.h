@@ -1,0 +1,81 @@
+// Host-side state of a libism handle.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ism.h"
+#include "ism_internal.h"
+
+namespace ism {
+
+struct Plan {
+    std::vector<RoomDev> rooms;
+    std::vector<ItemDev> items;
+    int64_t n_mics_total = 0;
+    int64_t pow_total = 0;
+    int seg_max = 0;
+    double est_taps = 0.0;
+    double est_records = 0.0;
+};
+
+struct GraphKey {
+    const void *fn = nullptr;
+    size_t upload = 0;
+    int grid = 0;
+    int lds = 0;
+    int n_rooms = 0;
+    bool operator==(const GraphKey &o) const
+    {
+        return fn == o.fn && upload == o.upload && grid == o.grid && lds == o.lds && n_rooms == o.n_rooms;
+    }
+};
+
+// A staging slot: pinned host image of the launch buffer, its device copy, the
+// event that marks the end of the last launch that read it, and the captured
+// launch graph.  Two slots alternate so that the host can plan the next batch
+// while the device still works on the previous one.
+struct Slot {
+    void *host = nullptr;
+    void *dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t event = nullptr;
+    bool used = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    GraphKey key;
+};
+
+struct ConvState;
+struct ServeState;
+
+}  // namespace ism
+
+struct ism_handle {
+    int device = 0;
+    int n_cu = 256;
+    int lds_per_cu = 160 * 1024;
+    int seg_len = 1024;
+    int fold = 8;
+    int graphs = 1;
+    std::string last_error;
+    ism::Slot slots[2];
+    int next_slot = 0;
+    ism::Plan plan;
+    hipStream_t cap_stream = nullptr; // stream used only to capture launch graphs
+    ism::Slot *last_slot = nullptr;   // slot of the last batch launch
+    void *last_stats = nullptr;       // its device work counters
+    ism::ConvState *conv = nullptr;
+};
+
+void ism_set_error(ism_handle *h, const char *fmt, ...);
+int ism_hip_fail(ism_handle *h, hipError_t e, const char *what);
+int ism_validate_common(ism_handle *h, double fs, double c, int fd_taps, int order_mode, int precision);
+int ism_validate_room(ism_handle *h, int idx, const ism_room &r, const double *mics);
+int ism_build_plan(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics, double fs, double c,
+                   int fd_taps, int seg_len, ism::Plan &plan);
+int ism_run_plan(ism_handle *h, const ism::Plan &plan, const double *mics, double fs, double c, int fd_taps,
+                 int order_mode, int precision, float *out, hipStream_t stream, double *t_ms);
+void ism_conv_release(ism_handle *h);
+void ism_serve_release(ism_handle *h);

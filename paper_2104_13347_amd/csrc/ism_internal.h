@@ -1,0 +1,75 @@
+// Internal layout shared by the HIP kernels and the host side of libism.so.
+#pragma once
+#include <stdint.h>
+
+namespace ism {
+
+// Work of one segment kernel launch lives in one device buffer: a LaunchDev
+// header, the room table, microphone positions, work items and the wall-power
+// tables.  Every scalar a kernel needs is read from the header, so a captured
+// graph of the launch sequence stays valid for any batch that fits the buffer.
+
+struct alignas(16) RoomDev {
+    double L[3];
+    double beta[6];
+    double src[3];
+    int32_t rir_len;
+    int32_t max_order;
+    int32_t n_mics;
+    int32_t mic_offset;
+    int64_t out_offset;
+    int32_t pow_offset;  // wall-power tables at pow_tab[pow_offset + wall * pow_stride + e]
+    int32_t pow_stride;  // exponents 0 .. pow_stride-1
+};
+
+// One work item: output samples [s0, s1) of the RIR of microphone `mic`
+// (absolute index into the microphone table) of room `room`.
+struct alignas(16) ItemDev {
+    int32_t room;
+    int32_t mic;
+    int32_t s0;
+    int32_t s1;
+};
+
+enum Variant : int32_t { VAR_FP32 = 0, VAR_LUT = 1 };
+
+struct alignas(16) LaunchDev {
+    double fs;
+    double c;
+    const RoomDev *rooms;
+    const double *mics;
+    const ItemDev *items;
+    double *pow_tab;
+    float *out;
+    uint32_t *counter;  // persistent-kernel work counter, zeroed by the prologue
+    unsigned long long *stats;  // [taps landing in outputs, records, images tested], zeroed by the prologue
+    int32_t n_rooms;
+    int32_t n_items;
+    int32_t K;            // (fd_taps - 1) / 2
+    int32_t order_mode;   // 0 index-L1, 1 reflections
+    int32_t fold;         // rounds between compensated folds (0: fold once at the end)
+    int32_t split32;      // 1: distance and delay split in FP32 (ablation)
+    int32_t seg_max;      // largest s1 - s0 of any item (sizes LDS)
+    int32_t pad_;
+};
+
+constexpr int kSegMaxLimit = 2048;  // largest supported segment (per-lane sums in registers)
+constexpr int kKMax = 127;          // largest half-length (255 taps)
+constexpr int kLutQ = 64;           // FP16 table steps per sample
+constexpr int kBufCap = 256;        // record ring (power of two)
+constexpr int kCols = 64;           // columns per enumeration chunk (one per lane)
+
+// LDS bytes of the segment kernel for a given segment capacity, K and variant.
+inline int seg_lds_bytes(int seg_max, int K, int variant)
+{
+    int acc = (seg_max + 4 * K + 63) / 64 * 64;         // float
+    int clm = (seg_max + 2 * K + 63) / 64 * 64;         // uint32
+    int bytes = acc * 4 + clm * 4;
+    bytes += kBufCap * 12;                              // f, g, n0rel
+    bytes += (kCols + 4) * 4 + kCols * 8 * 2 + kCols * 4 + kCols * 4 * 3 * 4;  // column chunk
+    bytes += (2 * K + 1) * 8;                           // generic-K trig table
+    if (variant == VAR_LUT) bytes += (2 * K + 1) * kLutQ * 4;
+    return bytes;
+}
+
+}  // namespace ism

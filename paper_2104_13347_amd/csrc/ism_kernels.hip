@@ -1,0 +1,606 @@
+// Image-source RIR kernels for gfx950 (paper section II.A: every image of the
+// source in a shoebox room adds a fractional-delay filter, centred on its delay,
+// into the RIR of each microphone).
+//
+// Design (one wave64 per workgroup, persistent over a queue of work items; an
+// item is the output segment [s0, s1) of one microphone's RIR):
+//
+//  * Enumeration in registers.  Only images whose rounded delay n0 can put a tap
+//    into the segment are visited: they lie in a spherical shell around the
+//    microphone.  The wave walks the (x, y) image columns 64 at a time; each
+//    lane derives the z-index intervals of its column that fall into the shell
+//    (at most four: two parities, each an interval with the inner hole cut
+//    out); a wave prefix sum flattens the images of 64 columns so that every
+//    lane evaluates one image per step.  Distance, delay and the integer /
+//    fractional split are FP64 and follow the same operation order as the
+//    definition ((dx^2 + dy^2) + dz^2, sqrt, (d fs) / c, floor(tau + 1/2)).
+//  * Records (f, g, n0) of valid images go to a 256-entry ring in LDS (stable,
+//    in enumeration order, via ballot + mbcnt).
+//  * Rounds: 64 records at a time, one per lane, the 2K+1 taps with k uniform
+//    across the wave (unrolled, constants folded).  Each tap is an LDS float add
+//    into the segment accumulator.  Lanes of one round must hold distinct n0 so
+//    that no two lanes of one ds_add hit the same address: a claim array with
+//    an LDS atomic min keeps the lowest lane of each n0 and defers the others to
+//    the ring's tail.  Every address therefore receives its adds in an order
+//    fixed by the data alone: the result is deterministic, with no float
+//    atomics on shared addresses and no scatter to HBM.
+//  * Compensated accumulation: every `fold` rounds each lane folds the FP32
+//    partial sums of its output samples into a Neumaier pair in registers.
+//  * The segment is written once, coalesced (lane-contiguous samples).
+//
+// Tap formula.  With t = k - f, sinc(t) = -(-1)^k sin(pi f) / (pi t), and the
+// Hann window w(t) = (1 + cos(P t)) / 2, P = pi / (K+1), expands by angle
+// addition into constants of k times per-record values of f:
+//     g h(k - f) = (-1)^k / (k - f) * (a0 + a1 cos(P k) + a2 sin(P k)),
+//     a0 = -g sin(pi f) / (2 pi), a1 = a0 cos(P f), a2 = a0 sin(P f).
+// Per tap: one subtraction (the sign (-1)^k folds into its operand order), one
+// v_rcp_f32, two FMAs, one multiply, one ds_add_f32.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ism_internal.h"
+
+namespace ism {
+
+#define DEV __device__ __forceinline__
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------- compile-time trig
+constexpr double cx_sin_red(double x)
+{  // |x| <= pi: Taylor series to well below double rounding
+    double x2 = x * x, term = x, sum = x;
+    for (int i = 1; i < 30; ++i) {
+        term *= -x2 / ((2.0 * i) * (2.0 * i + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double cx_cos_red(double x)
+{
+    double x2 = x * x, term = 1.0, sum = 1.0;
+    for (int i = 1; i < 30; ++i) {
+        term *= -x2 / ((2.0 * i - 1.0) * (2.0 * i));
+        sum += term;
+    }
+    return sum;
+}
+
+template <int K>
+struct TapConst {
+    float c[2 * K + 1];
+    float s[2 * K + 1];
+    constexpr TapConst() : c(), s()
+    {
+        for (int i = 0; i <= 2 * K; ++i) {
+            double x = kPi * (double)(i - K) / (double)(K + 1);  // |x| < pi
+            c[i] = (float)cx_cos_red(x);
+            s[i] = (float)cx_sin_red(x);
+        }
+    }
+};
+
+// ---------------------------------------------------------------- wave helpers
+DEV int lane_id() { return __lane_id(); }
+DEV uint64_t ballot(bool p) { return __ballot(p); }
+DEV int mbcnt(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+DEV int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+DEV int wave_excl_scan(int v, int &total)
+{
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(x, d, 64);
+        if (lane_id() >= d) x += y;
+    }
+    total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+DEV void lds_add(float *p, float v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+DEV void neumaier(float &s, float &c, float p)
+{
+    float t = s + p;
+    float e = (fabsf(s) >= fabsf(p)) ? ((s - t) + p) : ((p - t) + s);
+    c += e;
+    s = t;
+}
+
+// Per-record coefficients a0, a1, a2 of the tap formula (FP32; |f| <= 1/2).
+DEV void tap_coeffs(float f, float g, float P, bool wide, float &a0, float &a1, float &a2)
+{
+    const float x = 3.14159265358979f * f;  // |x| <= pi/2
+    const float x2 = x * x;
+    // sin(x)/x, Taylor series through x^12 (truncation < 5e-10 on |x| <= pi/2)
+    float p = fmaf(x2, 1.0f / 6227020800.0f, -1.0f / 39916800.0f);
+    p = fmaf(x2, p, 1.0f / 362880.0f);
+    p = fmaf(x2, p, -1.0f / 5040.0f);
+    p = fmaf(x2, p, 1.0f / 120.0f);
+    p = fmaf(x2, p, -1.0f / 6.0f);
+    p = fmaf(x2, p, 1.0f);
+    a0 = -0.5f * g * (f * p);  // -g sin(pi f) / (2 pi)
+    const float y = P * f;     // |y| <= pi / (2(K+1))
+    const float y2 = y * y;
+    float cy, sy;
+    if (!wide) {
+        // K >= 4: |y| <= pi/10, truncation below 3e-9
+        cy = fmaf(y2, fmaf(y2, fmaf(y2, -1.0f / 720.0f, 1.0f / 24.0f), -0.5f), 1.0f);
+        sy = y * fmaf(y2, fmaf(y2, fmaf(y2, -1.0f / 5040.0f, 1.0f / 120.0f), -1.0f / 6.0f), 1.0f);
+    } else {
+        // K < 4: |y| up to pi/2, Taylor series through y^12 / y^13 (truncation < 7e-8)
+        cy = fmaf(y2, 1.0f / 479001600.0f, -1.0f / 3628800.0f);
+        cy = fmaf(y2, cy, 1.0f / 40320.0f);
+        cy = fmaf(y2, cy, -1.0f / 720.0f);
+        cy = fmaf(y2, cy, 1.0f / 24.0f);
+        cy = fmaf(y2, cy, -0.5f);
+        cy = fmaf(y2, cy, 1.0f);
+        float q = fmaf(y2, 1.0f / 6227020800.0f, -1.0f / 39916800.0f);
+        q = fmaf(y2, q, 1.0f / 362880.0f);
+        q = fmaf(y2, q, -1.0f / 5040.0f);
+        q = fmaf(y2, q, 1.0f / 120.0f);
+        q = fmaf(y2, q, -1.0f / 6.0f);
+        q = fmaf(y2, q, 1.0f);
+        sy = y * q;
+    }
+    a1 = a0 * cy;
+    a2 = a0 * sy;
+}
+
+// 2K+1 taps of one record, K known at compile time: constants fold to literals.
+template <int K>
+DEV void taps_fp32_ct(float *accp, float f, float a0, float a1, float a2)
+{
+    constexpr TapConst<K> T{};
+#pragma unroll
+    for (int k = -K; k <= K; ++k) {
+        const float t = (k & 1) ? (f - (float)k) : ((float)k - f);
+        const float r = __builtin_amdgcn_rcpf(t);
+        const float num = fmaf(a2, T.s[k + K], fmaf(a1, T.c[k + K], a0));
+        lds_add(accp + k, num * r);
+    }
+}
+
+// Runtime K: constants from an LDS table (uniform address, broadcast read).
+DEV void taps_fp32_rt(float *accp, int K, const float2 *trig, float f, float a0, float a1, float a2)
+{
+    for (int k = -K; k <= K; ++k) {
+        const float2 cs = trig[k + K];
+        const float kf = (float)k;
+        const float t = (k & 1) ? (f - kf) : (kf - f);
+        const float r = __builtin_amdgcn_rcpf(t);
+        const float num = fmaf(a2, cs.y, fmaf(a1, cs.x, a0));
+        lds_add(accp + k, num * r);
+    }
+}
+
+// FP16 table variant: h(k - f) from pairs (h(k - f_j), h(k - f_{j+1})), f_j = -1/2 + j/Q,
+// linear interpolation, times g.
+template <int KT>
+DEV void taps_lut(float *accp, int Krt, const uint32_t *lut, float f, float g)
+{
+    const int K = KT > 0 ? KT : Krt;
+    const float p = (f + 0.5f) * (float)kLutQ;
+    int j = (int)p;
+    j = j > kLutQ - 1 ? kLutQ - 1 : (j < 0 ? 0 : j);
+    const float al = p - (float)j;
+    const uint32_t *row = lut + j;
+#pragma unroll 9
+    for (int k = -K; k <= K; ++k) {
+        const uint32_t pr = row[(k + K) * kLutQ];
+        const float h0 = (float)__builtin_bit_cast(_Float16, (unsigned short)(pr & 0xFFFFu));
+        const float h1 = (float)__builtin_bit_cast(_Float16, (unsigned short)(pr >> 16));
+        lds_add(accp + k, g * fmaf(al, h1 - h0, h0));
+    }
+}
+
+DEV double hann_sinc(double t, int K)
+{
+    double s = (t == 0.0) ? 1.0 : sin(kPi * t) / (kPi * t);
+    return s * 0.5 * (1.0 + cos(kPi * t / (double)(K + 1)));
+}
+
+// ---------------------------------------------------------------- prologue
+// Zero the work counter and build the wall-power tables beta^e (repeated
+// multiplication, so beta^0 = 1 for beta = 0), one thread per (room, wall).
+__global__ void ism_prologue(const LaunchDev *P)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid == 0) *P->counter = 0u;
+    if (gid < 3) P->stats[gid] = 0ull;
+    if (gid >= P->n_rooms * 6) return;
+    const int room = gid / 6, wall = gid % 6;
+    const RoomDev &R = P->rooms[room];
+    double *t = P->pow_tab + R.pow_offset + wall * R.pow_stride;
+    const double b = R.beta[wall];
+    double v = 1.0;
+    for (int e = 0; e < R.pow_stride; ++e) {
+        t[e] = v;
+        v *= b;
+    }
+}
+
+// ---------------------------------------------------------------- segment kernel
+struct Lds {
+    float *acc;
+    uint32_t *claim;
+    float *bf, *bg;
+    int32_t *bn;
+    int32_t *coff;      // kCols + 1 prefix offsets
+    double *crho2, *cbxy;
+    int32_t *cord;      // order index of the column (x and y part)
+    int32_t *iq0, *icum, *iw;  // 4 intervals per column
+    float2 *trig;
+    uint32_t *lut;
+};
+
+DEV Lds carve(char *base, int seg_max, int K, int variant)
+{
+    Lds s;
+    const int acc = (seg_max + 4 * K + 63) / 64 * 64;
+    const int clm = (seg_max + 2 * K + 63) / 64 * 64;
+    char *p = base;
+    s.crho2 = (double *)p; p += kCols * 8;
+    s.cbxy = (double *)p; p += kCols * 8;
+    s.acc = (float *)p; p += acc * 4;
+    s.claim = (uint32_t *)p; p += clm * 4;
+    s.bf = (float *)p; p += kBufCap * 4;
+    s.bg = (float *)p; p += kBufCap * 4;
+    s.bn = (int32_t *)p; p += kBufCap * 4;
+    s.coff = (int32_t *)p; p += (kCols + 4) * 4;
+    s.cord = (int32_t *)p; p += kCols * 4;
+    s.iq0 = (int32_t *)p; p += kCols * 4 * 4;
+    s.icum = (int32_t *)p; p += kCols * 4 * 4;
+    s.iw = (int32_t *)p; p += kCols * 4 * 4;
+    s.trig = (float2 *)p; p += (2 * K + 1) * 8;
+    s.lut = (uint32_t *)p;
+    (void)variant;
+    return s;
+}
+
+extern __shared__ __attribute__((aligned(16))) char ism_lds[];
+
+DEV long iabs(long a) { return a < 0 ? -a : a; }
+
+template <int KT, int VAR>
+__global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__ P)
+{
+    const int lane = lane_id();
+    const int K = KT > 0 ? KT : P->K;
+    const int seg_max = P->seg_max;
+    Lds S = carve(ism_lds, seg_max, K, VAR);
+    const double fs = P->fs, cs = P->c;
+    const int order_mode = P->order_mode;
+    const int fold = P->fold;
+    const int split32 = P->split32;
+    const float Pw = (float)(kPi / (double)(K + 1));
+
+    // per-launch tables
+    for (int i = lane; i <= 2 * K; i += 64) {
+        const double x = kPi * (double)(i - K) / (double)(K + 1);
+        S.trig[i] = make_float2((float)cos(x), (float)sin(x));
+    }
+    if (VAR == VAR_LUT) {
+        const int n = (2 * K + 1) * kLutQ;
+        for (int idx = lane; idx < n; idx += 64) {
+            const int k = idx / kLutQ - K, j = idx % kLutQ;
+            const double f0 = -0.5 + (double)j / kLutQ, f1 = -0.5 + (double)(j + 1) / kLutQ;
+            const unsigned short h0 = __builtin_bit_cast(unsigned short, (_Float16)(float)hann_sinc(k - f0, K));
+            const unsigned short h1 = __builtin_bit_cast(unsigned short, (_Float16)(float)hann_sinc(k - f1, K));
+            S.lut[idx] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+        }
+    }
+    {
+        const int acc_n = (seg_max + 4 * K + 63) / 64 * 64;
+        for (int i = lane; i < acc_n; i += 64) S.acc[i] = 0.0f;
+    }
+    __syncthreads();
+
+    constexpr int NJ = kSegMaxLimit / 64;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = (int)atomicAdd(P->counter, 1u);
+        item = uniform(__shfl(item, 0, 64));
+        if (item >= P->n_items) break;
+
+        const ItemDev it = P->items[item];
+        const RoomDev &R = P->rooms[it.room];
+        const double Lx = R.L[0], Ly = R.L[1], Lz = R.L[2];
+        const double sx = R.src[0], sy = R.src[1], sz = R.src[2];
+        const double rx = P->mics[3 * it.mic + 0], ry = P->mics[3 * it.mic + 1],
+                     rz = P->mics[3 * it.mic + 2];
+        const int rir_len = R.rir_len, N = R.max_order;
+        const int s0 = it.s0, s1 = it.s1, Sn = s1 - s0;
+        const int nlo = max(s0 - K, 0), nhi = min(s1 - 1 + K, rir_len - 1 + K);
+        const int rel = s0 - K;  // n0rel = n0 - rel in [0, Sn + 2K)
+        const double *pz0 = P->pow_tab + R.pow_offset + 4 * R.pow_stride;
+        const double *pzL = pz0 + R.pow_stride;
+        const double *px0 = P->pow_tab + R.pow_offset;
+        const int pmax = R.pow_stride - 1;
+
+        // distance shell of the records this segment needs (widened: every test below is exact)
+        const double dlo = fmax(0.0, ((double)nlo - 0.5) * cs / fs * (1.0 - 1e-12) - 1e-12);
+        const double dhi = ((double)nhi + 0.5) * cs / fs * (1.0 + 1e-12) + 1e-12;
+        const double dlo2 = dlo * dlo, dhi2 = dhi * dhi;
+        long alo = (long)floor((rx - dhi) / Lx) - 1, ahi = (long)ceil((rx + dhi) / Lx) + 1;
+        long blo = (long)floor((ry - dhi) / Ly) - 1, bhi = (long)ceil((ry + dhi) / Ly) + 1;
+        if (N >= 0) {
+            const long lim = order_mode == 0 ? 2L * N + 2 : (long)N + 1;
+            alo = max(alo, -lim); ahi = min(ahi, lim);
+            blo = max(blo, -lim); bhi = min(bhi, lim);
+        }
+        const int nb = (int)(bhi - blo + 1);
+        const int ncols = (int)(ahi - alo + 1) * nb;
+
+        float sum[NJ], cmp[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) { sum[j] = 0.0f; cmp[j] = 0.0f; }
+
+        int head = 0, cnt = 0, rounds = 0;
+        uint32_t n_taps = 0, n_rec = 0, n_img = 0;  // per lane
+
+        auto fold_now = [&]() {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int i = lane + 64 * j;
+                if (i < Sn) {
+                    float *a = S.acc + 2 * K + i;
+                    const float p = *a;
+                    *a = 0.0f;
+                    neumaier(sum[j], cmp[j], p);
+                }
+            }
+        };
+
+        auto round = [&]() {
+            const int nact = cnt < 64 ? cnt : 64;
+            const bool act = lane < nact;
+            const int slot = (head + lane) & (kBufCap - 1);
+            float f = 0.0f, g = 0.0f;
+            int nr = 0;
+            if (act) { f = S.bf[slot]; g = S.bg[slot]; nr = S.bn[slot]; }
+            if (act) S.claim[nr] = 0xFFFFFFFFu;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (act) atomicMin(&S.claim[nr], (uint32_t)lane);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const bool lead = act && (S.claim[nr] == (uint32_t)lane);
+            const bool dfr = act && !lead;
+            const uint64_t dm = ballot(dfr);
+            const int nd = __popcll(dm);
+            if (dfr) {
+                const int ts = (head + cnt + mbcnt(dm)) & (kBufCap - 1);
+                S.bf[ts] = f; S.bg[ts] = g; S.bn[ts] = nr;
+            }
+            head = (head + nact) & (kBufCap - 1);
+            cnt = cnt - nact + nd;
+            if (lead) {
+                // taps of this record that land in [s0, s1): n0 + k with n0 = nr + rel
+                const int lo = max(nr + rel - K, s0), hi = min(nr + rel + K, s1 - 1);
+                n_taps += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+                ++n_rec;
+                float *accp = S.acc + (nr + K);  // acc index of tap k is nr + K + k
+                if (VAR == VAR_LUT) {
+                    taps_lut<KT>(accp, K, S.lut, f, g);
+                } else {
+                    float a0, a1, a2;
+                    tap_coeffs(f, g, Pw, K < 4, a0, a1, a2);
+                    if (KT > 0) taps_fp32_ct<(KT > 0 ? KT : 1)>(accp, f, a0, a1, a2);
+                    else taps_fp32_rt(accp, K, S.trig, f, a0, a1, a2);
+                }
+            }
+            ++rounds;
+            if (fold > 0 && (rounds % fold) == 0) fold_now();
+        };
+
+        for (int c0 = 0; c0 < ncols; c0 += kCols) {
+            // ---- column chunk: one (a, b) column per lane
+            const int ci = c0 + lane;
+            int q0[4] = {0, 0, 0, 0}, len[4] = {0, 0, 0, 0}, wv[4] = {0, 0, 0, 0};
+            double rho2 = 0.0, bxy = 0.0;
+            int ordxy = 0;
+            if (ci < ncols) {
+                const int ca = ci / nb;
+                const long a = alo + ca, b = blo + (ci - ca * nb);
+                const int u = (int)(a & 1), v = (int)(b & 1);
+                const long n = (a + u) >> 1, l = (b + v) >> 1;
+                const double X = (u ? -sx : sx) + (2.0 * (double)n) * Lx;
+                const double Y = (v ? -sy : sy) + (2.0 * (double)l) * Ly;
+                const double dx = X - rx, dy = Y - ry;
+                rho2 = dx * dx + dy * dy;
+                long qlim_lo = -(1L << 40), qlim_hi = (1L << 40);
+                bool ok = rho2 < dhi2;
+                if (N >= 0) {
+                    const long oxy = order_mode == 0 ? iabs(n) + iabs(l) : iabs(2 * n - u) + iabs(2 * l - v);
+                    ordxy = (int)oxy;
+                    if (oxy > N) ok = false;
+                }
+                if (ok) {
+                    const int ex0 = (int)min(iabs(n - u), (long)pmax), exL = (int)min(iabs(n), (long)pmax);
+                    const int ey0 = (int)min(iabs(l - v), (long)pmax), eyL = (int)min(iabs(l), (long)pmax);
+                    bxy = ((px0[ex0] * px0[R.pow_stride + exL]) * px0[2 * R.pow_stride + ey0]) *
+                          px0[3 * R.pow_stride + eyL];
+                    const double zb = sqrt(dhi2 - rho2);
+                    const double za = dlo2 > rho2 ? sqrt(dlo2 - rho2) : 0.0;
+                    const double inv2L = 0.5 / Lz;
+                    int ni = 0;
+                    for (int w = 0; w < 2; ++w) {
+                        // dz = (+-sz + 2 q Lz) - rz
+                        const double off = rz - (w ? -sz : sz);
+                        long qlo = (long)ceil((off - zb) * inv2L - 1e-9);
+                        long qhi = (long)floor((off + zb) * inv2L + 1e-9);
+                        if (N >= 0) {
+                            const long rem = N - ordxy;
+                            if (order_mode == 0) { qlim_lo = -rem; qlim_hi = rem; }
+                            else { qlim_lo = (w - rem + 1) >> 1; qlim_hi = (w + rem) >> 1; }
+                            // (w - rem + 1) >> 1 = ceil((w - rem) / 2)
+                            qlo = max(qlo, qlim_lo); qhi = min(qhi, qlim_hi);
+                        }
+                        if (qlo > qhi) continue;
+                        long hlo = 1, hhi = 0;  // empty hole
+                        if (za > 0.0) {
+                            hlo = (long)ceil((off - za) * inv2L + 1e-9);
+                            hhi = (long)floor((off + za) * inv2L - 1e-9);
+                        }
+                        if (hlo <= hhi && hhi >= qlo && hlo <= qhi) {
+                            if (hlo > qlo) { q0[ni] = (int)qlo; len[ni] = (int)(hlo - qlo); wv[ni] = w; ++ni; }
+                            if (hhi < qhi) { q0[ni] = (int)(hhi + 1); len[ni] = (int)(qhi - hhi); wv[ni] = w; ++ni; }
+                        } else {
+                            q0[ni] = (int)qlo; len[ni] = (int)(qhi - qlo + 1); wv[ni] = w; ++ni;
+                        }
+                    }
+                }
+            }
+            const int ctot = len[0] + len[1] + len[2] + len[3];
+            int T;
+            const int off = wave_excl_scan(ctot, T);
+            __syncthreads();
+            S.coff[lane] = off;
+            if (lane == 63) S.coff[64] = T;
+            S.crho2[lane] = rho2;
+            S.cbxy[lane] = bxy;
+            S.cord[lane] = ordxy;
+            int cum = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                cum += len[i];
+                S.iq0[lane * 4 + i] = q0[i];
+                S.icum[lane * 4 + i] = cum;
+                S.iw[lane * 4 + i] = wv[i];
+            }
+            __syncthreads();
+
+            // ---- flattened images of the chunk, one per lane per step
+            for (int x0 = 0; x0 < T; x0 += 64) {
+                const int x = x0 + lane;
+                bool valid = false;
+                float rf = 0.0f, rg = 0.0f;
+                int rn = 0;
+                if (x < T) {
+                    ++n_img;
+                    int c = 0;
+#pragma unroll
+                    for (int st = 32; st >= 1; st >>= 1)
+                        if (S.coff[c + st] <= x) c += st;
+                    const int loc = x - S.coff[c];
+                    const int e0 = S.icum[c * 4 + 0], e1 = S.icum[c * 4 + 1], e2 = S.icum[c * 4 + 2];
+                    const int iv = (loc >= e0) + (loc >= e1) + (loc >= e2);
+                    const int before = iv == 0 ? 0 : S.icum[c * 4 + iv - 1];
+                    const long q = (long)S.iq0[c * 4 + iv] + (loc - before);
+                    const int w = S.iw[c * 4 + iv];
+                    bool ordok = true;
+                    if (N >= 0) {
+                        const long oz = order_mode == 0 ? iabs(q) : iabs(2 * q - w);
+                        ordok = (long)S.cord[c] + oz <= N;
+                    }
+                    const double Z = (w ? -sz : sz) + (2.0 * (double)q) * Lz;
+                    const double dz = Z - rz;
+                    const double d2 = S.crho2[c] + dz * dz;
+                    const double d = sqrt(d2);
+                    const double tau = d * fs / cs;
+                    const double n0d = floor(tau + 0.5);
+                    int n0 = (int)n0d;
+                    double fr = tau - n0d;
+                    if (split32) {
+                        // ablation: the same split in FP32 arithmetic
+                        const float d2f = (float)S.crho2[c] + (float)dz * (float)dz;
+                        const float tauf = sqrtf(d2f) * (float)fs / (float)cs;
+                        const float n0f = floorf(tauf + 0.5f);
+                        n0 = (int)n0f;
+                        fr = (double)(tauf - n0f);
+                    }
+                    valid = ordok && n0 >= nlo && n0 <= nhi;
+                    if (valid) {
+                        const int ez0 = (int)min(iabs(q - w), (long)pmax), ezL = (int)min(iabs(q), (long)pmax);
+                        const double B = (S.cbxy[c] * pz0[ez0]) * pzL[ezL];
+                        const double gd = B / (4.0 * kPi * d);
+                        rg = (float)gd;
+                        rf = (float)fr;
+                        if (rf == 0.0f) rf = 0x1p-40f;  // integer delay: exact Kronecker limit
+                        rn = n0 - rel;
+                    }
+                }
+                const uint64_t vm = ballot(valid);
+                if (valid) {
+                    const int ts = (head + cnt + mbcnt(vm)) & (kBufCap - 1);
+                    S.bf[ts] = rf; S.bg[ts] = rg; S.bn[ts] = rn;
+                }
+                cnt += __popcll(vm);
+                while (cnt >= 64) round();
+            }
+        }
+        while (cnt > 0) round();
+        fold_now();
+
+        // ---- store the segment (coalesced), then clear the accumulator
+        float *o = P->out + R.out_offset + (long)(it.mic - R.mic_offset) * rir_len + s0;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int i = lane + 64 * j;
+            if (i < Sn) o[i] = sum[j] + cmp[j];
+        }
+        const int acc_n = Sn + 4 * K;
+        for (int i = lane; i < acc_n; i += 64) S.acc[i] = 0.0f;
+        // work counters of the item (one atomic per wave)
+        unsigned long long t = n_taps, r = n_rec, im = n_img;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            t += __shfl_xor(t, d, 64);
+            r += __shfl_xor(r, d, 64);
+            im += __shfl_xor(im, d, 64);
+        }
+        if (lane == 0) {
+            atomicAdd(P->stats + 0, t);
+            atomicAdd(P->stats + 1, r);
+            atomicAdd(P->stats + 2, im);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- launch glue
+template <int KT, int VAR>
+static hipError_t launch_t(const LaunchDev *P, int grid, int lds, hipStream_t st)
+{
+    hipLaunchKernelGGL((ism_segments<KT, VAR>), dim3(grid), dim3(64), lds, st, P);
+    return hipGetLastError();
+}
+
+typedef hipError_t (*LaunchFn)(const LaunchDev *, int, int, hipStream_t);
+typedef const void *KernelSym;
+
+template <int KT, int VAR>
+static const void *sym_t() { return reinterpret_cast<const void *>(&ism_segments<KT, VAR>); }
+
+struct KernelEntry { LaunchFn fn; const void *sym; };
+
+KernelEntry select_segment_kernel(int K, int variant)
+{
+#define ISM_CASE(KK)                                                                      \
+    if (K == KK) {                                                                        \
+        if (variant == VAR_LUT) return {launch_t<KK, VAR_LUT>, sym_t<KK, VAR_LUT>()};      \
+        return {launch_t<KK, VAR_FP32>, sym_t<KK, VAR_FP32>()};                            \
+    }
+    ISM_CASE(4)
+    ISM_CASE(40)
+    ISM_CASE(63)
+#undef ISM_CASE
+    if (variant == VAR_LUT) return {launch_t<0, VAR_LUT>, sym_t<0, VAR_LUT>()};
+    return {launch_t<0, VAR_FP32>, sym_t<0, VAR_FP32>()};
+}
+
+hipError_t launch_prologue(const LaunchDev *P, int n_rooms, hipStream_t st)
+{
+    const int n = n_rooms * 6 > 0 ? n_rooms * 6 : 1;
+    hipLaunchKernelGGL(ism_prologue, dim3((n + 255) / 256), dim3(256), 0, st, P);
+    return hipGetLastError();
+}
+
+}  // namespace ism

@@ -1,0 +1,236 @@
+"""Thin ctypes binding of libism.so (C-ABI declared in include/ism.h).
+
+Argument marshalling only: every step of the RIR path runs in the library's HIP
+kernels.  torch supplies device memory (``Tensor.data_ptr()``) and streams
+(``torch.cuda.current_stream().cuda_stream``).  If the library is not built the
+import fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libism.so")
+
+ISM_OK, ISM_EINVAL, ISM_EDOMAIN, ISM_ENOMEM, ISM_EDEVICE, ISM_EBUSY = 0, -1, -2, -3, -4, -5
+ORDER_INDEX_L1, ORDER_REFLECTIONS = 0, 1
+PREC_FP32_COMP, PREC_FP16_LUT, PREC_FP32_SPLIT, PREC_FP32_PLAIN = 0, 1, 2, 3
+
+# exported symbols (kept in step with include/ism.h)
+EXPORTS = [
+    "ism_create", "ism_destroy", "ism_strerror", "ism_last_error", "ism_version", "ism_rir",
+    "ism_rir_batch", "ism_batch_plan_stats", "ism_last_counts", "ism_set_tuning", "ism_get_tuning",
+    "ism_autotune", "ism_convolve_batch",
+]
+
+ROOM_DTYPE = np.dtype([("L", np.float64, 3), ("beta", np.float64, 6), ("src", np.float64, 3),
+                       ("mic_offset", np.int32), ("n_mics", np.int32), ("max_order", np.int32),
+                       ("rir_len", np.int32), ("out_offset", np.int64)], align=True)
+assert ROOM_DTYPE.itemsize == 120
+
+
+class IsmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libism.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() or "
+                          "python paper_2104_13347_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, i32p, i64p, fp = (ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_float))
+    ci, cd = ctypes.c_int, ctypes.c_double
+    L.ism_create.argtypes = [ctypes.POINTER(vp)]
+    L.ism_create.restype = ci
+    L.ism_destroy.argtypes = [vp]
+    L.ism_destroy.restype = None
+    L.ism_strerror.argtypes = [ci]
+    L.ism_strerror.restype = ctypes.c_char_p
+    L.ism_last_error.argtypes = [vp]
+    L.ism_last_error.restype = ctypes.c_char_p
+    L.ism_version.restype = ci
+    L.ism_rir.argtypes = [vp, dp, dp, dp, ci, dp, cd, cd, ci, ci, ci, ci, ci, vp, vp]
+    L.ism_rir.restype = ci
+    L.ism_rir_batch.argtypes = [vp, ci, vp, dp, cd, cd, ci, ci, ci, vp, vp]
+    L.ism_rir_batch.restype = ci
+    L.ism_batch_plan_stats.argtypes = [vp, ci, vp, dp, cd, cd, ci, i64p, dp, dp]
+    L.ism_batch_plan_stats.restype = ci
+    L.ism_last_counts.argtypes = [vp, i64p]
+    L.ism_last_counts.restype = ci
+    L.ism_set_tuning.argtypes = [vp, ci, ci, ci]
+    L.ism_set_tuning.restype = ci
+    L.ism_get_tuning.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    L.ism_get_tuning.restype = ci
+    L.ism_autotune.argtypes = [vp, ci, vp, dp, cd, cd, ci, ci, ci, vp, vp, ctypes.POINTER(ci), ci,
+                               ctypes.POINTER(ci)]
+    L.ism_autotune.restype = ci
+    L.ism_convolve_batch.argtypes = [vp, ci, ci, vp, i64p, i32p, vp, ci, ci, fp, vp, ci, vp, vp]
+    L.ism_convolve_batch.restype = ci
+    _lib = L
+    return L
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def rooms_array(batch):
+    """Pack a scene batch (see scenes.pack) into the C ism_room layout."""
+    R = len(batch["rir_len"])
+    r = np.zeros(R, dtype=ROOM_DTYPE)
+    r["L"] = batch["L"]
+    r["beta"] = batch["beta"]
+    r["src"] = batch["src"]
+    r["mic_offset"] = batch["mic_offset"]
+    r["n_mics"] = batch["n_mics"]
+    r["max_order"] = batch["max_order"]
+    r["rir_len"] = batch["rir_len"]
+    r["out_offset"] = batch["out_offset"]
+    return r
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+class Handle:
+    """Owns an ism_handle (device buffers, pinned staging, tuning state, graphs)."""
+
+    def __init__(self):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        rc = self.lib.ism_create(ctypes.byref(h))
+        if rc != ISM_OK:
+            raise IsmError(rc, "ism_create failed: " + self.lib.ism_strerror(rc).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ism_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != ISM_OK:
+            raise IsmError(rc, self.lib.ism_last_error(self.h).decode() or
+                           self.lib.ism_strerror(rc).decode())
+
+    # -- tuning
+    def set_tuning(self, seg_len=0, fold=0, graphs=-1):
+        self._check(self.lib.ism_set_tuning(self.h, int(seg_len), int(fold), int(graphs)))
+
+    def get_tuning(self):
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.ism_get_tuning(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"seg_len": a.value, "fold": b.value, "graphs": c.value}
+
+    # -- RIRs
+    def rir(self, L, beta, src, mics, fs, c, max_order, rir_len, fd_taps,
+            order_mode=ORDER_INDEX_L1, precision=PREC_FP32_COMP, out=None, stream=None):
+        """One room: returns (or fills) a float32 device tensor [M, rir_len]."""
+        import torch
+        L = np.ascontiguousarray(L, dtype=np.float64)
+        beta = np.ascontiguousarray(beta, dtype=np.float64)
+        src = np.ascontiguousarray(src, dtype=np.float64)
+        mics = np.ascontiguousarray(np.atleast_2d(mics), dtype=np.float64)
+        M = mics.shape[0]
+        if out is None:
+            out = torch.empty((M, int(rir_len)), dtype=torch.float32, device="cuda")
+        rc = self.lib.ism_rir(self.h, _dptr(L), _dptr(beta), _dptr(src), int(M), _dptr(mics), float(fs),
+                              float(c), int(max_order), int(order_mode), int(rir_len), int(fd_taps),
+                              int(precision), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+        self._check(rc)
+        return out
+
+    def rir_batch(self, batch, precision=PREC_FP32_COMP, out=None, stream=None, rooms=None):
+        """A scene batch in one launch: returns (or fills) a flat float32 device tensor."""
+        import torch
+        if rooms is None:
+            rooms = rooms_array(batch)
+        mics = np.ascontiguousarray(batch["mics"], dtype=np.float64)
+        if out is None:
+            out = torch.empty(int(batch["out_size"]), dtype=torch.float32, device="cuda")
+        rc = self.lib.ism_rir_batch(self.h, len(rooms), rooms.ctypes.data_as(ctypes.c_void_p), _dptr(mics),
+                                    float(batch["fs"]), float(batch["c"]), int(batch["fd_taps"]),
+                                    int(batch["order_mode"]), int(precision), ctypes.c_void_p(out.data_ptr()),
+                                    _stream_handle(stream))
+        self._check(rc)
+        return out
+
+    def last_counts(self):
+        """(taps, records, images tested) of the last RIR call; waits for it."""
+        c = (ctypes.c_int64 * 3)()
+        self._check(self.lib.ism_last_counts(self.h, c))
+        return {"taps": int(c[0]), "records": int(c[1]), "images": int(c[2])}
+
+    def plan_stats(self, batch):
+        rooms = rooms_array(batch)
+        mics = np.ascontiguousarray(batch["mics"], dtype=np.float64)
+        n = ctypes.c_int64()
+        rec, taps = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.ism_batch_plan_stats(self.h, len(rooms), rooms.ctypes.data_as(ctypes.c_void_p),
+                                                  _dptr(mics), float(batch["fs"]), float(batch["c"]),
+                                                  int(batch["fd_taps"]), ctypes.byref(n), ctypes.byref(rec),
+                                                  ctypes.byref(taps)))
+        return {"items": n.value, "est_records": rec.value, "est_taps": taps.value}
+
+    def autotune(self, batch, candidates=None, precision=PREC_FP32_COMP, out=None, stream=None):
+        import torch
+        rooms = rooms_array(batch)
+        mics = np.ascontiguousarray(batch["mics"], dtype=np.float64)
+        if out is None:
+            out = torch.empty(int(batch["out_size"]), dtype=torch.float32, device="cuda")
+        cand = list(candidates or [])
+        carr = (ctypes.c_int * max(1, len(cand)))(*cand)
+        best = ctypes.c_int()
+        self._check(self.lib.ism_autotune(self.h, len(rooms), rooms.ctypes.data_as(ctypes.c_void_p), _dptr(mics),
+                                          float(batch["fs"]), float(batch["c"]), int(batch["fd_taps"]),
+                                          int(batch["order_mode"]), int(precision),
+                                          ctypes.c_void_p(out.data_ptr()), _stream_handle(stream), carr,
+                                          len(cand), ctypes.byref(best)))
+        return best.value
+
+    # -- source convolution
+    def convolve_batch(self, rirs, rir_offset, rir_len, M, src, out_len, snr_db=None, z=None, use_mfma=True,
+                       out=None, stream=None):
+        """RIRs (flat device tensor) convolved with sources [R, src_len] (device), plus noise."""
+        import torch
+        R = int(src.shape[0])
+        off = np.ascontiguousarray(rir_offset, dtype=np.int64)
+        ln = np.ascontiguousarray(rir_len, dtype=np.int32)
+        if out is None:
+            out = torch.empty((R, int(M), int(out_len)), dtype=torch.float32, device="cuda")
+        snr_p = None
+        if snr_db is not None:
+            snr = np.ascontiguousarray(snr_db, dtype=np.float32)
+            snr_p = snr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        rc = self.lib.ism_convolve_batch(self.h, R, int(M), ctypes.c_void_p(rirs.data_ptr()),
+                                         off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                         ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                         ctypes.c_void_p(src.data_ptr()), int(src.shape[1]), int(out_len), snr_p,
+                                         ctypes.c_void_p(z.data_ptr() if z is not None else 0), int(bool(use_mfma)),
+                                         ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+        self._check(rc)
+        return out

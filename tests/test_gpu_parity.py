@@ -1,0 +1,197 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle.
+
+Bar (per RIR): max |gpu - oracle| <= 1e-5 * max |oracle| for the FP32 paths,
+<= 2e-3 * max |oracle| for the FP16 table variant; tap counts (integers) equal
+exactly; repeated and batched runs bitwise equal.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_13347_amd import ism, scenes
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-5
+TOL_LUT = 2e-3
+
+
+def _say(msg):
+    sys.stdout.write(msg + "\n")
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def H(torch_cuda):
+    h = ism.Handle()
+    yield h
+    h.close()
+
+
+def oracle_batch(batch, rirs=None, nthreads=None):
+    if rirs is None:
+        rirs = [(r, m) for r in range(len(batch["rir_len"])) for m in range(int(batch["n_mics"][r]))]
+    out, taps = oracle.rir_list(batch, rirs, nthreads=nthreads)
+    return out, taps, rirs
+
+
+def rel_errors(batch, gpu, ref, rirs):
+    errs = []
+    for r, m in rirs:
+        L = int(batch["rir_len"][r])
+        o = int(batch["out_offset"][r]) + m * L
+        a, b = gpu[o:o + L].astype(np.float64), ref[o:o + L]
+        peak = float(np.max(np.abs(b)))
+        errs.append(float(np.max(np.abs(a - b))) / peak if peak > 0 else float(np.max(np.abs(a))))
+    return np.array(errs)
+
+
+def run(H, batch, precision=ism.PREC_FP32_COMP, seg_len=None, fold=None):
+    import torch
+    if seg_len or fold:
+        H.set_tuning(seg_len=seg_len or 0, fold=fold or 0)
+    out = H.rir_batch(batch, precision=precision)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    cnt = H.last_counts()
+    H.set_tuning(seg_len=1024, fold=8)
+    return res, cnt
+
+
+# ------------------------------------------------------------------ configurations
+@pytest.mark.parametrize("mode", [ism.ORDER_INDEX_L1, ism.ORDER_REFLECTIONS])
+@pytest.mark.parametrize("seg_len", [64, 1024, 2048])
+def test_c0_single_room(H, mode, seg_len):
+    b = scenes.c0()
+    b["order_mode"] = mode
+    _say(f"c0 mode={mode} seg_len={seg_len}")
+    gpu, cnt = run(H, b, seg_len=seg_len)
+    ref, taps, rirs = oracle_batch(b)
+    err = rel_errors(b, gpu, ref, rirs)
+    assert err.max() <= TOL_FP32, err
+    assert cnt["taps"] == taps == (1005974 if mode == 0 else 126441)
+
+
+@pytest.mark.parametrize("taps,rir_len,seg_len", [(9, 64, 64), (9, 300, 64), (21, 333, 128), (1, 200, 64),
+                                                 (81, 700, 192), (127, 900, 256), (255, 1000, 512)])
+def test_tiny_rooms_all_kernel_variants(H, taps, rir_len, seg_len):
+    b = scenes.tiny(seed=taps + rir_len, n_rooms=3, rir_len=rir_len, M=3, taps=taps)
+    _say(f"tiny taps={taps} len={rir_len} seg={seg_len}")
+    gpu, cnt = run(H, b, seg_len=seg_len)
+    ref, ntaps, rirs = oracle_batch(b)
+    err = rel_errors(b, gpu, ref, rirs)
+    assert err.max() <= TOL_FP32, err
+    assert cnt["taps"] == ntaps
+
+
+def test_c1_sixteen_rooms(H):
+    full = scenes.c1()
+    b = scenes.subset(full, range(16))
+    _say("c1 16 rooms")
+    gpu, cnt = run(H, b)
+    ref, taps, rirs = oracle_batch(b)
+    err = rel_errors(b, gpu, ref, rirs)
+    _say(f"c1 16 rooms max err {err.max():.3e}")
+    assert err.max() <= TOL_FP32
+    assert cnt["taps"] == taps
+
+
+def test_c1_full_batch_sampled(H):
+    # the 1024-room batch in the benchmark's launch configuration; 24 RIRs checked one by one
+    b = scenes.c1()
+    _say("c1 full batch")
+    gpu, cnt = run(H, b)
+    rng = np.random.default_rng(5)
+    rooms = rng.choice(len(b["rir_len"]), size=24, replace=False)
+    rirs = [(int(r), int(rng.integers(0, 8))) for r in rooms]
+    ref, _, _ = oracle_batch(b, rirs)
+    err = rel_errors(b, gpu, ref, rirs)
+    _say(f"c1 sampled max err {err.max():.3e}")
+    assert err.max() <= TOL_FP32
+    assert np.all(np.isfinite(gpu))
+    # every RIR has its direct path: nonzero energy in every output row
+    assert cnt["taps"] > 0.9e11
+
+
+def test_c3_precision_variants(H):
+    b = scenes.subset(scenes.c3(), [0, 1])
+    ref, taps, rirs = oracle_batch(b)
+    res = {}
+    for prec, name in [(ism.PREC_FP32_COMP, "comp"), (ism.PREC_FP32_PLAIN, "plain"),
+                       (ism.PREC_FP16_LUT, "lut"), (ism.PREC_FP32_SPLIT, "split32")]:
+        _say(f"c3 {name}")
+        gpu, cnt = run(H, b, precision=prec)
+        res[name] = rel_errors(b, gpu, ref, rirs).max()
+        if name != "split32":
+            assert cnt["taps"] == taps
+    _say(f"c3 errors {res}")
+    assert res["comp"] <= TOL_FP32
+    assert res["plain"] <= TOL_FP32
+    assert res["lut"] <= TOL_LUT
+    assert res["split32"] >= res["comp"]
+
+
+# ------------------------------------------------------------------ determinism
+def test_repeat_and_batched_vs_per_room_bitwise(H):
+    import torch
+    b = scenes.subset(scenes.c1(), range(6))
+    a1, _ = run(H, b)
+    a2, _ = run(H, b)
+    assert np.array_equal(a1, a2)
+    for r in range(6):
+        o, M, L = int(b["out_offset"][r]), int(b["n_mics"][r]), int(b["rir_len"][r])
+        mo = int(b["mic_offset"][r])
+        single = H.rir(b["L"][r], b["beta"][r], b["src"][r], b["mics"][mo:mo + M], b["fs"], b["c"], -1, L, 81)
+        torch.cuda.synchronize()
+        assert np.array_equal(single.cpu().numpy().ravel(), a1[o:o + M * L])
+
+
+def test_graph_replay_equals_direct_launch(H):
+    import torch
+    b = scenes.subset(scenes.c1(), range(4))
+    H.set_tuning(graphs=0)
+    a, _ = run(H, b)
+    H.set_tuning(graphs=1)
+    outs = []
+    for _ in range(3):           # replays with eager work in between
+        outs.append(run(H, b)[0])
+        torch.zeros(1 << 20, device="cuda").sum().item()
+    for o in outs:
+        assert np.array_equal(o, a)
+
+
+# ------------------------------------------------------------------ edge cases
+def test_edge_cases(H, torch_cuda):
+    torch = torch_cuda
+    # beta = 0: direct path only; integer delay: Kronecker impulse
+    out = H.rir([2.0, 2.0, 4.0], [0.0] * 6, [1.0, 1.0, 1.0], [[1.0, 1.0, 3.5]], 136.0, 340.0, -1, 32, 9)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()[0]
+    g = 1.0 / (4.0 * math.pi * 2.5)
+    assert abs(o[1] - g) <= 1e-5 * g
+    assert np.max(np.abs(np.delete(o, 1))) <= 1e-5 * g
+    # rir_len = 1, max_order = 0 (direct only), microphones on walls
+    for L, mics, N, n in [([5.0, 4.0, 3.0], [[5.0, 0.0, 3.0], [2.0, 2.0, 0.0]], 0, 1),
+                          ([5.0, 4.0, 3.0], [[5.0, 0.0, 3.0]], 3, 777)]:
+        out = H.rir(L, [0.6] * 6, [1.3, 2.1, 1.5], mics, 16000.0, 343.0, N, n, 81)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        for m, mic in enumerate(mics):
+            ref, _ = oracle.rir(L, [0.6] * 6, [1.3, 2.1, 1.5], mic, 16000.0, 343.0, N, 0, n, 81)
+            peak = max(np.max(np.abs(ref)), 1e-30)
+            assert np.max(np.abs(got[m] - ref)) <= 1e-5 * peak
+    # empty batch is a no-op
+    e = scenes.pack([], 16000.0, 343.0, 81, 0, "empty")
+    assert H.lib.ism_rir_batch(H.h, 0, None, None, 16000.0, 343.0, 81, 0, 0, None, None) == 0
