@@ -68,21 +68,26 @@ enum ism_status {
 enum ism_order_mode { ISM_ORDER_INDEX_L1 = 0, ISM_ORDER_REFLECTIONS = 1 };
 
 /*
- * Arithmetic of the tap evaluation.  In every mode the image positions,
- * distances, delays and the integer/fractional delay split are computed in
- * FP64 (except ISM_PREC_FP32_SPLIT).
- *   ISM_PREC_FP32_COMP   FP32 tap evaluation, FP32 partial sums folded into a
- *                        compensated (Neumaier) FP32 pair per output sample.
- *   ISM_PREC_FP16_LUT    the windowed sinc read from an FP16 table (64 steps
- *                        per sample, linear interpolation), FP32 accumulation.
+ * Arithmetic.  In every mode the image positions, distances, delays and the
+ * integer/fractional delay split are computed in FP64 (except the FP32-split
+ * ablation).
+ *   ISM_PREC_FP32        FP32 tap evaluation; each tap is quantised to a 32-bit
+ *                        fixed-point value (step below 1e-9 of a bound on the
+ *                        largest image gain of its output segment) and summed
+ *                        exactly in 64-bit integers: deterministic, and the only
+ *                        accumulation error is one quantisation per tap.
+ *   ISM_PREC_FP16_LUT    the windowed sinc read from an FP16 table (64 steps per
+ *                        sample, linear interpolation); same exact accumulation.
  *   ISM_PREC_FP32_SPLIT  ablation: distance and delay split in FP32.
- *   ISM_PREC_FP32_PLAIN  ablation: FP32 taps, plain FP32 accumulation.
+ *   ISM_PREC_FP32_ATOMIC ablation: FP32 taps summed with FP32 LDS atomics (plain
+ *                        FP32 accumulation; the order of the adds at each output
+ *                        sample is still fixed).
  */
 enum ism_precision {
-    ISM_PREC_FP32_COMP = 0,
+    ISM_PREC_FP32 = 0,
     ISM_PREC_FP16_LUT = 1,
     ISM_PREC_FP32_SPLIT = 2,
-    ISM_PREC_FP32_PLAIN = 3
+    ISM_PREC_FP32_ATOMIC = 3
 };
 
 /* One room of a batch.  Microphones of room i are mics[mic_offset .. mic_offset+n_mics);
@@ -144,24 +149,26 @@ int ism_batch_plan_stats(ism_handle *h, int n_rooms, const ism_room *rooms, cons
                          double *est_records, double *est_taps);
 
 /*
- * Work counters of the last ism_rir / ism_rir_batch call on this handle: counts[0]
- * = taps that landed in the outputs (one per image, microphone and output sample
- * of its filter inside [0, rir_len)), counts[1] = image records processed (an
- * image near a segment boundary is processed once per segment it reaches),
- * counts[2] = candidate images evaluated.  Waits for that call to finish.
+ * Work counters of the last ism_rir / ism_rir_batch call on this handle, written
+ * to counts[0..7]: [0] taps that landed in the outputs (one per image, microphone
+ * and output sample of its filter inside [0, rir_len)), [1] image records
+ * processed (an image near a segment boundary is processed once per segment it
+ * reaches), [2] candidate images evaluated, [3] tap rounds (64 lanes each),
+ * [4] column chunks, [5] enumeration steps, [6] records deferred by an equal
+ * delay in the same round, [7] reserved.  Waits for that call to finish.
  */
-int ism_last_counts(ism_handle *h, int64_t counts[3]);
+int ism_last_counts(ism_handle *h, int64_t counts[8]);
 
 /*
  * Tuning of the segment kernel: seg_len = output samples per work item
- * (multiple of 64, 64..2048), fold = rounds of FP32 partial sums between
- * compensated folds (>= 1), graphs = capture each batch launch sequence in a
- * hipGraph and replay it (1) or launch directly (0).  A value of 0 for seg_len
- * or fold, or -1 for graphs, keeps the current setting.  Settings apply to
- * later calls on this handle.
+ * (multiple of 64, 64..2048; 0 keeps the current value), wg_per_cu = cap on
+ * resident single-wave workgroups per compute unit of the persistent launch
+ * (0 = as many as fit, -1 keeps the current value), graphs = capture each batch
+ * launch sequence in a hipGraph and replay it (1) or launch directly (0; -1
+ * keeps the current value).  Settings apply to later calls on this handle.
  */
-int ism_set_tuning(ism_handle *h, int seg_len, int fold, int graphs);
-int ism_get_tuning(const ism_handle *h, int *seg_len, int *fold, int *graphs);
+int ism_set_tuning(ism_handle *h, int seg_len, int wg_per_cu, int graphs);
+int ism_get_tuning(const ism_handle *h, int *seg_len, int *wg_per_cu, int *graphs);
 
 /*
  * Autotuner: times the batch with each candidate segment length (64-multiples

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -72,6 +73,7 @@ extern "C" int ism_create(ism_handle **out)
         h->n_cu = prop.multiProcessorCount;
         h->lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
     }
+    if (const char *v = std::getenv("ISM_INTERLEAVE")) h->interleave = std::atoi(v) ? 1 : 0;
     *out = h;
     return ISM_OK;
 }
@@ -105,26 +107,26 @@ extern "C" const char *ism_strerror(int st)
 extern "C" const char *ism_last_error(const ism_handle *h) { return h ? h->last_error.c_str() : ""; }
 extern "C" int ism_version(void) { return ISM_VERSION; }
 
-extern "C" int ism_set_tuning(ism_handle *h, int seg_len, int fold, int graphs)
+extern "C" int ism_set_tuning(ism_handle *h, int seg_len, int wg_per_cu, int graphs)
 {
     if (!h) return ISM_EINVAL;
     if (seg_len != 0 && (seg_len < 64 || seg_len > kSegMaxLimit || seg_len % 64 != 0)) {
         ism_set_error(h, "seg_len must be a multiple of 64 in [64, %d]", kSegMaxLimit);
         return ISM_EINVAL;
     }
-    if (fold < 0) { ism_set_error(h, "fold must be >= 0"); return ISM_EINVAL; }
+    if (wg_per_cu < -1 || wg_per_cu > 64) { ism_set_error(h, "wg_per_cu must be in [-1, 64]"); return ISM_EINVAL; }
     if (graphs < -1 || graphs > 1) { ism_set_error(h, "graphs must be -1, 0 or 1"); return ISM_EINVAL; }
     if (seg_len) h->seg_len = seg_len;
-    if (fold) h->fold = fold;
+    if (wg_per_cu >= 0) h->wg_per_cu = wg_per_cu;
     if (graphs >= 0) h->graphs = graphs;
     return ISM_OK;
 }
 
-extern "C" int ism_get_tuning(const ism_handle *h, int *seg_len, int *fold, int *graphs)
+extern "C" int ism_get_tuning(const ism_handle *h, int *seg_len, int *wg_per_cu, int *graphs)
 {
     if (!h) return ISM_EINVAL;
     if (seg_len) *seg_len = h->seg_len;
-    if (fold) *fold = h->fold;
+    if (wg_per_cu) *wg_per_cu = h->wg_per_cu;
     if (graphs) *graphs = h->graphs;
     return ISM_OK;
 }
@@ -144,7 +146,7 @@ int ism_validate_common(ism_handle *h, double fs, double c, int fd_taps, int ord
         ism_set_error(h, "order_mode must be ISM_ORDER_INDEX_L1 or ISM_ORDER_REFLECTIONS");
         return ISM_EINVAL;
     }
-    if (precision < ISM_PREC_FP32_COMP || precision > ISM_PREC_FP32_PLAIN) {
+    if (precision < ISM_PREC_FP32 || precision > ISM_PREC_FP32_ATOMIC) {
         ism_set_error(h, "unknown precision %d", precision);
         return ISM_EINVAL;
     }
@@ -325,7 +327,9 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
     const int n_rooms = (int)plan.rooms.size();
     if (n_items == 0) return ISM_OK;
     if (h->device < 0) { ism_set_error(h, "no HIP device"); return ISM_EDEVICE; }
-    const int variant = precision == ISM_PREC_FP16_LUT ? VAR_LUT : VAR_FP32;
+    const int variant = precision == ISM_PREC_FP16_LUT      ? VAR_LUT
+                        : precision == ISM_PREC_FP32_ATOMIC ? VAR_F32ATOM
+                                                             : VAR_FX;
     KernelEntry ke = select_segment_kernel(K, variant);
     const int lds = seg_lds_bytes(plan.seg_max, K, variant);
     if (lds > 160 * 1024) { ism_set_error(h, "segment needs %d bytes of LDS", lds); return ISM_ENOMEM; }
@@ -362,9 +366,9 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
     L.n_items = n_items;
     L.K = K;
     L.order_mode = order_mode;
-    L.fold = precision == ISM_PREC_FP32_PLAIN ? 0 : h->fold;
     L.split32 = precision == ISM_PREC_FP32_SPLIT ? 1 : 0;
     L.seg_max = plan.seg_max;
+    L.interleave = h->interleave;
     std::memcpy(hb, &L, sizeof L);
     std::memcpy(hb + off_rooms, plan.rooms.data(), sizeof(RoomDev) * n_rooms);
     std::memcpy(hb + off_mics, mics, sizeof(double) * 3 * plan.n_mics_total);
@@ -373,6 +377,7 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ke.sym, 64, lds);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    if (h->wg_per_cu > 0) per_cu = std::min(per_cu, h->wg_per_cu);
     const int grid = (int)std::min<int64_t>(n_items, (int64_t)per_cu * h->n_cu);
     const LaunchDev *Pd = (const LaunchDev *)db;
 
@@ -420,17 +425,17 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
     return ISM_OK;
 }
 
-extern "C" int ism_last_counts(ism_handle *h, int64_t counts[3])
+extern "C" int ism_last_counts(ism_handle *h, int64_t counts[8])
 {
     if (!h || !counts) return ISM_EINVAL;
-    counts[0] = counts[1] = counts[2] = 0;
+    for (int i = 0; i < 8; ++i) counts[i] = 0;
     if (!h->last_slot || !h->last_stats) return ISM_OK;
     hipError_t e = hipEventSynchronize(h->last_slot->event);
     if (e != hipSuccess) return ism_hip_fail(h, e, "hipEventSynchronize");
-    unsigned long long v[3];
+    unsigned long long v[8];
     e = hipMemcpy(v, h->last_stats, sizeof v, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return ism_hip_fail(h, e, "hipMemcpy of the work counters");
-    for (int i = 0; i < 3; ++i) counts[i] = (int64_t)v[i];
+    for (int i = 0; i < 8; ++i) counts[i] = (int64_t)v[i];
     return ISM_OK;
 }
 

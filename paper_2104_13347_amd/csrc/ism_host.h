@@ -57,8 +57,9 @@ struct ism_handle {
     int n_cu = 256;
     int lds_per_cu = 160 * 1024;
     int seg_len = 1024;
-    int fold = 8;
+    int wg_per_cu = 0;  // 0: as many as fit
     int graphs = 1;
+    int interleave = 1;
     std::string last_error;
     ism::Slot slots[2];
     int next_slot = 0;

@@ -31,7 +31,7 @@ struct alignas(16) ItemDev {
     int32_t s1;
 };
 
-enum Variant : int32_t { VAR_FP32 = 0, VAR_LUT = 1 };
+enum Variant : int32_t { VAR_FX = 0, VAR_LUT = 1, VAR_F32ATOM = 2 };
 
 struct alignas(16) LaunchDev {
     double fs;
@@ -47,10 +47,10 @@ struct alignas(16) LaunchDev {
     int32_t n_items;
     int32_t K;            // (fd_taps - 1) / 2
     int32_t order_mode;   // 0 index-L1, 1 reflections
-    int32_t fold;         // rounds between compensated folds (0: fold once at the end)
+    int32_t reserved0;
     int32_t split32;      // 1: distance and delay split in FP32 (ablation)
     int32_t seg_max;      // largest s1 - s0 of any item (sizes LDS)
-    int32_t pad_;
+    int32_t interleave;   // enumeration order inside a column chunk (1: strided over columns)
 };
 
 constexpr int kSegMaxLimit = 2048;  // largest supported segment (per-lane sums in registers)
@@ -62,9 +62,9 @@ constexpr int kCols = 64;           // columns per enumeration chunk (one per la
 // LDS bytes of the segment kernel for a given segment capacity, K and variant.
 inline int seg_lds_bytes(int seg_max, int K, int variant)
 {
-    int acc = (seg_max + 4 * K + 63) / 64 * 64;         // float
-    int clm = (seg_max + 2 * K + 63) / 64 * 64;         // uint32
-    int bytes = acc * 4 + clm * 4;
+    int acc = (seg_max + 4 * K + 63) / 64 * 64;         // int64 (FP32 in the atomic ablation)
+    int clm = variant == VAR_F32ATOM ? (seg_max + 2 * K + 63) / 64 * 64 : 0;  // uint32
+    int bytes = acc * 8 + clm * 4;
     bytes += kBufCap * 12;                              // f, g, n0rel
     bytes += (kCols + 4) * 4 + kCols * 8 * 2 + kCols * 4 + kCols * 4 * 3 * 4;  // column chunk
     bytes += (2 * K + 1) * 8;                           // generic-K trig table

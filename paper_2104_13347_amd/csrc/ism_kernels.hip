@@ -17,15 +17,21 @@
 //  * Records (f, g, n0) of valid images go to a 256-entry ring in LDS (stable,
 //    in enumeration order, via ballot + mbcnt).
 //  * Rounds: 64 records at a time, one per lane, the 2K+1 taps with k uniform
-//    across the wave (unrolled, constants folded).  Each tap is an LDS float add
-//    into the segment accumulator.  Lanes of one round must hold distinct n0 so
-//    that no two lanes of one ds_add hit the same address: a claim array with
-//    an LDS atomic min keeps the lowest lane of each n0 and defers the others to
-//    the ring's tail.  Every address therefore receives its adds in an order
-//    fixed by the data alone: the result is deterministic, with no float
-//    atomics on shared addresses and no scatter to HBM.
-//  * Compensated accumulation: every `fold` rounds each lane folds the FP32
-//    partial sums of its output samples into a Neumaier pair in registers.
+//    across the wave (unrolled, constants folded).  Each tap is converted to a
+//    32-bit fixed-point value and added with a 64-bit integer LDS atomic into
+//    the segment accumulator.  Integer addition is associative, so the result
+//    does not depend on the order of the adds: it is deterministic by
+//    construction and exact apart from one quantisation per tap.  The scale is
+//    a power of two per work item, 2^30 / (a bound on the item's largest image
+//    gain), so no tap exceeds 2^30 and no 64-bit sum can overflow; the
+//    quantisation step is below 1e-9 of that gain bound.  (On gfx950 an LDS
+//    FP32 atomic add costs about 190 CU cycles per wave instruction, a 64-bit
+//    integer one about 6.)
+//  * The FP32-atomic ablation keeps FP32 LDS atomics; there the lanes of one
+//    round must hold distinct n0, so that no ds_add sees two lanes on one
+//    address: a claim array with an LDS atomic min keeps the lowest lane of
+//    each n0 and defers the others to the ring's tail, which fixes the order
+//    of the adds at every address.
 //  * The segment is written once, coalesced (lane-contiguous samples).
 //
 // Tap formula.  With t = k - f, sinc(t) = -(-1)^k sin(pi f) / (pi t), and the
@@ -34,7 +40,8 @@
 //     g h(k - f) = (-1)^k / (k - f) * (a0 + a1 cos(P k) + a2 sin(P k)),
 //     a0 = -g sin(pi f) / (2 pi), a1 = a0 cos(P f), a2 = a0 sin(P f).
 // Per tap: one subtraction (the sign (-1)^k folds into its operand order), one
-// v_rcp_f32, two FMAs, one multiply, one ds_add_f32.
+// v_rcp_f32, two FMAs, one multiply, a float-to-int conversion, a sign
+// extension and one ds_add_u64.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -107,14 +114,6 @@ DEV void lds_add(float *p, float v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-DEV void neumaier(float &s, float &c, float p)
-{
-    float t = s + p;
-    float e = (fabsf(s) >= fabsf(p)) ? ((s - t) + p) : ((p - t) + s);
-    c += e;
-    s = t;
-}
-
 // Per-record coefficients a0, a1, a2 of the tap formula (FP32; |f| <= 1/2).
 DEV void tap_coeffs(float f, float g, float P, bool wide, float &a0, float &a1, float &a2)
 {
@@ -155,9 +154,18 @@ DEV void tap_coeffs(float f, float g, float P, bool wide, float &a0, float &a1, 
     a2 = a0 * sy;
 }
 
+DEV void lds_add_fx(long long *p, float x)
+{
+    // x is already scaled; |x| < 2^31, truncation toward zero
+    const long long v = (long long)(int)x;
+    __hip_atomic_fetch_add((unsigned long long *)p, (unsigned long long)v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // 2K+1 taps of one record, K known at compile time: constants fold to literals.
-template <int K>
-DEV void taps_fp32_ct(float *accp, float f, float a0, float a1, float a2)
+// FX: fixed-point accumulation into acc64; otherwise FP32 LDS atomics into acc32.
+template <int K, bool FX>
+DEV void taps_fp32_ct(long long *acc64, float *acc32, float f, float a0, float a1, float a2)
 {
     constexpr TapConst<K> T{};
 #pragma unroll
@@ -165,12 +173,15 @@ DEV void taps_fp32_ct(float *accp, float f, float a0, float a1, float a2)
         const float t = (k & 1) ? (f - (float)k) : ((float)k - f);
         const float r = __builtin_amdgcn_rcpf(t);
         const float num = fmaf(a2, T.s[k + K], fmaf(a1, T.c[k + K], a0));
-        lds_add(accp + k, num * r);
+        if (FX) lds_add_fx(acc64 + k, num * r);
+        else lds_add(acc32 + k, num * r);
     }
 }
 
 // Runtime K: constants from an LDS table (uniform address, broadcast read).
-DEV void taps_fp32_rt(float *accp, int K, const float2 *trig, float f, float a0, float a1, float a2)
+template <bool FX>
+DEV void taps_fp32_rt(long long *acc64, float *acc32, int K, const float2 *trig, float f, float a0, float a1,
+                      float a2)
 {
     for (int k = -K; k <= K; ++k) {
         const float2 cs = trig[k + K];
@@ -178,14 +189,15 @@ DEV void taps_fp32_rt(float *accp, int K, const float2 *trig, float f, float a0,
         const float t = (k & 1) ? (f - kf) : (kf - f);
         const float r = __builtin_amdgcn_rcpf(t);
         const float num = fmaf(a2, cs.y, fmaf(a1, cs.x, a0));
-        lds_add(accp + k, num * r);
+        if (FX) lds_add_fx(acc64 + k, num * r);
+        else lds_add(acc32 + k, num * r);
     }
 }
 
 // FP16 table variant: h(k - f) from pairs (h(k - f_j), h(k - f_{j+1})), f_j = -1/2 + j/Q,
-// linear interpolation, times g.
+// linear interpolation, times the (scaled) gain; fixed-point accumulation.
 template <int KT>
-DEV void taps_lut(float *accp, int Krt, const uint32_t *lut, float f, float g)
+DEV void taps_lut(long long *acc64, int Krt, const uint32_t *lut, float f, float gs)
 {
     const int K = KT > 0 ? KT : Krt;
     const float p = (f + 0.5f) * (float)kLutQ;
@@ -198,7 +210,7 @@ DEV void taps_lut(float *accp, int Krt, const uint32_t *lut, float f, float g)
         const uint32_t pr = row[(k + K) * kLutQ];
         const float h0 = (float)__builtin_bit_cast(_Float16, (unsigned short)(pr & 0xFFFFu));
         const float h1 = (float)__builtin_bit_cast(_Float16, (unsigned short)(pr >> 16));
-        lds_add(accp + k, g * fmaf(al, h1 - h0, h0));
+        lds_add_fx(acc64 + k, gs * fmaf(al, h1 - h0, h0));
     }
 }
 
@@ -215,7 +227,7 @@ __global__ void ism_prologue(const LaunchDev *P)
 {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     if (gid == 0) *P->counter = 0u;
-    if (gid < 3) P->stats[gid] = 0ull;
+    if (gid < 8) P->stats[gid] = 0ull;
     if (gid >= P->n_rooms * 6) return;
     const int room = gid / 6, wall = gid % 6;
     const RoomDev &R = P->rooms[room];
@@ -230,8 +242,9 @@ __global__ void ism_prologue(const LaunchDev *P)
 
 // ---------------------------------------------------------------- segment kernel
 struct Lds {
-    float *acc;
-    uint32_t *claim;
+    long long *acc64;   // fixed-point accumulator (FX, LUT)
+    float *acc32;       // FP32 accumulator (FP32-atomic ablation), aliases acc64
+    uint32_t *claim;    // FP32-atomic ablation only
     float *bf, *bg;
     int32_t *bn;
     int32_t *coff;      // kCols + 1 prefix offsets
@@ -246,11 +259,12 @@ DEV Lds carve(char *base, int seg_max, int K, int variant)
 {
     Lds s;
     const int acc = (seg_max + 4 * K + 63) / 64 * 64;
-    const int clm = (seg_max + 2 * K + 63) / 64 * 64;
+    const int clm = variant == VAR_F32ATOM ? (seg_max + 2 * K + 63) / 64 * 64 : 0;
     char *p = base;
     s.crho2 = (double *)p; p += kCols * 8;
     s.cbxy = (double *)p; p += kCols * 8;
-    s.acc = (float *)p; p += acc * 4;
+    s.acc64 = (long long *)p;
+    s.acc32 = (float *)p; p += acc * 8;
     s.claim = (uint32_t *)p; p += clm * 4;
     s.bf = (float *)p; p += kBufCap * 4;
     s.bg = (float *)p; p += kBufCap * 4;
@@ -262,7 +276,6 @@ DEV Lds carve(char *base, int seg_max, int K, int variant)
     s.iw = (int32_t *)p; p += kCols * 4 * 4;
     s.trig = (float2 *)p; p += (2 * K + 1) * 8;
     s.lut = (uint32_t *)p;
-    (void)variant;
     return s;
 }
 
@@ -279,7 +292,6 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
     Lds S = carve(ism_lds, seg_max, K, VAR);
     const double fs = P->fs, cs = P->c;
     const int order_mode = P->order_mode;
-    const int fold = P->fold;
     const int split32 = P->split32;
     const float Pw = (float)(kPi / (double)(K + 1));
 
@@ -300,11 +312,10 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
     }
     {
         const int acc_n = (seg_max + 4 * K + 63) / 64 * 64;
-        for (int i = lane; i < acc_n; i += 64) S.acc[i] = 0.0f;
+        for (int i = lane; i < acc_n; i += 64) S.acc64[i] = 0;
     }
     __syncthreads();
 
-    constexpr int NJ = kSegMaxLimit / 64;
     for (;;) {
         int item = 0;
         if (lane == 0) item = (int)atomicAdd(P->counter, 1u);
@@ -330,6 +341,19 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
         const double dlo = fmax(0.0, ((double)nlo - 0.5) * cs / fs * (1.0 - 1e-12) - 1e-12);
         const double dhi = ((double)nhi + 0.5) * cs / fs * (1.0 + 1e-12) + 1e-12;
         const double dlo2 = dlo * dlo, dhi2 = dhi * dhi;
+        // Fixed-point scale 2^e: no image is closer than the direct path and every
+        // beta <= 1, so g <= 1/(4 pi max(dlo, |s - r|)) =: gb for every record of the
+        // item, and |tap| <= g (|h| <= 1); e is the largest exponent with 2^e gb < 2^30.
+        int escale = 0;
+        {
+            const double ddx = sx - rx, ddy = sy - ry, ddz = sz - rz;
+            const double ddir = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+            const double gb = 1.0 / (4.0 * kPi * fmax(dlo, ddir));
+            int E;
+            (void)frexp(gb, &E);  // gb = m 2^E, m in [1/2, 1)
+            escale = 30 - E;
+        }
+        const float fscale = VAR == VAR_F32ATOM ? 1.0f : ldexpf(1.0f, escale);
         long alo = (long)floor((rx - dhi) / Lx) - 1, ahi = (long)ceil((rx + dhi) / Lx) + 1;
         long blo = (long)floor((ry - dhi) / Ly) - 1, bhi = (long)ceil((ry + dhi) / Ly) + 1;
         if (N >= 0) {
@@ -340,25 +364,9 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
         const int nb = (int)(bhi - blo + 1);
         const int ncols = (int)(ahi - alo + 1) * nb;
 
-        float sum[NJ], cmp[NJ];
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) { sum[j] = 0.0f; cmp[j] = 0.0f; }
-
-        int head = 0, cnt = 0, rounds = 0;
+        int head = 0, cnt = 0;
         uint32_t n_taps = 0, n_rec = 0, n_img = 0;  // per lane
-
-        auto fold_now = [&]() {
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                const int i = lane + 64 * j;
-                if (i < Sn) {
-                    float *a = S.acc + 2 * K + i;
-                    const float p = *a;
-                    *a = 0.0f;
-                    neumaier(sum[j], cmp[j], p);
-                }
-            }
-        };
+        uint32_t n_rounds = 0, n_chunks = 0, n_steps = 0, n_defer = 0;  // per wave (uniform)
 
         auto round = [&]() {
             const int nact = cnt < 64 ? cnt : 64;
@@ -367,37 +375,43 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
             float f = 0.0f, g = 0.0f;
             int nr = 0;
             if (act) { f = S.bf[slot]; g = S.bg[slot]; nr = S.bn[slot]; }
-            if (act) S.claim[nr] = 0xFFFFFFFFu;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            if (act) atomicMin(&S.claim[nr], (uint32_t)lane);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            const bool lead = act && (S.claim[nr] == (uint32_t)lane);
-            const bool dfr = act && !lead;
-            const uint64_t dm = ballot(dfr);
-            const int nd = __popcll(dm);
-            if (dfr) {
-                const int ts = (head + cnt + mbcnt(dm)) & (kBufCap - 1);
-                S.bf[ts] = f; S.bg[ts] = g; S.bn[ts] = nr;
+            bool lead = act;
+            int nd = 0;
+            if (VAR == VAR_F32ATOM) {
+                if (act) S.claim[nr] = 0xFFFFFFFFu;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                if (act) atomicMin(&S.claim[nr], (uint32_t)lane);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                lead = act && (S.claim[nr] == (uint32_t)lane);
+                const bool dfr = act && !lead;
+                const uint64_t dm = ballot(dfr);
+                nd = __popcll(dm);
+                if (dfr) {
+                    const int ts = (head + cnt + mbcnt(dm)) & (kBufCap - 1);
+                    S.bf[ts] = f; S.bg[ts] = g; S.bn[ts] = nr;
+                }
             }
             head = (head + nact) & (kBufCap - 1);
             cnt = cnt - nact + nd;
+            ++n_rounds;
+            n_defer += nd;
             if (lead) {
                 // taps of this record that land in [s0, s1): n0 + k with n0 = nr + rel
                 const int lo = max(nr + rel - K, s0), hi = min(nr + rel + K, s1 - 1);
                 n_taps += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
                 ++n_rec;
-                float *accp = S.acc + (nr + K);  // acc index of tap k is nr + K + k
+                long long *a64 = S.acc64 + (nr + K);  // acc index of tap k is nr + K + k
+                float *a32 = S.acc32 + (nr + K);
                 if (VAR == VAR_LUT) {
-                    taps_lut<KT>(accp, K, S.lut, f, g);
+                    taps_lut<KT>(a64, K, S.lut, f, g * fscale);
                 } else {
                     float a0, a1, a2;
-                    tap_coeffs(f, g, Pw, K < 4, a0, a1, a2);
-                    if (KT > 0) taps_fp32_ct<(KT > 0 ? KT : 1)>(accp, f, a0, a1, a2);
-                    else taps_fp32_rt(accp, K, S.trig, f, a0, a1, a2);
+                    tap_coeffs(f, g * fscale, Pw, K < 4, a0, a1, a2);
+                    constexpr bool FX = VAR == VAR_FX;
+                    if (KT > 0) taps_fp32_ct<(KT > 0 ? KT : 1), FX>(a64, a32, f, a0, a1, a2);
+                    else taps_fp32_rt<FX>(a64, a32, K, S.trig, f, a0, a1, a2);
                 }
             }
-            ++rounds;
-            if (fold > 0 && (rounds % fold) == 0) fold_now();
         };
 
         for (int c0 = 0; c0 < ncols; c0 += kCols) {
@@ -458,6 +472,7 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
                     }
                 }
             }
+            ++n_chunks;
             const int ctot = len[0] + len[1] + len[2] + len[3];
             int T;
             const int off = wave_excl_scan(ctot, T);
@@ -478,8 +493,12 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
             __syncthreads();
 
             // ---- flattened images of the chunk, one per lane per step
-            for (int x0 = 0; x0 < T; x0 += 64) {
-                const int x = x0 + lane;
+            const int nsteps = (T + 63) / 64;
+            for (int js = 0; js < nsteps; ++js) {
+                // interleaved: the 64 lanes of a step take images spread over the whole
+                // chunk (different columns), so that their delays rarely coincide
+                const int x = P->interleave ? lane * nsteps + js : js * 64 + lane;
+                ++n_steps;
                 bool valid = false;
                 float rf = 0.0f, rg = 0.0f;
                 int rn = 0;
@@ -537,17 +556,18 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
             }
         }
         while (cnt > 0) round();
-        fold_now();
+        __syncthreads();
 
         // ---- store the segment (coalesced), then clear the accumulator
         float *o = P->out + R.out_offset + (long)(it.mic - R.mic_offset) * rir_len + s0;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const int i = lane + 64 * j;
-            if (i < Sn) o[i] = sum[j] + cmp[j];
+        if (VAR == VAR_F32ATOM) {
+            for (int i = lane; i < Sn; i += 64) o[i] = S.acc32[2 * K + i];
+        } else {
+            for (int i = lane; i < Sn; i += 64) o[i] = (float)ldexp((double)S.acc64[2 * K + i], -escale);
         }
         const int acc_n = Sn + 4 * K;
-        for (int i = lane; i < acc_n; i += 64) S.acc[i] = 0.0f;
+        __syncthreads();
+        for (int i = lane; i < acc_n; i += 64) S.acc64[i] = 0;
         // work counters of the item (one atomic per wave)
         unsigned long long t = n_taps, r = n_rec, im = n_img;
 #pragma unroll
@@ -560,6 +580,10 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
             atomicAdd(P->stats + 0, t);
             atomicAdd(P->stats + 1, r);
             atomicAdd(P->stats + 2, im);
+            atomicAdd(P->stats + 3, (unsigned long long)n_rounds);
+            atomicAdd(P->stats + 4, (unsigned long long)n_chunks);
+            atomicAdd(P->stats + 5, (unsigned long long)n_steps);
+            atomicAdd(P->stats + 6, (unsigned long long)n_defer);
         }
         __syncthreads();
     }
@@ -586,14 +610,16 @@ KernelEntry select_segment_kernel(int K, int variant)
 #define ISM_CASE(KK)                                                                      \
     if (K == KK) {                                                                        \
         if (variant == VAR_LUT) return {launch_t<KK, VAR_LUT>, sym_t<KK, VAR_LUT>()};      \
-        return {launch_t<KK, VAR_FP32>, sym_t<KK, VAR_FP32>()};                            \
+        if (variant == VAR_F32ATOM) return {launch_t<KK, VAR_F32ATOM>, sym_t<KK, VAR_F32ATOM>()}; \
+        return {launch_t<KK, VAR_FX>, sym_t<KK, VAR_FX>()};                                \
     }
     ISM_CASE(4)
     ISM_CASE(40)
     ISM_CASE(63)
 #undef ISM_CASE
     if (variant == VAR_LUT) return {launch_t<0, VAR_LUT>, sym_t<0, VAR_LUT>()};
-    return {launch_t<0, VAR_FP32>, sym_t<0, VAR_FP32>()};
+    if (variant == VAR_F32ATOM) return {launch_t<0, VAR_F32ATOM>, sym_t<0, VAR_F32ATOM>()};
+    return {launch_t<0, VAR_FX>, sym_t<0, VAR_FX>()};
 }
 
 hipError_t launch_prologue(const LaunchDev *P, int n_rooms, hipStream_t st)

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libism.so")
 
 ISM_OK, ISM_EINVAL, ISM_EDOMAIN, ISM_ENOMEM, ISM_EDEVICE, ISM_EBUSY = 0, -1, -2, -3, -4, -5
 ORDER_INDEX_L1, ORDER_REFLECTIONS = 0, 1
-PREC_FP32_COMP, PREC_FP16_LUT, PREC_FP32_SPLIT, PREC_FP32_PLAIN = 0, 1, 2, 3
+PREC_FP32, PREC_FP16_LUT, PREC_FP32_SPLIT, PREC_FP32_ATOMIC = 0, 1, 2, 3
 
 # exported symbols (kept in step with include/ism.h)
 EXPORTS = [
@@ -138,17 +138,17 @@ class Handle:
                            self.lib.ism_strerror(rc).decode())
 
     # -- tuning
-    def set_tuning(self, seg_len=0, fold=0, graphs=-1):
-        self._check(self.lib.ism_set_tuning(self.h, int(seg_len), int(fold), int(graphs)))
+    def set_tuning(self, seg_len=0, wg_per_cu=-1, graphs=-1):
+        self._check(self.lib.ism_set_tuning(self.h, int(seg_len), int(wg_per_cu), int(graphs)))
 
     def get_tuning(self):
         a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         self._check(self.lib.ism_get_tuning(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return {"seg_len": a.value, "fold": b.value, "graphs": c.value}
+        return {"seg_len": a.value, "wg_per_cu": b.value, "graphs": c.value}
 
     # -- RIRs
     def rir(self, L, beta, src, mics, fs, c, max_order, rir_len, fd_taps,
-            order_mode=ORDER_INDEX_L1, precision=PREC_FP32_COMP, out=None, stream=None):
+            order_mode=ORDER_INDEX_L1, precision=PREC_FP32, out=None, stream=None):
         """One room: returns (or fills) a float32 device tensor [M, rir_len]."""
         import torch
         L = np.ascontiguousarray(L, dtype=np.float64)
@@ -164,7 +164,7 @@ class Handle:
         self._check(rc)
         return out
 
-    def rir_batch(self, batch, precision=PREC_FP32_COMP, out=None, stream=None, rooms=None):
+    def rir_batch(self, batch, precision=PREC_FP32, out=None, stream=None, rooms=None):
         """A scene batch in one launch: returns (or fills) a flat float32 device tensor."""
         import torch
         if rooms is None:
@@ -181,9 +181,10 @@ class Handle:
 
     def last_counts(self):
         """(taps, records, images tested) of the last RIR call; waits for it."""
-        c = (ctypes.c_int64 * 3)()
+        c = (ctypes.c_int64 * 8)()
         self._check(self.lib.ism_last_counts(self.h, c))
-        return {"taps": int(c[0]), "records": int(c[1]), "images": int(c[2])}
+        return {"taps": int(c[0]), "records": int(c[1]), "images": int(c[2]), "rounds": int(c[3]),
+                "chunks": int(c[4]), "steps": int(c[5]), "deferred": int(c[6])}
 
     def plan_stats(self, batch):
         rooms = rooms_array(batch)
@@ -196,7 +197,7 @@ class Handle:
                                                   ctypes.byref(taps)))
         return {"items": n.value, "est_records": rec.value, "est_taps": taps.value}
 
-    def autotune(self, batch, candidates=None, precision=PREC_FP32_COMP, out=None, stream=None):
+    def autotune(self, batch, candidates=None, precision=PREC_FP32, out=None, stream=None):
         import torch
         rooms = rooms_array(batch)
         mics = np.ascontiguousarray(batch["mics"], dtype=np.float64)

@@ -93,9 +93,11 @@ def test_tuning_limits(handle):
         handle.set_tuning(seg_len=100)
     with pytest.raises(ism.IsmError):
         handle.set_tuning(seg_len=4096)
-    handle.set_tuning(seg_len=512, fold=4)
-    assert handle.get_tuning()["seg_len"] == 512 and handle.get_tuning()["fold"] == 4
-    handle.set_tuning(seg_len=1024, fold=8)
+    with pytest.raises(ism.IsmError):
+        handle.set_tuning(wg_per_cu=100)
+    handle.set_tuning(seg_len=512, wg_per_cu=4)
+    assert handle.get_tuning()["seg_len"] == 512 and handle.get_tuning()["wg_per_cu"] == 4
+    handle.set_tuning(seg_len=1024, wg_per_cu=0)
 
 
 def test_plan_item_count_is_exact(handle):

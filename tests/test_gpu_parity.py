@@ -58,15 +58,15 @@ def rel_errors(batch, gpu, ref, rirs):
     return np.array(errs)
 
 
-def run(H, batch, precision=ism.PREC_FP32_COMP, seg_len=None, fold=None):
+def run(H, batch, precision=ism.PREC_FP32, seg_len=None):
     import torch
-    if seg_len or fold:
-        H.set_tuning(seg_len=seg_len or 0, fold=fold or 0)
+    if seg_len:
+        H.set_tuning(seg_len=seg_len)
     out = H.rir_batch(batch, precision=precision)
     torch.cuda.synchronize()
     res = out.cpu().numpy()
     cnt = H.last_counts()
-    H.set_tuning(seg_len=1024, fold=8)
+    H.set_tuning(seg_len=1024)
     return res, cnt
 
 
@@ -129,7 +129,7 @@ def test_c3_precision_variants(H):
     b = scenes.subset(scenes.c3(), [0, 1])
     ref, taps, rirs = oracle_batch(b)
     res = {}
-    for prec, name in [(ism.PREC_FP32_COMP, "comp"), (ism.PREC_FP32_PLAIN, "plain"),
+    for prec, name in [(ism.PREC_FP32, "fp32"), (ism.PREC_FP32_ATOMIC, "atomic"),
                        (ism.PREC_FP16_LUT, "lut"), (ism.PREC_FP32_SPLIT, "split32")]:
         _say(f"c3 {name}")
         gpu, cnt = run(H, b, precision=prec)
@@ -137,10 +137,10 @@ def test_c3_precision_variants(H):
         if name != "split32":
             assert cnt["taps"] == taps
     _say(f"c3 errors {res}")
-    assert res["comp"] <= TOL_FP32
-    assert res["plain"] <= TOL_FP32
+    assert res["fp32"] <= TOL_FP32
+    assert res["atomic"] <= TOL_FP32
     assert res["lut"] <= TOL_LUT
-    assert res["split32"] >= res["comp"]
+    assert res["split32"] >= res["fp32"]
 
 
 # ------------------------------------------------------------------ determinism
