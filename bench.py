@@ -91,7 +91,19 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=200)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="run only a plain device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by room with no "
               "exchange, see DESIGN.md", file=sys.stderr)
@@ -139,7 +151,7 @@ def main():
                                   "81-tap Hann-windowed sinc, time-bounded image sets",
                       "rooms": args.rooms, "rirs": n_rirs, "taps_per_step": taps,
                       "records_per_step": counts["records"], "images_tested_per_step": counts["images"],
-                      "precision": ["fp32_comp", "fp16_lut", "fp32_split", "fp32_plain"][args.precision],
+                      "precision": ["fp32", "fp16_lut", "fp32_split", "fp32_atomic"][args.precision],
                       "tuning": H.get_tuning()},
            "rirs_per_s_batched": rirs_batched}
 
@@ -175,15 +187,16 @@ def main():
     c0 = scenes.c0()
     lat = []
     o1 = torch.empty((1, 4096), dtype=torch.float32, device=dev)
-    for i in range(args.latency_reps + 10):
+    for i in range(args.latency_reps + 10 if args.latency_reps > 0 else 0):
         torch.cuda.synchronize()
         t = time.perf_counter()
         H.rir(c0["L"][0], c0["beta"][0], c0["src"][0], c0["mics"], c0["fs"], c0["c"], 10, 4096, 81, out=o1)
         torch.cuda.synchronize()
         if i >= 10:
             lat.append((time.perf_counter() - t) * 1e3)
-    res["latency_ms_single_rir"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                                    "workload": "5x4x3 m room, index-L1 order 10, 1 mic, 4096 samples"}
+    if lat:
+        res["latency_ms_single_rir"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                                        "workload": "5x4x3 m room, index-L1 order 10, 1 mic, 4096 samples"}
     H.close()
 
     if not args.no_cpu_baseline:
