@@ -1,18 +1,423 @@
-// Source convolution + sensor noise (placeholder until the MFMA path lands).
+// Source convolution + sensor noise for a batch of rooms (paper section III.A:
+// the multichannel RIRs are convolved with source signals, then Gaussian noise
+// at a drawn SNR is added).
+//
+//   y[r][m][n] = sum_{j <= min(n, L_r - 1)} h[r][m][j] x[r][n - j],  n < out_len
+//   y += sigma_r z,  sigma_r^2 = mean_{m,n} y^2 * 10^(-snr_r / 10)
+//
+// MFMA path (block-Toeplitz GEMM, BF16 inputs, FP32 accumulation).  With
+// 32-sample output blocks t and 32-tap RIR blocks b,
+//   Y_t (32 x M) = sum_s T_s (32 x 32) H_{t-s} (32 x M),  T_s[i][j] = x[32 s + i - j].
+// T_s depends on s only, so one workgroup keeps 16 output blocks x 8 microphones
+// = 128 columns (four 32-column MFMA tiles sharing every A operand) and walks s.
+// Per s: A = T_s from x staged reversed in LDS (BF16; each lane's eight K
+// values are consecutive there, read as dwords and realigned with v_alignbit),
+// B = the RIR blocks b = t - s from a 16-slot LDS ring that gains one block per
+// step, eight v_mfma_f32_32x32x16_bf16.  No MAC is spent on the zero triangle
+// except the partial edges of blocks.
+//
+// FP32 path: direct convolution on the vector units (register-blocked, four
+// outputs per lane, RIR chunks and the matching source window staged in LDS).
+//
+// Noise: every output tile writes the sum of y^2 of its samples (FP64,
+// fixed-order wave reduction); the noise kernel adds those partial sums in tile
+// order for its room, derives sigma, and adds sigma * z.
 #include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "../../include/ism.h"
 #include "ism_host.h"
 
-void ism_conv_release(ism_handle *h) { (void)h; }
-void ism_serve_release(ism_handle *h) { (void)h; }
+namespace ism {
+
+#define DEV __device__ __forceinline__
+
+struct alignas(16) ConvRoom {
+    int64_t rir_off;   // FP32 RIRs: rirs[rir_off + m * rir_len + j]
+    int64_t h_off;     // BF16 padded RIRs: hb[h_off + m * nb * 32 + j]
+    int32_t rir_len;
+    int32_t nb;        // ceil(rir_len / 32)
+    float snr_db;
+    int32_t pad;
+};
+
+struct ConvState {
+    void *ws = nullptr;       // device: BF16 RIRs | tile power sums | room table
+    size_t cap = 0;
+    void *stage = nullptr;    // pinned staging for the room table
+    size_t stage_cap = 0;
+    hipEvent_t ev = nullptr;  // end of the last launch that read the staging buffer
+    bool used = false;
+};
+
+constexpr int CB = 32;            // block length (samples / taps)
+constexpr int CG = 16;            // output blocks per MFMA workgroup
+constexpr int CTILE = CB * CG;    // 512 output samples per workgroup
+constexpr int CM = 8;             // microphones per room on the MFMA path
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+DEV uint16_t f2bf(float f)
+{   // round to nearest even (inputs are finite)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// ------------------------------------------------------------------ RIRs -> padded BF16
+__global__ void conv_pack_h(const float *__restrict__ rirs, const ConvRoom *__restrict__ rooms, int M,
+                            uint16_t *__restrict__ hb)
+{
+    const int r = blockIdx.y, m = blockIdx.z;
+    const ConvRoom R = rooms[r];
+    const int n = R.nb * CB;
+    const float *src = rirs + R.rir_off + (int64_t)m * R.rir_len;
+    uint16_t *dst = hb + R.h_off + (int64_t)m * n;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+        dst[j] = j < R.rir_len ? f2bf(src[j]) : (uint16_t)0;
+}
+
+// ------------------------------------------------------------------ MFMA block-Toeplitz
+// grid (tiles, rooms), one wave.  LDS: reversed BF16 source window + 16-slot RIR ring.
+__global__ __launch_bounds__(64) void conv_mfma(const float *__restrict__ x, int src_len, int out_len,
+                                                const uint16_t *__restrict__ hb,
+                                                const ConvRoom *__restrict__ rooms,
+                                                float *__restrict__ y, double *__restrict__ psum,
+                                                int tiles_per_room, int xwin_cap)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    const int lane = threadIdx.x;
+    const int r = blockIdx.y, tile = blockIdx.x;
+    const int t0 = tile * CG;
+    const ConvRoom R = rooms[r];
+    const int nb = R.nb;
+    const int s_start = max(0, t0 - nb + 1);
+    const int s_end = t0 + CG - 1;
+    // source window: x indices [32 s_start - 31, 32 s_end + 31], stored reversed:
+    // xr[p] = x[xhi - p]
+    const int xhi = CB * s_end + CB - 1;
+    const int wlen = CB * (s_end - s_start) + 2 * CB - 1;
+    uint16_t *xr = (uint16_t *)lds;                        // xwin_cap elements (>= wlen + 32)
+    uint16_t *ring = (uint16_t *)(lds + xwin_cap * 2);     // [16][CM][CB]
+    const float *xs = x + (int64_t)r * src_len;
+    for (int p = lane; p < xwin_cap; p += 64) {
+        const int xi = xhi - p;
+        xr[p] = (p < wlen && xi >= 0 && xi < src_len) ? f2bf(xs[xi]) : (uint16_t)0;
+    }
+    // RIR ring: slot (b & 15) holds block b of all microphones (zeros outside [0, nb))
+    const uint16_t *hr = hb + R.h_off;
+    auto load_block = [&](int b) -> uint2 {
+        // lane covers 4 taps: mic = lane / 8, taps (lane % 8) * 4 .. + 3
+        if (b < 0 || b >= nb) return make_uint2(0u, 0u);
+        const uint16_t *p = hr + (int64_t)(lane >> 3) * nb * CB + (int64_t)b * CB + (lane & 7) * 4;
+        return *(const uint2 *)p;
+    };
+    auto store_block = [&](int b, uint2 v) {
+        uint16_t *p = ring + ((b & 15) * CM + (lane >> 3)) * CB + (lane & 7) * 4;
+        *(uint2 *)p = v;
+    };
+    for (int tl = 0; tl < CG; ++tl) {
+        const int b = t0 - s_start + tl;
+        store_block(b, load_block(b));
+    }
+    __syncthreads();
+
+    f32x16_t acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+        for (int q = 0; q < 16; ++q) acc[nt][q] = 0.0f;
+
+    const int i = lane & 31;           // A row / B column within a tile
+    const int kk0 = (lane >> 5) * 8;   // first K index of this lane's eight
+    const uint32_t *xr32 = (const uint32_t *)xr;
+    uint2 next = load_block(t0 - s_start - 1);   // block entering at s_start + 1
+    for (int s = s_start; s <= s_end; ++s) {
+        if (s > s_start) {
+            store_block(t0 - s, next);
+            __syncthreads();
+        }
+        if (s < s_end) next = load_block(t0 - s - 1);
+        // A fragments of T_s for K steps 0 and 1: x[32 s + i - 16 ks - kk0 - e], e = 0..7
+        bf16x8_t a[2];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const int p = xhi - CB * s - i + 16 * ks + kk0;     // xr index of e = 0
+            const int w = p >> 1;
+            const uint32_t sh = (uint32_t)(p & 1) * 16u;
+            uint32_t d[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) d[k] = xr32[w + k];
+            u32x4_t v;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = __builtin_amdgcn_alignbit(d[k + 1], d[k], sh);
+            a[ks] = __builtin_bit_cast(bf16x8_t, v);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int tl = nt * 4 + (i >> 3), m = i & 7;
+            const int b = t0 + tl - s;
+            const uint16_t *bp = ring + ((b & 15) * CM + m) * CB + kk0;
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const u32x4_t bv = *(const u32x4_t *)(bp + 16 * ks);
+                acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], __builtin_bit_cast(bf16x8_t, bv),
+                                                                   acc[nt], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+
+    // store: register q of tile nt holds row 8 (q / 4) + 4 (lane / 32) + (q % 4), column lane % 32
+    double pw = 0.0;
+    float *yr = y + (int64_t)r * CM * out_len;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int tl = nt * 4 + (i >> 3), m = i & 7;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int row = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+            const int n = CB * (t0 + tl) + row;
+            if (n < out_len) {
+                const float v = acc[nt][q];
+                yr[(int64_t)m * out_len + n] = v;
+                pw += (double)v * (double)v;
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) pw += __shfl_xor(pw, d, 64);
+    if (lane == 0) psum[(int64_t)r * tiles_per_room + tile] = pw;
+}
+
+// ------------------------------------------------------------------ FP32 direct
+// grid (tiles of 1024 outputs, M, rooms), 256 threads x 4 outputs; RIR chunks of 256 taps.
+constexpr int DT = 1024, DJ = 256;
+
+__global__ __launch_bounds__(256) void conv_direct(const float *__restrict__ rirs, const ConvRoom *__restrict__ rooms,
+                                                   const float *__restrict__ x, int src_len, int out_len, int M,
+                                                   float *__restrict__ y, double *__restrict__ psum,
+                                                   int tiles_per_room)
+{
+    __shared__ float hs[DJ];
+    __shared__ float xw[DT + DJ + 4];
+    const int tid = threadIdx.x;
+    const int tile = blockIdx.x, m = blockIdx.y, r = blockIdx.z;
+    const ConvRoom R = rooms[r];
+    const float *h = rirs + R.rir_off + (int64_t)m * R.rir_len;
+    const float *xs = x + (int64_t)r * src_len;
+    const int n0 = tile * DT;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    const int jmax = min(R.rir_len, n0 + DT);   // taps beyond the last output are never used
+    for (int j0 = 0; j0 < jmax; j0 += DJ) {
+        __syncthreads();
+        hs[tid] = (j0 + tid < R.rir_len) ? h[j0 + tid] : 0.0f;
+        // window: xw[q] = x[n0 - j0 - DJ + q], q in [0, DT + DJ)
+        for (int q = tid; q < DT + DJ + 4; q += 256) {
+            const int xi = n0 - j0 - DJ + q;
+            xw[q] = (q < DT + DJ && xi >= 0 && xi < src_len) ? xs[xi] : 0.0f;
+        }
+        __syncthreads();
+        // output n = n0 + 4 tid + u needs x[n - j] = xw[4 tid + u + DJ - jj] for j = j0 + jj
+        const int base = 4 * tid + DJ;
+        float x0 = xw[base + 0], x1 = xw[base + 1], x2 = xw[base + 2], x3 = xw[base + 3];
+#pragma unroll 8
+        for (int jj = 0; jj < DJ; ++jj) {
+            const float hv = hs[jj];
+            acc[0] = fmaf(hv, x0, acc[0]);
+            acc[1] = fmaf(hv, x1, acc[1]);
+            acc[2] = fmaf(hv, x2, acc[2]);
+            acc[3] = fmaf(hv, x3, acc[3]);
+            x3 = x2; x2 = x1; x1 = x0;
+            x0 = xw[base - jj - 1];
+        }
+    }
+    double pw = 0.0;
+    float *yo = y + ((int64_t)r * M + m) * out_len;
+    for (int u = 0; u < 4; ++u) {
+        const int n = n0 + 4 * tid + u;
+        if (n < out_len) {
+            yo[n] = acc[u];
+            pw += (double)acc[u] * (double)acc[u];
+        }
+    }
+    // fixed-order block reduction
+    __shared__ double red[256];
+    red[tid] = pw;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) psum[((int64_t)r * M + m) * tiles_per_room + tile] = red[0];
+}
+
+// ------------------------------------------------------------------ noise
+// grid (chunks, rooms); psum holds n_parts partial sums of y^2 per room, in order.
+__global__ void conv_noise(float *__restrict__ y, const float *__restrict__ z, const double *__restrict__ psum,
+                           const ConvRoom *__restrict__ rooms, int n_parts, int64_t per_room)
+{
+    const int r = blockIdx.y;
+    __shared__ float sigma_s;
+    if (threadIdx.x == 0) {
+        double P = 0.0;
+        for (int k = 0; k < n_parts; ++k) P += psum[(int64_t)r * n_parts + k];
+        P /= (double)per_room;
+        sigma_s = (float)sqrt(P * pow(10.0, -(double)rooms[r].snr_db / 10.0));
+    }
+    __syncthreads();
+    const float sg = sigma_s;
+    float *yr = y + (int64_t)r * per_room;
+    const float *zr = z + (int64_t)r * per_room;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per_room; i += (int64_t)gridDim.x * blockDim.x)
+        yr[i] = fmaf(sg, zr[i], yr[i]);
+}
+
+}  // namespace ism
+
+using namespace ism;
+
+void ism_conv_release(ism_handle *h)
+{
+    if (!h || !h->conv) return;
+    ConvState *c = h->conv;
+    if (c->ev) {
+        if (c->used) hipEventSynchronize(c->ev);
+        hipEventDestroy(c->ev);
+    }
+    if (c->ws) hipFree(c->ws);
+    if (c->stage) hipHostFree(c->stage);
+    delete c;
+    h->conv = nullptr;
+}
+
+static size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 
 extern "C" int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float *rirs, const int64_t *rir_offset,
                                   const int32_t *rir_len, const float *src, int src_len, int out_len,
                                   const float *snr_db, const float *z, int use_mfma, float *out, ism_stream stream)
 {
-    (void)n_rooms; (void)M; (void)rirs; (void)rir_offset; (void)rir_len; (void)src; (void)src_len;
-    (void)out_len; (void)snr_db; (void)z; (void)use_mfma; (void)out; (void)stream;
-    if (h) ism_set_error(h, "not implemented");
-    return ISM_EINVAL;
+    if (!h) return ISM_EINVAL;
+    h->last_error.clear();
+    if (n_rooms < 0 || M < 1 || src_len < 1 || out_len < 1) {
+        ism_set_error(h, "n_rooms >= 0, M >= 1, src_len >= 1 and out_len >= 1 required");
+        return ISM_EINVAL;
+    }
+    if (n_rooms == 0) return ISM_OK;
+    if (!rirs || !rir_offset || !rir_len || !src || !out) {
+        ism_set_error(h, "NULL argument");
+        return ISM_EINVAL;
+    }
+    if (snr_db && !z) {
+        ism_set_error(h, "noise deviates z are required when snr_db is given");
+        return ISM_EINVAL;
+    }
+    if (use_mfma && M != CM) {
+        ism_set_error(h, "the MFMA path takes %d microphones per room", CM);
+        return ISM_EINVAL;
+    }
+    if ((int64_t)out_len > (1LL << 28) || (int64_t)src_len > (1LL << 28)) {
+        ism_set_error(h, "signal length limit exceeded");
+        return ISM_EINVAL;
+    }
+    std::vector<ConvRoom> rooms(n_rooms);
+    int64_t hb_total = 0;
+    int nb_max = 0;
+    for (int r = 0; r < n_rooms; ++r) {
+        if (rir_len[r] < 1 || rir_len[r] > (1 << 24) || rir_offset[r] < 0) {
+            ism_set_error(h, "room %d: rir_len must be in [1, 2^24] and rir_offset >= 0", r);
+            return ISM_EINVAL;
+        }
+        if (snr_db && !std::isfinite(snr_db[r])) {
+            ism_set_error(h, "room %d: snr_db not finite", r);
+            return ISM_EINVAL;
+        }
+        ConvRoom &c = rooms[r];
+        c.rir_off = rir_offset[r];
+        c.rir_len = rir_len[r];
+        c.nb = (rir_len[r] + CB - 1) / CB;
+        c.h_off = hb_total;
+        c.snr_db = snr_db ? snr_db[r] : 0.0f;
+        c.pad = 0;
+        hb_total += (int64_t)M * c.nb * CB;
+        nb_max = std::max(nb_max, c.nb);
+    }
+    if (h->device < 0) { ism_set_error(h, "no HIP device"); return ISM_EDEVICE; }
+    if (!h->conv) h->conv = new (std::nothrow) ConvState();
+    if (!h->conv) return ISM_ENOMEM;
+    ConvState &C = *h->conv;
+    hipStream_t q = (hipStream_t)stream;
+
+    const int mt_tiles = (out_len + CTILE - 1) / CTILE;
+    const int dt_tiles = (out_len + DT - 1) / DT;
+    const int64_t n_parts = use_mfma ? mt_tiles : (int64_t)M * dt_tiles;
+    const size_t off_hb = 0;
+    const size_t off_ps = al256(off_hb + (use_mfma ? (size_t)hb_total * 2 : 0));
+    const size_t off_rm = al256(off_ps + sizeof(double) * (size_t)n_rooms * n_parts);
+    const size_t need = al256(off_rm + sizeof(ConvRoom) * n_rooms);
+    if (C.ev && C.used) {
+        hipError_t e = hipEventSynchronize(C.ev);
+        if (e != hipSuccess) return ism_hip_fail(h, e, "hipEventSynchronize");
+        C.used = false;
+    }
+    if (C.cap < need) {
+        if (C.ws) hipFree(C.ws);
+        C.ws = nullptr;
+        C.cap = 0;
+        if (hipMalloc(&C.ws, need) != hipSuccess) { ism_set_error(h, "conv workspace allocation failed"); return ISM_ENOMEM; }
+        C.cap = need;
+    }
+    const size_t rbytes = sizeof(ConvRoom) * n_rooms;
+    if (C.stage_cap < rbytes) {
+        if (C.stage) hipHostFree(C.stage);
+        C.stage = nullptr;
+        C.stage_cap = 0;
+        if (hipHostMalloc(&C.stage, rbytes, hipHostMallocDefault) != hipSuccess) {
+            ism_set_error(h, "pinned allocation failed");
+            return ISM_ENOMEM;
+        }
+        C.stage_cap = rbytes;
+    }
+    if (!C.ev && hipEventCreateWithFlags(&C.ev, hipEventDisableTiming) != hipSuccess) {
+        ism_set_error(h, "hipEventCreate failed");
+        return ISM_EDEVICE;
+    }
+    std::memcpy(C.stage, rooms.data(), rbytes);
+    char *ws = (char *)C.ws;
+    uint16_t *hb = (uint16_t *)(ws + off_hb);
+    double *ps = (double *)(ws + off_ps);
+    ConvRoom *rm = (ConvRoom *)(ws + off_rm);
+    hipError_t e = hipMemcpyAsync(rm, C.stage, rbytes, hipMemcpyHostToDevice, q);
+    if (e != hipSuccess) return ism_hip_fail(h, e, "hipMemcpyAsync");
+    if (use_mfma) {
+        hipLaunchKernelGGL(conv_pack_h, dim3(std::max(1, (nb_max * CB + 255) / 256), n_rooms, M), dim3(256), 0, q,
+                           rirs, rm, M, hb);
+        if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_pack_h launch");
+        // source window of the widest tile: 32 (s_end - s_start) + 63 with s range <= nb + 15 blocks, +32 slack
+        const int xcap = (CB * (std::min(nb_max, mt_tiles * CG) + CG) + 2 * CB + 32 + 63) / 64 * 64;
+        const int lds = xcap * 2 + 16 * CM * CB * 2;
+        if (lds > 160 * 1024) { ism_set_error(h, "RIR too long for the MFMA path (%d bytes of LDS)", lds); return ISM_EINVAL; }
+        hipLaunchKernelGGL(conv_mfma, dim3(mt_tiles, n_rooms), dim3(64), lds, q, src, src_len, out_len, hb, rm, out, ps,
+                           mt_tiles, xcap);
+        if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_mfma launch");
+    } else {
+        hipLaunchKernelGGL(conv_direct, dim3(dt_tiles, M, n_rooms), dim3(256), 0, q, rirs, rm, src, src_len, out_len, M,
+                           out, ps, dt_tiles);
+        if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_direct launch");
+    }
+    if (snr_db) {
+        const int64_t per_room = (int64_t)M * out_len;
+        const int chunks = (int)std::min<int64_t>(64, (per_room + 255) / 256);
+        hipLaunchKernelGGL(conv_noise, dim3(chunks, n_rooms), dim3(256), 0, q, out, z, ps, rm, (int)n_parts, per_room);
+        if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_noise launch");
+    }
+    if ((e = hipEventRecord(C.ev, q)) != hipSuccess) return ism_hip_fail(h, e, "hipEventRecord");
+    C.used = true;
+    return ISM_OK;
 }

@@ -186,3 +186,18 @@ def tiny(seed=7, n_rooms=4, fs=8000.0, c=C_SOUND, rir_len=64, M=2, taps=9):
         rooms.append({"L": L, "beta": beta, "src": src, "mics": mics, "max_order": -1,
                       "rir_len": rir_len})
     return pack(rooms, fs, c, taps, ORDER_INDEX_L1, "tiny")
+
+
+def synthetic_rirs(rir_len, M, seed=17, decay_s=0.15, fs=16000.0):
+    """Decaying-noise RIR-like arrays (inputs for convolution tests): per room, M rows of
+    N(0,1) * exp(-n / (decay_s fs)).  Returns (flat float32 array, per-room offsets)."""
+    rng = np.random.default_rng(seed)
+    rir_len = np.asarray(rir_len, dtype=np.int64)
+    offs = np.zeros(len(rir_len), dtype=np.int64)
+    if len(rir_len):
+        offs[1:] = np.cumsum(rir_len * M)[:-1]
+    out = np.empty(int((rir_len * M).sum()), dtype=np.float32)
+    for r, L in enumerate(rir_len):
+        env = np.exp(-np.arange(L) / (decay_s * fs))
+        out[offs[r]:offs[r] + M * L] = (rng.standard_normal((M, L)) * env).astype(np.float32).ravel()
+    return out, offs
