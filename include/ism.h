@@ -199,6 +199,52 @@ int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float *rirs,
                        int src_len, int out_len, const float *snr_db, const float *z,
                        int use_mfma, float *out, ism_stream stream);
 
+/*
+ * Serving engine: continuous batching of single-room requests (the dataset
+ * generator of section II.A run as a service, for requests of uneven room size,
+ * RIR length and microphone count arriving at any time).
+ *
+ * ism_server_create: n_lanes streams (1..16), each with its own launch state;
+ *   hbm_budget_bytes is allocated once as the output pool; a request is admitted,
+ *   in strict FIFO order, when its output (M x rir_len floats) fits in the pool and
+ *   a lane is free; up to max_batch_rooms admitted requests with equal fs, c,
+ *   fd_taps, order_mode and precision form one batched launch.  Batches on
+ *   different lanes run concurrently.  mock = 1 runs the scheduler without a
+ *   device (batches complete after a host-side delay; outputs are NULL).
+ * ism_server_submit: copies the room and its microphones (host), returns a ticket;
+ *   room->mic_offset and room->out_offset are ignored.  Thread-safe.
+ *   ISM_ENOMEM if the output can never fit the budget; validation errors as for
+ *   ism_rir.
+ * ism_server_poll: *state = 0 queued, 1 running, 2 done, 3 failed; when done,
+ *   *out_dev = device pointer to the M x rir_len result (owned by the engine until
+ *   release) and *latency_ms = completion - submission (host clock at the
+ *   engine's observation of the batch's completion event).  Returns the failure
+ *   status for a failed request.
+ * ism_server_copy_result: queues a device-to-device copy of a finished request's
+ *   result (M x rir_len floats) into dst on `stream` (ISM_EBUSY if not done yet).
+ * ism_server_release: frees a finished request (ISM_EBUSY while queued/running);
+ *   copies queued before release must have completed.
+ * ism_server_stats: [submitted, done, batches, max concurrent batches, pool
+ *   bytes, peak pool bytes in use, queued now, RIRs done].
+ * ism_server_replay: benchmark driver; submits rooms[i] (microphones at
+ *   mics + 3*rooms[i].mic_offset) at arrival_s[i] seconds after the call from a
+ *   client thread, releases each result when done, writes per-request latency
+ *   (ms) and the wall time from the call to the last completion.
+ * ism_server_destroy: stops the scheduler, waits for running batches, frees all.
+ */
+typedef struct ism_server ism_server;
+int ism_server_create(int n_lanes, size_t hbm_budget_bytes, int max_batch_rooms, int mock, ism_server **s);
+void ism_server_destroy(ism_server *s);
+int ism_server_submit(ism_server *s, const ism_room *room, const double *mics, double fs, double c, int fd_taps,
+                      int order_mode, int precision, uint64_t *ticket);
+int ism_server_poll(ism_server *s, uint64_t ticket, int *state, float **out_dev, double *latency_ms);
+int ism_server_copy_result(ism_server *s, uint64_t ticket, float *dst, ism_stream stream);
+int ism_server_release(ism_server *s, uint64_t ticket);
+int ism_server_stats(ism_server *s, int64_t stats[8]);
+const char *ism_server_last_error(ism_server *s);
+int ism_server_replay(ism_server *s, int n, const ism_room *rooms, const double *mics, const double *arrival_s,
+                      double fs, double c, int fd_taps, double *latency_ms, double *wall_s);
+
 #ifdef __cplusplus
 }
 #endif

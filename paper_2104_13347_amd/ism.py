@@ -23,7 +23,8 @@ PREC_FP32, PREC_FP16_LUT, PREC_FP32_SPLIT, PREC_FP32_ATOMIC = 0, 1, 2, 3
 EXPORTS = [
     "ism_create", "ism_destroy", "ism_strerror", "ism_last_error", "ism_version", "ism_rir",
     "ism_rir_batch", "ism_batch_plan_stats", "ism_last_counts", "ism_set_tuning", "ism_get_tuning",
-    "ism_autotune", "ism_convolve_batch",
+    "ism_autotune", "ism_convolve_batch", "ism_server_create", "ism_server_destroy", "ism_server_submit",
+    "ism_server_poll", "ism_server_copy_result", "ism_server_release", "ism_server_stats", "ism_server_last_error", "ism_server_replay",
 ]
 
 ROOM_DTYPE = np.dtype([("L", np.float64, 3), ("beta", np.float64, 6), ("src", np.float64, 3),
@@ -80,6 +81,24 @@ def load():
     L.ism_autotune.restype = ci
     L.ism_convolve_batch.argtypes = [vp, ci, ci, vp, i64p, i32p, vp, ci, ci, fp, vp, ci, vp, vp]
     L.ism_convolve_batch.restype = ci
+    L.ism_server_create.argtypes = [ci, ctypes.c_size_t, ci, ci, ctypes.POINTER(vp)]
+    L.ism_server_create.restype = ci
+    L.ism_server_destroy.argtypes = [vp]
+    L.ism_server_destroy.restype = None
+    L.ism_server_submit.argtypes = [vp, vp, dp, cd, cd, ci, ci, ci, ctypes.POINTER(ctypes.c_uint64)]
+    L.ism_server_submit.restype = ci
+    L.ism_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ci), ctypes.POINTER(vp), dp]
+    L.ism_server_poll.restype = ci
+    L.ism_server_copy_result.argtypes = [vp, ctypes.c_uint64, vp, vp]
+    L.ism_server_copy_result.restype = ci
+    L.ism_server_release.argtypes = [vp, ctypes.c_uint64]
+    L.ism_server_release.restype = ci
+    L.ism_server_stats.argtypes = [vp, i64p]
+    L.ism_server_stats.restype = ci
+    L.ism_server_last_error.argtypes = [vp]
+    L.ism_server_last_error.restype = ctypes.c_char_p
+    L.ism_server_replay.argtypes = [vp, ci, vp, dp, dp, cd, cd, ci, dp, dp]
+    L.ism_server_replay.restype = ci
     _lib = L
     return L
 
@@ -235,3 +254,85 @@ class Handle:
                                          ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
         self._check(rc)
         return out
+
+
+SERVER_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
+
+
+class Server:
+    """Continuous-batching RIR engine (ism_server_*)."""
+
+    def __init__(self, n_lanes=4, hbm_budget_bytes=8 << 30, max_batch_rooms=64, mock=False):
+        self.lib = load()
+        s = ctypes.c_void_p()
+        rc = self.lib.ism_server_create(int(n_lanes), int(hbm_budget_bytes), int(max_batch_rooms), int(bool(mock)),
+                                        ctypes.byref(s))
+        if rc != ISM_OK:
+            raise IsmError(rc, "ism_server_create failed: " + self.lib.ism_strerror(rc).decode())
+        self.s = s
+
+    def close(self):
+        if getattr(self, "s", None):
+            self.lib.ism_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != ISM_OK:
+            raise IsmError(rc, self.lib.ism_server_last_error(self.s).decode() or self.lib.ism_strerror(rc).decode())
+
+    def submit(self, L, beta, src, mics, rir_len, fs, c, fd_taps, max_order=-1, order_mode=ORDER_INDEX_L1,
+               precision=PREC_FP32):
+        r = np.zeros(1, dtype=ROOM_DTYPE)
+        mics = np.ascontiguousarray(np.atleast_2d(mics), dtype=np.float64)
+        r["L"], r["beta"], r["src"] = L, beta, src
+        r["n_mics"], r["max_order"], r["rir_len"] = mics.shape[0], max_order, rir_len
+        t = ctypes.c_uint64()
+        self._check(self.lib.ism_server_submit(self.s, r.ctypes.data_as(ctypes.c_void_p), _dptr(mics), float(fs),
+                                               float(c), int(fd_taps), int(order_mode), int(precision),
+                                               ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket):
+        st, ptr, lat = ctypes.c_int(), ctypes.c_void_p(), ctypes.c_double()
+        rc = self.lib.ism_server_poll(self.s, ctypes.c_uint64(ticket), ctypes.byref(st), ctypes.byref(ptr),
+                                      ctypes.byref(lat))
+        if st.value != 3:
+            self._check(rc)
+        return SERVER_STATES[st.value], ptr.value, lat.value
+
+    def result(self, ticket, M, rir_len, stream=None):
+        """Copy a finished result into a new device tensor [M, rir_len]."""
+        import torch
+        out = torch.empty((M, rir_len), dtype=torch.float32, device="cuda")
+        self._check(self.lib.ism_server_copy_result(self.s, ctypes.c_uint64(ticket), ctypes.c_void_p(out.data_ptr()),
+                                                    _stream_handle(stream)))
+        return out
+
+    def release(self, ticket):
+        self._check(self.lib.ism_server_release(self.s, ctypes.c_uint64(ticket)))
+
+    def stats(self):
+        st = (ctypes.c_int64 * 8)()
+        self._check(self.lib.ism_server_stats(self.s, st))
+        keys = ["submitted", "done", "batches", "max_concurrent_batches", "pool_bytes", "pool_peak_bytes",
+                "queued", "rirs_done"]
+        return dict(zip(keys, [int(v) for v in st]))
+
+    def replay(self, batch, arrival_s):
+        """Submit the rooms of a scene batch at the given arrival times; returns (latencies ms, wall s)."""
+        rooms = rooms_array(batch)
+        mics = np.ascontiguousarray(batch["mics"], dtype=np.float64)
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        lat = np.zeros(len(rooms))
+        wall = ctypes.c_double()
+        rc = self.lib.ism_server_replay(self.s, len(rooms), rooms.ctypes.data_as(ctypes.c_void_p), _dptr(mics),
+                                        _dptr(arr), float(batch["fs"]), float(batch["c"]), int(batch["fd_taps"]),
+                                        _dptr(lat), ctypes.byref(wall))
+        self._check(rc)
+        return lat, wall.value

@@ -1,0 +1,90 @@
+"""Serving engine on the GPU: continuous batching over several streams.
+Each request's result must be bitwise equal to the same room computed alone
+(ism_rir), the HBM budget must bound the pool, batches must overlap, and
+sampled results must match the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_13347_amd import ism, scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _wait_all(S, tickets, timeout=120.0):
+    import time
+    t0 = time.time()
+    pending = set(tickets)
+    lat = {}
+    while pending and time.time() - t0 < timeout:
+        for t in list(pending):
+            st, _, l = S.poll(t)
+            if st == "done":
+                lat[t] = l
+                pending.discard(t)
+            elif st == "failed":
+                raise AssertionError(f"request {t} failed")
+        time.sleep(0.001)
+    assert not pending, "timeout"
+    return lat
+
+
+def test_results_equal_alone_and_in_the_mix(torch_cuda):
+    torch = torch_cuda
+    reqs, gaps, meta = scenes.c2(n_requests=40)
+    S = ism.Server(n_lanes=4, hbm_budget_bytes=2 << 30, max_batch_rooms=6)
+    H = ism.Handle()
+    try:
+        tickets = [S.submit(r["L"], r["beta"], r["src"], r["mics"], r["rir_len"], meta["fs"], meta["c"],
+                            meta["fd_taps"]) for r in reqs]
+        lat = _wait_all(S, tickets)
+        st = S.stats()
+        sys.stdout.write(f"serve stats {st}\n")
+        assert st["max_concurrent_batches"] >= 2, "batches on different lanes must overlap"
+        assert st["pool_peak_bytes"] <= st["pool_bytes"]
+        for t, r in zip(tickets, reqs):
+            M, n = len(r["mics"]), r["rir_len"]
+            mix = S.result(t, M, n)
+            alone = H.rir(r["L"], r["beta"], r["src"], r["mics"], meta["fs"], meta["c"], -1, n, meta["fd_taps"])
+            torch.cuda.synchronize()
+            assert torch.equal(mix, alone), f"request {t} differs alone vs in the mix"
+            assert lat[t] > 0
+            S.release(t)
+        # two sampled requests against the oracle
+        for i in (0, 17):
+            r = reqs[i]
+            got = H.rir(r["L"], r["beta"], r["src"], r["mics"][:1], meta["fs"], meta["c"], -1, r["rir_len"], 81)
+            torch.cuda.synchronize()
+            ref, _ = oracle.rir(r["L"], r["beta"], r["src"], r["mics"][0], meta["fs"], meta["c"], -1, 0,
+                                r["rir_len"], 81)
+            assert np.max(np.abs(got.cpu().numpy()[0] - ref)) <= 1e-5 * np.max(np.abs(ref))
+    finally:
+        S.close()
+        H.close()
+
+
+def test_budget_bounds_pool_and_everything_completes(torch_cuda):
+    reqs, gaps, meta = scenes.c2(n_requests=60, seed=99)
+    sizes = [4 * len(r["mics"]) * r["rir_len"] for r in reqs]
+    budget = int(max(sizes) * 3)
+    S = ism.Server(n_lanes=3, hbm_budget_bytes=budget, max_batch_rooms=4)
+    try:
+        b = scenes.pack(reqs, meta["fs"], meta["c"], meta["fd_taps"], meta["order_mode"], "c2")
+        lat, wall = S.replay(b, np.cumsum(gaps) * 2e-4)
+        st = S.stats()
+        sys.stdout.write(f"budget {budget} stats {st} wall {wall:.3f}s p50 {np.median(lat):.2f} ms\n")
+        assert st["done"] == 60
+        assert st["pool_peak_bytes"] <= budget
+        assert np.all(lat > 0)
+    finally:
+        S.close()
