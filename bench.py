@@ -80,6 +80,90 @@ def cpu_baseline(batch, budget_s=12.0):
                       f"FP64 oracle, {nthreads} threads over RIRs, {dt:.1f} s"}
 
 
+def _time_it(torch, fn, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def bench_c3(H, torch):
+    """64 rooms 20x15x8 m, 48 kHz, 72000 samples, 16 mics, 127 taps: throughput per precision mode
+    (errors against the FP64 oracle are checked in the tests)."""
+    from paper_2104_13347_amd import ism, scenes
+    b = scenes.c3()
+    rooms = ism.rooms_array(b)
+    out = torch.empty(int(b["out_size"]), dtype=torch.float32, device="cuda")
+    res = {"workload": "64 rooms 20x15x8 m, per-wall beta U[0.85,0.95], 48 kHz, 72000 samples, 16 mics, 127 taps"}
+    for prec, name in [(ism.PREC_FP32, "fp32"), (ism.PREC_FP16_LUT, "fp16_lut"), (ism.PREC_FP32_SPLIT, "fp32_split")]:
+        ms = _time_it(torch, lambda: H.rir_batch(b, precision=prec, out=out, rooms=rooms))
+        taps = H.last_counts()["taps"]
+        res[name] = {"ms": ms, "taps_per_s": taps / (ms / 1e3), "rirs_per_s": 64 * 16 / (ms / 1e3), "taps": taps}
+    return res
+
+
+def bench_c4(H, torch):
+    """256 rooms (1024-room distribution, seed 2108), 8 mics: RIR batch on the GPU, then convolution
+    with 1 s white-noise sources and sensor noise at SNR U[0,30] dB."""
+    from paper_2104_13347_amd import ism, scenes
+    b = scenes.c4()
+    rooms = ism.rooms_array(b)
+    rirs = torch.empty(int(b["out_size"]), dtype=torch.float32, device="cuda")
+    x = torch.from_numpy(b["x"]).cuda()
+    z = torch.from_numpy(b["z"]).cuda()
+    y = torch.empty((256, 8, 16000), dtype=torch.float32, device="cuda")
+    lens = b["rir_len"]
+    offs = b["out_offset"]
+    rir_ms = _time_it(torch, lambda: H.rir_batch(b, out=rirs, rooms=rooms))
+    flops = 0.0
+    for L in lens:   # algorithmic MACs: sum over n < 16000 of min(n + 1, L)
+        L = int(L)
+        flops += 2.0 * 8 * (L * 16000 - L * (L - 1) / 2.0)
+    res = {"workload": "256 rooms x 8 mics, RIR 0.8*RT60*fs, 1 s N(0,1) source at 16 kHz, SNR U[0,30] dB",
+           "rir_batch_ms": rir_ms, "algorithmic_flops": flops}
+    for mfma, name in [(True, "bf16_mfma"), (False, "fp32_direct")]:
+        ms = _time_it(torch, lambda: H.convolve_batch(rirs, offs, lens, 8, x, 16000, snr_db=b["snr_db"], z=z,
+                                                      use_mfma=mfma, out=y))
+        tf = flops / (ms / 1e3) / 1e12
+        res[name] = {"ms": ms, "tflops": tf,
+                     "peak_tflops": 2500.0 if mfma else FP32_VECTOR_PEAK_TFLOPS,
+                     "frac": tf / (2500.0 if mfma else FP32_VECTOR_PEAK_TFLOPS)}
+    res["pipeline_ms"] = rir_ms + res["bf16_mfma"]["ms"]
+    return res
+
+
+def bench_c2(torch, n_requests):
+    """Serving: Poisson arrivals of single-room requests (RT60 U[0.1,1.0] s, RIR RT60*fs, M in
+    {4,8,16,32}).  First a saturated run (all requests at t=0) gives the sustainable rate; then
+    arrivals at 0.7 of that rate give latency percentiles."""
+    from paper_2104_13347_amd import ism, scenes
+    reqs, gaps, meta = scenes.c2(n_requests=n_requests)
+    b = scenes.pack(reqs, meta["fs"], meta["c"], meta["fd_taps"], meta["order_mode"], "c2")
+    n_rirs = int(b["n_mics"].sum())
+    S = ism.Server(n_lanes=4, hbm_budget_bytes=8 << 30, max_batch_rooms=64)
+    try:
+        lat0, wall0 = S.replay(b, np.zeros(n_requests))
+        rate = n_requests / wall0
+        lam = 0.7 * rate
+        lat, wall = S.replay(b, np.cumsum(gaps) / lam)
+        st = S.stats()
+    finally:
+        S.close()
+    return {"workload": f"{n_requests} requests, Poisson arrivals, RT60 U[0.1,1.0] s, M in {{4,8,16,32}}, 16 kHz",
+            "saturated": {"requests_per_s": rate, "rirs_per_s": n_rirs / wall0, "wall_s": wall0},
+            "poisson": {"lambda_per_s": lam, "p50_ms": float(np.percentile(lat, 50)),
+                        "p99_ms": float(np.percentile(lat, 99)), "rirs_per_s": n_rirs / wall, "wall_s": wall},
+            "lanes": 4, "hbm_budget_bytes": 8 << 30, "max_concurrent_batches": st["max_concurrent_batches"],
+            "batches": st["batches"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +175,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=200)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the serving, precision and convolution sections")
+    ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="run only a plain device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -197,6 +284,9 @@ def main():
     if lat:
         res["latency_ms_single_rir"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                                         "workload": "5x4x3 m room, index-L1 order 10, 1 mic, 4096 samples"}
+    if not args.no_extras:
+        res["extras"] = {"c3_precision": bench_c3(H, torch), "c4_convolution": bench_c4(H, torch),
+                         "c2_serving": bench_c2(torch, args.serve_requests)}
     H.close()
 
     if not args.no_cpu_baseline:

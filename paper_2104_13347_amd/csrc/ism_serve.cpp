@@ -106,6 +106,7 @@ struct Request {
     size_t bytes = 0, off = 0;
     int state = Q_QUEUED;
     int status = ISM_OK;
+    int64_t tag = -1;  // replay index
     double t_submit = 0, t_start = 0, t_done = 0;
 };
 
@@ -135,6 +136,8 @@ struct ism_server {
     std::atomic<bool> stop{false};
     std::thread worker;
     std::string err;
+    bool record_completions = false;                    // replay: queue (ticket, tag) of finished requests
+    std::vector<std::pair<uint64_t, int64_t>> completed;
     // statistics
     int64_t n_submitted = 0, n_done = 0, n_batches = 0, max_inflight_batches = 0;
     int64_t rirs_done = 0;
@@ -171,6 +174,7 @@ void ism_server::loop()
                 it->second.t_done = td;
                 ++n_done;
                 rirs_done += it->second.room.n_mics;
+                if (record_completions) completed.emplace_back(tk, it->second.tag);
             }
             L.batch.clear();
             L.busy = false;
@@ -225,6 +229,9 @@ void ism_server::loop()
                     r.state = Q_FAILED;
                     r.status = st;
                     r.t_done = now_s();
+                    if (r.off != (size_t)-1) pool.release(r.off, r.bytes);
+                    r.off = (size_t)-1;
+                    if (record_completions) completed.emplace_back(tk, r.tag);
                 }
                 err = ism_last_error(L.h);
                 continue;
@@ -291,8 +298,8 @@ extern "C" void ism_server_destroy(ism_server *s)
 
 extern "C" const char *ism_server_last_error(ism_server *s) { return s ? s->err.c_str() : ""; }
 
-extern "C" int ism_server_submit(ism_server *s, const ism_room *room, const double *mics, double fs, double c,
-                                 int fd_taps, int order_mode, int precision, uint64_t *ticket)
+static int submit_impl(ism_server *s, const ism_room *room, const double *mics, double fs, double c, int fd_taps,
+                       int order_mode, int precision, int64_t tag, uint64_t *ticket)
 {
     if (!s || !room || !mics || !ticket) return ISM_EINVAL;
     ism_room r = *room;
@@ -322,6 +329,7 @@ extern "C" int ism_server_submit(ism_server *s, const ism_room *room, const doub
     q.order_mode = order_mode;
     q.precision = precision;
     q.bytes = bytes;
+    q.tag = tag;
     q.t_submit = now_s();
     {
         std::lock_guard<std::mutex> g(s->mu);
@@ -333,6 +341,12 @@ extern "C" int ism_server_submit(ism_server *s, const ism_room *room, const doub
     }
     s->cv.notify_all();
     return ISM_OK;
+}
+
+extern "C" int ism_server_submit(ism_server *s, const ism_room *room, const double *mics, double fs, double c,
+                                 int fd_taps, int order_mode, int precision, uint64_t *ticket)
+{
+    return submit_impl(s, room, mics, fs, c, fd_taps, order_mode, precision, -1, ticket);
 }
 
 extern "C" int ism_server_poll(ism_server *s, uint64_t ticket, int *state, float **out_dev, double *latency_ms)
@@ -379,7 +393,7 @@ extern "C" int ism_server_release(ism_server *s, uint64_t ticket)
         auto it = s->reqs.find(ticket);
         if (it == s->reqs.end()) return ISM_EINVAL;
         if (it->second.state == Q_QUEUED || it->second.state == Q_RUNNING) return ISM_EBUSY;
-        if (it->second.state == Q_DONE) s->pool.release(it->second.off, it->second.bytes);
+        if (it->second.state == Q_DONE && it->second.off != (size_t)-1) s->pool.release(it->second.off, it->second.bytes);
         s->reqs.erase(it);
     }
     s->cv.notify_all();
@@ -406,9 +420,14 @@ extern "C" int ism_server_replay(ism_server *s, int n, const ism_room *rooms, co
                                  double *wall_s)
 {
     if (!s || n < 0 || (n > 0 && (!rooms || !mics || !arrival_s || !latency_ms))) return ISM_EINVAL;
-    std::vector<uint64_t> tickets(n, 0);
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->record_completions) return ISM_EBUSY;  // one replay at a time
+        s->record_completions = true;
+        s->completed.clear();
+    }
     std::vector<int> rc(n, ISM_OK);
-    std::atomic<int> submitted{0};
+    std::atomic<int> n_failed_submit{0};
     const double t0 = now_s();
     std::thread client([&] {
         for (int i = 0; i < n; ++i) {
@@ -417,36 +436,43 @@ extern "C" int ism_server_replay(ism_server *s, int n, const ism_room *rooms, co
                 const double left = due - now_s();
                 if (left > 200e-6) std::this_thread::sleep_for(std::chrono::microseconds((int64_t)(left * 0.5e6)));
             }
-            rc[i] = ism_server_submit(s, &rooms[i], mics + 3 * (size_t)rooms[i].mic_offset, fs, c, fd_taps, 0, 0,
-                                      &tickets[i]);
-            submitted.store(i + 1, std::memory_order_release);
+            uint64_t tk;
+            rc[i] = submit_impl(s, &rooms[i], mics + 3 * (size_t)rooms[i].mic_offset, fs, c, fd_taps, 0, 0, i, &tk);
+            if (rc[i] != ISM_OK) {
+                latency_ms[i] = -1.0;
+                n_failed_submit.fetch_add(1);
+            }
         }
     });
     int finished = 0, st = ISM_OK;
-    std::vector<char> fin(n, 0);
     double t_last = t0;
-    while (finished < n) {
-        const int ns = submitted.load(std::memory_order_acquire);
-        bool any = false;
-        for (int i = 0; i < ns; ++i) {
-            if (fin[i]) continue;
-            if (rc[i] != ISM_OK) { fin[i] = 1; ++finished; latency_ms[i] = -1; st = rc[i]; continue; }
+    std::vector<std::pair<uint64_t, int64_t>> batch;
+    while (finished + n_failed_submit.load() < n) {
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            batch.swap(s->completed);
+        }
+        for (auto &e : batch) {
             int state = 0;
             double lat = 0;
-            int r = ism_server_poll(s, tickets[i], &state, nullptr, &lat);
-            if (state >= Q_DONE) {
-                latency_ms[i] = lat;
-                if (r != ISM_OK) st = r;
-                ism_server_release(s, tickets[i]);
-                fin[i] = 1;
-                ++finished;
-                any = true;
-                t_last = now_s();
-            }
+            int r = ism_server_poll(s, e.first, &state, nullptr, &lat);
+            if (r != ISM_OK) st = r;
+            if (e.second >= 0 && e.second < n) latency_ms[e.second] = lat;
+            ism_server_release(s, e.first);
+            ++finished;
+            t_last = now_s();
         }
-        if (!any) std::this_thread::sleep_for(std::chrono::microseconds(50));
+        if (batch.empty()) std::this_thread::sleep_for(std::chrono::microseconds(50));
+        batch.clear();
     }
     client.join();
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->record_completions = false;
+        s->completed.clear();
+    }
+    for (int i = 0; i < n; ++i)
+        if (rc[i] != ISM_OK) st = rc[i];
     if (wall_s) *wall_s = t_last - t0;
     return st;
 }
