@@ -164,17 +164,37 @@ DEV void lds_add_fx(long long *p, float x)
 
 // 2K+1 taps of one record, K known at compile time: constants fold to literals.
 // FX: fixed-point accumulation into acc64; otherwise FP32 LDS atomics into acc32.
+// Taps +k and -k share one reciprocal: with p = f^2 - k^2 = (k - f)(-k - f),
+// 1/(k - f) = (-k - f)/p and 1/(-k - f) = (k - f)/p; the sign (-1)^k (the same
+// for +k and -k) is folded into the two numerators' factors.
 template <int K, bool FX>
 DEV void taps_fp32_ct(long long *acc64, float *acc32, float f, float a0, float a1, float a2)
 {
     constexpr TapConst<K> T{};
+    {   // k = 0: (-1)^0 / (0 - f)
+        const float r = __builtin_amdgcn_rcpf(-f);
+        const float num = fmaf(a2, T.s[K], fmaf(a1, T.c[K], a0));
+        if (FX) lds_add_fx(acc64, num * r);
+        else lds_add(acc32, num * r);
+    }
+    const float f2 = f * f;
 #pragma unroll
-    for (int k = -K; k <= K; ++k) {
-        const float t = (k & 1) ? (f - (float)k) : ((float)k - f);
-        const float r = __builtin_amdgcn_rcpf(t);
-        const float num = fmaf(a2, T.s[k + K], fmaf(a1, T.c[k + K], a0));
-        if (FX) lds_add_fx(acc64 + k, num * r);
-        else lds_add(acc32 + k, num * r);
+    for (int k = 1; k <= K; ++k) {
+        const float rp = __builtin_amdgcn_rcpf(f2 - (float)(k * k));
+        // (-1)^k / (k - f) = tp * rp and (-1)^k / (-k - f) = tm * rp
+        const float tp = (k & 1) ? ((float)k + f) : (-(float)k - f);
+        const float tm = (k & 1) ? (f - (float)k) : ((float)k - f);
+        const float np = fmaf(a2, T.s[K + k], fmaf(a1, T.c[K + k], a0));
+        const float nm = fmaf(a2, T.s[K - k], fmaf(a1, T.c[K - k], a0));
+        const float vp = (np * tp) * rp;
+        const float vm = (nm * tm) * rp;
+        if (FX) {
+            lds_add_fx(acc64 + k, vp);
+            lds_add_fx(acc64 - k, vm);
+        } else {
+            lds_add(acc32 + k, vp);
+            lds_add(acc32 - k, vm);
+        }
     }
 }
 
@@ -291,6 +311,7 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
     const int seg_max = P->seg_max;
     Lds S = carve(ism_lds, seg_max, K, VAR);
     const double fs = P->fs, cs = P->c;
+    const double fsc = fs / cs;
     const int order_mode = P->order_mode;
     const int split32 = P->split32;
     const float Pw = (float)(kPi / (double)(K + 1));
@@ -494,6 +515,15 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
 
             // ---- flattened images of the chunk, one per lane per step
             const int nsteps = (T + 63) / 64;
+            // each lane walks increasing flattened indices: find its first column once,
+            // then advance column and interval incrementally
+            int c = 0;
+            {
+                const int xs = P->interleave ? lane * nsteps : lane;
+#pragma unroll
+                for (int st = 32; st >= 1; st >>= 1)
+                    if (S.coff[c + st] <= xs) c += st;
+            }
             for (int js = 0; js < nsteps; ++js) {
                 // interleaved: the 64 lanes of a step take images spread over the whole
                 // chunk (different columns), so that their delays rarely coincide
@@ -504,10 +534,7 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
                 int rn = 0;
                 if (x < T) {
                     ++n_img;
-                    int c = 0;
-#pragma unroll
-                    for (int st = 32; st >= 1; st >>= 1)
-                        if (S.coff[c + st] <= x) c += st;
+                    while (S.coff[c + 1] <= x) ++c;
                     const int loc = x - S.coff[c];
                     const int e0 = S.icum[c * 4 + 0], e1 = S.icum[c * 4 + 1], e2 = S.icum[c * 4 + 2];
                     const int iv = (loc >= e0) + (loc >= e1) + (loc >= e2);
@@ -523,7 +550,14 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
                     const double dz = Z - rz;
                     const double d2 = S.crho2[c] + dz * dz;
                     const double d = sqrt(d2);
-                    const double tau = d * fs / cs;
+                    // tau = (d fs) / c as in the definition; d * (fs/c) differs by at most an
+                    // ulp or two, which can change floor(tau + 1/2) only right at a rounding
+                    // boundary: there the exact quotient is taken
+                    double tau = d * fsc;
+                    {
+                        const double h = tau + 0.5, fl = floor(h);
+                        if (h - fl < 1e-12 * h || (fl + 1.0) - h < 1e-12 * h) tau = d * fs / cs;
+                    }
                     const double n0d = floor(tau + 0.5);
                     int n0 = (int)n0d;
                     double fr = tau - n0d;
@@ -539,8 +573,8 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
                     if (valid) {
                         const int ez0 = (int)min(iabs(q - w), (long)pmax), ezL = (int)min(iabs(q), (long)pmax);
                         const double B = (S.cbxy[c] * pz0[ez0]) * pzL[ezL];
-                        const double gd = B / (4.0 * kPi * d);
-                        rg = (float)gd;
+                        // g = B / (4 pi d) to FP32 accuracy
+                        rg = (float)B * (0.0795774715459477f * __builtin_amdgcn_rcpf((float)d));
                         rf = (float)fr;
                         if (rf == 0.0f) rf = 0x1p-40f;  // integer delay: exact Kronecker limit
                         rn = n0 - rel;

@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libism.so")
+LIB_PATH = os.environ.get("ISM_LIB") or os.path.join(_HERE, "libism.so")
 
 ISM_OK, ISM_EINVAL, ISM_EDOMAIN, ISM_ENOMEM, ISM_EDEVICE, ISM_EBUSY = 0, -1, -2, -3, -4, -5
 ORDER_INDEX_L1, ORDER_REFLECTIONS = 0, 1
