@@ -27,7 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "image-source taps/s + RIRs/s (batched vs plain, same GPU); p50/p99 RIR latency"
-FLOPS_PER_TAP = 12          # nominal algorithmic flops per tap
+# nominal algorithmic flops per tap of the rational tap form: subtract, reciprocal, two FMAs
+# (4 flops), two multiplies, and 4 for an accurate (compensated) accumulation
+FLOPS_PER_TAP = 12
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
@@ -177,6 +179,8 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the serving, precision and convolution sections")
+    ap.add_argument("--extras", default="c3,c4,c2",
+                    help="comma list of extra sections to run: c3 precision, c4 convolution, c2 serving")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="run only a plain device copy of this many bytes (HBM counter calibration)")
@@ -193,7 +197,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by room with no "
-              "exchange, see DESIGN.md", file=sys.stderr)
+              "exchange between GPUs", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -284,9 +288,15 @@ def main():
     if lat:
         res["latency_ms_single_rir"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                                         "workload": "5x4x3 m room, index-L1 order 10, 1 mic, 4096 samples"}
-    if not args.no_extras:
-        res["extras"] = {"c3_precision": bench_c3(H, torch), "c4_convolution": bench_c4(H, torch),
-                         "c2_serving": bench_c2(torch, args.serve_requests)}
+    extras = set() if args.no_extras else {e.strip() for e in args.extras.split(",") if e.strip()}
+    if extras:
+        res["extras"] = {}
+        if "c3" in extras:
+            res["extras"]["c3_precision"] = bench_c3(H, torch)
+        if "c4" in extras:
+            res["extras"]["c4_convolution"] = bench_c4(H, torch)
+        if "c2" in extras:
+            res["extras"]["c2_serving"] = bench_c2(torch, args.serve_requests)
     H.close()
 
     if not args.no_cpu_baseline:

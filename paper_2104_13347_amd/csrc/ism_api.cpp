@@ -375,8 +375,16 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
     std::memcpy(hb + off_items, plan.items.data(), sizeof(ItemDev) * n_items);
 
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ke.sym, 64, lds);
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    hipError_t e = hipSuccess;
+    if (h->occ_sym == ke.sym && h->occ_lds == lds) {
+        per_cu = h->occ_per_cu;
+    } else {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ke.sym, 64, lds);
+        if (e != hipSuccess || per_cu < 1) per_cu = 1;
+        h->occ_sym = ke.sym;
+        h->occ_lds = lds;
+        h->occ_per_cu = per_cu;
+    }
     if (h->wg_per_cu > 0) per_cu = std::min(per_cu, h->wg_per_cu);
     const int grid = (int)std::min<int64_t>(n_items, (int64_t)per_cu * h->n_cu);
     const LaunchDev *Pd = (const LaunchDev *)db;

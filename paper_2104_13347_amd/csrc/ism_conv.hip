@@ -10,8 +10,9 @@
 //   Y_t (32 x M) = sum_s T_s (32 x 32) H_{t-s} (32 x M),  T_s[i][j] = x[32 s + i - j].
 // T_s depends on s only, so one workgroup keeps 16 output blocks x 8 microphones
 // = 128 columns (four 32-column MFMA tiles sharing every A operand) and walks s.
-// Per s: A = T_s from x staged reversed in LDS (BF16; each lane's eight K
-// values are consecutive there, read as dwords and realigned with v_alignbit),
+// Per s: A = T_s from a 128-sample source ring in LDS (BF16, reversed and stored
+// twice, so each lane's eight K values are consecutive there; read as dwords and
+// realigned with v_alignbit), the ring gaining one 32-sample block per step,
 // B = the RIR blocks b = t - s from a 16-slot LDS ring that gains one block per
 // step, eight v_mfma_f32_32x32x16_bf16.  No MAC is spent on the zero triangle
 // except the partial edges of blocks.
@@ -85,14 +86,20 @@ __global__ void conv_pack_h(const float *__restrict__ rirs, const ConvRoom *__re
 }
 
 // ------------------------------------------------------------------ MFMA block-Toeplitz
-// grid (tiles, rooms), one wave.  LDS: reversed BF16 source window + 16-slot RIR ring.
+// grid (tiles, rooms), one wave.  LDS: a 128-sample source ring (BF16, reversed,
+// stored twice so that any 10-sample window is contiguous) and a 16-slot RIR ring.
+constexpr int XR = 128;   // source ring length (samples)
+constexpr int CRS = 40;   // RIR ring row stride (u16): 80 B rows keep the eight microphones' 16-B
+                          // reads of one step on eight different bank groups
+
 __global__ __launch_bounds__(64) void conv_mfma(const float *__restrict__ x, int src_len, int out_len,
                                                 const uint16_t *__restrict__ hb,
                                                 const ConvRoom *__restrict__ rooms,
                                                 float *__restrict__ y, double *__restrict__ psum,
-                                                int tiles_per_room, int xwin_cap)
+                                                int tiles_per_room)
 {
-    extern __shared__ __attribute__((aligned(16))) char lds[];
+    __shared__ __attribute__((aligned(16))) uint16_t xring[2 * XR];
+    __shared__ __attribute__((aligned(16))) uint16_t ring[16 * CM * CRS];
     const int lane = threadIdx.x;
     const int r = blockIdx.y, tile = blockIdx.x;
     const int t0 = tile * CG;
@@ -100,32 +107,56 @@ __global__ __launch_bounds__(64) void conv_mfma(const float *__restrict__ x, int
     const int nb = R.nb;
     const int s_start = max(0, t0 - nb + 1);
     const int s_end = t0 + CG - 1;
-    // source window: x indices [32 s_start - 31, 32 s_end + 31], stored reversed:
-    // xr[p] = x[xhi - p]
-    const int xhi = CB * s_end + CB - 1;
-    const int wlen = CB * (s_end - s_start) + 2 * CB - 1;
-    uint16_t *xr = (uint16_t *)lds;                        // xwin_cap elements (>= wlen + 32)
-    uint16_t *ring = (uint16_t *)(lds + xwin_cap * 2);     // [16][CM][CB]
     const float *xs = x + (int64_t)r * src_len;
-    for (int p = lane; p < xwin_cap; p += 64) {
-        const int xi = xhi - p;
-        xr[p] = (p < wlen && xi >= 0 && xi < src_len) ? f2bf(xs[xi]) : (uint16_t)0;
-    }
-    // RIR ring: slot (b & 15) holds block b of all microphones (zeros outside [0, nb))
     const uint16_t *hr = hb + R.h_off;
+    // Global loads use clamped (always valid) addresses and keep the raw value; the zero
+    // outside the signal is applied when the value is written to LDS, so no load has to
+    // complete before the step that consumes it.
+    auto load_x = [&](int sb) -> float {           // lane covers sample 32 sb + lane % 32
+        const int X = CB * sb + (lane & 31);
+        return xs[min(max(X, 0), src_len - 1)];
+    };
+    // source ring: sample X sits at (-X) mod 128 and again 128 entries later, so that any
+    // 8 consecutive samples read downwards in time are contiguous
+    auto store_x = [&](int sb, float v) {
+        if (lane < 32) {
+            const int X = CB * sb + lane;
+            const uint16_t bv = (X >= 0 && X < src_len) ? f2bf(v) : (uint16_t)0;
+            const int p = (-X) & (XR - 1);
+            xring[p] = bv;
+            xring[p + XR] = bv;
+        }
+    };
+    // RIR ring: slot (b & 15) holds block b of all microphones (zeros outside [0, nb));
+    // lane covers 4 taps: mic = lane / 8, taps (lane % 8) * 4 .. + 3
     auto load_block = [&](int b) -> uint2 {
-        // lane covers 4 taps: mic = lane / 8, taps (lane % 8) * 4 .. + 3
-        if (b < 0 || b >= nb) return make_uint2(0u, 0u);
-        const uint16_t *p = hr + (int64_t)(lane >> 3) * nb * CB + (int64_t)b * CB + (lane & 7) * 4;
-        return *(const uint2 *)p;
+        const int bc = min(max(b, 0), nb - 1);
+        return *(const uint2 *)(hr + (int64_t)(lane >> 3) * nb * CB + (int64_t)bc * CB + (lane & 7) * 4);
     };
     auto store_block = [&](int b, uint2 v) {
-        uint16_t *p = ring + ((b & 15) * CM + (lane >> 3)) * CB + (lane & 7) * 4;
-        *(uint2 *)p = v;
+        if (b < 0 || b >= nb) v = make_uint2(0u, 0u);
+        *(uint2 *)(ring + ((b & 15) * CM + (lane >> 3)) * CRS + (lane & 7) * 4) = v;
     };
-    for (int tl = 0; tl < CG; ++tl) {
-        const int b = t0 - s_start + tl;
-        store_block(b, load_block(b));
+    {
+        float x0[3];
+        uint2 h0[CG];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) x0[j] = load_x(s_start - 2 + j);
+#pragma unroll
+        for (int tl = 0; tl < CG; ++tl) h0[tl] = load_block(t0 - s_start + tl);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) store_x(s_start - 2 + j, x0[j]);
+#pragma unroll
+        for (int tl = 0; tl < CG; ++tl) store_block(t0 - s_start + tl, h0[tl]);
+    }
+    // prefetch queue: the blocks entering the rings at step u sit in slot (u - s_start - 1) % PD
+    constexpr int PD = 4;
+    float xq[PD];
+    uint2 hq[PD];
+#pragma unroll
+    for (int j = 0; j < PD; ++j) {
+        xq[j] = load_x(s_start + 1 + j);
+        hq[j] = load_block(t0 - s_start - 1 - j);
     }
     __syncthreads();
 
@@ -136,19 +167,15 @@ __global__ __launch_bounds__(64) void conv_mfma(const float *__restrict__ x, int
 
     const int i = lane & 31;           // A row / B column within a tile
     const int kk0 = (lane >> 5) * 8;   // first K index of this lane's eight
-    const uint32_t *xr32 = (const uint32_t *)xr;
-    uint2 next = load_block(t0 - s_start - 1);   // block entering at s_start + 1
-    for (int s = s_start; s <= s_end; ++s) {
-        if (s > s_start) {
-            store_block(t0 - s, next);
-            __syncthreads();
-        }
-        if (s < s_end) next = load_block(t0 - s - 1);
-        // A fragments of T_s for K steps 0 and 1: x[32 s + i - 16 ks - kk0 - e], e = 0..7
+    const uint32_t *xr32 = (const uint32_t *)xring;
+    // one step: Y_t += T_s H_{t - s} for the 16 output blocks t0 .. t0 + 15
+    auto step = [&](int s) {
+        // A fragments of T_s for K steps 0 and 1: x[X - e], X = 32 s + i - 16 ks - kk0, e = 0..7
         bf16x8_t a[2];
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-            const int p = xhi - CB * s - i + 16 * ks + kk0;     // xr index of e = 0
+            const int X = CB * s + i - 16 * ks - kk0;
+            const int p = (-X) & (XR - 1);               // ring entry of e = 0
             const int w = p >> 1;
             const uint32_t sh = (uint32_t)(p & 1) * 16u;
             uint32_t d[5];
@@ -159,20 +186,41 @@ __global__ __launch_bounds__(64) void conv_mfma(const float *__restrict__ x, int
             for (int k = 0; k < 4; ++k) v[k] = __builtin_amdgcn_alignbit(d[k + 1], d[k], sh);
             a[ks] = __builtin_bit_cast(bf16x8_t, v);
         }
+        u32x4_t bv[2][4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             const int tl = nt * 4 + (i >> 3), m = i & 7;
             const int b = t0 + tl - s;
-            const uint16_t *bp = ring + ((b & 15) * CM + m) * CB + kk0;
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                const u32x4_t bv = *(const u32x4_t *)(bp + 16 * ks);
-                acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], __builtin_bit_cast(bf16x8_t, bv),
-                                                                   acc[nt], 0, 0, 0);
-            }
+            const uint16_t *bp = ring + ((b & 15) * CM + m) * CRS + kk0;
+            bv[0][nt] = *(const u32x4_t *)bp;
+            bv[1][nt] = *(const u32x4_t *)(bp + 16);
         }
+        // K step outermost: the four tiles' MFMAs are independent of each other
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], __builtin_bit_cast(bf16x8_t, bv[ks][nt]),
+                                                                   acc[nt], 0, 0, 0);
+    };
+    auto advance = [&](int u, int j) {
+        __syncthreads();   // the previous step's ring reads precede these writes
+        store_block(t0 - u, hq[j]);
+        store_x(u, xq[j]);
+        hq[j] = load_block(t0 - u - PD);
+        xq[j] = load_x(u + PD);
         __syncthreads();
+        step(u);
+    };
+    step(s_start);
+    int u0 = s_start + 1;
+    for (; u0 + PD - 1 <= s_end; u0 += PD) {   // whole groups: no branch inside
+#pragma unroll
+        for (int j = 0; j < PD; ++j) advance(u0 + j, j);
     }
+#pragma unroll
+    for (int j = 0; j < PD - 1; ++j)
+        if (u0 + j <= s_end) advance(u0 + j, j);
 
     // store: register q of tile nt holds row 8 (q / 4) + 4 (lane / 32) + (q % 4), column lane % 32
     double pw = 0.0;
@@ -399,12 +447,8 @@ extern "C" int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float
         hipLaunchKernelGGL(conv_pack_h, dim3(std::max(1, (nb_max * CB + 255) / 256), n_rooms, M), dim3(256), 0, q,
                            rirs, rm, M, hb);
         if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_pack_h launch");
-        // source window of the widest tile: 32 (s_end - s_start) + 63 with s range <= nb + 15 blocks, +32 slack
-        const int xcap = (CB * (std::min(nb_max, mt_tiles * CG) + CG) + 2 * CB + 32 + 63) / 64 * 64;
-        const int lds = xcap * 2 + 16 * CM * CB * 2;
-        if (lds > 160 * 1024) { ism_set_error(h, "RIR too long for the MFMA path (%d bytes of LDS)", lds); return ISM_EINVAL; }
-        hipLaunchKernelGGL(conv_mfma, dim3(mt_tiles, n_rooms), dim3(64), lds, q, src, src_len, out_len, hb, rm, out, ps,
-                           mt_tiles, xcap);
+        hipLaunchKernelGGL(conv_mfma, dim3(mt_tiles, n_rooms), dim3(64), 0, q, src, src_len, out_len, hb, rm, out, ps,
+                           mt_tiles);
         if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_mfma launch");
     } else {
         hipLaunchKernelGGL(conv_direct, dim3(dt_tiles, M, n_rooms), dim3(256), 0, q, rirs, rm, src, src_len, out_len, M,

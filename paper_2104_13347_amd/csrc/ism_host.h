@@ -60,6 +60,9 @@ struct ism_handle {
     int wg_per_cu = 0;  // 0: as many as fit
     int graphs = 1;
     int interleave = 1;
+    const void *occ_sym = nullptr;  // cached occupancy of the last segment kernel / LDS size
+    int occ_lds = -1;
+    int occ_per_cu = 1;
     std::string last_error;
     ism::Slot slots[2];
     int next_slot = 0;
