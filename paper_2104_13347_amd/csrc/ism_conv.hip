@@ -44,7 +44,8 @@ struct alignas(16) ConvRoom {
     int32_t rir_len;
     int32_t nb;        // ceil(rir_len / 32)
     float snr_db;
-    int32_t pad;
+    int32_t order;     // grid row j of the convolution kernels takes room rooms[j].order
+                       // (rooms by decreasing RIR length, so the longest start first)
 };
 
 struct ConvState {
@@ -92,7 +93,7 @@ constexpr int XR = 128;   // source ring length (samples)
 constexpr int CRS = 40;   // RIR ring row stride (u16): 80 B rows keep the eight microphones' 16-B
                           // reads of one step on eight different bank groups
 
-__global__ __launch_bounds__(64) void conv_mfma(const float *__restrict__ x, int src_len, int out_len,
+__global__ __launch_bounds__(64, 4) void conv_mfma(const float *__restrict__ x, int src_len, int out_len,
                                                 const uint16_t *__restrict__ hb,
                                                 const ConvRoom *__restrict__ rooms,
                                                 float *__restrict__ y, double *__restrict__ psum,
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(64) void conv_mfma(const float *__restrict__ x, int
     __shared__ __attribute__((aligned(16))) uint16_t xring[2 * XR];
     __shared__ __attribute__((aligned(16))) uint16_t ring[16 * CM * CRS];
     const int lane = threadIdx.x;
-    const int r = blockIdx.y, tile = blockIdx.x;
+    const int r = rooms[blockIdx.y].order, tile = blockIdx.x;
     const int t0 = tile * CG;
     const ConvRoom R = rooms[r];
     const int nb = R.nb;
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(256) void conv_direct(const float *__restrict__ rir
     __shared__ float hs[DJ];
     __shared__ float xw[DT + DJ + 4];
     const int tid = threadIdx.x;
-    const int tile = blockIdx.x, m = blockIdx.y, r = blockIdx.z;
+    const int tile = blockIdx.x, m = blockIdx.y, r = rooms[blockIdx.z].order;
     const ConvRoom R = rooms[r];
     const float *h = rirs + R.rir_off + (int64_t)m * R.rir_len;
     const float *xs = x + (int64_t)r * src_len;
@@ -392,9 +393,15 @@ extern "C" int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float
         c.nb = (rir_len[r] + CB - 1) / CB;
         c.h_off = hb_total;
         c.snr_db = snr_db ? snr_db[r] : 0.0f;
-        c.pad = 0;
+        c.order = r;
         hb_total += (int64_t)M * c.nb * CB;
         nb_max = std::max(nb_max, c.nb);
+    }
+    {
+        std::vector<int32_t> ord(n_rooms);
+        for (int r = 0; r < n_rooms; ++r) ord[r] = r;
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return rooms[a].nb > rooms[b].nb; });
+        for (int r = 0; r < n_rooms; ++r) rooms[r].order = ord[r];
     }
     if (h->device < 0) { ism_set_error(h, "no HIP device"); return ISM_EDEVICE; }
     if (!h->conv) h->conv = new (std::nothrow) ConvState();
