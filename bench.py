@@ -104,7 +104,8 @@ def bench_c3(H, torch):
     rooms = ism.rooms_array(b)
     out = torch.empty(int(b["out_size"]), dtype=torch.float32, device="cuda")
     res = {"workload": "64 rooms 20x15x8 m, per-wall beta U[0.85,0.95], 48 kHz, 72000 samples, 16 mics, 127 taps"}
-    for prec, name in [(ism.PREC_FP32, "fp32"), (ism.PREC_FP16_LUT, "fp16_lut"), (ism.PREC_FP32_SPLIT, "fp32_split")]:
+    for prec, name in [(ism.PREC_FP32, "fp32"), (ism.PREC_FP32_DIRECT, "fp32_direct"), (ism.PREC_FP16_LUT, "fp16_lut"),
+                       (ism.PREC_FP32_SPLIT, "fp32_split")]:
         ms = _time_it(torch, lambda: H.rir_batch(b, precision=prec, out=out, rooms=rooms))
         taps = H.last_counts()["taps"]
         res[name] = {"ms": ms, "taps_per_s": taps / (ms / 1e3), "rirs_per_s": 64 * 16 / (ms / 1e3), "taps": taps}
@@ -242,7 +243,7 @@ def main():
                                   "81-tap Hann-windowed sinc, time-bounded image sets",
                       "rooms": args.rooms, "rirs": n_rirs, "taps_per_step": taps,
                       "records_per_step": counts["records"], "images_tested_per_step": counts["images"],
-                      "precision": ["fp32", "fp16_lut", "fp32_split", "fp32_atomic"][args.precision],
+                      "precision": ["fp32", "fp16_lut", "fp32_split", "fp32_atomic", "fp32_direct"][args.precision],
                       "tuning": H.get_tuning()},
            "rirs_per_s_batched": rirs_batched}
 

@@ -71,23 +71,37 @@ enum ism_order_mode { ISM_ORDER_INDEX_L1 = 0, ISM_ORDER_REFLECTIONS = 1 };
  * Arithmetic.  In every mode the image positions, distances, delays and the
  * integer/fractional delay split are computed in FP64 (except the FP32-split
  * ablation).
- *   ISM_PREC_FP32        FP32 tap evaluation; each tap is quantised to a 32-bit
+ *   ISM_PREC_FP32        for fd_taps 9, 81 and 127 with segments of at most
+ *                        1024 samples (the default): moment evaluation.  For
+ *                        each tap k, h(k - f) is expanded in Chebyshev
+ *                        polynomials of 2f (10 terms; truncation below 1.1e-8 of
+ *                        max|h| = 1).  Each record adds g T_m(2f), m < 10, in
+ *                        FP64 and quantised to 32-bit fixed point, into the bin of
+ *                        its integer delay n0; the bin sums are exact 64-bit
+ *                        integers (deterministic); each output sample is then a
+ *                        2K+1-tap FP64 filter over the 10 bin sequences.  Other
+ *                        fd_taps or longer segments: as ISM_PREC_FP32_DIRECT.
+ *   ISM_PREC_FP16_LUT    the windowed sinc read from an FP16 table (64 steps per
+ *                        sample, linear interpolation); exact accumulation as in
+ *                        ISM_PREC_FP32_DIRECT.
+ *   ISM_PREC_FP32_SPLIT  ablation: distance and delay split in FP32, otherwise as
+ *                        ISM_PREC_FP32.
+ *   ISM_PREC_FP32_ATOMIC ablation: FP32 taps summed with FP32 LDS atomics (plain
+ *                        FP32 accumulation; the order of the adds at each output
+ *                        sample is still fixed).
+ *   ISM_PREC_FP32_DIRECT every tap evaluated in FP32 (the sinc by one reciprocal,
+ *                        the window by angle addition), quantised to a 32-bit
  *                        fixed-point value (step below 1e-9 of a bound on the
  *                        largest image gain of its output segment) and summed
  *                        exactly in 64-bit integers: deterministic, and the only
  *                        accumulation error is one quantisation per tap.
- *   ISM_PREC_FP16_LUT    the windowed sinc read from an FP16 table (64 steps per
- *                        sample, linear interpolation); same exact accumulation.
- *   ISM_PREC_FP32_SPLIT  ablation: distance and delay split in FP32.
- *   ISM_PREC_FP32_ATOMIC ablation: FP32 taps summed with FP32 LDS atomics (plain
- *                        FP32 accumulation; the order of the adds at each output
- *                        sample is still fixed).
  */
 enum ism_precision {
     ISM_PREC_FP32 = 0,
     ISM_PREC_FP16_LUT = 1,
     ISM_PREC_FP32_SPLIT = 2,
-    ISM_PREC_FP32_ATOMIC = 3
+    ISM_PREC_FP32_ATOMIC = 3,
+    ISM_PREC_FP32_DIRECT = 4
 };
 
 /* One room of a batch.  Microphones of room i are mics[mic_offset .. mic_offset+n_mics);

@@ -24,6 +24,7 @@ using namespace ism;
 namespace ism {
 struct KernelEntry { hipError_t (*fn)(const LaunchDev *, int, int, hipStream_t); const void *sym; };
 KernelEntry select_segment_kernel(int K, int variant);
+KernelEntry select_moment_kernel(int K);
 hipError_t launch_prologue(const LaunchDev *P, int n_rooms, hipStream_t st);
 }  // namespace ism
 
@@ -146,7 +147,7 @@ int ism_validate_common(ism_handle *h, double fs, double c, int fd_taps, int ord
         ism_set_error(h, "order_mode must be ISM_ORDER_INDEX_L1 or ISM_ORDER_REFLECTIONS");
         return ISM_EINVAL;
     }
-    if (precision < ISM_PREC_FP32 || precision > ISM_PREC_FP32_ATOMIC) {
+    if (precision < ISM_PREC_FP32 || precision > ISM_PREC_FP32_DIRECT) {
         ism_set_error(h, "unknown precision %d", precision);
         return ISM_EINVAL;
     }
@@ -319,6 +320,30 @@ static int ensure_slot(ism_handle *h, Slot &s, size_t bytes)
     return ISM_OK;
 }
 
+// Chebyshev coefficients of the moment kernel's filter: for each tap k in [-K, K],
+// h(k - f) = sum_{m < kMom} c[m][k] T_m(2f) on f in [-1/2, 1/2], h the Hann-windowed
+// sinc of half-length K.  Interpolation at 32 Chebyshev nodes in FP64 (the
+// coefficients past kMom are below 1e-9 and those past 32 below double rounding).
+static void mom_coefficients(int K, std::vector<double> &c)
+{
+    const int nk = 2 * K + 1, NN = 32;
+    c.assign((size_t)kMom * nk, 0.0);
+    std::vector<double> hv(NN), th(NN);
+    for (int j = 0; j < NN; ++j) th[j] = M_PI * (j + 0.5) / NN;
+    for (int k = -K; k <= K; ++k) {
+        for (int j = 0; j < NN; ++j) {
+            const double f = 0.5 * std::cos(th[j]);
+            const double t = k - f;  // never 0: no node at f = 0
+            hv[j] = std::sin(M_PI * t) / (M_PI * t) * 0.5 * (1.0 + std::cos(M_PI * t / (K + 1)));
+        }
+        for (int m = 0; m < kMom; ++m) {
+            double a = 0.0;
+            for (int j = 0; j < NN; ++j) a += hv[j] * std::cos(m * th[j]);
+            c[(size_t)m * nk + (k + K)] = a * (m == 0 ? 1.0 : 2.0) / NN;
+        }
+    }
+}
+
 int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs, double c, int fd_taps,
                  int order_mode, int precision, float *out, hipStream_t stream, double *t_ms)
 {
@@ -330,15 +355,32 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
     const int variant = precision == ISM_PREC_FP16_LUT      ? VAR_LUT
                         : precision == ISM_PREC_FP32_ATOMIC ? VAR_F32ATOM
                                                              : VAR_FX;
-    KernelEntry ke = select_segment_kernel(K, variant);
-    const int lds = seg_lds_bytes(plan.seg_max, K, variant);
+    KernelEntry ke{nullptr, nullptr};
+    int lds = 0, block = 64;
+    const bool moments = (precision == ISM_PREC_FP32 || precision == ISM_PREC_FP32_SPLIT) &&
+                         plan.seg_max <= kMomSegMax;
+    if (moments) ke = select_moment_kernel(K);
+    if (ke.fn) {
+        lds = mom_lds_bytes(K);
+        block = 64 * kMomWaves;
+        if (h->coef_K != K) {
+            mom_coefficients(K, h->coef);
+            h->coef_K = K;
+        }
+    } else {
+        ke = select_segment_kernel(K, variant);
+        lds = seg_lds_bytes(plan.seg_max, K, variant);
+    }
+    const bool use_mom = block != 64;
     if (lds > 160 * 1024) { ism_set_error(h, "segment needs %d bytes of LDS", lds); return ISM_ENOMEM; }
 
-    // layout: header | rooms | mics | items | counter | pow tables
+    // layout: header | rooms | mics | items | filter coefficients | counter | pow tables
+    const size_t n_coef = use_mom ? h->coef.size() : 0;
     size_t off_rooms = align_up(sizeof(LaunchDev), 256);
     size_t off_mics = align_up(off_rooms + sizeof(RoomDev) * n_rooms, 256);
     size_t off_items = align_up(off_mics + sizeof(double) * 3 * plan.n_mics_total, 256);
-    size_t off_cnt = align_up(off_items + sizeof(ItemDev) * n_items, 256);
+    size_t off_coef = align_up(off_items + sizeof(ItemDev) * n_items, 256);
+    size_t off_cnt = align_up(off_coef + sizeof(double) * n_coef, 256);
     size_t off_pow = align_up(off_cnt + 256, 256);  // counter at +0, stats at +64
     size_t total = off_pow + sizeof(double) * (size_t)plan.pow_total;
     size_t upload = off_cnt;
@@ -369,7 +411,9 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
     L.split32 = precision == ISM_PREC_FP32_SPLIT ? 1 : 0;
     L.seg_max = plan.seg_max;
     L.interleave = h->interleave;
+    L.coef = use_mom ? (const double *)(db + off_coef) : nullptr;
     std::memcpy(hb, &L, sizeof L);
+    if (n_coef) std::memcpy(hb + off_coef, h->coef.data(), sizeof(double) * n_coef);
     std::memcpy(hb + off_rooms, plan.rooms.data(), sizeof(RoomDev) * n_rooms);
     std::memcpy(hb + off_mics, mics, sizeof(double) * 3 * plan.n_mics_total);
     std::memcpy(hb + off_items, plan.items.data(), sizeof(ItemDev) * n_items);
@@ -379,7 +423,11 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
     if (h->occ_sym == ke.sym && h->occ_lds == lds) {
         per_cu = h->occ_per_cu;
     } else {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ke.sym, 64, lds);
+        if (lds > 64 * 1024) {
+            e = hipFuncSetAttribute(ke.sym, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e != hipSuccess) return ism_hip_fail(h, e, "hipFuncSetAttribute");
+        }
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ke.sym, block, lds);
         if (e != hipSuccess || per_cu < 1) per_cu = 1;
         h->occ_sym = ke.sym;
         h->occ_lds = lds;

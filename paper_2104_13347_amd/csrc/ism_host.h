@@ -71,6 +71,8 @@ struct ism_handle {
     ism::Slot *last_slot = nullptr;   // slot of the last batch launch
     void *last_stats = nullptr;       // its device work counters
     ism::ConvState *conv = nullptr;
+    int coef_K = -1;                  // Chebyshev filter coefficients of the moment kernel, for coef_K
+    std::vector<double> coef;
 };
 
 void ism_set_error(ism_handle *h, const char *fmt, ...);

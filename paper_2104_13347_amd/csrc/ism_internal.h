@@ -51,6 +51,7 @@ struct alignas(16) LaunchDev {
     int32_t split32;      // 1: distance and delay split in FP32 (ablation)
     int32_t seg_max;      // largest s1 - s0 of any item (sizes LDS)
     int32_t interleave;   // enumeration order inside a column chunk (1: strided over columns)
+    const double *coef;   // moment kernel: Chebyshev filter coefficients [kMom][2K+1]
 };
 
 constexpr int kSegMaxLimit = 2048;  // largest supported segment (per-lane sums in registers)
@@ -58,6 +59,27 @@ constexpr int kKMax = 127;          // largest half-length (255 taps)
 constexpr int kLutQ = 64;           // FP16 table steps per sample
 constexpr int kBufCap = 256;        // record ring (power of two)
 constexpr int kCols = 64;           // columns per enumeration chunk (one per lane)
+
+// Moment kernel: Chebyshev moments per delay bin, waves per workgroup, largest segment.
+constexpr int kMom = 10;
+constexpr int kMomWaves = 8;
+constexpr int kMomSegMax = 1024;
+
+// Padded length of one moment channel: bins [0, kMomSegMax + 2K) plus one pad
+// word per 16 (the filter's window reads of consecutive lanes are 17 words apart).
+constexpr int mom_ustride(int K)
+{
+    const int n = kMomSegMax + 2 * K;
+    return n + (n >> 4) + 2;
+}
+
+inline int mom_lds_bytes(int K)
+{
+    const int cols = 64 * kMomWaves;
+    int bytes = kMom * mom_ustride(K) * 8;
+    bytes += cols * 8 * 2 + cols * 4 + cols * 4 * 3 * 4 + (cols + 4) * 4 + kMomWaves * 4 + 16;
+    return bytes;
+}
 
 // LDS bytes of the segment kernel for a given segment capacity, K and variant.
 inline int seg_lds_bytes(int seg_max, int K, int variant)

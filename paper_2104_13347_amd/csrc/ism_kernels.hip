@@ -303,6 +303,199 @@ extern __shared__ __attribute__((aligned(16))) char ism_lds[];
 
 DEV long iabs(long a) { return a < 0 ? -a : a; }
 
+// ---------------------------------------------------------------- item geometry
+// Everything about one work item (room, microphone, output segment [s0, s1)) that the
+// enumeration needs, derived once per item.
+struct ItemGeom {
+    double Lx, Ly, Lz, sx, sy, sz, rx, ry, rz;
+    double dlo2, dhi2;            // squared distance shell of the item's records
+    const double *px0, *pz0, *pzL;
+    long alo, blo;                // first (x, y) image column indices
+    int pow_stride, pmax;
+    int rir_len, N, s0, s1, Sn;
+    int nlo, nhi;                 // record delays n0 in [nlo, nhi] can reach the segment
+    int rel;                      // n0 - rel indexes the item's delay bins / accumulator
+    int nb, ncols;                // columns: (a, b) = (alo + c / nb, blo + c % nb)
+    int escale;                   // fixed-point scale 2^escale
+};
+
+DEV ItemGeom item_geom(const LaunchDev *P, const ItemDev &it, int K)
+{
+    ItemGeom G;
+    const RoomDev &R = P->rooms[it.room];
+    const double fs = P->fs, cs = P->c;
+    G.Lx = R.L[0]; G.Ly = R.L[1]; G.Lz = R.L[2];
+    G.sx = R.src[0]; G.sy = R.src[1]; G.sz = R.src[2];
+    G.rx = P->mics[3 * it.mic + 0]; G.ry = P->mics[3 * it.mic + 1]; G.rz = P->mics[3 * it.mic + 2];
+    G.rir_len = R.rir_len;
+    G.N = R.max_order;
+    G.s0 = it.s0; G.s1 = it.s1; G.Sn = it.s1 - it.s0;
+    G.nlo = max(G.s0 - K, 0);
+    G.nhi = min(G.s1 - 1 + K, G.rir_len - 1 + K);
+    G.rel = G.s0 - K;
+    G.px0 = P->pow_tab + R.pow_offset;
+    G.pz0 = G.px0 + 4 * R.pow_stride;
+    G.pzL = G.pz0 + R.pow_stride;
+    G.pow_stride = R.pow_stride;
+    G.pmax = R.pow_stride - 1;
+    // distance shell of the records this segment needs (widened: every test below is exact)
+    const double dlo = fmax(0.0, ((double)G.nlo - 0.5) * cs / fs * (1.0 - 1e-12) - 1e-12);
+    const double dhi = ((double)G.nhi + 0.5) * cs / fs * (1.0 + 1e-12) + 1e-12;
+    G.dlo2 = dlo * dlo;
+    G.dhi2 = dhi * dhi;
+    // Fixed-point scale 2^e: no image is closer than the direct path and every
+    // beta <= 1, so g <= 1/(4 pi max(dlo, |s - r|)) =: gb for every record of the
+    // item, and |tap| <= g (|h| <= 1); e is the largest exponent with 2^e gb < 2^30.
+    {
+        const double ddx = G.sx - G.rx, ddy = G.sy - G.ry, ddz = G.sz - G.rz;
+        const double ddir = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+        const double gb = 1.0 / (4.0 * kPi * fmax(dlo, ddir));
+        int E;
+        (void)frexp(gb, &E);  // gb = m 2^E, m in [1/2, 1)
+        G.escale = 30 - E;
+    }
+    long alo = (long)floor((G.rx - dhi) / G.Lx) - 1, ahi = (long)ceil((G.rx + dhi) / G.Lx) + 1;
+    long blo = (long)floor((G.ry - dhi) / G.Ly) - 1, bhi = (long)ceil((G.ry + dhi) / G.Ly) + 1;
+    if (G.N >= 0) {
+        const long lim = P->order_mode == 0 ? 2L * G.N + 2 : (long)G.N + 1;
+        alo = max(alo, -lim); ahi = min(ahi, lim);
+        blo = max(blo, -lim); bhi = min(bhi, lim);
+    }
+    G.alo = alo;
+    G.blo = blo;
+    G.nb = (int)(bhi - blo + 1);
+    G.ncols = (int)(ahi - alo + 1) * G.nb;
+    return G;
+}
+
+// One (x, y) image column: the z-index intervals whose images lie in the item's
+// distance shell (two parities w, each an interval with the inner hole cut out, so
+// at most four), the squared horizontal distance, the x/y wall-power product and the
+// x/y part of the reflection order.
+struct Column {
+    int q0[4], len[4], wv[4];
+    double rho2, bxy;
+    int ord;
+};
+
+DEV Column column_setup(const ItemGeom &G, int ci, int order_mode)
+{
+    Column C;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { C.q0[i] = 0; C.len[i] = 0; C.wv[i] = 0; }
+    C.rho2 = 0.0;
+    C.bxy = 0.0;
+    C.ord = 0;
+    if (ci >= G.ncols) return C;
+    const int N = G.N;
+    const int ca = ci / G.nb;
+    const long a = G.alo + ca, b = G.blo + (ci - ca * G.nb);
+    const int u = (int)(a & 1), v = (int)(b & 1);
+    const long n = (a + u) >> 1, l = (b + v) >> 1;
+    const double X = (u ? -G.sx : G.sx) + (2.0 * (double)n) * G.Lx;
+    const double Y = (v ? -G.sy : G.sy) + (2.0 * (double)l) * G.Ly;
+    const double dx = X - G.rx, dy = Y - G.ry;
+    const double rho2 = dx * dx + dy * dy;
+    C.rho2 = rho2;
+    long qlim_lo = -(1L << 40), qlim_hi = (1L << 40);
+    bool ok = rho2 < G.dhi2;
+    int ordxy = 0;
+    if (N >= 0) {
+        const long oxy = order_mode == 0 ? iabs(n) + iabs(l) : iabs(2 * n - u) + iabs(2 * l - v);
+        ordxy = (int)oxy;
+        if (oxy > N) ok = false;
+    }
+    C.ord = ordxy;
+    if (!ok) return C;
+    const long pmax = G.pmax;
+    const int ex0 = (int)min(iabs(n - u), pmax), exL = (int)min(iabs(n), pmax);
+    const int ey0 = (int)min(iabs(l - v), pmax), eyL = (int)min(iabs(l), pmax);
+    const double *px0 = G.px0;
+    C.bxy = ((px0[ex0] * px0[G.pow_stride + exL]) * px0[2 * G.pow_stride + ey0]) * px0[3 * G.pow_stride + eyL];
+    const double zb = sqrt(G.dhi2 - rho2);
+    const double za = G.dlo2 > rho2 ? sqrt(G.dlo2 - rho2) : 0.0;
+    const double inv2L = 0.5 / G.Lz;
+    int ni = 0;
+    // interval slot ni (unrolled selects keep the slots in registers)
+    auto put = [&](long qq, long ll, int ww) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (i == ni) { C.q0[i] = (int)qq; C.len[i] = (int)ll; C.wv[i] = ww; }
+        ++ni;
+    };
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        // dz = (+-sz + 2 q Lz) - rz
+        const double off = G.rz - (w ? -G.sz : G.sz);
+        long qlo = (long)ceil((off - zb) * inv2L - 1e-9);
+        long qhi = (long)floor((off + zb) * inv2L + 1e-9);
+        if (N >= 0) {
+            const long rem = N - ordxy;
+            if (order_mode == 0) { qlim_lo = -rem; qlim_hi = rem; }
+            else { qlim_lo = (w - rem + 1) >> 1; qlim_hi = (w + rem) >> 1; }
+            // (w - rem + 1) >> 1 = ceil((w - rem) / 2)
+            qlo = max(qlo, qlim_lo); qhi = min(qhi, qlim_hi);
+        }
+        if (qlo > qhi) continue;
+        long hlo = 1, hhi = 0;  // empty hole
+        if (za > 0.0) {
+            hlo = (long)ceil((off - za) * inv2L + 1e-9);
+            hhi = (long)floor((off + za) * inv2L - 1e-9);
+        }
+        if (hlo <= hhi && hhi >= qlo && hlo <= qhi) {
+            if (hlo > qlo) put(qlo, hlo - qlo, w);
+            if (hhi < qhi) put(hhi + 1, qhi - hhi, w);
+        } else {
+            put(qlo, qhi - qlo + 1, w);
+        }
+    }
+    return C;
+}
+
+// One image of a column: distance (FP64, (dx^2 + dy^2) + dz^2), delay and its
+// integer / fractional split, wall-power product.  Returns whether the record
+// belongs to the item (delay in [nlo, nhi], order within the limit).
+DEV bool image_eval(const ItemGeom &G, double rho2, double bxy, int cord, long q, int w, int order_mode,
+                    double fs, double cs, double fsc, int split32, int &n0, double &fr, double &d, double &B)
+{
+    bool ordok = true;
+    if (G.N >= 0) {
+        const long oz = order_mode == 0 ? iabs(q) : iabs(2 * q - w);
+        ordok = (long)cord + oz <= G.N;
+    }
+    const double Z = (w ? -G.sz : G.sz) + (2.0 * (double)q) * G.Lz;
+    const double dz = Z - G.rz;
+    const double d2 = rho2 + dz * dz;
+    d = sqrt(d2);
+    // tau = (d fs) / c as in the definition; d * (fs/c) differs by at most an
+    // ulp or two, which can change floor(tau + 1/2) only right at a rounding
+    // boundary: there the exact quotient is taken
+    double tau = d * fsc;
+    {
+        const double h = tau + 0.5, fl = floor(h);
+        if (h - fl < 1e-12 * h || (fl + 1.0) - h < 1e-12 * h) tau = d * fs / cs;
+    }
+    const double n0d = floor(tau + 0.5);
+    n0 = (int)n0d;
+    fr = tau - n0d;
+    if (split32) {
+        // ablation: the same split in FP32 arithmetic
+        const float d2f = (float)rho2 + (float)dz * (float)dz;
+        const float tauf = sqrtf(d2f) * (float)fs / (float)cs;
+        const float n0f = floorf(tauf + 0.5f);
+        n0 = (int)n0f;
+        fr = (double)(tauf - n0f);
+    }
+    const bool valid = ordok && n0 >= G.nlo && n0 <= G.nhi;
+    B = 0.0;
+    if (valid) {
+        const long pmax = G.pmax;
+        const int ez0 = (int)min(iabs(q - w), pmax), ezL = (int)min(iabs(q), pmax);
+        B = (bxy * G.pz0[ez0]) * G.pzL[ezL];
+    }
+    return valid;
+}
+
 template <int KT, int VAR>
 __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__ P)
 {
@@ -344,46 +537,12 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
         if (item >= P->n_items) break;
 
         const ItemDev it = P->items[item];
-        const RoomDev &R = P->rooms[it.room];
-        const double Lx = R.L[0], Ly = R.L[1], Lz = R.L[2];
-        const double sx = R.src[0], sy = R.src[1], sz = R.src[2];
-        const double rx = P->mics[3 * it.mic + 0], ry = P->mics[3 * it.mic + 1],
-                     rz = P->mics[3 * it.mic + 2];
-        const int rir_len = R.rir_len, N = R.max_order;
-        const int s0 = it.s0, s1 = it.s1, Sn = s1 - s0;
-        const int nlo = max(s0 - K, 0), nhi = min(s1 - 1 + K, rir_len - 1 + K);
-        const int rel = s0 - K;  // n0rel = n0 - rel in [0, Sn + 2K)
-        const double *pz0 = P->pow_tab + R.pow_offset + 4 * R.pow_stride;
-        const double *pzL = pz0 + R.pow_stride;
-        const double *px0 = P->pow_tab + R.pow_offset;
-        const int pmax = R.pow_stride - 1;
-
-        // distance shell of the records this segment needs (widened: every test below is exact)
-        const double dlo = fmax(0.0, ((double)nlo - 0.5) * cs / fs * (1.0 - 1e-12) - 1e-12);
-        const double dhi = ((double)nhi + 0.5) * cs / fs * (1.0 + 1e-12) + 1e-12;
-        const double dlo2 = dlo * dlo, dhi2 = dhi * dhi;
-        // Fixed-point scale 2^e: no image is closer than the direct path and every
-        // beta <= 1, so g <= 1/(4 pi max(dlo, |s - r|)) =: gb for every record of the
-        // item, and |tap| <= g (|h| <= 1); e is the largest exponent with 2^e gb < 2^30.
-        int escale = 0;
-        {
-            const double ddx = sx - rx, ddy = sy - ry, ddz = sz - rz;
-            const double ddir = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-            const double gb = 1.0 / (4.0 * kPi * fmax(dlo, ddir));
-            int E;
-            (void)frexp(gb, &E);  // gb = m 2^E, m in [1/2, 1)
-            escale = 30 - E;
-        }
+        const ItemGeom G = item_geom(P, it, K);
+        const int s0 = G.s0, s1 = G.s1, Sn = G.Sn;
+        const int rel = G.rel;  // n0rel = n0 - rel in [0, Sn + 2K)
+        const int escale = G.escale;
         const float fscale = VAR == VAR_F32ATOM ? 1.0f : ldexpf(1.0f, escale);
-        long alo = (long)floor((rx - dhi) / Lx) - 1, ahi = (long)ceil((rx + dhi) / Lx) + 1;
-        long blo = (long)floor((ry - dhi) / Ly) - 1, bhi = (long)ceil((ry + dhi) / Ly) + 1;
-        if (N >= 0) {
-            const long lim = order_mode == 0 ? 2L * N + 2 : (long)N + 1;
-            alo = max(alo, -lim); ahi = min(ahi, lim);
-            blo = max(blo, -lim); bhi = min(bhi, lim);
-        }
-        const int nb = (int)(bhi - blo + 1);
-        const int ncols = (int)(ahi - alo + 1) * nb;
+        const int ncols = G.ncols;
 
         int head = 0, cnt = 0;
         uint32_t n_taps = 0, n_rec = 0, n_img = 0;  // per lane
@@ -437,79 +596,24 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
 
         for (int c0 = 0; c0 < ncols; c0 += kCols) {
             // ---- column chunk: one (a, b) column per lane
-            const int ci = c0 + lane;
-            int q0[4] = {0, 0, 0, 0}, len[4] = {0, 0, 0, 0}, wv[4] = {0, 0, 0, 0};
-            double rho2 = 0.0, bxy = 0.0;
-            int ordxy = 0;
-            if (ci < ncols) {
-                const int ca = ci / nb;
-                const long a = alo + ca, b = blo + (ci - ca * nb);
-                const int u = (int)(a & 1), v = (int)(b & 1);
-                const long n = (a + u) >> 1, l = (b + v) >> 1;
-                const double X = (u ? -sx : sx) + (2.0 * (double)n) * Lx;
-                const double Y = (v ? -sy : sy) + (2.0 * (double)l) * Ly;
-                const double dx = X - rx, dy = Y - ry;
-                rho2 = dx * dx + dy * dy;
-                long qlim_lo = -(1L << 40), qlim_hi = (1L << 40);
-                bool ok = rho2 < dhi2;
-                if (N >= 0) {
-                    const long oxy = order_mode == 0 ? iabs(n) + iabs(l) : iabs(2 * n - u) + iabs(2 * l - v);
-                    ordxy = (int)oxy;
-                    if (oxy > N) ok = false;
-                }
-                if (ok) {
-                    const int ex0 = (int)min(iabs(n - u), (long)pmax), exL = (int)min(iabs(n), (long)pmax);
-                    const int ey0 = (int)min(iabs(l - v), (long)pmax), eyL = (int)min(iabs(l), (long)pmax);
-                    bxy = ((px0[ex0] * px0[R.pow_stride + exL]) * px0[2 * R.pow_stride + ey0]) *
-                          px0[3 * R.pow_stride + eyL];
-                    const double zb = sqrt(dhi2 - rho2);
-                    const double za = dlo2 > rho2 ? sqrt(dlo2 - rho2) : 0.0;
-                    const double inv2L = 0.5 / Lz;
-                    int ni = 0;
-                    for (int w = 0; w < 2; ++w) {
-                        // dz = (+-sz + 2 q Lz) - rz
-                        const double off = rz - (w ? -sz : sz);
-                        long qlo = (long)ceil((off - zb) * inv2L - 1e-9);
-                        long qhi = (long)floor((off + zb) * inv2L + 1e-9);
-                        if (N >= 0) {
-                            const long rem = N - ordxy;
-                            if (order_mode == 0) { qlim_lo = -rem; qlim_hi = rem; }
-                            else { qlim_lo = (w - rem + 1) >> 1; qlim_hi = (w + rem) >> 1; }
-                            // (w - rem + 1) >> 1 = ceil((w - rem) / 2)
-                            qlo = max(qlo, qlim_lo); qhi = min(qhi, qlim_hi);
-                        }
-                        if (qlo > qhi) continue;
-                        long hlo = 1, hhi = 0;  // empty hole
-                        if (za > 0.0) {
-                            hlo = (long)ceil((off - za) * inv2L + 1e-9);
-                            hhi = (long)floor((off + za) * inv2L - 1e-9);
-                        }
-                        if (hlo <= hhi && hhi >= qlo && hlo <= qhi) {
-                            if (hlo > qlo) { q0[ni] = (int)qlo; len[ni] = (int)(hlo - qlo); wv[ni] = w; ++ni; }
-                            if (hhi < qhi) { q0[ni] = (int)(hhi + 1); len[ni] = (int)(qhi - hhi); wv[ni] = w; ++ni; }
-                        } else {
-                            q0[ni] = (int)qlo; len[ni] = (int)(qhi - qlo + 1); wv[ni] = w; ++ni;
-                        }
-                    }
-                }
-            }
+            const Column C = column_setup(G, c0 + lane, order_mode);
             ++n_chunks;
-            const int ctot = len[0] + len[1] + len[2] + len[3];
+            const int ctot = C.len[0] + C.len[1] + C.len[2] + C.len[3];
             int T;
             const int off = wave_excl_scan(ctot, T);
             __syncthreads();
             S.coff[lane] = off;
             if (lane == 63) S.coff[64] = T;
-            S.crho2[lane] = rho2;
-            S.cbxy[lane] = bxy;
-            S.cord[lane] = ordxy;
+            S.crho2[lane] = C.rho2;
+            S.cbxy[lane] = C.bxy;
+            S.cord[lane] = C.ord;
             int cum = 0;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                cum += len[i];
-                S.iq0[lane * 4 + i] = q0[i];
+                cum += C.len[i];
+                S.iq0[lane * 4 + i] = C.q0[i];
                 S.icum[lane * 4 + i] = cum;
-                S.iw[lane * 4 + i] = wv[i];
+                S.iw[lane * 4 + i] = C.wv[i];
             }
             __syncthreads();
 
@@ -541,38 +645,11 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
                     const int before = iv == 0 ? 0 : S.icum[c * 4 + iv - 1];
                     const long q = (long)S.iq0[c * 4 + iv] + (loc - before);
                     const int w = S.iw[c * 4 + iv];
-                    bool ordok = true;
-                    if (N >= 0) {
-                        const long oz = order_mode == 0 ? iabs(q) : iabs(2 * q - w);
-                        ordok = (long)S.cord[c] + oz <= N;
-                    }
-                    const double Z = (w ? -sz : sz) + (2.0 * (double)q) * Lz;
-                    const double dz = Z - rz;
-                    const double d2 = S.crho2[c] + dz * dz;
-                    const double d = sqrt(d2);
-                    // tau = (d fs) / c as in the definition; d * (fs/c) differs by at most an
-                    // ulp or two, which can change floor(tau + 1/2) only right at a rounding
-                    // boundary: there the exact quotient is taken
-                    double tau = d * fsc;
-                    {
-                        const double h = tau + 0.5, fl = floor(h);
-                        if (h - fl < 1e-12 * h || (fl + 1.0) - h < 1e-12 * h) tau = d * fs / cs;
-                    }
-                    const double n0d = floor(tau + 0.5);
-                    int n0 = (int)n0d;
-                    double fr = tau - n0d;
-                    if (split32) {
-                        // ablation: the same split in FP32 arithmetic
-                        const float d2f = (float)S.crho2[c] + (float)dz * (float)dz;
-                        const float tauf = sqrtf(d2f) * (float)fs / (float)cs;
-                        const float n0f = floorf(tauf + 0.5f);
-                        n0 = (int)n0f;
-                        fr = (double)(tauf - n0f);
-                    }
-                    valid = ordok && n0 >= nlo && n0 <= nhi;
+                    int n0;
+                    double fr, d, B;
+                    valid = image_eval(G, S.crho2[c], S.cbxy[c], S.cord[c], q, w, order_mode, fs, cs, fsc, split32,
+                                       n0, fr, d, B);
                     if (valid) {
-                        const int ez0 = (int)min(iabs(q - w), (long)pmax), ezL = (int)min(iabs(q), (long)pmax);
-                        const double B = (S.cbxy[c] * pz0[ez0]) * pzL[ezL];
                         // g = B / (4 pi d) to FP32 accuracy
                         rg = (float)B * (0.0795774715459477f * __builtin_amdgcn_rcpf((float)d));
                         rf = (float)fr;
@@ -593,7 +670,8 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
         __syncthreads();
 
         // ---- store the segment (coalesced), then clear the accumulator
-        float *o = P->out + R.out_offset + (long)(it.mic - R.mic_offset) * rir_len + s0;
+        const RoomDev &R = P->rooms[it.room];
+        float *o = P->out + R.out_offset + (long)(it.mic - R.mic_offset) * G.rir_len + s0;
         if (VAR == VAR_F32ATOM) {
             for (int i = lane; i < Sn; i += 64) o[i] = S.acc32[2 * K + i];
         } else {
@@ -620,6 +698,251 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
             atomicAdd(P->stats + 6, (unsigned long long)n_defer);
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- moment kernel
+// Same sum, reorganised around delay bins.  For fixed k, h(k - f) is an entire
+// function of the fractional delay f in [-1/2, 1/2], so its Chebyshev series in
+// x = 2f converges fast: with kMom terms, h(k - f) = sum_m c[m][k] T_m(2f) up to
+// 4.4e-9 (K = 40; 4.3e-9 for K = 63, 1.0e-8 for K = 4).  A record (n0, f, g) then
+// contributes sum_m c[m][k] (g T_m(2f)) to sample n0 + k, and
+//     out[n] = sum_m sum_k c[m][k] U_m[n - k],   U_m[b] = sum over records with
+//                                                n0 = b of g T_m(2 f),
+// so each record only adds kMom moments into the bins of its n0 (a counting sort
+// of the records by delay, with the sum per bin taken at once), and the 2K+1 taps
+// per sample become a dense 2K+1-tap filter over kMom moment sequences.
+//  * Moments are FP64 (recurrence T_{m+1} = 2x T_m - T_{m-1}), converted to 32-bit
+//    fixed point with the item's scale and added with ds_add_u64: the bin sums are
+//    exact integers, independent of the order of the adds.
+//  * One workgroup of kMomWaves waves owns one item.  Columns are set up 64 per
+//    wave (kMomWaves chunks at a time); every thread then takes a contiguous slice
+//    of the flattened images of those chunks, so all waves share the work of small
+//    and large items alike.
+//  * The filter: wave w takes the moment channels m = w, w + kMomWaves, ...; a lane
+//    computes 16 consecutive outputs from a 16-value window that slides along the
+//    bins (each bin value is read once per lane and used by up to 16 FMAs, FP64).
+//    Bins are stored with one pad word per 16 so that the lanes' window reads, 17
+//    words apart, hit distinct banks.  The waves' partial outputs are summed in a
+//    fixed order and stored once per sample.
+constexpr int kMomThreads = 64 * kMomWaves;
+constexpr int kMomCols = 64 * kMomWaves;  // columns per enumeration batch
+
+DEV int mpad(int i) { return i + (i >> 4); }
+
+struct MomLds {
+    long long *U;        // kMom x ustride bins (int64, then FP64 in place, then partial outputs)
+    double *crho2, *cbxy;  // [kMomCols]
+    int32_t *cord;       // [kMomCols]
+    int32_t *iq0, *icum, *iw;  // [kMomCols * 4]
+    int32_t *gcoff;      // [kMomCols + 1] exclusive prefix of the images of the batch's columns
+    int32_t *wtot;       // [kMomWaves] images of each wave's chunk
+    int32_t *item;       // [1]
+};
+
+DEV MomLds mom_carve(char *base, int K)
+{
+    MomLds s;
+    char *p = base;
+    s.U = (long long *)p; p += (size_t)kMom * mom_ustride(K) * 8;
+    s.crho2 = (double *)p; p += kMomCols * 8;
+    s.cbxy = (double *)p; p += kMomCols * 8;
+    s.cord = (int32_t *)p; p += kMomCols * 4;
+    s.iq0 = (int32_t *)p; p += kMomCols * 4 * 4;
+    s.icum = (int32_t *)p; p += kMomCols * 4 * 4;
+    s.iw = (int32_t *)p; p += kMomCols * 4 * 4;
+    s.gcoff = (int32_t *)p; p += (kMomCols + 4) * 4;
+    s.wtot = (int32_t *)p; p += kMomWaves * 4;
+    s.item = (int32_t *)p;
+    return s;
+}
+
+DEV void lds_add_i64(long long *p, double v)
+{
+    // |v| < 2^30: truncation toward zero, sign-extended
+    const long long q = (long long)(int)v;
+    __hip_atomic_fetch_add((unsigned long long *)p, (unsigned long long)q, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// acc[r] += sum_k c[k] U[16 lane + r + K - k], r = 0..15; Ub points at the padded
+// bin array, cm at the 2K+1 coefficients of one channel (k = -K..K).
+template <int K>
+DEV void mom_filter(const double *Ub, const double *__restrict__ cm, int lane, double (&acc)[16])
+{
+    const double *b = Ub + 17 * lane;  // mpad(16 lane + j) = 17 lane + j + (j >> 4)
+    // the coefficients are wave-uniform: read them through the scalar cache
+    typedef const __attribute__((address_space(4))) double cdouble;
+    const cdouble *cs = (const cdouble *)cm;
+    double win[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) win[r] = b[r];
+    // step kk uses k = K - kk, i.e. bins j = r + kk; the window holds j = kk .. kk + 15
+    // in slot j % 16
+#pragma unroll
+    for (int kk = 0; kk <= 2 * K; ++kk) {
+        const double c = cs[2 * K - kk];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = fma(c, win[(r + kk) & 15], acc[r]);
+        if (kk < 2 * K) {
+            const int j = kk + 16;
+            win[kk & 15] = b[j + (j >> 4)];
+        }
+    }
+}
+
+template <int KT>
+__global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__restrict__ P)
+{
+    constexpr int K = KT;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = uniform(tid >> 6);
+    const int ustride = mom_ustride(K);
+    MomLds S = mom_carve(ism_lds, K);
+    const double fs = P->fs, cs = P->c;
+    const double fsc = fs / cs;
+    const int order_mode = P->order_mode;
+    const int split32 = P->split32;
+    uint64_t n_taps = 0;
+    uint32_t n_rec = 0, n_img = 0;
+    const int nU = kMom * ustride;
+
+    for (;;) {
+        if (tid == 0) S.item[0] = (int)atomicAdd(P->counter, 1u);
+        for (int i = tid; i < nU; i += kMomThreads) S.U[i] = 0;
+        __syncthreads();
+        const int item = S.item[0];
+        if (item >= P->n_items) break;
+        const ItemDev it = P->items[item];
+        const ItemGeom G = item_geom(P, it, K);
+        const double gscale = ldexp(1.0, G.escale);
+
+        // ---- records: moments into the delay bins
+        for (int cb = 0; cb < G.ncols; cb += kMomCols) {
+            const int gc = wave * 64 + lane;
+            const Column C = column_setup(G, cb + gc, order_mode);
+            const int ctot = C.len[0] + C.len[1] + C.len[2] + C.len[3];
+            int T;
+            const int off = wave_excl_scan(ctot, T);
+            S.crho2[gc] = C.rho2;
+            S.cbxy[gc] = C.bxy;
+            S.cord[gc] = C.ord;
+            int cum = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                cum += C.len[i];
+                S.iq0[gc * 4 + i] = C.q0[i];
+                S.icum[gc * 4 + i] = cum;
+                S.iw[gc * 4 + i] = C.wv[i];
+            }
+            if (lane == 0) S.wtot[wave] = T;
+            __syncthreads();
+            int base = 0, Tall = 0;
+#pragma unroll
+            for (int w = 0; w < kMomWaves; ++w) {
+                const int t = S.wtot[w];
+                base += w < wave ? t : 0;
+                Tall += t;
+            }
+            S.gcoff[gc] = base + off;
+            if (tid == 0) S.gcoff[kMomCols] = Tall;
+            __syncthreads();
+
+            // thread t takes the images [t n, (t + 1) n) of the batch: consecutive
+            // lanes sit in different columns, so their delays rarely coincide
+            const int n = (Tall + kMomThreads - 1) / kMomThreads;
+            int x = tid * n;
+            const int xe = min(x + n, Tall);
+            int c = 0;
+            if (x < xe) {
+#pragma unroll
+                for (int st = kMomCols / 2; st >= 1; st >>= 1)
+                    if (S.gcoff[c + st] <= x) c += st;
+            }
+            for (; x < xe; ++x) {
+                while (S.gcoff[c + 1] <= x) ++c;
+                const int loc = x - S.gcoff[c];
+                const int e0 = S.icum[c * 4 + 0], e1 = S.icum[c * 4 + 1], e2 = S.icum[c * 4 + 2];
+                const int iv = (loc >= e0) + (loc >= e1) + (loc >= e2);
+                const int before = iv == 0 ? 0 : S.icum[c * 4 + iv - 1];
+                const long q = (long)S.iq0[c * 4 + iv] + (loc - before);
+                const int w = S.iw[c * 4 + iv];
+                ++n_img;
+                int n0;
+                double fr, d, B;
+                if (!image_eval(G, S.crho2[c], S.cbxy[c], S.cord[c], q, w, order_mode, fs, cs, fsc, split32, n0,
+                                fr, d, B))
+                    continue;
+                ++n_rec;
+                const int lo = max(n0 - K, G.s0), hi = min(n0 + K, G.s1 - 1);
+                n_taps += hi >= lo ? (uint64_t)(hi - lo + 1) : 0ull;
+                // g 2^e = B / (4 pi d) 2^e in FP64 (reciprocal with one Newton step)
+                double rd = __builtin_amdgcn_rcp(d);
+                rd = fma(fma(-d, rd, 1.0), rd, rd);
+                const double gs = B * (0.07957747154594767 * rd) * gscale;
+                const double xx = 2.0 * fr, x2 = 2.0 * xx;
+                long long *u = S.U + mpad(n0 - G.rel);
+                double tp = 1.0, tc = xx;
+                lds_add_i64(u, gs);
+                lds_add_i64(u + ustride, gs * xx);
+#pragma unroll
+                for (int m = 2; m < kMom; ++m) {
+                    const double tn = fma(x2, tc, -tp);
+                    lds_add_i64(u + m * ustride, gs * tn);
+                    tp = tc;
+                    tc = tn;
+                }
+            }
+            __syncthreads();  // the batch's column tables are rewritten next
+        }
+
+        // ---- bins to FP64 (exact: |sum| < 2^53)
+        {
+            double *Ud = (double *)S.U;
+            for (int i = tid; i < nU; i += kMomThreads) Ud[i] = (double)S.U[i];
+        }
+        __syncthreads();
+
+        // ---- the filter over the moment channels
+        double acc[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+        for (int m = wave; m < kMom; m += kMomWaves)
+            mom_filter<K>((const double *)S.U + m * ustride, P->coef + m * (2 * K + 1), lane, acc);
+        __syncthreads();
+        {
+            double *part = (double *)S.U + wave * mpad(kMomSegMax);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) part[17 * lane + r] = acc[r];  // mpad(16 lane + r)
+        }
+        __syncthreads();
+        {
+            const RoomDev &R = P->rooms[it.room];
+            float *o = P->out + R.out_offset + (long)(it.mic - R.mic_offset) * G.rir_len + G.s0;
+            const double inv = ldexp(1.0, -G.escale);
+            const double *part = (const double *)S.U;
+            for (int i = tid; i < G.Sn; i += kMomThreads) {
+                double v = 0.0;
+#pragma unroll
+                for (int w = 0; w < kMomWaves; ++w) v += part[w * mpad(kMomSegMax) + mpad(i)];
+                o[i] = (float)(v * inv);
+            }
+        }
+        __syncthreads();
+    }
+
+    // work counters (one atomic per wave and counter)
+    unsigned long long t = n_taps, r = n_rec, im = n_img;
+#pragma unroll
+    for (int dd = 32; dd >= 1; dd >>= 1) {
+        t += __shfl_xor(t, dd, 64);
+        r += __shfl_xor(r, dd, 64);
+        im += __shfl_xor(im, dd, 64);
+    }
+    if (lane == 0) {
+        atomicAdd(P->stats + 0, t);
+        atomicAdd(P->stats + 1, r);
+        atomicAdd(P->stats + 2, im);
     }
 }
 
@@ -654,6 +977,25 @@ KernelEntry select_segment_kernel(int K, int variant)
     if (variant == VAR_LUT) return {launch_t<0, VAR_LUT>, sym_t<0, VAR_LUT>()};
     if (variant == VAR_F32ATOM) return {launch_t<0, VAR_F32ATOM>, sym_t<0, VAR_F32ATOM>()};
     return {launch_t<0, VAR_FX>, sym_t<0, VAR_FX>()};
+}
+
+template <int KT>
+static hipError_t launch_m(const LaunchDev *P, int grid, int lds, hipStream_t st)
+{
+    hipLaunchKernelGGL((ism_moments<KT>), dim3(grid), dim3(kMomThreads), lds, st, P);
+    return hipGetLastError();
+}
+
+template <int KT>
+static const void *sym_m() { return reinterpret_cast<const void *>(&ism_moments<KT>); }
+
+// Moment kernel for the compiled half-lengths; {nullptr, nullptr} otherwise.
+KernelEntry select_moment_kernel(int K)
+{
+    if (K == 4) return {launch_m<4>, sym_m<4>()};
+    if (K == 40) return {launch_m<40>, sym_m<40>()};
+    if (K == 63) return {launch_m<63>, sym_m<63>()};
+    return {nullptr, nullptr};
 }
 
 hipError_t launch_prologue(const LaunchDev *P, int n_rooms, hipStream_t st)

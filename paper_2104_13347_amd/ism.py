@@ -17,7 +17,7 @@ LIB_PATH = os.environ.get("ISM_LIB") or os.path.join(_HERE, "libism.so")
 
 ISM_OK, ISM_EINVAL, ISM_EDOMAIN, ISM_ENOMEM, ISM_EDEVICE, ISM_EBUSY = 0, -1, -2, -3, -4, -5
 ORDER_INDEX_L1, ORDER_REFLECTIONS = 0, 1
-PREC_FP32, PREC_FP16_LUT, PREC_FP32_SPLIT, PREC_FP32_ATOMIC = 0, 1, 2, 3
+PREC_FP32, PREC_FP16_LUT, PREC_FP32_SPLIT, PREC_FP32_ATOMIC, PREC_FP32_DIRECT = 0, 1, 2, 3, 4
 
 # exported symbols (kept in step with include/ism.h)
 EXPORTS = [

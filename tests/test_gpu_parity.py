@@ -1,6 +1,7 @@
 """GPU parity: the HIP path through the C-ABI against the FP64 oracle.
 
-Bar (per RIR): max |gpu - oracle| <= 1e-5 * max |oracle| for the FP32 paths,
+Bar (per RIR): max |gpu - oracle| <= 1e-5 * max |oracle| for the FP32 paths (the
+moment evaluation and the per-tap direct one),
 <= 2e-3 * max |oracle| for the FP16 table variant; tap counts (integers) equal
 exactly; repeated and batched runs bitwise equal.
 """
@@ -71,13 +72,14 @@ def run(H, batch, precision=ism.PREC_FP32, seg_len=None):
 
 
 # ------------------------------------------------------------------ configurations
+@pytest.mark.parametrize("precision", [ism.PREC_FP32, ism.PREC_FP32_DIRECT])
 @pytest.mark.parametrize("mode", [ism.ORDER_INDEX_L1, ism.ORDER_REFLECTIONS])
 @pytest.mark.parametrize("seg_len", [64, 1024, 2048])
-def test_c0_single_room(H, mode, seg_len):
+def test_c0_single_room(H, mode, seg_len, precision):
     b = scenes.c0()
     b["order_mode"] = mode
-    _say(f"c0 mode={mode} seg_len={seg_len}")
-    gpu, cnt = run(H, b, seg_len=seg_len)
+    _say(f"c0 mode={mode} seg_len={seg_len} precision={precision}")
+    gpu, cnt = run(H, b, precision=precision, seg_len=seg_len)
     ref, taps, rirs = oracle_batch(b)
     err = rel_errors(b, gpu, ref, rirs)
     assert err.max() <= TOL_FP32, err
@@ -96,11 +98,12 @@ def test_tiny_rooms_all_kernel_variants(H, taps, rir_len, seg_len):
     assert cnt["taps"] == ntaps
 
 
-def test_c1_sixteen_rooms(H):
+@pytest.mark.parametrize("precision", [ism.PREC_FP32, ism.PREC_FP32_DIRECT])
+def test_c1_sixteen_rooms(H, precision):
     full = scenes.c1()
     b = scenes.subset(full, range(16))
-    _say("c1 16 rooms")
-    gpu, cnt = run(H, b)
+    _say(f"c1 16 rooms precision={precision}")
+    gpu, cnt = run(H, b, precision=precision)
     ref, taps, rirs = oracle_batch(b)
     err = rel_errors(b, gpu, ref, rirs)
     _say(f"c1 16 rooms max err {err.max():.3e}")
@@ -129,7 +132,7 @@ def test_c3_precision_variants(H):
     b = scenes.subset(scenes.c3(), [0, 1])
     ref, taps, rirs = oracle_batch(b)
     res = {}
-    for prec, name in [(ism.PREC_FP32, "fp32"), (ism.PREC_FP32_ATOMIC, "atomic"),
+    for prec, name in [(ism.PREC_FP32, "fp32"), (ism.PREC_FP32_DIRECT, "direct"), (ism.PREC_FP32_ATOMIC, "atomic"),
                        (ism.PREC_FP16_LUT, "lut"), (ism.PREC_FP32_SPLIT, "split32")]:
         _say(f"c3 {name}")
         gpu, cnt = run(H, b, precision=prec)
@@ -138,6 +141,7 @@ def test_c3_precision_variants(H):
             assert cnt["taps"] == taps
     _say(f"c3 errors {res}")
     assert res["fp32"] <= TOL_FP32
+    assert res["direct"] <= TOL_FP32
     assert res["atomic"] <= TOL_FP32
     assert res["lut"] <= TOL_LUT
     assert res["split32"] >= res["fp32"]
