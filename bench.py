@@ -41,10 +41,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(taps_per_launch):
-    """HBM bytes per launch from the committed counter summary, if it was taken on the current
-    kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "ism_segments_c1_traffic.json")
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary of `kernel` on the 1024-room
+    batch, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_c1_traffic.json")
     if not os.path.exists(path):
         return None
     try:
@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--seg-len", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the per-tap (direct) evaluation of the same batch")
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the serving, precision and convolution sections")
@@ -249,10 +251,11 @@ def main():
 
     # roofline of the segment kernel (the launch is one graph: upload + prologue + segments)
     achieved = FLOPS_PER_TAP * taps / (k_ms / 1e3) / 1e12
-    traffic = measured_traffic(taps)
+    kernel = "ism_moments" if args.precision in (0, 2) else "ism_segments"
+    traffic = measured_traffic(kernel)
     res["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                        "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
-                       "kernel": "ism_segments", "launch_ms": k_ms,
+                       "kernel": kernel, "launch_ms": k_ms,
                        "flops_per_tap": FLOPS_PER_TAP, "taps_per_launch": taps}
 
     # plain: the same kernels launched once per room, host loop, one stream
