@@ -357,8 +357,10 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
                                                              : VAR_FX;
     KernelEntry ke{nullptr, nullptr};
     int lds = 0, block = 64;
+    int pow_max = 0;
+    for (const RoomDev &r : plan.rooms) pow_max = std::max(pow_max, r.pow_stride);
     const bool moments = (precision == ISM_PREC_FP32 || precision == ISM_PREC_FP32_SPLIT) &&
-                         plan.seg_max <= kMomSegMax;
+                         plan.seg_max <= kMomSegMax && pow_max <= kPowCap;
     if (moments) ke = select_moment_kernel(K);
     if (ke.fn) {
         lds = mom_lds_bytes(K);

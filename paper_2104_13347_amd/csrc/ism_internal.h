@@ -62,8 +62,10 @@ constexpr int kCols = 64;           // columns per enumeration chunk (one per la
 
 // Moment kernel: Chebyshev moments per delay bin, waves per workgroup, largest segment.
 constexpr int kMom = 10;
-constexpr int kMomWaves = 8;
+constexpr int kMomWaves = 16;       // waves per workgroup (one item per workgroup)
+constexpr int kMomSetupWaves = 8;   // waves that set up a batch of image columns, 64 each
 constexpr int kMomSegMax = 1024;
+constexpr int kPowCap = 256;        // z wall-power tables held in LDS (exponents 0 .. kPowCap-1)
 
 // Padded length of one moment channel: bins [0, kMomSegMax + 2K) plus one pad
 // word per 16 (the filter's window reads of consecutive lanes are 17 words apart).
@@ -75,9 +77,10 @@ constexpr int mom_ustride(int K)
 
 inline int mom_lds_bytes(int K)
 {
-    const int cols = 64 * kMomWaves;
+    const int cols = 64 * kMomSetupWaves;
     int bytes = kMom * mom_ustride(K) * 8;
-    bytes += cols * 8 * 2 + cols * 4 + cols * 4 * 3 * 4 + (cols + 4) * 4 + kMomWaves * 4 + 16;
+    bytes += cols * 8 * 2 + cols * 16 * 2 + cols * 4 + (cols + 4) * 4 + kMomSetupWaves * 4 + 16;
+    bytes += 2 * kPowCap * 8;
     return bytes;
 }
 

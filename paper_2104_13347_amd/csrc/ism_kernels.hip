@@ -455,13 +455,14 @@ DEV Column column_setup(const ItemGeom &G, int ci, int order_mode)
 // One image of a column: distance (FP64, (dx^2 + dy^2) + dz^2), delay and its
 // integer / fractional split, wall-power product.  Returns whether the record
 // belongs to the item (delay in [nlo, nhi], order within the limit).
-DEV bool image_eval(const ItemGeom &G, double rho2, double bxy, int cord, long q, int w, int order_mode,
-                    double fs, double cs, double fsc, int split32, int &n0, double &fr, double &d, double &B)
+DEV bool image_eval(const ItemGeom &G, const double *pz0, const double *pzL, double rho2, double bxy, int cord,
+                    int q, int w, int order_mode, double fs, double cs, double fsc, int split32, int &n0, double &fr,
+                    double &d, double &B)
 {
     bool ordok = true;
     if (G.N >= 0) {
-        const long oz = order_mode == 0 ? iabs(q) : iabs(2 * q - w);
-        ordok = (long)cord + oz <= G.N;
+        const int oz = order_mode == 0 ? abs(q) : abs(2 * q - w);
+        ordok = cord + oz <= G.N;
     }
     const double Z = (w ? -G.sz : G.sz) + (2.0 * (double)q) * G.Lz;
     const double dz = Z - G.rz;
@@ -489,9 +490,8 @@ DEV bool image_eval(const ItemGeom &G, double rho2, double bxy, int cord, long q
     const bool valid = ordok && n0 >= G.nlo && n0 <= G.nhi;
     B = 0.0;
     if (valid) {
-        const long pmax = G.pmax;
-        const int ez0 = (int)min(iabs(q - w), pmax), ezL = (int)min(iabs(q), pmax);
-        B = (bxy * G.pz0[ez0]) * G.pzL[ezL];
+        const int ez0 = min(abs(q - w), G.pmax), ezL = min(abs(q), G.pmax);
+        B = (bxy * pz0[ez0]) * pzL[ezL];
     }
     return valid;
 }
@@ -643,12 +643,12 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
                     const int e0 = S.icum[c * 4 + 0], e1 = S.icum[c * 4 + 1], e2 = S.icum[c * 4 + 2];
                     const int iv = (loc >= e0) + (loc >= e1) + (loc >= e2);
                     const int before = iv == 0 ? 0 : S.icum[c * 4 + iv - 1];
-                    const long q = (long)S.iq0[c * 4 + iv] + (loc - before);
+                    const int q = S.iq0[c * 4 + iv] + (loc - before);
                     const int w = S.iw[c * 4 + iv];
                     int n0;
                     double fr, d, B;
-                    valid = image_eval(G, S.crho2[c], S.cbxy[c], S.cord[c], q, w, order_mode, fs, cs, fsc, split32,
-                                       n0, fr, d, B);
+                    valid = image_eval(G, G.pz0, G.pzL, S.crho2[c], S.cbxy[c], S.cord[c], q, w, order_mode, fs, cs,
+                                       fsc, split32, n0, fr, d, B);
                     if (valid) {
                         // g = B / (4 pi d) to FP32 accuracy
                         rg = (float)B * (0.0795774715459477f * __builtin_amdgcn_rcpf((float)d));
@@ -726,18 +726,20 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
 //    words apart, hit distinct banks.  The waves' partial outputs are summed in a
 //    fixed order and stored once per sample.
 constexpr int kMomThreads = 64 * kMomWaves;
-constexpr int kMomCols = 64 * kMomWaves;  // columns per enumeration batch
+constexpr int kMomCols = 64 * kMomSetupWaves;  // columns per enumeration batch
 
 DEV int mpad(int i) { return i + (i >> 4); }
 
 struct MomLds {
-    long long *U;        // kMom x ustride bins (int64, then FP64 in place, then partial outputs)
+    long long *U;          // kMom x ustride bins (int64, then FP64 in place, then partial outputs)
     double *crho2, *cbxy;  // [kMomCols]
-    int32_t *cord;       // [kMomCols]
-    int32_t *iq0, *icum, *iw;  // [kMomCols * 4]
-    int32_t *gcoff;      // [kMomCols + 1] exclusive prefix of the images of the batch's columns
-    int32_t *wtot;       // [kMomWaves] images of each wave's chunk
-    int32_t *item;       // [1]
+    int4 *icum;            // [kMomCols] running image counts of the column's four intervals
+    int4 *iqw;             // [kMomCols] first z index of each interval times 2, plus its parity
+    int32_t *cord;         // [kMomCols]
+    int32_t *gcoff;        // [kMomCols + 1] exclusive prefix of the images of the batch's columns
+    int32_t *wtot;         // [kMomSetupWaves] images of each setup wave's chunk
+    double *pz0, *pzL;     // [kPowCap] z wall powers of the item's room
+    int32_t *item;         // [1]
 };
 
 DEV MomLds mom_carve(char *base, int K)
@@ -747,12 +749,13 @@ DEV MomLds mom_carve(char *base, int K)
     s.U = (long long *)p; p += (size_t)kMom * mom_ustride(K) * 8;
     s.crho2 = (double *)p; p += kMomCols * 8;
     s.cbxy = (double *)p; p += kMomCols * 8;
+    s.pz0 = (double *)p; p += kPowCap * 8;
+    s.pzL = (double *)p; p += kPowCap * 8;
+    s.icum = (int4 *)p; p += kMomCols * 16;
+    s.iqw = (int4 *)p; p += kMomCols * 16;
     s.cord = (int32_t *)p; p += kMomCols * 4;
-    s.iq0 = (int32_t *)p; p += kMomCols * 4 * 4;
-    s.icum = (int32_t *)p; p += kMomCols * 4 * 4;
-    s.iw = (int32_t *)p; p += kMomCols * 4 * 4;
     s.gcoff = (int32_t *)p; p += (kMomCols + 4) * 4;
-    s.wtot = (int32_t *)p; p += kMomWaves * 4;
+    s.wtot = (int32_t *)p; p += kMomSetupWaves * 4;
     s.item = (int32_t *)p;
     return s;
 }
@@ -816,35 +819,37 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         const ItemDev it = P->items[item];
         const ItemGeom G = item_geom(P, it, K);
         const double gscale = ldexp(1.0, G.escale);
+        for (int i = tid; i < G.pow_stride; i += kMomThreads) {  // pow_stride <= kPowCap (host)
+            S.pz0[i] = G.pz0[i];
+            S.pzL[i] = G.pzL[i];
+        }
 
         // ---- records: moments into the delay bins
         for (int cb = 0; cb < G.ncols; cb += kMomCols) {
             const int gc = wave * 64 + lane;
-            const Column C = column_setup(G, cb + gc, order_mode);
-            const int ctot = C.len[0] + C.len[1] + C.len[2] + C.len[3];
-            int T;
-            const int off = wave_excl_scan(ctot, T);
-            S.crho2[gc] = C.rho2;
-            S.cbxy[gc] = C.bxy;
-            S.cord[gc] = C.ord;
-            int cum = 0;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                cum += C.len[i];
-                S.iq0[gc * 4 + i] = C.q0[i];
-                S.icum[gc * 4 + i] = cum;
-                S.iw[gc * 4 + i] = C.wv[i];
+            int off = 0;
+            if (wave < kMomSetupWaves) {
+                const Column C = column_setup(G, cb + gc, order_mode);
+                const int ctot = C.len[0] + C.len[1] + C.len[2] + C.len[3];
+                int T;
+                off = wave_excl_scan(ctot, T);
+                S.crho2[gc] = C.rho2;
+                S.cbxy[gc] = C.bxy;
+                S.cord[gc] = C.ord;
+                S.icum[gc] = make_int4(C.len[0], C.len[0] + C.len[1], C.len[0] + C.len[1] + C.len[2], ctot);
+                S.iqw[gc] = make_int4(2 * C.q0[0] + C.wv[0], 2 * C.q0[1] + C.wv[1], 2 * C.q0[2] + C.wv[2],
+                                      2 * C.q0[3] + C.wv[3]);
+                if (lane == 0) S.wtot[wave] = T;
             }
-            if (lane == 0) S.wtot[wave] = T;
             __syncthreads();
             int base = 0, Tall = 0;
 #pragma unroll
-            for (int w = 0; w < kMomWaves; ++w) {
+            for (int w = 0; w < kMomSetupWaves; ++w) {
                 const int t = S.wtot[w];
                 base += w < wave ? t : 0;
                 Tall += t;
             }
-            S.gcoff[gc] = base + off;
+            if (wave < kMomSetupWaves) S.gcoff[gc] = base + off;
             if (tid == 0) S.gcoff[kMomCols] = Tall;
             __syncthreads();
 
@@ -862,16 +867,18 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             for (; x < xe; ++x) {
                 while (S.gcoff[c + 1] <= x) ++c;
                 const int loc = x - S.gcoff[c];
-                const int e0 = S.icum[c * 4 + 0], e1 = S.icum[c * 4 + 1], e2 = S.icum[c * 4 + 2];
-                const int iv = (loc >= e0) + (loc >= e1) + (loc >= e2);
-                const int before = iv == 0 ? 0 : S.icum[c * 4 + iv - 1];
-                const long q = (long)S.iq0[c * 4 + iv] + (loc - before);
-                const int w = S.iw[c * 4 + iv];
+                const int4 cu = S.icum[c];
+                const int4 qw = S.iqw[c];
+                const int iv = (loc >= cu.x) + (loc >= cu.y) + (loc >= cu.z);
+                const int before = iv == 0 ? 0 : iv == 1 ? cu.x : iv == 2 ? cu.y : cu.z;
+                const int qwv = iv == 0 ? qw.x : iv == 1 ? qw.y : iv == 2 ? qw.z : qw.w;
+                const int q = (qwv >> 1) + (loc - before);
+                const int w = qwv & 1;
                 ++n_img;
                 int n0;
                 double fr, d, B;
-                if (!image_eval(G, S.crho2[c], S.cbxy[c], S.cord[c], q, w, order_mode, fs, cs, fsc, split32, n0,
-                                fr, d, B))
+                if (!image_eval(G, S.pz0, S.pzL, S.crho2[c], S.cbxy[c], S.cord[c], q, w, order_mode, fs, cs, fsc,
+                                split32, n0, fr, d, B))
                     continue;
                 ++n_rec;
                 const int lo = max(n0 - K, G.s0), hi = min(n0 + K, G.s1 - 1);
@@ -907,10 +914,10 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         double acc[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[r] = 0.0;
-        for (int m = wave; m < kMom; m += kMomWaves)
-            mom_filter<K>((const double *)S.U + m * ustride, P->coef + m * (2 * K + 1), lane, acc);
+        if (wave < kMom)  // one moment channel per wave
+            mom_filter<K>((const double *)S.U + wave * ustride, P->coef + wave * (2 * K + 1), lane, acc);
         __syncthreads();
-        {
+        if (wave < kMom) {
             double *part = (double *)S.U + wave * mpad(kMomSegMax);
 #pragma unroll
             for (int r = 0; r < 16; ++r) part[17 * lane + r] = acc[r];  // mpad(16 lane + r)
@@ -924,7 +931,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             for (int i = tid; i < G.Sn; i += kMomThreads) {
                 double v = 0.0;
 #pragma unroll
-                for (int w = 0; w < kMomWaves; ++w) v += part[w * mpad(kMomSegMax) + mpad(i)];
+                for (int w = 0; w < kMom; ++w) v += part[w * mpad(kMomSegMax) + mpad(i)];
                 o[i] = (float)(v * inv);
             }
         }
