@@ -452,6 +452,23 @@ DEV Column column_setup(const ItemGeom &G, int ci, int order_mode)
     return C;
 }
 
+// Square root of a normal positive double (a >= 2^-767), correctly rounded:
+// Goldschmidt iteration from the hardware reciprocal-square-root estimate with two
+// Newton corrections of the root (the general sqrt adds only range scaling and
+// special-value handling, which the squared distances here never need).
+DEV double sqrt_normal(double a)
+{
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y, hh = y * 0.5;
+    const double r = fma(-hh, g, 0.5);
+    g = fma(g, r, g);
+    hh = fma(hh, r, hh);
+    double e = fma(-g, g, a);
+    g = fma(e, hh, g);
+    e = fma(-g, g, a);
+    return fma(e, hh, g);
+}
+
 // One image of a column: distance (FP64, (dx^2 + dy^2) + dz^2), delay and its
 // integer / fractional split, wall-power product.  Returns whether the record
 // belongs to the item (delay in [nlo, nhi], order within the limit).
@@ -467,7 +484,7 @@ DEV bool image_eval(const ItemGeom &G, const double *pz0, const double *pzL, dou
     const double Z = (w ? -G.sz : G.sz) + (2.0 * (double)q) * G.Lz;
     const double dz = Z - G.rz;
     const double d2 = rho2 + dz * dz;
-    d = sqrt(d2);
+    d = sqrt_normal(d2);  // d2 >= (closest image distance)^2, far above 2^-767
     // tau = (d fs) / c as in the definition; d * (fs/c) differs by at most an
     // ulp or two, which can change floor(tau + 1/2) only right at a rounding
     // boundary: there the exact quotient is taken
@@ -818,7 +835,8 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         if (item >= P->n_items) break;
         const ItemDev it = P->items[item];
         const ItemGeom G = item_geom(P, it, K);
-        const double gscale = ldexp(1.0, G.escale);
+        const double gk = 0.07957747154594767 * ldexp(1.0, G.escale);  // 2^e / (4 pi), exact scaling
+        uint32_t item_taps = 0;
         for (int i = tid; i < G.pow_stride; i += kMomThreads) {  // pow_stride <= kPowCap (host)
             S.pz0[i] = G.pz0[i];
             S.pzL[i] = G.pzL[i];
@@ -881,12 +899,12 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                                 split32, n0, fr, d, B))
                     continue;
                 ++n_rec;
-                const int lo = max(n0 - K, G.s0), hi = min(n0 + K, G.s1 - 1);
-                n_taps += hi >= lo ? (uint64_t)(hi - lo + 1) : 0ull;
+                // taps landing in [s0, s1): 2K + 1 minus those cut at either end (n0 in [nlo, nhi])
+                item_taps += (uint32_t)(2 * K + 1 - max(0, G.s0 + K - n0) - max(0, n0 + K + 1 - G.s1));
                 // g 2^e = B / (4 pi d) 2^e in FP64 (reciprocal with one Newton step)
                 double rd = __builtin_amdgcn_rcp(d);
                 rd = fma(fma(-d, rd, 1.0), rd, rd);
-                const double gs = B * (0.07957747154594767 * rd) * gscale;
+                const double gs = B * (rd * gk);
                 const double xx = 2.0 * fr, x2 = 2.0 * xx;
                 long long *u = S.U + mpad(n0 - G.rel);
                 double tp = 1.0, tc = xx;
@@ -902,6 +920,8 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             }
             __syncthreads();  // the batch's column tables are rewritten next
         }
+
+        n_taps += item_taps;
 
         // ---- bins to FP64 (exact: |sum| < 2^53)
         {
