@@ -63,7 +63,7 @@ constexpr int kCols = 64;           // columns per enumeration chunk (one per la
 // Moment kernel: Chebyshev moments per delay bin, waves per workgroup, largest segment.
 constexpr int kMom = 10;
 constexpr int kMomWaves = 16;       // waves per workgroup (one item per workgroup)
-constexpr int kMomSetupWaves = 8;   // waves that set up a batch of image columns, 64 each
+constexpr int kMomSetupWaves = 16;  // waves that set up a batch of image columns, 64 each
 constexpr int kMomSegMax = 1024;
 constexpr int kPowCap = 256;        // z wall-power tables held in LDS (exponents 0 .. kPowCap-1)
 
