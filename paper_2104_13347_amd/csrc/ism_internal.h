@@ -65,7 +65,7 @@ constexpr int kMom = 10;
 constexpr int kMomWaves = 16;       // waves per workgroup (one item per workgroup)
 constexpr int kMomSetupWaves = 16;  // waves that set up a batch of image columns, 64 each
 constexpr int kMomSegMax = 1024;
-constexpr int kPowCap = 256;        // z wall-power tables held in LDS (exponents 0 .. kPowCap-1)
+constexpr int kPowCap = 128;        // moment kernel: wall exponents below kPowCap (z powers in LDS)
 
 // Padded length of one moment channel: bins [0, kMomSegMax + 2K) plus one pad
 // word per 16 (the filter's window reads of consecutive lanes are 17 words apart).
@@ -79,8 +79,8 @@ inline int mom_lds_bytes(int K)
 {
     const int cols = 64 * kMomSetupWaves;
     int bytes = kMom * mom_ustride(K) * 8;
-    bytes += cols * 8 * 2 + cols * 16 * 2 + cols * 4 + (cols + 4) * 4 + kMomSetupWaves * 4 + 16;
-    bytes += 2 * kPowCap * 8;
+    bytes += cols * 48 + (cols + 4) * 4 + kMomSetupWaves * 4 + 16;  // column records, prefix
+    bytes += 4 * kPowCap * 8;                                      // z wall powers
     return bytes;
 }
 

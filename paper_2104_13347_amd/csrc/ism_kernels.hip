@@ -470,11 +470,10 @@ DEV double sqrt_normal(double a)
 }
 
 // One image of a column: distance (FP64, (dx^2 + dy^2) + dz^2), delay and its
-// integer / fractional split, wall-power product.  Returns whether the record
-// belongs to the item (delay in [nlo, nhi], order within the limit).
-DEV bool image_eval(const ItemGeom &G, const double *pz0, const double *pzL, double rho2, double bxy, int cord,
-                    int q, int w, int order_mode, double fs, double cs, double fsc, int split32, int &n0, double &fr,
-                    double &d, double &B)
+// integer / fractional split.  Returns whether the record belongs to the item
+// (delay in [nlo, nhi], order within the limit).
+DEV bool image_eval(const ItemGeom &G, double rho2, int cord, int q, int w, int order_mode, double fs, double cs,
+                    double fsc, int split32, int &n0, double &fr, double &d)
 {
     bool ordok = true;
     if (G.N >= 0) {
@@ -504,13 +503,7 @@ DEV bool image_eval(const ItemGeom &G, const double *pz0, const double *pzL, dou
         n0 = (int)n0f;
         fr = (double)(tauf - n0f);
     }
-    const bool valid = ordok && n0 >= G.nlo && n0 <= G.nhi;
-    B = 0.0;
-    if (valid) {
-        const int ez0 = min(abs(q - w), G.pmax), ezL = min(abs(q), G.pmax);
-        B = (bxy * pz0[ez0]) * pzL[ezL];
-    }
-    return valid;
+    return ordok && n0 >= G.nlo && n0 <= G.nhi;
 }
 
 template <int KT, int VAR>
@@ -663,10 +656,11 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
                     const int q = S.iq0[c * 4 + iv] + (loc - before);
                     const int w = S.iw[c * 4 + iv];
                     int n0;
-                    double fr, d, B;
-                    valid = image_eval(G, G.pz0, G.pzL, S.crho2[c], S.cbxy[c], S.cord[c], q, w, order_mode, fs, cs,
-                                       fsc, split32, n0, fr, d, B);
+                    double fr, d;
+                    valid = image_eval(G, S.crho2[c], S.cord[c], q, w, order_mode, fs, cs, fsc, split32, n0, fr, d);
                     if (valid) {
+                        const int ez0 = min(abs(q - w), G.pmax), ezL = min(abs(q), G.pmax);
+                        const double B = (S.cbxy[c] * G.pz0[ez0]) * G.pzL[ezL];
                         // g = B / (4 pi d) to FP32 accuracy
                         rg = (float)B * (0.0795774715459477f * __builtin_amdgcn_rcpf((float)d));
                         rf = (float)fr;
@@ -747,15 +741,21 @@ constexpr int kMomCols = 64 * kMomSetupWaves;  // columns per enumeration batch
 
 DEV int mpad(int i) { return i + (i >> 4); }
 
+// One column of an enumeration batch: squared horizontal distance, x/y wall-power
+// product, running image counts of its intervals (with the x/y reflection order in the
+// last slot) and each interval's first z index times 2 plus its parity.
+struct alignas(16) MomCol {
+    double rho2, bxy;
+    int4 cum;  // cum[0..2] = images in intervals 0, 0..1, 0..2; .w = x/y order
+    int4 qw;
+};
+
 struct MomLds {
     long long *U;          // kMom x ustride bins (int64, then FP64 in place, then partial outputs)
-    double *crho2, *cbxy;  // [kMomCols]
-    int4 *icum;            // [kMomCols] running image counts of the column's four intervals
-    int4 *iqw;             // [kMomCols] first z index of each interval times 2, plus its parity
-    int32_t *cord;         // [kMomCols]
+    MomCol *col;           // [kMomCols]
     int32_t *gcoff;        // [kMomCols + 1] exclusive prefix of the images of the batch's columns
     int32_t *wtot;         // [kMomSetupWaves] images of each setup wave's chunk
-    double *pz0, *pzL;     // [kPowCap] z wall powers of the item's room
+    double *pzz;           // [4 kPowCap] z wall powers by (2 q + w), q in (-kPowCap, kPowCap)
     int32_t *item;         // [1]
 };
 
@@ -764,13 +764,8 @@ DEV MomLds mom_carve(char *base, int K)
     MomLds s;
     char *p = base;
     s.U = (long long *)p; p += (size_t)kMom * mom_ustride(K) * 8;
-    s.crho2 = (double *)p; p += kMomCols * 8;
-    s.cbxy = (double *)p; p += kMomCols * 8;
-    s.pz0 = (double *)p; p += kPowCap * 8;
-    s.pzL = (double *)p; p += kPowCap * 8;
-    s.icum = (int4 *)p; p += kMomCols * 16;
-    s.iqw = (int4 *)p; p += kMomCols * 16;
-    s.cord = (int32_t *)p; p += kMomCols * 4;
+    s.col = (MomCol *)p; p += kMomCols * sizeof(MomCol);
+    s.pzz = (double *)p; p += 4 * kPowCap * 8;
     s.gcoff = (int32_t *)p; p += (kMomCols + 4) * 4;
     s.wtot = (int32_t *)p; p += kMomSetupWaves * 4;
     s.item = (int32_t *)p;
@@ -837,9 +832,12 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         const ItemGeom G = item_geom(P, it, K);
         const double gk = 0.07957747154594767 * ldexp(1.0, G.escale);  // 2^e / (4 pi), exact scaling
         uint32_t item_taps = 0;
-        for (int i = tid; i < G.pow_stride; i += kMomThreads) {  // pow_stride <= kPowCap (host)
-            S.pz0[i] = G.pz0[i];
-            S.pzL[i] = G.pzL[i];
+        // z wall powers by image: pzz[2 (q + kPowCap) + w] = beta_z0^|q - w| beta_zL^|q|
+        // (|q| <= pmax < kPowCap for every image of the item: pow_stride <= kPowCap on the host)
+        for (int i = tid; i < 4 * kPowCap; i += kMomThreads) {
+            const int q = (i >> 1) - kPowCap, w = i & 1;
+            const int ez0 = min(abs(q - w), G.pmax), ezL = min(abs(q), G.pmax);
+            S.pzz[i] = G.pz0[ez0] * G.pzL[ezL];
         }
 
         // ---- records: moments into the delay bins
@@ -851,12 +849,13 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                 const int ctot = C.len[0] + C.len[1] + C.len[2] + C.len[3];
                 int T;
                 off = wave_excl_scan(ctot, T);
-                S.crho2[gc] = C.rho2;
-                S.cbxy[gc] = C.bxy;
-                S.cord[gc] = C.ord;
-                S.icum[gc] = make_int4(C.len[0], C.len[0] + C.len[1], C.len[0] + C.len[1] + C.len[2], ctot);
-                S.iqw[gc] = make_int4(2 * C.q0[0] + C.wv[0], 2 * C.q0[1] + C.wv[1], 2 * C.q0[2] + C.wv[2],
-                                      2 * C.q0[3] + C.wv[3]);
+                MomCol mc;
+                mc.rho2 = C.rho2;
+                mc.bxy = C.bxy;
+                mc.cum = make_int4(C.len[0], C.len[0] + C.len[1], C.len[0] + C.len[1] + C.len[2], C.ord);
+                mc.qw = make_int4(2 * C.q0[0] + C.wv[0], 2 * C.q0[1] + C.wv[1], 2 * C.q0[2] + C.wv[2],
+                                  2 * C.q0[3] + C.wv[3]);
+                S.col[gc] = mc;
                 if (lane == 0) S.wtot[wave] = T;
             }
             __syncthreads();
@@ -885,8 +884,9 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             for (; x < xe; ++x) {
                 while (S.gcoff[c + 1] <= x) ++c;
                 const int loc = x - S.gcoff[c];
-                const int4 cu = S.icum[c];
-                const int4 qw = S.iqw[c];
+                const MomCol &mc = S.col[c];
+                const int4 cu = mc.cum;
+                const int4 qw = mc.qw;
                 const int iv = (loc >= cu.x) + (loc >= cu.y) + (loc >= cu.z);
                 const int before = iv == 0 ? 0 : iv == 1 ? cu.x : iv == 2 ? cu.y : cu.z;
                 const int qwv = iv == 0 ? qw.x : iv == 1 ? qw.y : iv == 2 ? qw.z : qw.w;
@@ -894,10 +894,11 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                 const int w = qwv & 1;
                 ++n_img;
                 int n0;
-                double fr, d, B;
-                if (!image_eval(G, S.pz0, S.pzL, S.crho2[c], S.cbxy[c], S.cord[c], q, w, order_mode, fs, cs, fsc,
-                                split32, n0, fr, d, B))
+                double fr, d;
+                if (!image_eval(G, mc.rho2, cu.w, q, w, order_mode, fs, cs, fsc, split32, n0, fr, d))
                     continue;
+                const int qc = min(max(q, 1 - kPowCap), kPowCap - 1);  // |q| <= pmax already
+                const double B = mc.bxy * S.pzz[2 * (qc + kPowCap) + w];
                 ++n_rec;
                 // taps landing in [s0, s1): 2K + 1 minus those cut at either end (n0 in [nlo, nhi])
                 item_taps += (uint32_t)(2 * K + 1 - max(0, G.s0 + K - n0) - max(0, n0 + K + 1 - G.s1));
@@ -907,13 +908,14 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                 const double gs = B * (rd * gk);
                 const double xx = 2.0 * fr, x2 = 2.0 * xx;
                 long long *u = S.U + mpad(n0 - G.rel);
+                long long *u2 = u + 5 * ustride;  // channels 5.. from a second base (16-bit offsets)
                 double tp = 1.0, tc = xx;
                 lds_add_i64(u, gs);
                 lds_add_i64(u + ustride, gs * xx);
 #pragma unroll
                 for (int m = 2; m < kMom; ++m) {
                     const double tn = fma(x2, tc, -tp);
-                    lds_add_i64(u + m * ustride, gs * tn);
+                    lds_add_i64(m < 5 ? u + m * ustride : u2 + (m - 5) * ustride, gs * tn);
                     tp = tc;
                     tc = tn;
                 }
