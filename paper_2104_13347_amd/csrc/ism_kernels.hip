@@ -378,7 +378,8 @@ struct Column {
     int ord;
 };
 
-DEV Column column_setup(const ItemGeom &G, int ci, int order_mode)
+// px: x0, xL, y0, yL wall-power tables, `ps` apart (exponents 0 .. pmax)
+DEV Column column_setup(const ItemGeom &G, int ci, int order_mode, const double *px, int ps)
 {
     Column C;
 #pragma unroll
@@ -410,8 +411,7 @@ DEV Column column_setup(const ItemGeom &G, int ci, int order_mode)
     const long pmax = G.pmax;
     const int ex0 = (int)min(iabs(n - u), pmax), exL = (int)min(iabs(n), pmax);
     const int ey0 = (int)min(iabs(l - v), pmax), eyL = (int)min(iabs(l), pmax);
-    const double *px0 = G.px0;
-    C.bxy = ((px0[ex0] * px0[G.pow_stride + exL]) * px0[2 * G.pow_stride + ey0]) * px0[3 * G.pow_stride + eyL];
+    C.bxy = ((px[ex0] * px[ps + exL]) * px[2 * ps + ey0]) * px[3 * ps + eyL];
     const double zb = sqrt(G.dhi2 - rho2);
     const double za = G.dlo2 > rho2 ? sqrt(G.dlo2 - rho2) : 0.0;
     const double inv2L = 0.5 / G.Lz;
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
 
         for (int c0 = 0; c0 < ncols; c0 += kCols) {
             // ---- column chunk: one (a, b) column per lane
-            const Column C = column_setup(G, c0 + lane, order_mode);
+            const Column C = column_setup(G, c0 + lane, order_mode, G.px0, G.pow_stride);
             ++n_chunks;
             const int ctot = C.len[0] + C.len[1] + C.len[2] + C.len[3];
             int T;
@@ -756,6 +756,7 @@ struct MomLds {
     int32_t *gcoff;        // [kMomCols + 1] exclusive prefix of the images of the batch's columns
     int32_t *wtot;         // [kMomSetupWaves] images of each setup wave's chunk
     double *pzz;           // [4 kPowCap] z wall powers by (2 q + w), q in (-kPowCap, kPowCap)
+    double *pxy;           // [4 kPowCap] x0, xL, y0, yL wall powers, kPowCap apart
     int32_t *item;         // [1]
 };
 
@@ -766,6 +767,7 @@ DEV MomLds mom_carve(char *base, int K)
     s.U = (long long *)p; p += (size_t)kMom * mom_ustride(K) * 8;
     s.col = (MomCol *)p; p += kMomCols * sizeof(MomCol);
     s.pzz = (double *)p; p += 4 * kPowCap * 8;
+    s.pxy = (double *)p; p += 4 * kPowCap * 8;
     s.gcoff = (int32_t *)p; p += (kMomCols + 4) * 4;
     s.wtot = (int32_t *)p; p += kMomSetupWaves * 4;
     s.item = (int32_t *)p;
@@ -826,7 +828,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         if (tid == 0) S.item[0] = (int)atomicAdd(P->counter, 1u);
         for (int i = tid; i < nU; i += kMomThreads) S.U[i] = 0;
         __syncthreads();
-        const int item = S.item[0];
+        const int item = uniform(S.item[0]);
         if (item >= P->n_items) break;
         const ItemDev it = P->items[item];
         const ItemGeom G = item_geom(P, it, K);
@@ -838,14 +840,17 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             const int q = (i >> 1) - kPowCap, w = i & 1;
             const int ez0 = min(abs(q - w), G.pmax), ezL = min(abs(q), G.pmax);
             S.pzz[i] = G.pz0[ez0] * G.pzL[ezL];
+            const int wall = i / kPowCap, e = min(i % kPowCap, G.pmax);
+            S.pxy[i] = G.px0[wall * G.pow_stride + e];
         }
+        __syncthreads();  // tables complete before the first column setup
 
         // ---- records: moments into the delay bins
         for (int cb = 0; cb < G.ncols; cb += kMomCols) {
             const int gc = wave * 64 + lane;
             int off = 0;
             if (wave < kMomSetupWaves) {
-                const Column C = column_setup(G, cb + gc, order_mode);
+                const Column C = column_setup(G, cb + gc, order_mode, S.pxy, kPowCap);
                 const int ctot = C.len[0] + C.len[1] + C.len[2] + C.len[3];
                 int T;
                 off = wave_excl_scan(ctot, T);
