@@ -48,6 +48,8 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         L.ism_oracle_fd_tap.restype = ctypes.c_double
         L.ism_oracle_fd_tap.argtypes = [ctypes.c_double, ctypes.c_int]
+        L.ism_oracle_lagrange_tap.restype = ctypes.c_double
+        L.ism_oracle_lagrange_tap.argtypes = [ctypes.c_int, ctypes.c_double]
         L.ism_oracle_images.restype = ctypes.c_long
         L.ism_oracle_images.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp,
                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_long]
@@ -82,6 +84,12 @@ def fd_tap(t: float, taps: int) -> float:
     """Hann-windowed sinc kernel h(t) with half-length K = (taps-1)/2 (section II.A filter, as
     specified for these workloads: windowed sinc in place of the paper's Lagrange filter)."""
     return lib().ism_oracle_fd_tap(float(t), (int(taps) - 1) // 2)
+
+
+def lagrange_tap(j: int, D: float) -> float:
+    """Coefficient j (0..7) of the 7th-order Lagrange fractional-delay interpolator at delay D
+    (section II.A: the paper's own filter; selected by fd_taps = 8)."""
+    return lib().ism_oracle_lagrange_tap(int(j), float(D))
 
 
 def images(L, src, max_order: int, mode: int):

@@ -29,6 +29,10 @@
  *   n0 = floor(tau + 1/2); taps at n = n0 + k, k = -K..K, kept if 0 <= n < len
  *   out[n] = sum over images, in lexicographic (n,l,q,u,v,w) order, of
  *            g * h(n - tau), plain FP64 accumulation.
+ *   taps == 8 selects the paper's own filter instead, the 7th-order Lagrange
+ *   interpolator: n0 = floor(tau), taps at n = n0 - 3 + j, j = 0..7, with
+ *   h_j = prod_{i != j} (D - i) / (j - i), D = tau - (n0 - 3) in [3, 4) (the
+ *   delay sits between the two middle taps); time bound n0 - 3 <= len - 1.
  *   Image sets: order_mode 0 (index L1): |n|+|l|+|q| <= N, all 8 parities;
  *               order_mode 1 (reflections): |2n-u|+|2l-v|+|2q-w| <= N;
  *               max_order < 0: every image whose tap support meets [0, len).
@@ -64,6 +68,16 @@ double ism_oracle_fd_tap(double t, int K)
     double s = (t == 0.0) ? 1.0 : sin(M_PI * t) / (M_PI * t);
     double w = 0.5 * (1.0 + cos(M_PI * t / half));
     return s * w;
+}
+
+/* Coefficient j (0..7) of the 7th-order Lagrange fractional-delay interpolator
+   at delay D (taps at 0..7): the Lagrange basis polynomial of node j. */
+double ism_oracle_lagrange_tap(int j, double D)
+{
+    double h = 1.0;
+    for (int i = 0; i < 8; ++i)
+        if (i != j) h *= (D - (double)i) / (double)(j - i);
+    return h;
 }
 
 /* Image position (closed form of the mirror construction). */
@@ -127,22 +141,26 @@ int ism_oracle_rir(const double L[3], const double beta[6], const double src[3],
                    const double mic[3], double fs, double c, int max_order, int mode,
                    int len, int taps, double *out, ism_oracle_stats *stats)
 {
-    if (taps < 1 || (taps % 2) == 0 || len < 1 || fs <= 0 || c <= 0) return -1;
-    int K = (taps - 1) / 2;
+    const int lag = taps == 8;  /* 7th-order Lagrange; otherwise a windowed sinc */
+    if (taps < 1 || (!lag && (taps % 2) == 0) || len < 1 || fs <= 0 || c <= 0) return -1;
+    int K = lag ? 4 : (taps - 1) / 2;
     memset(out, 0, sizeof(double) * (size_t)len);
     ism_oracle_stats st = {0, 0, 0, 0};
 
-    /* index box: for the time bound, every image with n0 - K <= len - 1, i.e.
-       tau < len - 1 + K + 1/2, lies within distance dmax of the microphone. */
+    /* index box: for the time bound, every image whose first tap is at or before
+       len - 1 lies within distance dmax of the microphone (sinc: n0 - K <= len - 1,
+       i.e. tau < len - 1 + K + 1/2; Lagrange: floor(tau) - 3 <= len - 1). */
     long bx, by, bz;
     if (max_order >= 0) {
         bx = by = bz = max_order + 1;
     } else {
-        double dmax = ((double)len - 1.0 + (double)K + 0.5) * c / fs;
+        double dmax = (lag ? (double)len + 3.0 : (double)len - 1.0 + (double)K + 0.5) * c / fs;
         bx = (long)ceil(dmax / (2.0 * L[0])) + 2;
         by = (long)ceil(dmax / (2.0 * L[1])) + 2;
         bz = (long)ceil(dmax / (2.0 * L[2])) + 2;
     }
+    /* taps of an image: n = first .. first + ntap - 1 */
+    const int ntap = lag ? 8 : 2 * K + 1;
     for (long n = -bx; n <= bx; ++n)
         for (long l = -by; l <= by; ++l)
             for (long q = -bz; q <= bz; ++q)
@@ -155,21 +173,24 @@ int ism_oracle_rir(const double L[3], const double beta[6], const double src[3],
                             double dx = p[0] - mic[0], dy = p[1] - mic[1], dz = p[2] - mic[2];
                             double d = sqrt(dx * dx + dy * dy + dz * dz);
                             double tau = d * fs / c;
-                            long n0 = (long)floor(tau + 0.5);
-                            if (max_order < 0 && n0 - K > len - 1) continue; /* outside the time bound */
+                            long n0 = lag ? (long)floor(tau) : (long)floor(tau + 0.5);
+                            long first = lag ? n0 - 3 : n0 - K;
+                            if (max_order < 0 && first > len - 1) continue; /* outside the time bound */
                             ++st.images;
                             long refl = labs_l(2 * n - u) + labs_l(2 * l - v) + labs_l(2 * q - w);
                             if (refl > st.max_refl) st.max_refl = refl;
-                            if (n0 + K < 0 || n0 - K > len - 1) continue;
+                            if (first + ntap - 1 < 0 || first > len - 1) continue;
                             ++st.contrib;
                             double B = ipow(beta[0], labs_l(n - u)) * ipow(beta[1], labs_l(n)) *
                                        ipow(beta[2], labs_l(l - v)) * ipow(beta[3], labs_l(l)) *
                                        ipow(beta[4], labs_l(q - w)) * ipow(beta[5], labs_l(q));
                             double g = B / (4.0 * M_PI * d);
-                            for (int k = -K; k <= K; ++k) {
-                                long idx = n0 + k;
+                            for (int j = 0; j < ntap; ++j) {
+                                long idx = first + j;
                                 if (idx < 0 || idx >= len) continue;
-                                out[idx] += g * ism_oracle_fd_tap((double)idx - tau, K);
+                                double h = lag ? ism_oracle_lagrange_tap(j, tau - (double)first)
+                                               : ism_oracle_fd_tap((double)idx - tau, K);
+                                out[idx] += g * h;
                                 ++st.taps;
                             }
                         }

@@ -258,3 +258,91 @@ def test_convolution_matches_numpy_and_noise_hits_the_snr():
     yn = oracle.conv_room(h, x, 100, snr_db=12.5, z=z)
     snr = 10.0 * np.log10(np.mean(y * y) / np.mean((yn - y) ** 2))
     assert snr == pytest.approx(12.5, abs=1e-9)
+
+
+# ---------------------------------------------------------------- the paper's 7th-order Lagrange filter
+def _lagrange_basis_scipy(j, D):
+    from scipy.interpolate import lagrange
+    vals = np.zeros(8)
+    vals[j] = 1.0
+    return float(lagrange(np.arange(8.0), vals)(D))
+
+
+def test_lagrange_coefficients_match_scipy_and_reproduce_polynomials():
+    # section II.A filter: the 7th-order Lagrange interpolator (8 coefficients).  Against scipy's
+    # interpolating polynomial, and the defining properties: partition of unity and exact
+    # reproduction of every polynomial of degree <= 7 at the fractional position D.
+    rng = np.random.default_rng(3)
+    for D in np.concatenate([[3.0, 3.5, 3.999999], rng.uniform(3.0, 4.0, 20)]):
+        h = np.array([oracle.lagrange_tap(j, D) for j in range(8)])
+        ref = np.array([_lagrange_basis_scipy(j, D) for j in range(8)])
+        assert np.max(np.abs(h - ref)) < 1e-9
+        assert abs(h.sum() - 1.0) < 1e-13
+        for p in range(1, 8):
+            assert abs(np.dot(h, np.arange(8.0) ** p) - D ** p) < 1e-9 * max(1.0, D ** p)
+        # degree 8 is not reproduced between the nodes (the filter really is 7th order)
+        if 3.001 < D < 3.999:
+            assert abs(np.dot(h, np.arange(8.0) ** 8) - D ** 8) > 1e-6
+    assert [oracle.lagrange_tap(j, 3.0) for j in range(8)] == [0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0]
+
+
+def test_lagrange_kronecker_for_integer_delay():
+    out, _ = _rir((2.0, 2.0, 4.0), (0.0,) * 6, (1.0, 1.0, 1.0), (1.0, 1.0, 3.5), fs=136.0, c=340.0,
+                  n=32, taps=8)
+    g = 1.0 / (4.0 * math.pi * 2.5)
+    assert out[1] == pytest.approx(g, rel=1e-15)
+    assert np.max(np.abs(np.delete(out, 1))) < 1e-15 * g
+    # the direct image alone (reflection order 0): taps n0 - 3 .. n0 + 4 = -2 .. 5, six inside
+    _, st = _rir((2.0, 2.0, 4.0), (0.0,) * 6, (1.0, 1.0, 1.0), (1.0, 1.0, 3.5), fs=136.0, c=340.0,
+                 N=0, mode=1, n=32, taps=8)
+    assert st["images"] == 1 and st["taps"] == 6
+
+
+def test_lagrange_direct_path_moments():
+    # beta = 0: eight samples n0-3..n0+4 (n0 = floor(tau)) carry the direct path; their sum is
+    # the gain and their moments of order <= 7 are those of an impulse at exactly tau
+    L, s, r = (5.0, 4.0, 3.0), (1.3, 2.1, 1.5), (3.6, 1.7, 1.2)
+    out, _ = _rir(L, (0.0,) * 6, s, r, n=512, taps=8)
+    d = float(np.linalg.norm(np.subtract(s, r)))
+    tau = d * 16000.0 / 343.0
+    g = 1.0 / (4.0 * math.pi * d)
+    nz = np.nonzero(out)[0]
+    assert list(nz) == list(range(math.floor(tau) - 3, math.floor(tau) + 5))
+    n = np.arange(512.0)
+    x = n - 100.0            # centred moments keep the powers well conditioned
+    for p in range(0, 8):
+        assert np.dot(out, x ** p) == pytest.approx(g * (tau - 100.0) ** p, rel=1e-9, abs=1e-12)
+    _, st = _rir(L, (0.0,) * 6, s, r, N=0, mode=1, n=512, taps=8)
+    assert st["images"] == 1 and st["taps"] == 8
+
+
+def _brute_force_lagrange_rir(L, beta, s, r, fs, c, n):
+    """Mirror-construction images, floor split, taps from scipy's interpolating polynomial."""
+    dmax = (n + 3) * c / fs
+    depth = [int(math.ceil(dmax / L[a])) + 2 for a in range(3)]
+    axes = [mirror_images_1d(float(s[a]), float(L[a]), depth[a]) for a in range(3)]
+    out = np.zeros(n)
+    for x, (x0, xL, _) in axes[0].items():
+        for y, (y0, yL, _) in axes[1].items():
+            for z, (z0, zL, _) in axes[2].items():
+                d = math.sqrt((x - r[0]) ** 2 + (y - r[1]) ** 2 + (z - r[2]) ** 2)
+                tau = d * fs / c
+                first = math.floor(tau) - 3
+                if first > n - 1:
+                    continue
+                g = (beta[0] ** x0 * beta[1] ** xL * beta[2] ** y0 * beta[3] ** yL *
+                     beta[4] ** z0 * beta[5] ** zL) / (4.0 * math.pi * d)
+                for j in range(8):
+                    if 0 <= first + j < n:
+                        out[first + j] += g * _lagrange_basis_scipy(j, tau - first)
+    return out
+
+
+def test_brute_force_tiny_rooms_lagrange():
+    b = scenes.tiny(seed=12, n_rooms=2, rir_len=48, M=2, taps=9)
+    for i in range(2):
+        for m in range(2):
+            mic = b["mics"][b["mic_offset"][i] + m]
+            ref = _brute_force_lagrange_rir(b["L"][i], b["beta"][i], b["src"][i], mic, b["fs"], b["c"], 48)
+            got, _ = oracle.rir(b["L"][i], b["beta"][i], b["src"][i], mic, b["fs"], b["c"], -1, 0, 48, 8)
+            assert np.max(np.abs(got - ref)) < 1e-9 * np.max(np.abs(ref))
