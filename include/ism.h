@@ -9,11 +9,12 @@
  * that wall's pressure reflection coefficient, times 1/(4 pi d), and its delay
  * d*fs/c, split into an integer part n0 = floor(tau + 1/2) and a fraction
  * f = tau - n0.  A fractional-delay filter centred on tau is added into the
- * RIR at samples n0-K .. n0+K.  The filter here is the Hann-windowed sinc
- * h(t) = sinc(t) * (1 + cos(pi t / (K+1))) / 2, K = (fd_taps - 1) / 2 (the
- * paper's own filter is a 7th-order Lagrange interpolator; the windowed sinc
- * is the filter of the workloads this library serves).  Taps outside
- * [0, rir_len) are dropped.  Image n,l,q in Z, u,v,w in {0,1} sits at
+ * RIR at samples n0-K .. n0+K.  The filter is the Hann-windowed sinc
+ * h(t) = sinc(t) * (1 + cos(pi t / (K+1))) / 2, K = (fd_taps - 1) / 2 (odd
+ * fd_taps, the filter of the workloads this library serves), or, for
+ * fd_taps = 8, the paper's own 7th-order Lagrange interpolator: n0 = floor(tau),
+ * taps at n0-3 .. n0+4, tap j = prod_{i != j} (D - i) / (j - i) with
+ * D = tau - (n0 - 3) in [3, 4).  Taps outside [0, rir_len) are dropped.  Image n,l,q in Z, u,v,w in {0,1} sits at
  * ((1-2u) sx + 2n Lx, (1-2v) sy + 2l Ly, (1-2w) sz + 2q Lz) and is damped by
  * beta[0]^|n-u| beta[1]^|n| beta[2]^|l-v| beta[3]^|l| beta[4]^|q-w| beta[5]^|q|
  * (beta order: x0, xL, y0, yL, z0, zL).
@@ -134,7 +135,10 @@ int ism_version(void);
  *   mics: host, M x 3 positions (m), row-major.
  *   fs (Hz), c (m/s): sample rate and speed of sound.
  *   max_order, order_mode: image set (see above).
- *   rir_len: samples per RIR; fd_taps: odd filter length 2K+1 (<= 255).
+ *   rir_len: samples per RIR; fd_taps: odd windowed-sinc length 2K+1 (<= 255), or
+ *            8 for the 7th-order Lagrange filter (ISM_PREC_FP32 / _SPLIT only; segments of
+ *            at most 1024 samples are planned for it; rooms whose RIR length needs wall
+ *            exponents of 128 or more are rejected with ISM_EINVAL).
  *   precision: ism_precision.
  *   out: device, M x rir_len floats, row-major, fully overwritten.
  */

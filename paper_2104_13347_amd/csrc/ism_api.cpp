@@ -139,8 +139,14 @@ int ism_validate_common(ism_handle *h, double fs, double c, int fd_taps, int ord
 {
     if (!finite_pos(fs)) { ism_set_error(h, "fs must be finite and > 0"); return ISM_EINVAL; }
     if (!finite_pos(c)) { ism_set_error(h, "c must be finite and > 0"); return ISM_EINVAL; }
-    if (fd_taps < 1 || fd_taps % 2 == 0 || fd_taps > 2 * kKMax + 1) {
-        ism_set_error(h, "fd_taps must be odd and in [1, %d]", 2 * kKMax + 1);
+    if (fd_taps != kLagrangeTaps && (fd_taps < 1 || fd_taps % 2 == 0 || fd_taps > 2 * kKMax + 1)) {
+        ism_set_error(h, "fd_taps must be odd and in [1, %d] (windowed sinc) or %d (Lagrange)", 2 * kKMax + 1,
+                      kLagrangeTaps);
+        return ISM_EINVAL;
+    }
+    if (fd_taps == kLagrangeTaps && precision != ISM_PREC_FP32 && precision != ISM_PREC_FP32_SPLIT) {
+        ism_set_error(h, "the Lagrange filter (fd_taps = %d) runs with ISM_PREC_FP32 or ISM_PREC_FP32_SPLIT",
+                      kLagrangeTaps);
         return ISM_EINVAL;
     }
     if (order_mode != ISM_ORDER_INDEX_L1 && order_mode != ISM_ORDER_REFLECTIONS) {
@@ -221,7 +227,8 @@ static double item_cost(const ism_room &r, double fs, double c, int K, int s0, i
 int ism_build_plan(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics, double fs,
                    double c, int fd_taps, int seg_len, Plan &plan)
 {
-    const int K = (fd_taps - 1) / 2;
+    const int K = half_length(fd_taps);
+    if (fd_taps == kLagrangeTaps) seg_len = std::min(seg_len, kMomSegMax);  // moment kernel only
     plan.rooms.resize(n_rooms);
     plan.items.clear();
     plan.seg_max = 0;
@@ -321,10 +328,15 @@ static int ensure_slot(ism_handle *h, Slot &s, size_t bytes)
 }
 
 // Chebyshev coefficients of the moment kernel's filter: for each tap k in [-K, K],
-// h(k - f) = sum_{m < kMom} c[m][k] T_m(2f) on f in [-1/2, 1/2], h the Hann-windowed
-// sinc of half-length K.  Interpolation at 32 Chebyshev nodes in FP64 (the
-// coefficients past kMom are below 1e-9 and those past 32 below double rounding).
-static void mom_coefficients(int K, std::vector<double> &c)
+// h_k(x) = sum_{m < kMom} c[m][k] T_m(x) on x in [-1, 1], by interpolation at 32
+// Chebyshev nodes in FP64 (the coefficients past kMom are below 1e-9 and those past 32
+// below double rounding).
+//  * windowed sinc: x = 2f, f in [-1/2, 1/2], h_k = h(k - f), h the Hann-windowed sinc of
+//    half-length K;
+//  * 7th-order Lagrange (K = 4): x = 2f - 1, f = tau - floor(tau) in [0, 1), tap k at
+//    n0 + k is the basis polynomial of node j = k + 3 at D = f + 3 (zero for k = -4); a
+//    polynomial of degree 7 in x, so the expansion is exact.
+static void mom_coefficients(int K, bool lagrange, std::vector<double> &c)
 {
     const int nk = 2 * K + 1, NN = 32;
     c.assign((size_t)kMom * nk, 0.0);
@@ -332,9 +344,21 @@ static void mom_coefficients(int K, std::vector<double> &c)
     for (int j = 0; j < NN; ++j) th[j] = M_PI * (j + 0.5) / NN;
     for (int k = -K; k <= K; ++k) {
         for (int j = 0; j < NN; ++j) {
-            const double f = 0.5 * std::cos(th[j]);
-            const double t = k - f;  // never 0: no node at f = 0
-            hv[j] = std::sin(M_PI * t) / (M_PI * t) * 0.5 * (1.0 + std::cos(M_PI * t / (K + 1)));
+            const double x = std::cos(th[j]);
+            if (lagrange) {
+                const int node = k + 3;
+                double v = 0.0;
+                if (node >= 0 && node < 8) {
+                    const double D = 0.5 * (x + 1.0) + 3.0;
+                    v = 1.0;
+                    for (int i = 0; i < 8; ++i)
+                        if (i != node) v *= (D - i) / (double)(node - i);
+                }
+                hv[j] = v;
+            } else {
+                const double t = k - 0.5 * x;  // never 0: no node at x = 0
+                hv[j] = std::sin(M_PI * t) / (M_PI * t) * 0.5 * (1.0 + std::cos(M_PI * t / (K + 1)));
+            }
         }
         for (int m = 0; m < kMom; ++m) {
             double a = 0.0;
@@ -347,7 +371,8 @@ static void mom_coefficients(int K, std::vector<double> &c)
 int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs, double c, int fd_taps,
                  int order_mode, int precision, float *out, hipStream_t stream, double *t_ms)
 {
-    const int K = (fd_taps - 1) / 2;
+    const int K = half_length(fd_taps);
+    const bool lagrange = fd_taps == kLagrangeTaps;
     const int n_items = (int)plan.items.size();
     const int n_rooms = (int)plan.rooms.size();
     if (n_items == 0) return ISM_OK;
@@ -365,10 +390,15 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
     if (ke.fn) {
         lds = mom_lds_bytes(K);
         block = 64 * kMomWaves;
-        if (h->coef_K != K) {
-            mom_coefficients(K, h->coef);
-            h->coef_K = K;
+        const int key = lagrange ? -1000 : K;  // distinct from every K and from the initial -1
+        if (h->coef_K != key) {
+            mom_coefficients(K, lagrange, h->coef);
+            h->coef_K = key;
         }
+    } else if (lagrange) {
+        ism_set_error(h, "the Lagrange filter needs segments of at most %d samples and wall-exponent tables of "
+                      "at most %d entries (a room too small for its RIR length)", kMomSegMax, kPowCap);
+        return ISM_EINVAL;
     } else {
         ke = select_segment_kernel(K, variant);
         lds = seg_lds_bytes(plan.seg_max, K, variant);
@@ -411,6 +441,7 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
     L.K = K;
     L.order_mode = order_mode;
     L.split32 = precision == ISM_PREC_FP32_SPLIT ? 1 : 0;
+    L.lagrange = lagrange ? 1 : 0;
     L.seg_max = plan.seg_max;
     L.interleave = h->interleave;
     L.coef = use_mom ? (const double *)(db + off_coef) : nullptr;

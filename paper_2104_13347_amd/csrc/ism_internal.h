@@ -47,7 +47,7 @@ struct alignas(16) LaunchDev {
     int32_t n_items;
     int32_t K;            // (fd_taps - 1) / 2
     int32_t order_mode;   // 0 index-L1, 1 reflections
-    int32_t reserved0;
+    int32_t lagrange;     // 1: the 7th-order Lagrange filter (taps n0-3..n0+4, n0 = floor(tau)), K = 4
     int32_t split32;      // 1: distance and delay split in FP32 (ablation)
     int32_t seg_max;      // largest s1 - s0 of any item (sizes LDS)
     int32_t interleave;   // enumeration order inside a column chunk (1: strided over columns)
@@ -56,6 +56,11 @@ struct alignas(16) LaunchDev {
 
 constexpr int kSegMaxLimit = 2048;  // largest supported segment (per-lane sums in registers)
 constexpr int kKMax = 127;          // largest half-length (255 taps)
+constexpr int kLagrangeTaps = 8;    // fd_taps value that selects the 7th-order Lagrange filter
+
+// Half-length of the symmetric tap window that holds the filter: (fd_taps - 1) / 2 for the
+// windowed sinc, 4 for the Lagrange filter (taps k = -3..4 about n0; tap -4 is zero).
+constexpr int half_length(int fd_taps) { return fd_taps == kLagrangeTaps ? 4 : (fd_taps - 1) / 2; }
 constexpr int kLutQ = 64;           // FP16 table steps per sample
 constexpr int kBufCap = 256;        // record ring (power of two)
 constexpr int kCols = 64;           // columns per enumeration chunk (one per lane)

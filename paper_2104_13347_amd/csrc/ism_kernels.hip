@@ -330,17 +330,21 @@ DEV ItemGeom item_geom(const LaunchDev *P, const ItemDev &it, int K)
     G.rir_len = R.rir_len;
     G.N = R.max_order;
     G.s0 = it.s0; G.s1 = it.s1; G.Sn = it.s1 - it.s0;
-    G.nlo = max(G.s0 - K, 0);
-    G.nhi = min(G.s1 - 1 + K, G.rir_len - 1 + K);
+    // taps k = kmin..kmax about n0 reach [s0, s1) for n0 in [s0 - kmax, s1 - 1 - kmin]
+    const int kmin = P->lagrange ? -3 : -K, kmax = P->lagrange ? 4 : K;
+    G.nlo = max(G.s0 - kmax, 0);
+    G.nhi = min(G.s1 - 1 - kmin, G.rir_len - 1 - kmin);
     G.rel = G.s0 - K;
     G.px0 = P->pow_tab + R.pow_offset;
     G.pz0 = G.px0 + 4 * R.pow_stride;
     G.pzL = G.pz0 + R.pow_stride;
     G.pow_stride = R.pow_stride;
     G.pmax = R.pow_stride - 1;
-    // distance shell of the records this segment needs (widened: every test below is exact)
-    const double dlo = fmax(0.0, ((double)G.nlo - 0.5) * cs / fs * (1.0 - 1e-12) - 1e-12);
-    const double dhi = ((double)G.nhi + 0.5) * cs / fs * (1.0 + 1e-12) + 1e-12;
+    // distance shell of the records this segment needs (widened: every test below is exact);
+    // n0 = floor(tau + half) puts tau in [n0 - half, n0 + 1 - half)
+    const double half = P->lagrange ? 0.0 : 0.5;
+    const double dlo = fmax(0.0, ((double)G.nlo - half) * cs / fs * (1.0 - 1e-12) - 1e-12);
+    const double dhi = ((double)G.nhi + 1.0 - half) * cs / fs * (1.0 + 1e-12) + 1e-12;
     G.dlo2 = dlo * dlo;
     G.dhi2 = dhi * dhi;
     // Fixed-point scale 2^e: no image is closer than the direct path and every
@@ -473,7 +477,7 @@ DEV double sqrt_normal(double a)
 // integer / fractional split.  Returns whether the record belongs to the item
 // (delay in [nlo, nhi], order within the limit).
 DEV bool image_eval(const ItemGeom &G, double rho2, int cord, int q, int w, int order_mode, double fs, double cs,
-                    double fsc, int split32, int &n0, double &fr, double &d)
+                    double fsc, int split32, double half, int &n0, double &fr, double &d)
 {
     bool ordok = true;
     if (G.N >= 0) {
@@ -485,21 +489,21 @@ DEV bool image_eval(const ItemGeom &G, double rho2, int cord, int q, int w, int 
     const double d2 = rho2 + dz * dz;
     d = sqrt_normal(d2);  // d2 >= (closest image distance)^2, far above 2^-767
     // tau = (d fs) / c as in the definition; d * (fs/c) differs by at most an
-    // ulp or two, which can change floor(tau + 1/2) only right at a rounding
+    // ulp or two, which can change floor(tau + half) only right at a rounding
     // boundary: there the exact quotient is taken
     double tau = d * fsc;
     {
-        const double h = tau + 0.5, fl = floor(h);
+        const double h = tau + half, fl = floor(h);
         if (h - fl < 1e-12 * h || (fl + 1.0) - h < 1e-12 * h) tau = d * fs / cs;
     }
-    const double n0d = floor(tau + 0.5);
+    const double n0d = floor(tau + half);
     n0 = (int)n0d;
     fr = tau - n0d;
     if (split32) {
         // ablation: the same split in FP32 arithmetic
         const float d2f = (float)rho2 + (float)dz * (float)dz;
         const float tauf = sqrtf(d2f) * (float)fs / (float)cs;
-        const float n0f = floorf(tauf + 0.5f);
+        const float n0f = floorf(tauf + (float)half);
         n0 = (int)n0f;
         fr = (double)(tauf - n0f);
     }
@@ -657,7 +661,8 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
                     const int w = S.iw[c * 4 + iv];
                     int n0;
                     double fr, d;
-                    valid = image_eval(G, S.crho2[c], S.cord[c], q, w, order_mode, fs, cs, fsc, split32, n0, fr, d);
+                    valid = image_eval(G, S.crho2[c], S.cord[c], q, w, order_mode, fs, cs, fsc, split32, 0.5, n0, fr,
+                                       d);
                     if (valid) {
                         const int ez0 = min(abs(q - w), G.pmax), ezL = min(abs(q), G.pmax);
                         const double B = (S.cbxy[c] * G.pz0[ez0]) * G.pzL[ezL];
@@ -820,6 +825,9 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
     const double fsc = fs / cs;
     const int order_mode = P->order_mode;
     const int split32 = P->split32;
+    const bool lagrange = P->lagrange != 0;
+    const double half = lagrange ? 0.0 : 0.5, xoff = lagrange ? 1.0 : 0.0;
+    const int kmin = lagrange ? -3 : -K, kmax = lagrange ? 4 : K;
     uint64_t n_taps = 0;
     uint32_t n_rec = 0, n_img = 0;
     const int nU = kMom * ustride;
@@ -900,18 +908,19 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                 ++n_img;
                 int n0;
                 double fr, d;
-                if (!image_eval(G, mc.rho2, cu.w, q, w, order_mode, fs, cs, fsc, split32, n0, fr, d))
+                if (!image_eval(G, mc.rho2, cu.w, q, w, order_mode, fs, cs, fsc, split32, half, n0, fr, d))
                     continue;
                 const int qc = min(max(q, 1 - kPowCap), kPowCap - 1);  // |q| <= pmax already
                 const double B = mc.bxy * S.pzz[2 * (qc + kPowCap) + w];
                 ++n_rec;
-                // taps landing in [s0, s1): 2K + 1 minus those cut at either end (n0 in [nlo, nhi])
-                item_taps += (uint32_t)(2 * K + 1 - max(0, G.s0 + K - n0) - max(0, n0 + K + 1 - G.s1));
+                // taps landing in [s0, s1): kmax - kmin + 1 minus those cut at either end
+                item_taps += (uint32_t)(kmax - kmin + 1 - max(0, G.s0 - kmin - n0) - max(0, n0 + kmax + 1 - G.s1));
                 // g 2^e = B / (4 pi d) 2^e in FP64 (reciprocal with one Newton step)
                 double rd = __builtin_amdgcn_rcp(d);
                 rd = fma(fma(-d, rd, 1.0), rd, rd);
                 const double gs = B * (rd * gk);
-                const double xx = 2.0 * fr, x2 = 2.0 * xx;
+                // Chebyshev variable: x = 2f for f in [-1/2, 1/2) (sinc), 2f - 1 for f in [0, 1)
+                const double xx = fma(2.0, fr, -xoff), x2 = 2.0 * xx;
                 long long *u = S.U + mpad(n0 - G.rel);
                 long long *u2 = u + 5 * ustride;  // channels 5.. from a second base (16-bit offsets)
                 double tp = 1.0, tc = xx;

@@ -57,7 +57,8 @@ def _call(h, **kw):
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(fd_taps=8), ism.ISM_EINVAL),
+    (dict(fd_taps=6), ism.ISM_EINVAL),
+    (dict(fd_taps=8, precision=4), ism.ISM_EINVAL),
     (dict(fd_taps=0), ism.ISM_EINVAL),
     (dict(fd_taps=257), ism.ISM_EINVAL),
     (dict(rir_len=0), ism.ISM_EINVAL),

@@ -199,3 +199,37 @@ def test_edge_cases(H, torch_cuda):
     # empty batch is a no-op
     e = scenes.pack([], 16000.0, 343.0, 81, 0, "empty")
     assert H.lib.ism_rir_batch(H.h, 0, None, None, 16000.0, 343.0, 81, 0, 0, None, None) == 0
+
+
+# ------------------------------------------------------------------ the paper's Lagrange filter
+@pytest.mark.parametrize("mode", [ism.ORDER_INDEX_L1, ism.ORDER_REFLECTIONS])
+@pytest.mark.parametrize("seg_len", [64, 1024, 2048])
+def test_c0_lagrange(H, mode, seg_len):
+    b = scenes.c0()
+    b["order_mode"] = mode
+    b["fd_taps"] = 8
+    _say(f"c0 lagrange mode={mode} seg_len={seg_len}")
+    gpu, cnt = run(H, b, seg_len=seg_len)
+    ref, taps, rirs = oracle_batch(b)
+    err = rel_errors(b, gpu, ref, rirs)
+    _say(f"c0 lagrange max err {err.max():.3e}")
+    assert err.max() <= TOL_FP32, err
+    assert cnt["taps"] == taps
+
+
+def test_c1_lagrange_sixteen_rooms_and_tiny_rooms(H):
+    b = scenes.subset(scenes.c1(), range(16))
+    b["fd_taps"] = 8
+    _say("c1 16 rooms lagrange")
+    gpu, cnt = run(H, b)
+    ref, taps, rirs = oracle_batch(b)
+    err = rel_errors(b, gpu, ref, rirs)
+    _say(f"c1 lagrange max err {err.max():.3e}")
+    assert err.max() <= TOL_FP32
+    assert cnt["taps"] == taps
+    t = scenes.tiny(seed=77, n_rooms=3, rir_len=300, M=3, taps=9)
+    t["fd_taps"] = 8
+    gpu, cnt = run(H, t, seg_len=64)
+    ref, taps, rirs = oracle_batch(t)
+    assert rel_errors(t, gpu, ref, rirs).max() <= TOL_FP32
+    assert cnt["taps"] == taps
