@@ -278,6 +278,18 @@ def main():
         res["taps_per_s_plain"] = taps / plain_s
         res["batched_vs_plain"] = rirs_batched / res["rirs_per_s_plain"]
 
+    # ablation: the same batch with every tap evaluated (per-tap kernel)
+    if not args.no_ablation and args.precision == 0:
+        ms = _time_it(torch, lambda: H.rir_batch(batch, precision=ism.PREC_FP32_DIRECT, out=out, rooms=rooms), reps=3)
+        res["ablation_fp32_direct"] = {"ms": ms, "taps_per_s": H.last_counts()["taps"] / (ms / 1e3),
+                                       "kernel": "ism_segments"}
+        # the paper's own 7th-order Lagrange filter (8 taps) on the same batch
+        lb = dict(batch)
+        lb["fd_taps"] = 8
+        ms = _time_it(torch, lambda: H.rir_batch(lb, precision=ism.PREC_FP32, out=out, rooms=rooms), reps=3)
+        res["lagrange_fd8"] = {"ms": ms, "taps_per_s": H.last_counts()["taps"] / (ms / 1e3),
+                               "rirs_per_s": n_rirs / (ms / 1e3), "kernel": "ism_moments"}
+
     # single-RIR latency (the 5x4x3 m order-10 room, one mic, 4096 samples), launch to completion
     c0 = scenes.c0()
     lat = []
