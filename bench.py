@@ -112,6 +112,28 @@ def bench_c3(H, torch):
     return res
 
 
+def bench_paper(H, torch):
+    """The paper's room dataset: 7 x 10 x 3.7 m, RT 0.5 s, 48 000 torus source positions x the
+    7-microphone array = 336 000 RIRs of 8000 samples (16 kHz), in one batched launch, with the
+    paper's 7th-order Lagrange filter and with the 81-tap windowed sinc."""
+    from paper_2104_13347_amd import ism, scenes
+    b = scenes.paper_room1()
+    rooms = ism.rooms_array(b)
+    out = torch.empty(int(b["out_size"]), dtype=torch.float32, device="cuda")
+    n_rirs = int(b["n_mics"].sum())
+    res = {"workload": "paper room 1: 7x10x3.7 m, RT 0.5 s, 48000 sources x 7 mics = 336000 RIRs x 8000 "
+                       "samples at 16 kHz", "rirs": n_rirs, "output_bytes": int(b["out_size"]) * 4}
+    for taps, name in [(8, "lagrange_fd8"), (81, "sinc_fd81")]:
+        b["fd_taps"] = taps
+        ms = _time_it(torch, lambda: H.rir_batch(b, precision=ism.PREC_FP32, out=out, rooms=rooms), reps=2)
+        cnt = H.last_counts()
+        res[name] = {"ms": ms, "rirs_per_s": n_rirs / (ms / 1e3), "taps_per_s": cnt["taps"] / (ms / 1e3),
+                     "records": cnt["records"], "taps": cnt["taps"]}
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_c4(H, torch):
     """256 rooms (1024-room distribution, seed 2108), 8 mics: RIR batch on the GPU, then convolution
     with 1 s white-noise sources and sensor noise at SNR U[0,30] dB."""
@@ -182,8 +204,9 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the serving, precision and convolution sections")
-    ap.add_argument("--extras", default="c3,c4,c2",
-                    help="comma list of extra sections to run: c3 precision, c4 convolution, c2 serving")
+    ap.add_argument("--extras", default="c3,c4,paper,c2",
+                    help="comma list of extra sections to run: c3 precision, c4 convolution, paper (the "
+                         "paper's 336 000-RIR room dataset), c2 serving")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="run only a plain device copy of this many bytes (HBM counter calibration)")
@@ -311,6 +334,8 @@ def main():
             res["extras"]["c3_precision"] = bench_c3(H, torch)
         if "c4" in extras:
             res["extras"]["c4_convolution"] = bench_c4(H, torch)
+        if "paper" in extras:
+            res["extras"]["paper_room1_dataset"] = bench_paper(H, torch)
         if "c2" in extras:
             res["extras"]["c2_serving"] = bench_c2(torch, args.serve_requests)
     H.close()

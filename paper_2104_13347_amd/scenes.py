@@ -18,7 +18,11 @@ SNR), at the sizes of the five benchmark configurations:
 * ``c3``  64 rooms 20x15x8 m, per-wall beta U[0.85,0.95], 48 kHz, 72000
           samples, 16 mics on a Fibonacci sphere r = 10 cm, 127 taps;
 * ``c4``  256 rooms of the c1 distribution (8 mics), 1 s N(0,1) sources,
-          SNR U[0,30] dB.
+          SNR U[0,30] dB;
+* ``paper_room1``  the paper's first training room: 7 x 10 x 3.7 m, RT 0.5 s,
+          the 7-microphone array (centre + 6 on an 8 cm circle) at (4, 6, 1.5) m,
+          sources uniform in the torus of central radius 2 m, +-0.5 m radially and
+          +-7 degrees in elevation around it (48 000 positions per room).
 
 Seeds default to 2104 + config index.  The paper's recordings are not
 available; white-noise sources stand in for them.
@@ -106,6 +110,41 @@ def subset(batch, idx):
                       "rir_len": int(batch["rir_len"][i]), "rt60": float(batch["rt60"][i])})
     return pack(rooms, batch["fs"], batch["c"], batch["fd_taps"], batch["order_mode"],
                 batch["name"] + "-subset")
+
+
+def uma8_array(center, rot=0.0):
+    """The 7-microphone array of the paper: one at the centre, six evenly spread on a circle
+    of 8 cm diameter, horizontal."""
+    ring = circle_array(center, 6, 0.04, rot)
+    return np.concatenate([np.asarray(center, dtype=np.float64)[None, :], ring])
+
+
+def torus_sources(rng, center, n, R=2.0, dR=0.5, dphi_deg=7.0):
+    """Positions uniform in volume in the torus around ``center``: distance R +- dR from it,
+    any azimuth, elevation within +-dphi (spherical volume element r^2 cos(phi))."""
+    r = np.cbrt(rng.uniform((R - dR) ** 3, (R + dR) ** 3, n))
+    th = rng.uniform(0.0, 2.0 * math.pi, n)
+    s = math.sin(math.radians(dphi_deg))
+    ph = np.arcsin(rng.uniform(-s, s, n))
+    return np.asarray(center) + np.stack([r * np.cos(ph) * np.cos(th), r * np.cos(ph) * np.sin(th),
+                                          r * np.sin(ph)], axis=1)
+
+
+def paper_room1(n_sources=48000, seed=2109, fs=16000.0, c=C_SOUND, fd_taps=8):
+    """The paper's first training room (section II.A and the dataset description): every source
+    position is one entry of the batch, with the 7-microphone array; RIRs up to the
+    reverberation time.  The paper names no sampling rate: 16 kHz here.  Reflection
+    coefficients from Sabine's formula (the paper fits them with Lehmann's method)."""
+    rng = np.random.default_rng(seed)
+    L = np.array([7.0, 10.0, 3.7])
+    rt = 0.5
+    beta, _ = sabine_beta(L, rt, c)
+    center = np.array([4.0, 6.0, 1.5])
+    mics = uma8_array(center)
+    src = torus_sources(rng, center, n_sources)
+    rooms = [{"L": L, "beta": np.full(6, float(beta)), "src": src[i], "mics": mics, "max_order": -1,
+              "rir_len": int(round(rt * fs)), "rt60": rt} for i in range(n_sources)]
+    return pack(rooms, fs, c, fd_taps, ORDER_INDEX_L1, "paper_room1")
 
 
 def c0():

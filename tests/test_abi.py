@@ -122,3 +122,18 @@ def test_no_device_fails_loudly(handle):
     rc = _call(handle)
     assert rc == ism.ISM_EDEVICE
     assert "device" in handle.lib.ism_last_error(handle.h).decode()
+
+
+def test_paper_room_scene_geometry():
+    b = scenes.paper_room1(n_sources=2000, seed=5)
+    c = np.array([4.0, 6.0, 1.5])
+    r = np.linalg.norm(b["src"] - c, axis=1)
+    assert r.min() >= 1.5 and r.max() <= 2.5
+    elev = np.degrees(np.arcsin((b["src"][:, 2] - c[2]) / r))
+    assert np.abs(elev).max() <= 7.0 + 1e-9
+    # uniform in volume: the median radius solves r^3 = ((1.5^3 + 2.5^3) / 2)
+    assert abs(np.median(r) - ((1.5 ** 3 + 2.5 ** 3) / 2) ** (1 / 3)) < 0.03
+    m = b["mics"][:7]
+    assert np.allclose(m[0], c)
+    assert np.allclose(np.linalg.norm(m[1:] - c, axis=1), 0.04)
+    assert b["rir_len"][0] == 8000 and b["fd_taps"] == 8 and len(b["rir_len"]) == 2000

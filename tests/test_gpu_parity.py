@@ -233,3 +233,17 @@ def test_c1_lagrange_sixteen_rooms_and_tiny_rooms(H):
     ref, taps, rirs = oracle_batch(t)
     assert rel_errors(t, gpu, ref, rirs).max() <= TOL_FP32
     assert cnt["taps"] == taps
+
+
+def test_paper_room_dataset_sources(H):
+    # the paper's room (7 x 10 x 3.7 m, RT 0.5 s, 7-microphone array, torus sources): three
+    # source positions, both filters, against the oracle
+    for taps in (8, 81):
+        b = scenes.paper_room1(n_sources=3, fd_taps=taps)
+        _say(f"paper room taps={taps}")
+        gpu, cnt = run(H, b)
+        ref, ntaps, rirs = oracle_batch(b)
+        err = rel_errors(b, gpu, ref, rirs)
+        _say(f"paper room taps={taps} max err {err.max():.3e}")
+        assert err.max() <= TOL_FP32
+        assert cnt["taps"] == ntaps
