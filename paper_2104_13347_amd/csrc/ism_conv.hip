@@ -102,7 +102,18 @@ __global__ __launch_bounds__(64, 4) void conv_mfma(const float *__restrict__ x, 
     __shared__ __attribute__((aligned(16))) uint16_t xring[2 * XR];
     __shared__ __attribute__((aligned(16))) uint16_t ring[16 * CM * CRS];
     const int lane = threadIdx.x;
-    const int r = rooms[blockIdx.y].order, tile = blockIdx.x;
+    // Workgroups are dealt to the 8 XCDs round-robin in launch order, and each XCD has
+    // its own L2.  With the room count a multiple of 8, the k-th workgroup on XCD x takes
+    // tile k mod T of room row x + 8 (k / T): all tiles of a room share one L2, and the
+    // XCDs still take the rooms longest-first.
+    int row = blockIdx.y, tile = blockIdx.x;
+    if ((gridDim.y & 7) == 0) {
+        const int L = blockIdx.x + gridDim.x * blockIdx.y;
+        const int x = L & 7, k = L >> 3;
+        row = x + 8 * (k / (int)gridDim.x);
+        tile = k % (int)gridDim.x;
+    }
+    const int r = rooms[row].order;
     const int t0 = tile * CG;
     const ConvRoom R = rooms[r];
     const int nb = R.nb;

@@ -247,3 +247,19 @@ def test_paper_room_dataset_sources(H):
         _say(f"paper room taps={taps} max err {err.max():.3e}")
         assert err.max() <= TOL_FP32
         assert cnt["taps"] == ntaps
+
+
+def test_long_rir_in_a_thin_room_uses_the_per_tap_kernel(H, torch_cuda):
+    # wall exponents up to about 130 (a 0.3 m room height, 3500 samples): the moment kernel
+    # holds at most 128 in LDS, so the windowed sinc falls back to the per-tap kernel and the
+    # Lagrange filter, which has no per-tap kernel, is refused
+    torch = torch_cuda
+    L, beta, s, m = [3.0, 3.0, 0.3], [0.6] * 6, [1.0, 1.2, 0.1], [[2.1, 1.7, 0.2]]
+    out = H.rir(L, beta, s, m, 16000.0, 343.0, -1, 3500, 81)
+    torch.cuda.synchronize()
+    ref, st = oracle.rir(L, beta, s, m[0], 16000.0, 343.0, -1, 0, 3500, 81)
+    got = out.cpu().numpy()[0]
+    assert np.max(np.abs(got - ref)) <= TOL_FP32 * np.max(np.abs(ref))
+    assert H.last_counts()["taps"] == st["taps"]
+    with pytest.raises(ism.IsmError):
+        H.rir(L, beta, s, m, 16000.0, 343.0, -1, 3500, 8)
