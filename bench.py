@@ -41,9 +41,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch from the committed counter summary of `kernel` on the 1024-room
-    batch, if it was taken on the current kernel source; else None."""
+def committed_counters(kernel):
+    """The committed counter summary of `kernel` on the 1024-room batch, if it was taken on
+    the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_c1_traffic.json")
     if not os.path.exists(path):
         return None
@@ -53,7 +53,13 @@ def measured_traffic(kernel):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, or None."""
+    d = committed_counters(kernel)
+    return d.get("hbm_bytes_per_launch") if d else None
 
 
 def cpu_baseline(batch, budget_s=12.0):
@@ -280,6 +286,15 @@ def main():
                        "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
                        "kernel": kernel, "launch_ms": k_ms,
                        "flops_per_tap": FLOPS_PER_TAP, "taps_per_launch": taps}
+    # what the kernel executes (committed counters of the same source), beside the nominal rate
+    cc = committed_counters(kernel)
+    if cc and "executed" in cc:
+        ex = cc["executed"]
+        res["roofline"]["executed"] = {
+            "fp64_tflops": ex["fp64_flops_per_launch"] / (k_ms / 1e3) / 1e12, "fp64_peak_tflops": 78.6,
+            "valu_issue_fraction": ex["valu_issue_fraction"],
+            "note": "FP64 flops counted by rocprofv3 per launch / this run's launch time; VALU issue "
+                    "fraction = VALU wave-instructions x 4 cycles / (1024 SIMDs x kernel cycles)"}
 
     # plain: the same kernels launched once per room, host loop, one stream
     if not args.no_plain:
