@@ -84,7 +84,7 @@ inline int mom_lds_bytes(int K)
 {
     const int cols = 64 * kMomSetupWaves;
     int bytes = kMom * mom_ustride(K) * 8;
-    bytes += cols * 48 + (cols + 4) * 4 + kMomSetupWaves * 4 + 16;  // column records, prefix
+    bytes += cols * 48 + kMomSetupWaves * 4 + 16;                  // column records
     bytes += 2 * 4 * kPowCap * 8;                                  // z and x/y wall powers
     return bytes;
 }

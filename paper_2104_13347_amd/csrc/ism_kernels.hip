@@ -742,23 +742,40 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
 //    words apart, hit distinct banks.  The waves' partial outputs are summed in a
 //    fixed order and stored once per sample.
 constexpr int kMomThreads = 64 * kMomWaves;
+static_assert(kMomSetupWaves == kMomWaves, "every wave sets up 64 columns of a batch");
 constexpr int kMomCols = 64 * kMomSetupWaves;  // columns per enumeration batch
 
 DEV int mpad(int i) { return i + (i >> 4); }
 
 // One column of an enumeration batch: squared horizontal distance, x/y wall-power
-// product, running image counts of its intervals (with the x/y reflection order in the
-// last slot) and each interval's first z index times 2 plus its parity.
+// product, the column's images [start, end) in the batch's flattened order, and its
+// intervals (non-empty ones first) as 16-bit fields: lengths, and first z index times 2
+// plus parity.  16 bits hold them: with wall exponents below kPowCap, |q| < kPowCap and
+// an interval has fewer than 2 kPowCap + 1 images.
 struct alignas(16) MomCol {
     double rho2, bxy;
-    int4 cum;  // cum[0..2] = images in intervals 0, 0..1, 0..2; .w = x/y order
-    int4 qw;
+    int32_t start, end;
+    uint32_t len01, len23;  // lengths of intervals 0, 1 (low, high half) and 2, 3
+    int32_t qw01, qw23;     // 2 q0 + w of intervals 0, 1 and 2, 3 (signed halves)
+    int32_t cord;           // x/y part of the reflection order
+    int32_t pad;
 };
+
+DEV int col_len(const MomCol &m, int iv)
+{
+    const uint32_t v = iv < 2 ? m.len01 : m.len23;
+    return (int)((v >> (16 * (iv & 1))) & 0xFFFFu);
+}
+
+DEV int col_qw(const MomCol &m, int iv)
+{
+    const int32_t v = iv < 2 ? m.qw01 : m.qw23;
+    return (iv & 1) ? (v >> 16) : (int32_t)(int16_t)(v & 0xFFFF);
+}
 
 struct MomLds {
     long long *U;          // kMom x ustride bins (int64, then FP64 in place, then partial outputs)
     MomCol *col;           // [kMomCols]
-    int32_t *gcoff;        // [kMomCols + 1] exclusive prefix of the images of the batch's columns
     int32_t *wtot;         // [kMomSetupWaves] images of each setup wave's chunk
     double *pzz;           // [4 kPowCap] z wall powers by (2 q + w), q in (-kPowCap, kPowCap)
     double *pxy;           // [4 kPowCap] x0, xL, y0, yL wall powers, kPowCap apart
@@ -773,7 +790,6 @@ DEV MomLds mom_carve(char *base, int K)
     s.col = (MomCol *)p; p += kMomCols * sizeof(MomCol);
     s.pzz = (double *)p; p += 4 * kPowCap * 8;
     s.pxy = (double *)p; p += 4 * kPowCap * 8;
-    s.gcoff = (int32_t *)p; p += (kMomCols + 4) * 4;
     s.wtot = (int32_t *)p; p += kMomSetupWaves * 4;
     s.item = (int32_t *)p;
     return s;
@@ -856,85 +872,104 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         // ---- records: moments into the delay bins
         for (int cb = 0; cb < G.ncols; cb += kMomCols) {
             const int gc = wave * 64 + lane;
-            int off = 0;
-            if (wave < kMomSetupWaves) {
-                const Column C = column_setup(G, cb + gc, order_mode, S.pxy, kPowCap);
-                const int ctot = C.len[0] + C.len[1] + C.len[2] + C.len[3];
-                int T;
-                off = wave_excl_scan(ctot, T);
-                MomCol mc;
-                mc.rho2 = C.rho2;
-                mc.bxy = C.bxy;
-                mc.cum = make_int4(C.len[0], C.len[0] + C.len[1], C.len[0] + C.len[1] + C.len[2], C.ord);
-                mc.qw = make_int4(2 * C.q0[0] + C.wv[0], 2 * C.q0[1] + C.wv[1], 2 * C.q0[2] + C.wv[2],
-                                  2 * C.q0[3] + C.wv[3]);
-                S.col[gc] = mc;
-                if (lane == 0) S.wtot[wave] = T;
-            }
+            const Column C = column_setup(G, cb + gc, order_mode, S.pxy, kPowCap);
+            const int ctot = C.len[0] + C.len[1] + C.len[2] + C.len[3];
+            int T;
+            const int off = wave_excl_scan(ctot, T);
+            if (lane == 0) S.wtot[wave] = T;
             __syncthreads();
             int base = 0, Tall = 0;
 #pragma unroll
-            for (int w = 0; w < kMomSetupWaves; ++w) {
+            for (int w = 0; w < kMomWaves; ++w) {
                 const int t = S.wtot[w];
                 base += w < wave ? t : 0;
                 Tall += t;
             }
-            if (wave < kMomSetupWaves) S.gcoff[gc] = base + off;
-            if (tid == 0) S.gcoff[kMomCols] = Tall;
+            {
+                MomCol mc;
+                mc.rho2 = C.rho2;
+                mc.bxy = C.bxy;
+                mc.start = base + off;
+                mc.end = base + off + ctot;
+                mc.len01 = (uint32_t)C.len[0] | ((uint32_t)C.len[1] << 16);
+                mc.len23 = (uint32_t)C.len[2] | ((uint32_t)C.len[3] << 16);
+                mc.qw01 = (int32_t)(((uint32_t)(2 * C.q0[0] + C.wv[0]) & 0xFFFFu) | ((uint32_t)(2 * C.q0[1] + C.wv[1]) << 16));
+                mc.qw23 = (int32_t)(((uint32_t)(2 * C.q0[2] + C.wv[2]) & 0xFFFFu) | ((uint32_t)(2 * C.q0[3] + C.wv[3]) << 16));
+                mc.cord = C.ord;
+                mc.pad = 0;
+                S.col[gc] = mc;
+            }
             __syncthreads();
 
-            // thread t takes the images [t n, (t + 1) n) of the batch: consecutive
-            // lanes sit in different columns, so their delays rarely coincide
+            // thread t takes the images [t n, (t + 1) n) of the batch: consecutive lanes
+            // sit in different columns, so their delays rarely coincide.  The walk state
+            // (column record, interval, z index, images left in the interval) stays in
+            // registers; the next record is read only when the column ends.
             const int n = (Tall + kMomThreads - 1) / kMomThreads;
             int x = tid * n;
             const int xe = min(x + n, Tall);
-            int c = 0;
             if (x < xe) {
+                int c = 0;
 #pragma unroll
                 for (int st = kMomCols / 2; st >= 1; st >>= 1)
-                    if (S.gcoff[c + st] <= x) c += st;
-            }
-            for (; x < xe; ++x) {
-                while (S.gcoff[c + 1] <= x) ++c;
-                const int loc = x - S.gcoff[c];
-                const MomCol &mc = S.col[c];
-                const int4 cu = mc.cum;
-                const int4 qw = mc.qw;
-                const int iv = (loc >= cu.x) + (loc >= cu.y) + (loc >= cu.z);
-                const int before = iv == 0 ? 0 : iv == 1 ? cu.x : iv == 2 ? cu.y : cu.z;
-                const int qwv = iv == 0 ? qw.x : iv == 1 ? qw.y : iv == 2 ? qw.z : qw.w;
-                const int q = (qwv >> 1) + (loc - before);
-                const int w = qwv & 1;
-                ++n_img;
-                int n0;
-                double fr, d;
-                if (!image_eval(G, mc.rho2, cu.w, q, w, order_mode, fs, cs, fsc, split32, half, n0, fr, d))
-                    continue;
-                const int qc = min(max(q, 1 - kPowCap), kPowCap - 1);  // |q| <= pmax already
-                const double B = mc.bxy * S.pzz[2 * (qc + kPowCap) + w];
-                ++n_rec;
-                // taps landing in [s0, s1): kmax - kmin + 1 minus those cut at either end
-                item_taps += (uint32_t)(kmax - kmin + 1 - max(0, G.s0 - kmin - n0) - max(0, n0 + kmax + 1 - G.s1));
-                // g 2^e = B / (4 pi d) 2^e in FP64 (reciprocal with one Newton step)
-                double rd = __builtin_amdgcn_rcp(d);
-                rd = fma(fma(-d, rd, 1.0), rd, rd);
-                const double gs = B * (rd * gk);
-                // Chebyshev variable: x = 2f for f in [-1/2, 1/2) (sinc), 2f - 1 for f in [0, 1)
-                const double xx = fma(2.0, fr, -xoff), x2 = 2.0 * xx;
-                long long *u = S.U + mpad(n0 - G.rel);
-                long long *u2 = u + 5 * ustride;  // channels 5.. from a second base (16-bit offsets)
-                double tp = 1.0, tc = xx;
-                lds_add_i64(u, gs);
-                lds_add_i64(u + ustride, gs * xx);
+                    if (S.col[c + st].start <= x) c += st;
+                MomCol mc = S.col[c];
+                int loc = x - mc.start, iv = 0;
 #pragma unroll
-                for (int m = 2; m < kMom; ++m) {
-                    const double tn = fma(x2, tc, -tp);
-                    lds_add_i64(m < 5 ? u + m * ustride : u2 + (m - 5) * ustride, gs * tn);
-                    tp = tc;
-                    tc = tn;
+                for (int i = 0; i < 3; ++i) {
+                    const int l = col_len(mc, iv);
+                    if (loc >= l) { loc -= l; ++iv; }
+                }
+                int qwv = col_qw(mc, iv);
+                int q = (qwv >> 1) + loc, w = qwv & 1, rem = col_len(mc, iv) - loc;
+                for (;;) {
+                    ++n_img;
+                    int n0;
+                    double fr, d;
+                    if (image_eval(G, mc.rho2, mc.cord, q, w, order_mode, fs, cs, fsc, split32, half, n0, fr, d)) {
+                        const int qc = min(max(q, 1 - kPowCap), kPowCap - 1);  // |q| <= pmax already
+                        const double B = mc.bxy * S.pzz[2 * (qc + kPowCap) + w];
+                        ++n_rec;
+                        // taps landing in [s0, s1): kmax - kmin + 1 minus those cut at either end
+                        item_taps += (uint32_t)(kmax - kmin + 1 - max(0, G.s0 - kmin - n0) -
+                                                max(0, n0 + kmax + 1 - G.s1));
+                        // g 2^e = B / (4 pi d) 2^e in FP64 (reciprocal with one Newton step)
+                        double rd = __builtin_amdgcn_rcp(d);
+                        rd = fma(fma(-d, rd, 1.0), rd, rd);
+                        const double gs = B * (rd * gk);
+                        // Chebyshev variable: x = 2f for f in [-1/2, 1/2) (sinc), 2f - 1 for f in [0, 1)
+                        const double xx = fma(2.0, fr, -xoff), x2 = 2.0 * xx;
+                        long long *u = S.U + mpad(n0 - G.rel);
+                        long long *u2 = u + 5 * ustride;  // channels 5.. from a second base (16-bit offsets)
+                        double tp = 1.0, tc = xx;
+                        lds_add_i64(u, gs);
+                        lds_add_i64(u + ustride, gs * xx);
+#pragma unroll
+                        for (int m = 2; m < kMom; ++m) {
+                            const double tn = fma(x2, tc, -tp);
+                            lds_add_i64(m < 5 ? u + m * ustride : u2 + (m - 5) * ustride, gs * tn);
+                            tp = tc;
+                            tc = tn;
+                        }
+                    }
+                    if (++x >= xe) break;
+                    ++q;
+                    if (--rem == 0) {  // next non-empty interval, in this column or a later one
+                        ++iv;
+                        int l = iv < 4 ? col_len(mc, iv) : 0;
+                        while (l == 0) {
+                            mc = S.col[++c];
+                            iv = 0;
+                            l = col_len(mc, 0);
+                        }
+                        qwv = col_qw(mc, iv);
+                        q = qwv >> 1;
+                        w = qwv & 1;
+                        rem = l;
+                    }
                 }
             }
-            __syncthreads();  // the batch's column tables are rewritten next
+            __syncthreads();  // the batch's column records are rewritten next
         }
 
         n_taps += item_taps;
