@@ -209,7 +209,9 @@ static int pow_stride_for(const ism_room &r, double fs, double c, int K)
     if (r.max_order >= 0) e = (long)r.max_order + 4;
     else {
         double dmax = ((double)r.rir_len - 1.0 + K + 0.5) * c / fs;
-        e = (long)std::ceil(dmax / (2.0 * Lmin)) + 4;
+        const double q = std::ceil(dmax / (2.0 * Lmin));
+        if (!(q < (double)(1L << 22))) return 1 << 22;  // rejected by the caller
+        e = (long)q + 4;
     }
     return (int)std::min<long>(e + 1, 1L << 22);
 }
@@ -249,6 +251,15 @@ int ism_build_plan(ism_handle *h, int n_rooms, const ism_room *rooms, const doub
         d.mic_offset = r.mic_offset;
         d.out_offset = r.out_offset;
         d.pow_stride = pow_stride_for(r, fs, c, K);
+        {   // image columns of one item (the kernels index them in 32 bits, below 2^24)
+            const double dmax = r.max_order >= 0 ? 2.0 * (r.max_order + 2) * std::max(r.L[0], r.L[1])
+                                                 : ((double)r.rir_len + K + 0.5) * c / fs;
+            const double cols = (2.0 * dmax / r.L[0] + 5.0) * (2.0 * dmax / r.L[1] + 5.0);
+            if (!(cols < 16777216.0) || d.pow_stride >= (1 << 22)) {
+                ism_set_error(h, "room %d: too many images for its RIR length (room too small or RIR too long)", i);
+                return ISM_EINVAL;
+            }
+        }
         if (pow_total + 6LL * d.pow_stride > (1LL << 30)) {
             ism_set_error(h, "wall-power tables exceed the size limit");
             return ISM_ENOMEM;

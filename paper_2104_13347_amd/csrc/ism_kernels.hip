@@ -301,7 +301,6 @@ DEV Lds carve(char *base, int seg_max, int K, int variant)
 
 extern __shared__ __attribute__((aligned(16))) char ism_lds[];
 
-DEV long iabs(long a) { return a < 0 ? -a : a; }
 
 // ---------------------------------------------------------------- item geometry
 // Everything about one work item (room, microphone, output segment [s0, s1)) that the
@@ -310,7 +309,8 @@ struct ItemGeom {
     double Lx, Ly, Lz, sx, sy, sz, rx, ry, rz;
     double dlo2, dhi2;            // squared distance shell of the item's records
     const double *px0, *pz0, *pzL;
-    long alo, blo;                // first (x, y) image column indices
+    int alo, blo;                 // first (x, y) image column indices
+    float inv_nb;                 // 1 / nb
     int pow_stride, pmax;
     int rir_len, N, s0, s1, Sn;
     int nlo, nhi;                 // record delays n0 in [nlo, nhi] can reach the segment
@@ -365,10 +365,11 @@ DEV ItemGeom item_geom(const LaunchDev *P, const ItemDev &it, int K)
         alo = max(alo, -lim); ahi = min(ahi, lim);
         blo = max(blo, -lim); bhi = min(bhi, lim);
     }
-    G.alo = alo;
-    G.blo = blo;
+    G.alo = (int)alo;
+    G.blo = (int)blo;
     G.nb = (int)(bhi - blo + 1);
     G.ncols = (int)(ahi - alo + 1) * G.nb;
+    G.inv_nb = 1.0f / (float)G.nb;
     return G;
 }
 
@@ -393,58 +394,60 @@ DEV Column column_setup(const ItemGeom &G, int ci, int order_mode, const double 
     C.ord = 0;
     if (ci >= G.ncols) return C;
     const int N = G.N;
-    const int ca = ci / G.nb;
-    const long a = G.alo + ca, b = G.blo + (ci - ca * G.nb);
-    const int u = (int)(a & 1), v = (int)(b & 1);
-    const long n = (a + u) >> 1, l = (b + v) >> 1;
+    // ci / nb from a float reciprocal, corrected to the exact quotient (ci < 2^24)
+    int ca = (int)((float)ci * G.inv_nb);
+    ca -= ca * G.nb > ci;
+    ca += (ca + 1) * G.nb <= ci;
+    const int a = G.alo + ca, b = G.blo + (ci - ca * G.nb);
+    const int u = a & 1, v = b & 1;
+    const int n = (a + u) >> 1, l = (b + v) >> 1;
     const double X = (u ? -G.sx : G.sx) + (2.0 * (double)n) * G.Lx;
     const double Y = (v ? -G.sy : G.sy) + (2.0 * (double)l) * G.Ly;
     const double dx = X - G.rx, dy = Y - G.ry;
     const double rho2 = dx * dx + dy * dy;
     C.rho2 = rho2;
-    long qlim_lo = -(1L << 40), qlim_hi = (1L << 40);
+    int qlim_lo = -(1 << 30), qlim_hi = 1 << 30;
     bool ok = rho2 < G.dhi2;
     int ordxy = 0;
     if (N >= 0) {
-        const long oxy = order_mode == 0 ? iabs(n) + iabs(l) : iabs(2 * n - u) + iabs(2 * l - v);
-        ordxy = (int)oxy;
-        if (oxy > N) ok = false;
+        ordxy = order_mode == 0 ? abs(n) + abs(l) : abs(2 * n - u) + abs(2 * l - v);
+        if (ordxy > N) ok = false;
     }
     C.ord = ordxy;
     if (!ok) return C;
-    const long pmax = G.pmax;
-    const int ex0 = (int)min(iabs(n - u), pmax), exL = (int)min(iabs(n), pmax);
-    const int ey0 = (int)min(iabs(l - v), pmax), eyL = (int)min(iabs(l), pmax);
+    const int pmax = G.pmax;
+    const int ex0 = min(abs(n - u), pmax), exL = min(abs(n), pmax);
+    const int ey0 = min(abs(l - v), pmax), eyL = min(abs(l), pmax);
     C.bxy = ((px[ex0] * px[ps + exL]) * px[2 * ps + ey0]) * px[3 * ps + eyL];
     const double zb = sqrt(G.dhi2 - rho2);
     const double za = G.dlo2 > rho2 ? sqrt(G.dlo2 - rho2) : 0.0;
     const double inv2L = 0.5 / G.Lz;
     int ni = 0;
     // interval slot ni (unrolled selects keep the slots in registers)
-    auto put = [&](long qq, long ll, int ww) {
+    auto put = [&](int qq, int ll, int ww) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            if (i == ni) { C.q0[i] = (int)qq; C.len[i] = (int)ll; C.wv[i] = ww; }
+            if (i == ni) { C.q0[i] = qq; C.len[i] = ll; C.wv[i] = ww; }
         ++ni;
     };
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
-        // dz = (+-sz + 2 q Lz) - rz
+        // dz = (+-sz + 2 q Lz) - rz; |q| stays far below 2^31 (wall exponents < 2^22, host)
         const double off = G.rz - (w ? -G.sz : G.sz);
-        long qlo = (long)ceil((off - zb) * inv2L - 1e-9);
-        long qhi = (long)floor((off + zb) * inv2L + 1e-9);
+        int qlo = (int)ceil((off - zb) * inv2L - 1e-9);
+        int qhi = (int)floor((off + zb) * inv2L + 1e-9);
         if (N >= 0) {
-            const long rem = N - ordxy;
+            const int rem = N - ordxy;
             if (order_mode == 0) { qlim_lo = -rem; qlim_hi = rem; }
             else { qlim_lo = (w - rem + 1) >> 1; qlim_hi = (w + rem) >> 1; }
             // (w - rem + 1) >> 1 = ceil((w - rem) / 2)
             qlo = max(qlo, qlim_lo); qhi = min(qhi, qlim_hi);
         }
         if (qlo > qhi) continue;
-        long hlo = 1, hhi = 0;  // empty hole
+        int hlo = 1, hhi = 0;  // empty hole
         if (za > 0.0) {
-            hlo = (long)ceil((off - za) * inv2L + 1e-9);
-            hhi = (long)floor((off + za) * inv2L - 1e-9);
+            hlo = (int)ceil((off - za) * inv2L + 1e-9);
+            hhi = (int)floor((off + za) * inv2L - 1e-9);
         }
         if (hlo <= hhi && hhi >= qlo && hlo <= qhi) {
             if (hlo > qlo) put(qlo, hlo - qlo, w);
@@ -743,6 +746,7 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
 //    fixed order and stored once per sample.
 constexpr int kMomThreads = 64 * kMomWaves;
 static_assert(kMomSetupWaves == kMomWaves, "every wave sets up 64 columns of a batch");
+static_assert(kMom < kMomWaves, "one wave without a filter channel fetches the next item");
 constexpr int kMomCols = 64 * kMomSetupWaves;  // columns per enumeration batch
 
 DEV int mpad(int i) { return i + (i >> 4); }
@@ -779,7 +783,7 @@ struct MomLds {
     int32_t *wtot;         // [kMomSetupWaves] images of each setup wave's chunk
     double *pzz;           // [4 kPowCap] z wall powers by (2 q + w), q in (-kPowCap, kPowCap)
     double *pxy;           // [4 kPowCap] x0, xL, y0, yL wall powers, kPowCap apart
-    int32_t *item;         // [1]
+    int32_t *item;         // [2] current and next item
 };
 
 DEV MomLds mom_carve(char *base, int K)
@@ -848,26 +852,40 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
     uint32_t n_rec = 0, n_img = 0;
     const int nU = kMom * ustride;
 
-    for (;;) {
-        if (tid == 0) S.item[0] = (int)atomicAdd(P->counter, 1u);
-        for (int i = tid; i < nU; i += kMomThreads) S.U[i] = 0;
-        __syncthreads();
-        const int item = uniform(S.item[0]);
+    // wall-power tables of the room of `item` into LDS, by `nthr` threads from `t0`:
+    // pzz[2 (q + kPowCap) + w] = beta_z0^|q - w| beta_zL^|q|; pxy = x0, xL, y0, yL powers,
+    // kPowCap apart (|q|, exponents <= pmax < kPowCap: pow_stride <= kPowCap on the host)
+    auto fill_tables = [&](int item, int t0, int nthr) {
+        const RoomDev &R = P->rooms[P->items[item].room];
+        const double *px = P->pow_tab + R.pow_offset;
+        const double *pz0 = px + 4 * R.pow_stride, *pzL = pz0 + R.pow_stride;
+        const int pmax = R.pow_stride - 1;
+        for (int i = t0; i < 4 * kPowCap; i += nthr) {
+            const int q = (i >> 1) - kPowCap, w = i & 1;
+            const int ez0 = min(abs(q - w), pmax), ezL = min(abs(q), pmax);
+            S.pzz[i] = pz0[ez0] * pzL[ezL];
+            const int wall = i / kPowCap, e = min(i % kPowCap, pmax);
+            S.pxy[i] = px[wall * R.pow_stride + e];
+        }
+    };
+    // The index of the current item alternates between S.item[0] and S.item[1]: the wave
+    // that has no filter channel fetches the next item and fills its tables while the
+    // others filter.
+    if (tid == 0) S.item[0] = (int)atomicAdd(P->counter, 1u);
+    __syncthreads();
+    {
+        const int first = uniform(S.item[0]);
+        if (first < P->n_items) fill_tables(first, tid, kMomThreads);
+    }
+    for (int iter = 0;; ++iter) {
+        const int item = uniform(S.item[iter & 1]);
         if (item >= P->n_items) break;
+        for (int i = tid; i < nU; i += kMomThreads) S.U[i] = 0;
         const ItemDev it = P->items[item];
         const ItemGeom G = item_geom(P, it, K);
         const double gk = 0.07957747154594767 * ldexp(1.0, G.escale);  // 2^e / (4 pi), exact scaling
         uint32_t item_taps = 0;
-        // z wall powers by image: pzz[2 (q + kPowCap) + w] = beta_z0^|q - w| beta_zL^|q|
-        // (|q| <= pmax < kPowCap for every image of the item: pow_stride <= kPowCap on the host)
-        for (int i = tid; i < 4 * kPowCap; i += kMomThreads) {
-            const int q = (i >> 1) - kPowCap, w = i & 1;
-            const int ez0 = min(abs(q - w), G.pmax), ezL = min(abs(q), G.pmax);
-            S.pzz[i] = G.pz0[ez0] * G.pzL[ezL];
-            const int wall = i / kPowCap, e = min(i % kPowCap, G.pmax);
-            S.pxy[i] = G.px0[wall * G.pow_stride + e];
-        }
-        __syncthreads();  // tables complete before the first column setup
+        __syncthreads();  // bins zeroed, tables of this item complete
 
         // ---- records: moments into the delay bins
         for (int cb = 0; cb < G.ncols; cb += kMomCols) {
@@ -985,8 +1003,15 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         double acc[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[r] = 0.0;
-        if (wave < kMom)  // one moment channel per wave
+        if (wave < kMom) {  // one moment channel per wave
             mom_filter<K>((const double *)S.U + wave * ustride, P->coef + wave * (2 * K + 1), lane, acc);
+        } else if (wave == kMom) {  // meanwhile: the next item and its tables
+            int nxt = 0;
+            if (lane == 0) nxt = (int)atomicAdd(P->counter, 1u);
+            nxt = uniform(__shfl(nxt, 0, 64));
+            if (lane == 0) S.item[(iter + 1) & 1] = nxt;
+            if (nxt < P->n_items) fill_tables(nxt, lane, 64);
+        }
         __syncthreads();
         if (wave < kMom) {
             double *part = (double *)S.U + wave * mpad(kMomSegMax);

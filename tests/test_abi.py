@@ -137,3 +137,10 @@ def test_paper_room_scene_geometry():
     assert np.allclose(m[0], c)
     assert np.allclose(np.linalg.norm(m[1:] - c, axis=1), 0.04)
     assert b["rir_len"][0] == 8000 and b["fd_taps"] == 8 and len(b["rir_len"]) == 2000
+
+
+def test_room_too_small_for_its_rir_length_is_rejected(handle):
+    # image columns past the kernels' 32-bit indexing: a 1 cm room with a 10 s RIR
+    assert _call(handle, L=[0.01, 0.01, 0.01], src=[0.005, 0.005, 0.005], mics=[[0.002, 0.002, 0.002]],
+                 rir_len=160000, max_order=-1) == ism.ISM_EINVAL
+    assert "too many images" in handle.lib.ism_last_error(handle.h).decode()
