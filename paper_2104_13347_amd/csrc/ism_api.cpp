@@ -270,7 +270,7 @@ int ism_build_plan(ism_handle *h, int n_rooms, const ism_room *rooms, const doub
         for (int m = 0; m < r.n_mics; ++m) {
             for (int s0 = 0; s0 < r.rir_len; s0 += seg_len) {
                 const int s1 = std::min(s0 + seg_len, r.rir_len);
-                ItemDev it{i, r.mic_offset + m, s0, s1};
+                ItemDev it{i, r.mic_offset + m, s0, s1, d.pow_offset, d.pow_stride, {0, 0}};
                 plan.items.push_back(it);
                 const double cst = item_cost(r, fs, c, K, s0, s1);
                 cost.push_back((float)cst);

@@ -29,6 +29,9 @@ struct alignas(16) ItemDev {
     int32_t mic;
     int32_t s0;
     int32_t s1;
+    int32_t pow_offset;  // the room's wall-power tables (copies of its RoomDev fields)
+    int32_t pow_stride;
+    int32_t pad[2];
 };
 
 enum Variant : int32_t { VAR_FX = 0, VAR_LUT = 1, VAR_F32ATOM = 2 };
@@ -70,6 +73,7 @@ constexpr int kMom = 10;
 constexpr int kMomWaves = 16;       // waves per workgroup (one item per workgroup)
 constexpr int kMomSetupWaves = 16;  // waves that set up a batch of image columns, 64 each
 constexpr int kMomSegMax = 1024;
+constexpr int kCfPad = 20;          // zeros on either side of each FP32 filter coefficient row
 constexpr int kPowCap = 128;        // moment kernel: wall exponents below kPowCap (z powers in LDS)
 
 // Padded length of one moment channel: bins [0, kMomSegMax + 2K) plus one pad
@@ -86,6 +90,7 @@ inline int mom_lds_bytes(int K)
     int bytes = kMom * mom_ustride(K) * 8;
     bytes += cols * 48 + kMomSetupWaves * 4 + 16;                  // column records
     bytes += 2 * 4 * kPowCap * 8;                                  // z and x/y wall powers
+    bytes += kMom * (2 * K + 1 + 2 * kCfPad) * 4;                  // FP32 filter coefficients
     return bytes;
 }
 

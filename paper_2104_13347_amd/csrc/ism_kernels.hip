@@ -302,6 +302,27 @@ DEV Lds carve(char *base, int seg_max, int K, int variant)
 extern __shared__ __attribute__((aligned(16))) char ism_lds[];
 
 
+// ---------------------------------------------------------------- read-only launch tables
+// Rooms, items and microphones do not change while a kernel runs.  Read through the
+// constant address space, a wave-uniform index becomes a scalar load (scalar cache, no
+// vector registers, no wait on the vector-memory counter).
+typedef const __attribute__((address_space(4))) ItemDev CItemDev;
+typedef const __attribute__((address_space(4))) RoomDev CRoomDev;
+typedef const __attribute__((address_space(4))) double CDouble;
+
+DEV ItemDev load_item(const LaunchDev *P, int i)
+{
+    CItemDev *p = (CItemDev *)P->items + i;
+    ItemDev it;
+    it.room = p->room;
+    it.mic = p->mic;
+    it.s0 = p->s0;
+    it.s1 = p->s1;
+    return it;
+}
+
+DEV CRoomDev *room_ptr(const LaunchDev *P, int room) { return (CRoomDev *)P->rooms + room; }
+
 // ---------------------------------------------------------------- item geometry
 // Everything about one work item (room, microphone, output segment [s0, s1)) that the
 // enumeration needs, derived once per item.
@@ -322,11 +343,12 @@ struct ItemGeom {
 DEV ItemGeom item_geom(const LaunchDev *P, const ItemDev &it, int K)
 {
     ItemGeom G;
-    const RoomDev &R = P->rooms[it.room];
+    CRoomDev &R = *room_ptr(P, it.room);
+    CDouble *mic = (CDouble *)P->mics + 3 * it.mic;
     const double fs = P->fs, cs = P->c;
     G.Lx = R.L[0]; G.Ly = R.L[1]; G.Lz = R.L[2];
     G.sx = R.src[0]; G.sy = R.src[1]; G.sz = R.src[2];
-    G.rx = P->mics[3 * it.mic + 0]; G.ry = P->mics[3 * it.mic + 1]; G.rz = P->mics[3 * it.mic + 2];
+    G.rx = mic[0]; G.ry = mic[1]; G.rz = mic[2];
     G.rir_len = R.rir_len;
     G.N = R.max_order;
     G.s0 = it.s0; G.s1 = it.s1; G.Sn = it.s1 - it.s0;
@@ -553,7 +575,7 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
         item = uniform(__shfl(item, 0, 64));
         if (item >= P->n_items) break;
 
-        const ItemDev it = P->items[item];
+        const ItemDev it = load_item(P, item);
         const ItemGeom G = item_geom(P, it, K);
         const int s0 = G.s0, s1 = G.s1, Sn = G.Sn;
         const int rel = G.rel;  // n0rel = n0 - rel in [0, Sn + 2K)
@@ -689,7 +711,7 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
         __syncthreads();
 
         // ---- store the segment (coalesced), then clear the accumulator
-        const RoomDev &R = P->rooms[it.room];
+        CRoomDev &R = *room_ptr(P, it.room);
         float *o = P->out + R.out_offset + (long)(it.mic - R.mic_offset) * G.rir_len + s0;
         if (VAR == VAR_F32ATOM) {
             for (int i = lane; i < Sn; i += 64) o[i] = S.acc32[2 * K + i];
@@ -746,7 +768,6 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
 //    fixed order and stored once per sample.
 constexpr int kMomThreads = 64 * kMomWaves;
 static_assert(kMomSetupWaves == kMomWaves, "every wave sets up 64 columns of a batch");
-static_assert(kMom < kMomWaves, "one wave without a filter channel fetches the next item");
 constexpr int kMomCols = 64 * kMomSetupWaves;  // columns per enumeration batch
 
 DEV int mpad(int i) { return i + (i >> 4); }
@@ -783,6 +804,7 @@ struct MomLds {
     int32_t *wtot;         // [kMomSetupWaves] images of each setup wave's chunk
     double *pzz;           // [4 kPowCap] z wall powers by (2 q + w), q in (-kPowCap, kPowCap)
     double *pxy;           // [4 kPowCap] x0, xL, y0, yL wall powers, kPowCap apart
+    float *cf;             // [kMom][2K + 1 + 2 kCfPad] FP32 filter coefficients, zero-padded
     int32_t *item;         // [2] current and next item
 };
 
@@ -794,6 +816,7 @@ DEV MomLds mom_carve(char *base, int K)
     s.col = (MomCol *)p; p += kMomCols * sizeof(MomCol);
     s.pzz = (double *)p; p += 4 * kPowCap * 8;
     s.pxy = (double *)p; p += 4 * kPowCap * 8;
+    s.cf = (float *)p; p += (size_t)kMom * (2 * K + 1 + 2 * kCfPad) * 4;
     s.wtot = (int32_t *)p; p += kMomSetupWaves * 4;
     s.item = (int32_t *)p;
     return s;
@@ -807,29 +830,28 @@ DEV void lds_add_i64(long long *p, double v)
                            __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// acc[r] += sum_k c[k] U[16 lane + r + K - k], r = 0..15; Ub points at the padded
-// bin array, cm at the 2K+1 coefficients of one channel (k = -K..K).
-template <int K>
-DEV void mom_filter(const double *Ub, const double *__restrict__ cm, int lane, double (&acc)[16])
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// NS MFMA K-steps of the filter GEMM (see the kernel): step i feeds bins j = 4 (s0 + i) + kq
+// (kq = lane / 16) of output block b = lane % 16 of the tile, and coefficient row r = lane % 16.
+// ub points at this lane's bin of step 0 (padded layout: bin offsets 4 i + i / 4), ab at its
+// coefficient of step 0 (4 fewer per step; zeros pad both ends).  With MASK, the last step's
+// bins j >= J (J not a multiple of 4) are replaced by zero and read from bin J - 1.
+template <int NS, bool MASK, int J>
+DEV void mom_mfma_steps(const float *ub, const float *ab, int kq, f32x4_t &acc)
 {
-    const double *b = Ub + 17 * lane;  // mpad(16 lane + j) = 17 lane + j + (j >> 4)
-    // the coefficients are wave-uniform: read them through the scalar cache
-    typedef const __attribute__((address_space(4))) double cdouble;
-    const cdouble *cs = (const cdouble *)cm;
-    double win[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) win[r] = b[r];
-    // step kk uses k = K - kk, i.e. bins j = r + kk; the window holds j = kk .. kk + 15
-    // in slot j % 16
-#pragma unroll
-    for (int kk = 0; kk <= 2 * K; ++kk) {
-        const double c = cs[2 * K - kk];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = fma(c, win[(r + kk) & 15], acc[r]);
-        if (kk < 2 * K) {
-            const int j = kk + 16;
-            win[kk & 15] = b[j + (j >> 4)];
+    for (int i = 0; i < NS; ++i) {
+        const float a = ab[-4 * i];
+        float bv;
+        if (MASK && i == NS - 1) {
+            const bool in = kq < (J & 3);
+            bv = ub[4 * i + (i >> 2) - (in ? 0 : kq - (J & 3) + 1)];
+            bv = in ? bv : 0.0f;
+        } else {
+            bv = ub[4 * i + (i >> 2)];
         }
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
     }
 }
 
@@ -837,6 +859,8 @@ template <int KT>
 __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__restrict__ P)
 {
     constexpr int K = KT;
+    static_assert(kMom * mom_ustride(KT) * 4 <= kMomCols * (int)sizeof(MomCol),
+                  "the FP32 bins fit the column-record area");
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = uniform(tid >> 6);
     const int ustride = mom_ustride(K);
@@ -852,39 +876,60 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
     uint32_t n_rec = 0, n_img = 0;
     const int nU = kMom * ustride;
 
-    // wall-power tables of the room of `item` into LDS, by `nthr` threads from `t0`:
-    // pzz[2 (q + kPowCap) + w] = beta_z0^|q - w| beta_zL^|q|; pxy = x0, xL, y0, yL powers,
-    // kPowCap apart (|q|, exponents <= pmax < kPowCap: pow_stride <= kPowCap on the host)
-    auto fill_tables = [&](int item, int t0, int nthr) {
-        const RoomDev &R = P->rooms[P->items[item].room];
-        const double *px = P->pow_tab + R.pow_offset;
-        const double *pz0 = px + 4 * R.pow_stride, *pzL = pz0 + R.pow_stride;
-        const int pmax = R.pow_stride - 1;
-        for (int i = t0; i < 4 * kPowCap; i += nthr) {
-            const int q = (i >> 1) - kPowCap, w = i & 1;
-            const int ez0 = min(abs(q - w), pmax), ezL = min(abs(q), pmax);
-            S.pzz[i] = pz0[ez0] * pzL[ezL];
-            const int wall = i / kPowCap, e = min(i % kPowCap, pmax);
-            S.pxy[i] = px[wall * R.pow_stride + e];
-        }
+    // wall-power tables of an item's room into LDS, one entry i < kTab per thread:
+    // pzz[i = 2 (q + kPowCap) + w] = beta_z0^|q - w| beta_zL^|q|; pxy[i] = x0, xL, y0, yL
+    // powers, kPowCap apart (|q|, exponents <= pmax < kPowCap: pow_stride <= kPowCap on the
+    // host).  The entry's loads (table_load, into registers) are issued well before its
+    // stores (table_store), with other work between.
+    constexpr int kTab = 4 * kPowCap;
+    typedef const __attribute__((address_space(1))) double GDouble;
+    auto table_load = [&](int pow_offset, int stride, int i, double (&v)[3]) {
+        // opaque copy of i: keeps the index arithmetic here instead of being hoisted out
+        // of the item loop, where it would hold registers through the walk
+        asm volatile("" : "+v"(i));
+        const int pmax = stride - 1;
+        GDouble *px = (GDouble *)P->pow_tab + pow_offset;
+        GDouble *pz0 = px + 4 * stride, *pzL = pz0 + stride;
+        const int q = (i >> 1) - kPowCap, w = i & 1;
+        v[0] = pz0[min(abs(q - w), pmax)];
+        v[1] = pzL[min(abs(q), pmax)];
+        v[2] = px[(i / kPowCap) * stride + min(i % kPowCap, pmax)];
     };
-    // The index of the current item alternates between S.item[0] and S.item[1]: the wave
-    // that has no filter channel fetches the next item and fills its tables while the
-    // others filter.
+    auto table_store = [&](int i, const double (&v)[3]) {
+        S.pzz[i] = v[0] * v[1];
+        S.pxy[i] = v[2];
+    };
+    // The index of the current item alternates between S.item[0] and S.item[1]: the last
+    // wave fetches the next item at the start of the current one; its tables are filled
+    // during the filter.
+    constexpr int CFS = 2 * K + 1 + 2 * kCfPad;  // coefficient row stride
+    for (int i = tid; i < kMom * CFS; i += kMomThreads) {
+        const int m = i / CFS, c = i - m * CFS - kCfPad;
+        S.cf[i] = (c >= 0 && c <= 2 * K) ? (float)P->coef[m * (2 * K + 1) + c] : 0.0f;
+    }
     if (tid == 0) S.item[0] = (int)atomicAdd(P->counter, 1u);
     __syncthreads();
     {
         const int first = uniform(S.item[0]);
-        if (first < P->n_items) fill_tables(first, tid, kMomThreads);
+        if (first < P->n_items && tid < kTab) {
+            CItemDev &f = ((CItemDev *)P->items)[first];
+            double tv[3];
+            table_load(f.pow_offset, f.pow_stride, tid, tv);
+            table_store(tid, tv);
+        }
     }
     for (int iter = 0;; ++iter) {
         const int item = uniform(S.item[iter & 1]);
         if (item >= P->n_items) break;
         for (int i = tid; i < nU; i += kMomThreads) S.U[i] = 0;
-        const ItemDev it = P->items[item];
+        const ItemDev it = load_item(P, item);
         const ItemGeom G = item_geom(P, it, K);
         const double gk = 0.07957747154594767 * ldexp(1.0, G.escale);  // 2^e / (4 pi), exact scaling
         uint32_t item_taps = 0;
+        // the next item's index, fetched now, published at the first batch barrier and first
+        // used after the enumeration (every item has at least one column batch)
+        int nxt_fetch = 0;
+        if (wave == kMomWaves - 1 && lane == 0) nxt_fetch = (int)atomicAdd(P->counter, 1u);
         __syncthreads();  // bins zeroed, tables of this item complete
 
         // ---- records: moments into the delay bins
@@ -895,6 +940,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             int T;
             const int off = wave_excl_scan(ctot, T);
             if (lane == 0) S.wtot[wave] = T;
+            if (cb == 0 && wave == kMomWaves - 1 && lane == 0) S.item[(iter + 1) & 1] = nxt_fetch;
             __syncthreads();
             int base = 0, Tall = 0;
 #pragma unroll
@@ -992,42 +1038,67 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
 
         n_taps += item_taps;
 
-        // ---- bins to FP64 (exact: |sum| < 2^53)
-        {
-            double *Ud = (double *)S.U;
-            for (int i = tid; i < nU; i += kMomThreads) Ud[i] = (double)S.U[i];
+        // the next item's wall-power table location, loaded now (vector memory: its wait
+        // does not hold up the LDS work below) for the table entries loaded during the filter
+        const int nxt = uniform(S.item[(iter + 1) & 1]);
+        const bool fill = nxt < P->n_items && tid < kTab;
+        int nxt_pow_offset = 0, nxt_pow_stride = 1;
+        if (fill) {
+            const __attribute__((address_space(1))) ItemDev *ni =
+                (const __attribute__((address_space(1))) ItemDev *)P->items + nxt;
+            nxt_pow_offset = ni->pow_offset;
+            nxt_pow_stride = ni->pow_stride;
         }
+
+        // ---- bins to FP32 (the exact integer sums, rounded once) in the column-record area
+        float *Uf = (float *)S.col;
+        for (int i = tid; i < nU; i += kMomThreads) Uf[i] = (float)S.U[i];
         __syncthreads();
 
-        // ---- the filter over the moment channels
-        double acc[16];
+        // ---- the filter as a GEMM on the matrix cores (v_mfma_f32_16x16x4f32):
+        //      OUT[r][b] = sum_m sum_j A_m[r][j] B_m[j][b], output sample 16 b + r,
+        //      A_m[r][j] = c_m[2K - (j - r)] (zero outside the band), B_m[j][b] = bin 16 b + j.
+        // Wave w takes the 16 output blocks of tile w % 4 (256 samples) and the tasks
+        // (channel, part of 8 K-steps) w / 4, w / 4 + 4, ...; the 4 waves of a tile are summed
+        // after.
+        {
+            constexpr int J = 16 + 2 * K;                    // bins feeding one output block
+            constexpr int NS = (J + 3) / 4;                  // K-steps per channel
+            constexpr int PS = 8;                            // K-steps per task
+            constexpr int NPART = (NS + PS - 1) / PS;
+            constexpr int LS = NS - PS * (NPART - 1);        // K-steps of the last part
+            constexpr bool MASK = (J & 3) != 0;
+            const int tile = wave & 3, r16 = lane & 15, kq = lane >> 4;
+            f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            // the next item's wall-power table entries: loads issued before the tasks, stored
+            // after them (this item no longer reads the tables)
+            double tv[3];
+            if (fill) table_load(nxt_pow_offset, nxt_pow_stride, tid, tv);
+            for (int task = wave >> 2; task < kMom * NPART; task += 4) {
+                const int m = task / NPART, part = task - m * NPART;
+                const int s0 = part * PS;  // a multiple of 4: padded bin offsets split
+                const float *ub = Uf + m * ustride + 17 * (16 * tile + r16) + 4 * s0 + s0 / 4 + kq;
+                const float *ab = S.cf + m * CFS + kCfPad + 2 * K - 4 * s0 - kq + r16;
+                if (part < NPART - 1) mom_mfma_steps<PS, false, J>(ub, ab, kq, acc);
+                else mom_mfma_steps<LS, MASK, J>(ub, ab, kq, acc);
+            }
+            if (fill) table_store(tid, tv);
+            // the int64 bins are no longer read: their area takes the partial tiles
+            float *part = (float *)S.U + wave * 256;  // D[i][b]: b = lane % 16, i = 4 (lane / 16) + v
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = 0.0;
-        if (wave < kMom) {  // one moment channel per wave
-            mom_filter<K>((const double *)S.U + wave * ustride, P->coef + wave * (2 * K + 1), lane, acc);
-        } else if (wave == kMom) {  // meanwhile: the next item and its tables
-            int nxt = 0;
-            if (lane == 0) nxt = (int)atomicAdd(P->counter, 1u);
-            nxt = uniform(__shfl(nxt, 0, 64));
-            if (lane == 0) S.item[(iter + 1) & 1] = nxt;
-            if (nxt < P->n_items) fill_tables(nxt, lane, 64);
-        }
-        __syncthreads();
-        if (wave < kMom) {
-            double *part = (double *)S.U + wave * mpad(kMomSegMax);
-#pragma unroll
-            for (int r = 0; r < 16; ++r) part[17 * lane + r] = acc[r];  // mpad(16 lane + r)
+            for (int v = 0; v < 4; ++v) part[(4 * kq + v) * 16 + r16] = acc[v];
         }
         __syncthreads();
         {
-            const RoomDev &R = P->rooms[it.room];
+            CRoomDev &R = *room_ptr(P, it.room);
             float *o = P->out + R.out_offset + (long)(it.mic - R.mic_offset) * G.rir_len + G.s0;
             const double inv = ldexp(1.0, -G.escale);
-            const double *part = (const double *)S.U;
+            const float *part = (const float *)S.U;
             for (int i = tid; i < G.Sn; i += kMomThreads) {
+                const int blk = i >> 4, row = i & 15, tl = blk >> 4, col = blk & 15;
                 double v = 0.0;
 #pragma unroll
-                for (int w = 0; w < kMom; ++w) v += part[w * mpad(kMomSegMax) + mpad(i)];
+                for (int q = 0; q < 4; ++q) v += (double)part[(tl + 4 * q) * 256 + row * 16 + col];
                 o[i] = (float)(v * inv);
             }
         }
