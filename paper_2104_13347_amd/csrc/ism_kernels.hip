@@ -406,8 +406,13 @@ struct Column {
 };
 
 // px: x0, xL, y0, yL wall-power tables, `ps` apart (exponents 0 .. pmax)
+// With STAGED, the wave lowers its issue priority as it passes the stages (3 at entry, 2 after
+// the horizontal distance, 1 after the intervals), so that waves set up their columns side
+// by side instead of the oldest first.
+template <bool STAGED = false>
 DEV Column column_setup(const ItemGeom &G, int ci, int order_mode, const double *px, int ps)
 {
+    if (STAGED) __builtin_amdgcn_s_setprio(3);
     Column C;
 #pragma unroll
     for (int i = 0; i < 4; ++i) { C.q0[i] = 0; C.len[i] = 0; C.wv[i] = 0; }
@@ -428,6 +433,7 @@ DEV Column column_setup(const ItemGeom &G, int ci, int order_mode, const double 
     const double dx = X - G.rx, dy = Y - G.ry;
     const double rho2 = dx * dx + dy * dy;
     C.rho2 = rho2;
+    if (STAGED) __builtin_amdgcn_s_setprio(2);
     int qlim_lo = -(1 << 30), qlim_hi = 1 << 30;
     bool ok = rho2 < G.dhi2;
     int ordxy = 0;
@@ -478,6 +484,7 @@ DEV Column column_setup(const ItemGeom &G, int ci, int order_mode, const double 
             put(qlo, qhi - qlo + 1, w);
         }
     }
+    if (STAGED) __builtin_amdgcn_s_setprio(1);
     return C;
 }
 
@@ -526,6 +533,42 @@ DEV bool image_eval(const ItemGeom &G, double rho2, int cord, int q, int w, int 
     fr = tau - n0d;
     if (split32) {
         // ablation: the same split in FP32 arithmetic
+        const float d2f = (float)rho2 + (float)dz * (float)dz;
+        const float tauf = sqrtf(d2f) * (float)fs / (float)cs;
+        const float n0f = floorf(tauf + (float)half);
+        n0 = (int)n0f;
+        fr = (double)(tauf - n0f);
+    }
+    return ordok && n0 >= G.nlo && n0 <= G.nhi;
+}
+
+// image_eval for the moment kernel's walk: the z image offset zw = +-sz is held per interval,
+// and the rounding-boundary test works on the fractional part: |fr + ec| > ethr, with
+// ec = half - 1/2 and ethr = 1/2 - 1e-12 H for an H at least tau + half of every image
+// that can become a record (a superset of image_eval's test; the exact quotient is the
+// definition's, so taking it more often changes nothing).
+DEV bool image_eval_z(const ItemGeom &G, double rho2, int cord, int q, int w, double zw, int order_mode,
+                      double fs, double cs, double fsc, int split32, double half, double ec, double ethr,
+                      int &n0, double &fr, double &d)
+{
+    bool ordok = true;
+    if (G.N >= 0) {
+        const int oz = order_mode == 0 ? abs(q) : abs(2 * q - w);
+        ordok = cord + oz <= G.N;
+    }
+    const double Z = zw + (2.0 * (double)q) * G.Lz;
+    const double dz = Z - G.rz;
+    d = sqrt_normal(rho2 + dz * dz);
+    double tau = d * fsc;
+    double fl = floor(tau + half);
+    fr = tau - fl;
+    if (fabs(fr + ec) > ethr) {
+        tau = d * fs / cs;
+        fl = floor(tau + half);
+        fr = tau - fl;
+    }
+    n0 = (int)fl;
+    if (split32) {
         const float d2f = (float)rho2 + (float)dz * (float)dz;
         const float tauf = sqrtf(d2f) * (float)fs / (float)cs;
         const float n0f = floorf(tauf + (float)half);
@@ -822,12 +865,12 @@ DEV MomLds mom_carve(char *base, int K)
     return s;
 }
 
-DEV void lds_add_i64(long long *p, double v)
+DEV void lds_add_u31(long long *p, double v)
 {
-    // |v| < 2^30: truncation toward zero, sign-extended
-    const long long q = (long long)(int)v;
-    __hip_atomic_fetch_add((unsigned long long *)p, (unsigned long long)q, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    // 0 <= v < 2^31 (a slightly negative rounding result saturates to 0): truncated,
+    // zero high word
+    const unsigned long long q = (unsigned long long)(uint32_t)v;
+    __hip_atomic_fetch_add((unsigned long long *)p, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
@@ -925,7 +968,13 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         const ItemDev it = load_item(P, item);
         const ItemGeom G = item_geom(P, it, K);
         const double gk = 0.07957747154594767 * ldexp(1.0, G.escale);  // 2^e / (4 pi), exact scaling
-        uint32_t item_taps = 0;
+        // taps landing in [s0, s1) per record: W minus those cut at either end,
+        // max(0, tL - n0) + max(0, n0 - tR) = |med3(n0, lo, hi) - n0| + max(0, tL - tR)
+        const int tL = G.s0 - kmin, tR = G.s1 - 1 - kmax;
+        const int tlo = min(tL, tR), thi = max(tL, tR);
+        uint32_t rec_item = 0, loss_item = 0;
+        // rounding-boundary test of the delay split (image_eval_z)
+        const double ec = half - 0.5, ethr = 0.5 - 1e-12 * ((double)G.nhi + 2.0);
         // the next item's index, fetched now, published at the first batch barrier and first
         // used after the enumeration (every item has at least one column batch)
         int nxt_fetch = 0;
@@ -935,7 +984,8 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         // ---- records: moments into the delay bins
         for (int cb = 0; cb < G.ncols; cb += kMomCols) {
             const int gc = wave * 64 + lane;
-            const Column C = column_setup(G, cb + gc, order_mode, S.pxy, kPowCap);
+            const Column C = column_setup<true>(G, cb + gc, order_mode, S.pxy, kPowCap);
+            __builtin_amdgcn_s_setprio(0);
             const int ctot = C.len[0] + C.len[1] + C.len[2] + C.len[3];
             int T;
             const int off = wave_excl_scan(ctot, T);
@@ -952,7 +1002,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             {
                 MomCol mc;
                 mc.rho2 = C.rho2;
-                mc.bxy = C.bxy;
+                mc.bxy = C.bxy * gk;  // x/y wall powers times 2^e / (4 pi)
                 mc.start = base + off;
                 mc.end = base + off + ctot;
                 mc.len01 = (uint32_t)C.len[0] | ((uint32_t)C.len[1] << 16);
@@ -973,6 +1023,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             int x = tid * n;
             const int xe = min(x + n, Tall);
             if (x < xe) {
+                n_img += (uint32_t)(xe - x);
                 int c = 0;
 #pragma unroll
                 for (int st = kMomCols / 2; st >= 1; st >>= 1)
@@ -986,32 +1037,47 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                 }
                 int qwv = col_qw(mc, iv);
                 int q = (qwv >> 1) + loc, w = qwv & 1, rem = col_len(mc, iv) - loc;
+                double zw = w ? -G.sz : G.sz;
                 for (;;) {
-                    ++n_img;
+                    // issue priority from the share of images left (3, 2, 1, 0 by quarters): a
+                    // wave that runs ahead yields to the others, so that the waves of a SIMD
+                    // finish together instead of the oldest first (the batch ends at a barrier)
+                    {
+                        const int left4 = 4 * __builtin_amdgcn_readfirstlane(xe - x);
+                        if (left4 > 3 * n) __builtin_amdgcn_s_setprio(3);
+                        else if (left4 > 2 * n) __builtin_amdgcn_s_setprio(2);
+                        else if (left4 > n) __builtin_amdgcn_s_setprio(1);
+                        else __builtin_amdgcn_s_setprio(0);
+                    }
                     int n0;
                     double fr, d;
-                    if (image_eval(G, mc.rho2, mc.cord, q, w, order_mode, fs, cs, fsc, split32, half, n0, fr, d)) {
+                    if (image_eval_z(G, mc.rho2, mc.cord, q, w, zw, order_mode, fs, cs, fsc, split32, half, ec,
+                                     ethr, n0, fr, d)) {
                         const int qc = min(max(q, 1 - kPowCap), kPowCap - 1);  // |q| <= pmax already
-                        const double B = mc.bxy * S.pzz[2 * (qc + kPowCap) + w];
-                        ++n_rec;
-                        // taps landing in [s0, s1): kmax - kmin + 1 minus those cut at either end
-                        item_taps += (uint32_t)(kmax - kmin + 1 - max(0, G.s0 - kmin - n0) -
-                                                max(0, n0 + kmax + 1 - G.s1));
-                        // g 2^e = B / (4 pi d) 2^e in FP64 (reciprocal with one Newton step)
+                        const double Bg = mc.bxy * S.pzz[2 * (qc + kPowCap) + w];
+                        ++rec_item;
+                        {
+                            const uint32_t a = (uint32_t)min(max(n0, tlo), thi), b = (uint32_t)n0;
+                            loss_item += max(a, b) - min(a, b);
+                        }
+                        // g 2^e = B 2^e / (4 pi d) in FP64 (reciprocal with one Newton step)
                         double rd = __builtin_amdgcn_rcp(d);
                         rd = fma(fma(-d, rd, 1.0), rd, rd);
-                        const double gs = B * (rd * gk);
+                        const double gs = Bg * rd;
                         // Chebyshev variable: x = 2f for f in [-1/2, 1/2) (sinc), 2f - 1 for f in [0, 1)
-                        const double xx = fma(2.0, fr, -xoff), x2 = 2.0 * xx;
-                        long long *u = S.U + mpad(n0 - G.rel);
+                        const double xx = fma(2.0, fr, -xoff), x2 = xx + xx;
+                        // bins: channel 0 adds g, channel m >= 1 adds g (T_m + 1) in [0, 2g]:
+                        // non-negative, so no sign extension; the bias (channel 0's sum) is
+                        // taken off when the bins are read
+                        long long *u = S.U + (n0 - G.rel);
                         long long *u2 = u + 5 * ustride;  // channels 5.. from a second base (16-bit offsets)
                         double tp = 1.0, tc = xx;
-                        lds_add_i64(u, gs);
-                        lds_add_i64(u + ustride, gs * xx);
+                        lds_add_u31(u, gs);
+                        lds_add_u31(u + ustride, fma(gs, xx, gs));
 #pragma unroll
                         for (int m = 2; m < kMom; ++m) {
                             const double tn = fma(x2, tc, -tp);
-                            lds_add_i64(m < 5 ? u + m * ustride : u2 + (m - 5) * ustride, gs * tn);
+                            lds_add_u31(m < 5 ? u + m * ustride : u2 + (m - 5) * ustride, fma(gs, tn, gs));
                             tp = tc;
                             tc = tn;
                         }
@@ -1029,14 +1095,17 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                         qwv = col_qw(mc, iv);
                         q = qwv >> 1;
                         w = qwv & 1;
+                        zw = w ? -G.sz : G.sz;
                         rem = l;
                     }
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
             __syncthreads();  // the batch's column records are rewritten next
         }
 
-        n_taps += item_taps;
+        n_rec += rec_item;
+        n_taps += (unsigned long long)rec_item * (unsigned)(kmax - kmin + 1 - max(0, tL - tR)) - loss_item;
 
         // the next item's wall-power table location, loaded now (vector memory: its wait
         // does not hold up the LDS work below) for the table entries loaded during the filter
@@ -1052,7 +1121,18 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
 
         // ---- bins to FP32 (the exact integer sums, rounded once) in the column-record area
         float *Uf = (float *)S.col;
-        for (int i = tid; i < nU; i += kMomThreads) Uf[i] = (float)S.U[i];
+        // channel m >= 1 minus channel 0 (the bias), rounded once; one pad word per 16 bins
+        for (int p = tid; p < nU; p += kMomThreads) {
+            const int m = p / ustride, pp = p - m * ustride;
+            const int a = pp / 17, b = pp - 17 * a;
+            float v = 0.0f;
+            if (b < 16) {
+                const int i = 16 * a + b;
+                const long long sm = S.U[m * ustride + i];
+                v = (float)(m ? sm - S.U[i] : sm);
+            }
+            Uf[p] = v;
+        }
         __syncthreads();
 
         // ---- the filter as a GEMM on the matrix cores (v_mfma_f32_16x16x4f32):
