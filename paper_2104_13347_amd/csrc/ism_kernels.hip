@@ -1121,17 +1121,16 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
 
         // ---- bins to FP32 (the exact integer sums, rounded once) in the column-record area
         float *Uf = (float *)S.col;
-        // channel m >= 1 minus channel 0 (the bias), rounded once; one pad word per 16 bins
-        for (int p = tid; p < nU; p += kMomThreads) {
-            const int m = p / ustride, pp = p - m * ustride;
-            const int a = pp / 17, b = pp - 17 * a;
-            float v = 0.0f;
-            if (b < 16) {
-                const int i = 16 * a + b;
-                const long long sm = S.U[m * ustride + i];
-                v = (float)(m ? sm - S.U[i] : sm);
+        // channel m >= 1 minus channel 0 (the bias), rounded once: the sums are below 2^53, so
+        // the conversion to double is exact; one pad word per 16 bins (pad words are not read)
+        {
+            constexpr int nb = kMomSegMax + 2 * K;  // bins a channel can hold
+            for (int e = tid; e < kMom * nb; e += kMomThreads) {
+                const int m = e / nb, i = e - m * nb;
+                long long v = S.U[m * ustride + i];
+                if (m) v -= S.U[i];
+                Uf[m * ustride + i + (i >> 4)] = (float)(double)v;
             }
-            Uf[p] = v;
         }
         __syncthreads();
 
