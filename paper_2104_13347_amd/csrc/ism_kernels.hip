@@ -1017,19 +1017,21 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
 
             // thread t takes the images [t n, (t + 1) n) of the batch: consecutive lanes
             // sit in different columns, so their delays rarely coincide.  The walk state
-            // (column record, interval, z index, images left in the interval) stays in
-            // registers; the next record is read only when the column ends.
-            const int n = (Tall + kMomThreads - 1) / kMomThreads;
-            int x = tid * n;
-            const int xe = min(x + n, Tall);
-            if (x < xe) {
-                n_img += (uint32_t)(xe - x);
+            // (column record, interval, z index, images left in the interval, z-power table
+            // index) stays in registers; the next record is read only when the column ends.
+            // The loop runs n times in every wave (scalar control); lanes past their last
+            // image idle.
+            const int n = __builtin_amdgcn_readfirstlane((Tall + kMomThreads - 1) / kMomThreads);
+            const int x0 = tid * n;
+            const int cnt = max(0, min(n, Tall - x0));
+            n_img += (uint32_t)cnt;
+            if (cnt > 0) {
                 int c = 0;
 #pragma unroll
                 for (int st = kMomCols / 2; st >= 1; st >>= 1)
-                    if (S.col[c + st].start <= x) c += st;
+                    if (S.col[c + st].start <= x0) c += st;
                 MomCol mc = S.col[c];
-                int loc = x - mc.start, iv = 0;
+                int loc = x0 - mc.start, iv = 0;
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     const int l = col_len(mc, iv);
@@ -1038,27 +1040,28 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                 int qwv = col_qw(mc, iv);
                 int q = (qwv >> 1) + loc, w = qwv & 1, rem = col_len(mc, iv) - loc;
                 double zw = w ? -G.sz : G.sz;
-                for (;;) {
+                int pz = 2 * (q + kPowCap) + w;  // S.pzz index of (q, w); |q| <= pmax < kPowCap
+                for (int k = 0; k < n; ++k) {
                     // issue priority from the share of images left (3, 2, 1, 0 by quarters): a
                     // wave that runs ahead yields to the others, so that the waves of a SIMD
                     // finish together instead of the oldest first (the batch ends at a barrier)
                     {
-                        const int left4 = 4 * __builtin_amdgcn_readfirstlane(xe - x);
+                        const int left4 = 4 * (n - k);
                         if (left4 > 3 * n) __builtin_amdgcn_s_setprio(3);
                         else if (left4 > 2 * n) __builtin_amdgcn_s_setprio(2);
                         else if (left4 > n) __builtin_amdgcn_s_setprio(1);
                         else __builtin_amdgcn_s_setprio(0);
                     }
+                    if (k >= cnt) continue;
                     int n0;
                     double fr, d;
                     if (image_eval_z(G, mc.rho2, mc.cord, q, w, zw, order_mode, fs, cs, fsc, split32, half, ec,
                                      ethr, n0, fr, d)) {
-                        const int qc = min(max(q, 1 - kPowCap), kPowCap - 1);  // |q| <= pmax already
-                        const double Bg = mc.bxy * S.pzz[2 * (qc + kPowCap) + w];
+                        const double Bg = mc.bxy * S.pzz[pz];
                         ++rec_item;
-                        {
-                            const uint32_t a = (uint32_t)min(max(n0, tlo), thi), b = (uint32_t)n0;
-                            loss_item += max(a, b) - min(a, b);
+                        {   // loss += |med3(n0, tlo, thi) - n0| (both non-negative)
+                            const uint32_t a = (uint32_t)min(max(n0, tlo), thi);
+                            asm("v_sad_u32 %0, %1, %2, %0" : "+v"(loss_item) : "v"(a), "v"(n0));
                         }
                         // g 2^e = B 2^e / (4 pi d) in FP64 (reciprocal with one Newton step)
                         double rd = __builtin_amdgcn_rcp(d);
@@ -1070,21 +1073,25 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                         // non-negative, so no sign extension; the bias (channel 0's sum) is
                         // taken off when the bins are read
                         long long *u = S.U + (n0 - G.rel);
-                        long long *u2 = u + 5 * ustride;  // channels 5.. from a second base (16-bit offsets)
+                        // channels 7.. from a second base (LDS instruction offsets have 16 bits);
+                        // the opaque index keeps the compiler from folding it back per channel
+                        int i7 = n0 - G.rel + 7 * ustride;
+                        asm("" : "+v"(i7));
+                        long long *u7 = S.U + i7;
                         double tp = 1.0, tc = xx;
                         lds_add_u31(u, gs);
                         lds_add_u31(u + ustride, fma(gs, xx, gs));
 #pragma unroll
                         for (int m = 2; m < kMom; ++m) {
                             const double tn = fma(x2, tc, -tp);
-                            lds_add_u31(m < 5 ? u + m * ustride : u2 + (m - 5) * ustride, fma(gs, tn, gs));
+                            lds_add_u31(m < 7 ? u + m * ustride : u7 + (m - 7) * ustride, fma(gs, tn, gs));
                             tp = tc;
                             tc = tn;
                         }
                     }
-                    if (++x >= xe) break;
                     ++q;
-                    if (--rem == 0) {  // next non-empty interval, in this column or a later one
+                    pz += 2;
+                    if (--rem == 0 && k + 1 < cnt) {  // next non-empty interval, in this column or a later one
                         ++iv;
                         int l = iv < 4 ? col_len(mc, iv) : 0;
                         while (l == 0) {
@@ -1096,6 +1103,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                         q = qwv >> 1;
                         w = qwv & 1;
                         zw = w ? -G.sz : G.sz;
+                        pz = 2 * (q + kPowCap) + w;
                         rem = l;
                     }
                 }
