@@ -329,6 +329,7 @@ DEV CRoomDev *room_ptr(const LaunchDev *P, int room) { return (CRoomDev *)P->roo
 struct ItemGeom {
     double Lx, Ly, Lz, sx, sy, sz, rx, ry, rz;
     double dlo2, dhi2;            // squared distance shell of the item's records
+    double zeps;                  // margin of the column intervals' z bounds (in z-index units)
     const double *px0, *pz0, *pzL;
     int alo, blo;                 // first (x, y) image column indices
     float inv_nb;                 // 1 / nb
@@ -369,6 +370,10 @@ DEV ItemGeom item_geom(const LaunchDev *P, const ItemDev &it, int K)
     const double dhi = ((double)G.nhi + 1.0 - half) * cs / fs * (1.0 + 1e-12) + 1e-12;
     G.dlo2 = dlo * dlo;
     G.dhi2 = dhi * dhi;
+    // the column intervals' z bounds come from FP32 square roots (relative error below
+    // 2^-22 with the FP32 rounding of the argument): widened by this margin in z-index
+    // units they still hold every image of the shell
+    G.zeps = 1e-9 + 4e-7 * dhi * (0.5 / G.Lz);
     // Fixed-point scale 2^e: no image is closer than the direct path and every
     // beta <= 1, so g <= 1/(4 pi max(dlo, |s - r|)) =: gb for every record of the
     // item, and |tap| <= g (|h| <= 1); e is the largest exponent with 2^e gb < 2^30.
@@ -447,8 +452,11 @@ DEV Column column_setup(const ItemGeom &G, int ci, int order_mode, const double 
     const int ex0 = min(abs(n - u), pmax), exL = min(abs(n), pmax);
     const int ey0 = min(abs(l - v), pmax), eyL = min(abs(l), pmax);
     C.bxy = ((px[ex0] * px[ps + exL]) * px[2 * ps + ey0]) * px[3 * ps + eyL];
-    const double zb = sqrt(G.dhi2 - rho2);
-    const double za = G.dlo2 > rho2 ? sqrt(G.dlo2 - rho2) : 0.0;
+    // z extent of the shell on this column; FP32 square roots, the bounds below widen the
+    // intervals (and narrow the hole) by G.zeps, so any extra image lies outside the
+    // shell and fails the delay test
+    const double zb = (double)__builtin_amdgcn_sqrtf((float)(G.dhi2 - rho2));
+    const double za = G.dlo2 > rho2 ? (double)__builtin_amdgcn_sqrtf((float)(G.dlo2 - rho2)) : 0.0;
     const double inv2L = 0.5 / G.Lz;
     int ni = 0;
     // interval slot ni (unrolled selects keep the slots in registers)
@@ -462,8 +470,8 @@ DEV Column column_setup(const ItemGeom &G, int ci, int order_mode, const double 
     for (int w = 0; w < 2; ++w) {
         // dz = (+-sz + 2 q Lz) - rz; |q| stays far below 2^31 (wall exponents < 2^22, host)
         const double off = G.rz - (w ? -G.sz : G.sz);
-        int qlo = (int)ceil((off - zb) * inv2L - 1e-9);
-        int qhi = (int)floor((off + zb) * inv2L + 1e-9);
+        int qlo = (int)ceil((off - zb) * inv2L - G.zeps);
+        int qhi = (int)floor((off + zb) * inv2L + G.zeps);
         if (N >= 0) {
             const int rem = N - ordxy;
             if (order_mode == 0) { qlim_lo = -rem; qlim_hi = rem; }
@@ -474,8 +482,8 @@ DEV Column column_setup(const ItemGeom &G, int ci, int order_mode, const double 
         if (qlo > qhi) continue;
         int hlo = 1, hhi = 0;  // empty hole
         if (za > 0.0) {
-            hlo = (int)ceil((off - za) * inv2L + 1e-9);
-            hhi = (int)floor((off + za) * inv2L - 1e-9);
+            hlo = (int)ceil((off - za) * inv2L + G.zeps);
+            hhi = (int)floor((off + za) * inv2L - G.zeps);
         }
         if (hlo <= hhi && hhi >= qlo && hlo <= qhi) {
             if (hlo > qlo) put(qlo, hlo - qlo, w);
