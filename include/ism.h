@@ -75,8 +75,8 @@ enum ism_order_mode { ISM_ORDER_INDEX_L1 = 0, ISM_ORDER_REFLECTIONS = 1 };
  *   ISM_PREC_FP32        for fd_taps 9, 81 and 127 with segments of at most
  *                        1024 samples (the default): moment evaluation.  For
  *                        each tap k, h(k - f) is expanded in Chebyshev
- *                        polynomials of 2f (10 terms; truncation below 1.1e-8 of
- *                        max|h| = 1).  Each record adds g T_m(2f), m < 10, in
+ *                        polynomials of 2f (9 terms; truncation below 4.1e-8 of
+ *                        max|h| = 1).  Each record adds g T_m(2f), m < 9, in
  *                        FP64 and quantised to 32-bit fixed point, into the bin of
  *                        its integer delay n0; the bin sums are exact 64-bit
  *                        integers (deterministic), rounded once to FP32; each

@@ -69,7 +69,7 @@ constexpr int kBufCap = 256;        // record ring (power of two)
 constexpr int kCols = 64;           // columns per enumeration chunk (one per lane)
 
 // Moment kernel: Chebyshev moments per delay bin, waves per workgroup, largest segment.
-constexpr int kMom = 10;
+constexpr int kMom = 9;
 constexpr int kMomWaves = 16;       // waves per workgroup (one item per workgroup)
 constexpr int kMomSetupWaves = 16;  // waves that set up a batch of image columns, 64 each
 constexpr int kMomSegMax = 1024;
@@ -84,10 +84,14 @@ constexpr int mom_ustride(int K)
     return n + (n >> 4) + 2;
 }
 
+// Bytes of the moment kernel's int64 bins, rounded up to 128 so that the 16-byte column
+// records after them stay aligned.
+constexpr int mom_u_bytes(int K) { return (kMom * mom_ustride(K) * 8 + 127) & ~127; }
+
 inline int mom_lds_bytes(int K)
 {
     const int cols = 64 * kMomSetupWaves;
-    int bytes = kMom * mom_ustride(K) * 8;
+    int bytes = mom_u_bytes(K);
     bytes += cols * 48 + kMomSetupWaves * 4 + 16;                  // column records
     bytes += 2 * 4 * kPowCap * 8;                                  // z and x/y wall powers
     bytes += kMom * (2 * K + 1 + 2 * kCfPad) * 4;                  // FP32 filter coefficients

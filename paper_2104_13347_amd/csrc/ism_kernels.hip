@@ -796,27 +796,26 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
 // ---------------------------------------------------------------- moment kernel
 // Same sum, reorganised around delay bins.  For fixed k, h(k - f) is an entire
 // function of the fractional delay f in [-1/2, 1/2], so its Chebyshev series in
-// x = 2f converges fast: with kMom terms, h(k - f) = sum_m c[m][k] T_m(2f) up to
-// 4.4e-9 (K = 40; 4.3e-9 for K = 63, 1.0e-8 for K = 4).  A record (n0, f, g) then
-// contributes sum_m c[m][k] (g T_m(2f)) to sample n0 + k, and
+// x = 2f converges fast: with kMom = 9 terms, h(k - f) = sum_m c[m][k] T_m(2f) up to
+// 3.3e-8 of max|h| = 1 (K = 40 and 63; 4.1e-8 for K = 4), below FP32 rounding; the
+// 7th-order Lagrange filter is a polynomial of degree 7 in f, so its series is exact.
+// A record (n0, f, g) then contributes sum_m c[m][k] (g T_m(2f)) to sample n0 + k, and
 //     out[n] = sum_m sum_k c[m][k] U_m[n - k],   U_m[b] = sum over records with
 //                                                n0 = b of g T_m(2 f),
 // so each record only adds kMom moments into the bins of its n0 (a counting sort
 // of the records by delay, with the sum per bin taken at once), and the 2K+1 taps
 // per sample become a dense 2K+1-tap filter over kMom moment sequences.
-//  * Moments are FP64 (recurrence T_{m+1} = 2x T_m - T_{m-1}), converted to 32-bit
-//    fixed point with the item's scale and added with ds_add_u64: the bin sums are
-//    exact integers, independent of the order of the adds.
+//  * Moments are FP64 (recurrence T_{m+1} = 2x T_m - T_{m-1}), scaled by the item's
+//    2^e, made non-negative (channel m >= 1 adds g (T_m + 1)), truncated to 32 bits and
+//    added with ds_add_u64: the bin sums are exact integers, independent of the order
+//    of the adds.  Channel 0's sum is taken off the others when the bins are read.
 //  * One workgroup of kMomWaves waves owns one item.  Columns are set up 64 per
 //    wave (kMomWaves chunks at a time); every thread then takes a contiguous slice
 //    of the flattened images of those chunks, so all waves share the work of small
 //    and large items alike.
-//  * The filter: wave w takes the moment channels m = w, w + kMomWaves, ...; a lane
-//    computes 16 consecutive outputs from a 16-value window that slides along the
-//    bins (each bin value is read once per lane and used by up to 16 FMAs, FP64).
-//    Bins are stored with one pad word per 16 so that the lanes' window reads, 17
-//    words apart, hit distinct banks.  The waves' partial outputs are summed in a
-//    fixed order and stored once per sample.
+//  * The filter is a GEMM on the matrix cores over the FP32 bins (see the kernel);
+//    the partial tiles of the waves are summed in a fixed order and stored once per
+//    sample.
 constexpr int kMomThreads = 64 * kMomWaves;
 static_assert(kMomSetupWaves == kMomWaves, "every wave sets up 64 columns of a batch");
 constexpr int kMomCols = 64 * kMomSetupWaves;  // columns per enumeration batch
@@ -863,7 +862,7 @@ DEV MomLds mom_carve(char *base, int K)
 {
     MomLds s;
     char *p = base;
-    s.U = (long long *)p; p += (size_t)kMom * mom_ustride(K) * 8;
+    s.U = (long long *)p; p += mom_u_bytes(K);
     s.col = (MomCol *)p; p += kMomCols * sizeof(MomCol);
     s.pzz = (double *)p; p += 4 * kPowCap * 8;
     s.pxy = (double *)p; p += 4 * kPowCap * 8;
