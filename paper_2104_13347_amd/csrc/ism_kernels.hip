@@ -109,6 +109,20 @@ DEV int wave_excl_scan(int v, int &total)
     return x - v;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave by DPP moves (no LDS round trips):
+// row_shr 1, 2, 4, 8 within rows of 16 lanes, then row_bcast:15 and row_bcast:31 carry
+// the row totals into the later rows.
+DEV int wave_incl_scan_dpp(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+    return x;
+}
+
 DEV void lds_add(float *p, float v)
 {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -411,13 +425,8 @@ struct Column {
 };
 
 // px: x0, xL, y0, yL wall-power tables, `ps` apart (exponents 0 .. pmax)
-// With STAGED, the wave lowers its issue priority as it passes the stages (3 at entry, 2 after
-// the horizontal distance, 1 after the intervals), so that waves set up their columns side
-// by side instead of the oldest first.
-template <bool STAGED = false>
 DEV Column column_setup(const ItemGeom &G, int ci, int order_mode, const double *px, int ps)
 {
-    if (STAGED) __builtin_amdgcn_s_setprio(3);
     Column C;
 #pragma unroll
     for (int i = 0; i < 4; ++i) { C.q0[i] = 0; C.len[i] = 0; C.wv[i] = 0; }
@@ -438,7 +447,6 @@ DEV Column column_setup(const ItemGeom &G, int ci, int order_mode, const double 
     const double dx = X - G.rx, dy = Y - G.ry;
     const double rho2 = dx * dx + dy * dy;
     C.rho2 = rho2;
-    if (STAGED) __builtin_amdgcn_s_setprio(2);
     int qlim_lo = -(1 << 30), qlim_hi = 1 << 30;
     bool ok = rho2 < G.dhi2;
     int ordxy = 0;
@@ -492,7 +500,6 @@ DEV Column column_setup(const ItemGeom &G, int ci, int order_mode, const double 
             put(qlo, qhi - qlo + 1, w);
         }
     }
-    if (STAGED) __builtin_amdgcn_s_setprio(1);
     return C;
 }
 
@@ -794,6 +801,98 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
 }
 
 // ---------------------------------------------------------------- moment kernel
+// One column of the moment kernel's enumeration batch, set up without branches (the same
+// images as column_setup): horizontal distance, x/y wall powers, and per parity w the
+// z-index range [qlo, qhi] of the shell minus the hole [hlo, hhi] under it, as the
+// intervals "below" [qlo, hlo - 1] and "above" [hhi + 1, qhi] (or the whole range when
+// the hole misses it).  The four candidate intervals are packed with the non-empty ones
+// first, as 16-bit lengths and 2 q0 + w values.  Columns past the item's last and
+// columns outside the shell get length 0.  Issue priority steps down through the stages
+// (3, 2, 1) so that the waves set up their columns side by side.
+struct MomColSetup {
+    double rho2, bxy;
+    uint64_t lens, qws;  // 4 x 16 bits each, non-empty intervals first
+    int ctot, ord;
+};
+
+DEV MomColSetup mom_column(const ItemGeom &G, int ci, int order_mode, const double *px, int ps)
+{
+    __builtin_amdgcn_s_setprio(3);
+    MomColSetup R;
+    const int N = G.N;
+    const bool inrange = ci < G.ncols;
+    ci = inrange ? ci : 0;
+    // ci / nb from a float reciprocal, corrected to the exact quotient (ci < 2^24)
+    int ca = (int)((float)ci * G.inv_nb);
+    ca -= ca * G.nb > ci;
+    ca += (ca + 1) * G.nb <= ci;
+    const int a = G.alo + ca, b = G.blo + (ci - ca * G.nb);
+    const int u = a & 1, v = b & 1;
+    const int n = (a + u) >> 1, l = (b + v) >> 1;
+    const double X = (u ? -G.sx : G.sx) + (2.0 * (double)n) * G.Lx;
+    const double Y = (v ? -G.sy : G.sy) + (2.0 * (double)l) * G.Ly;
+    const double dx = X - G.rx, dy = Y - G.ry;
+    const double rho2 = dx * dx + dy * dy;
+    R.rho2 = rho2;
+    __builtin_amdgcn_s_setprio(2);
+    const int ordxy = order_mode == 0 ? abs(n) + abs(l) : abs(2 * n - u) + abs(2 * l - v);
+    R.ord = ordxy;
+    const bool ok = inrange && rho2 < G.dhi2 && (N < 0 || ordxy <= N);
+    const int pmax = G.pmax;
+    const int ex0 = min(abs(n - u), pmax), exL = min(abs(n), pmax);
+    const int ey0 = min(abs(l - v), pmax), eyL = min(abs(l), pmax);
+    R.bxy = ((px[ex0] * px[ps + exL]) * px[2 * ps + ey0]) * px[3 * ps + eyL];
+    // z extent of the shell on this column; FP32 square roots, the bounds below widen the
+    // intervals (and narrow the hole) by G.zeps, so any extra image lies outside the
+    // shell and fails the delay test
+    const double zb = (double)__builtin_amdgcn_sqrtf((float)fmax(G.dhi2 - rho2, 0.0));
+    const double za = (double)__builtin_amdgcn_sqrtf((float)fmax(G.dlo2 - rho2, 0.0));
+    const bool hole = G.dlo2 > rho2;
+    const double inv2L = 0.5 / G.Lz;
+    uint32_t len[4];
+    int qw[4];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        // dz = (+-sz + 2 q Lz) - rz; |q| stays far below 2^31 (wall exponents < 2^22, host)
+        const double off = G.rz - (w ? -G.sz : G.sz);
+        int qlo = (int)ceil((off - zb) * inv2L - G.zeps);
+        int qhi = (int)floor((off + zb) * inv2L + G.zeps);
+        if (N >= 0) {
+            const int rem = N - ordxy;
+            // (w - rem + 1) >> 1 = ceil((w - rem) / 2)
+            const int lo = order_mode == 0 ? -rem : (w - rem + 1) >> 1;
+            const int hi = order_mode == 0 ? rem : (w + rem) >> 1;
+            qlo = max(qlo, lo);
+            qhi = min(qhi, hi);
+        }
+        const int hlo = hole ? (int)ceil((off - za) * inv2L + G.zeps) : 1;
+        const int hhi = hole ? (int)floor((off + za) * inv2L - G.zeps) : 0;
+        const bool cut = hlo <= hhi && hhi >= qlo && hlo <= qhi;
+        const int lb = cut ? hlo - qlo : qhi - qlo + 1;  // "below" (or the whole range)
+        const int la = cut ? qhi - hhi : 0;              // "above"
+        len[2 * w] = ok ? (uint32_t)max(lb, 0) : 0u;
+        len[2 * w + 1] = ok ? (uint32_t)max(la, 0) : 0u;
+        qw[2 * w] = 2 * qlo + w;
+        qw[2 * w + 1] = 2 * (hhi + 1) + w;
+    }
+    __builtin_amdgcn_s_setprio(1);
+    // pack: slot i goes to field pos_i = number of non-empty slots before it (an empty
+    // slot contributes zero wherever it lands)
+    uint64_t lens = 0, qws = 0;
+    int pos = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint64_t sh = 16u * (uint32_t)pos;
+        lens |= (uint64_t)len[i] << sh;
+        qws |= (uint64_t)(len[i] ? ((uint32_t)qw[i] & 0xFFFFu) : 0u) << sh;
+        pos += len[i] ? 1 : 0;
+    }
+    R.lens = lens;
+    R.qws = qws;
+    R.ctot = (int)(len[0] + len[1] + len[2] + len[3]);
+    return R;
+}
+
 // Same sum, reorganised around delay bins.  For fixed k, h(k - f) is an entire
 // function of the fractional delay f in [-1/2, 1/2], so its Chebyshev series in
 // x = 2f converges fast: with kMom = 9 terms, h(k - f) = sum_m c[m][k] T_m(2f) up to
@@ -991,11 +1090,12 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         // ---- records: moments into the delay bins
         for (int cb = 0; cb < G.ncols; cb += kMomCols) {
             const int gc = wave * 64 + lane;
-            const Column C = column_setup<true>(G, cb + gc, order_mode, S.pxy, kPowCap);
+            const MomColSetup C = mom_column(G, cb + gc, order_mode, S.pxy, kPowCap);
             __builtin_amdgcn_s_setprio(0);
-            const int ctot = C.len[0] + C.len[1] + C.len[2] + C.len[3];
-            int T;
-            const int off = wave_excl_scan(ctot, T);
+            const int ctot = C.ctot;
+            const int incl = wave_incl_scan_dpp(ctot);
+            const int T = __builtin_amdgcn_readlane(incl, 63);
+            const int off = incl - ctot;
             if (lane == 0) S.wtot[wave] = T;
             if (cb == 0 && wave == kMomWaves - 1 && lane == 0) S.item[(iter + 1) & 1] = nxt_fetch;
             __syncthreads();
@@ -1012,10 +1112,10 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                 mc.bxy = C.bxy * gk;  // x/y wall powers times 2^e / (4 pi)
                 mc.start = base + off;
                 mc.end = base + off + ctot;
-                mc.len01 = (uint32_t)C.len[0] | ((uint32_t)C.len[1] << 16);
-                mc.len23 = (uint32_t)C.len[2] | ((uint32_t)C.len[3] << 16);
-                mc.qw01 = (int32_t)(((uint32_t)(2 * C.q0[0] + C.wv[0]) & 0xFFFFu) | ((uint32_t)(2 * C.q0[1] + C.wv[1]) << 16));
-                mc.qw23 = (int32_t)(((uint32_t)(2 * C.q0[2] + C.wv[2]) & 0xFFFFu) | ((uint32_t)(2 * C.q0[3] + C.wv[3]) << 16));
+                mc.len01 = (uint32_t)C.lens;
+                mc.len23 = (uint32_t)(C.lens >> 32);
+                mc.qw01 = (int32_t)(uint32_t)C.qws;
+                mc.qw23 = (int32_t)(uint32_t)(C.qws >> 32);
                 mc.cord = C.ord;
                 mc.pad = 0;
                 S.col[gc] = mc;
