@@ -79,9 +79,11 @@ enum ism_order_mode { ISM_ORDER_INDEX_L1 = 0, ISM_ORDER_REFLECTIONS = 1 };
  *                        max|h| = 1).  Each record adds g T_m(2f), m < 9, in
  *                        FP64 and quantised to 32-bit fixed point, into the bin of
  *                        its integer delay n0; the bin sums are exact 64-bit
- *                        integers (deterministic), rounded once to FP32; each
- *                        output sample is then a 2K+1-tap filter over the 10 bin
- *                        sequences, FP32 products and sums on the matrix cores.
+ *                        integers (deterministic), rounded once to FP32 and
+ *                        split into FP16 pairs (hi + lo, 22 significant bits);
+ *                        each output sample is then a 2K+1-tap filter over the 9
+ *                        bin sequences on the matrix cores (FP16 pair products,
+ *                        FP32 sums).
  *                        Other fd_taps or longer segments: as ISM_PREC_FP32_DIRECT.
  *   ISM_PREC_FP16_LUT    the windowed sinc read from an FP16 table (64 steps per
  *                        sample, linear interpolation); exact accumulation as in

@@ -456,6 +456,15 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
     L.seg_max = plan.seg_max;
     L.interleave = h->interleave;
     L.coef = use_mom ? (const double *)(db + off_coef) : nullptr;
+    L.coef_exp = 0;
+    L.reserved1 = 0;
+    if (use_mom) {  // power-of-two scale that brings the largest coefficient to (2^13, 2^14]
+        double cmax = 0.0;
+        for (double v : h->coef) cmax = std::max(cmax, std::fabs(v));
+        int E = 0;
+        (void)std::frexp(cmax, &E);  // cmax = m 2^E, m in [1/2, 1)
+        L.coef_exp = cmax > 0.0 ? 14 - E : 0;
+    }
     std::memcpy(hb, &L, sizeof L);
     if (n_coef) std::memcpy(hb + off_coef, h->coef.data(), sizeof(double) * n_coef);
     std::memcpy(hb + off_rooms, plan.rooms.data(), sizeof(RoomDev) * n_rooms);

@@ -54,6 +54,8 @@ struct alignas(16) LaunchDev {
     int32_t split32;      // 1: distance and delay split in FP32 (ablation)
     int32_t seg_max;      // largest s1 - s0 of any item (sizes LDS)
     int32_t interleave;   // enumeration order inside a column chunk (1: strided over columns)
+    int32_t coef_exp;     // moment kernel: the coefficients are scaled by 2^coef_exp (max <= 2^14)
+    int32_t reserved1;
     const double *coef;   // moment kernel: Chebyshev filter coefficients [kMom][2K+1]
 };
 
@@ -73,16 +75,20 @@ constexpr int kMom = 9;
 constexpr int kMomWaves = 16;       // waves per workgroup (one item per workgroup)
 constexpr int kMomSetupWaves = 16;  // waves that set up a batch of image columns, 64 each
 constexpr int kMomSegMax = 1024;
-constexpr int kCfPad = 20;          // zeros on either side of each FP32 filter coefficient row
 constexpr int kPowCap = 128;        // moment kernel: wall exponents below kPowCap (z powers in LDS)
 
-// Padded length of one moment channel: bins [0, kMomSegMax + 2K) plus one pad
-// word per 16 (the filter's window reads of consecutive lanes are 17 words apart).
-constexpr int mom_ustride(int K)
+// Moment kernel bins of one channel: delays n0 - (s0 - K) in [0, kMomSegMax + 2K).
+constexpr int mom_ustride(int K) { return kMomSegMax + 2 * K; }
+// The filter's K dimension per 16-sample output block (16 + 2K bins), rounded up to the
+// 32 of one FP16 matrix-core step.
+constexpr int mom_jp(int K) { return (16 + 2 * K + 31) / 32 * 32; }
+// FP16 bins of one channel: every bin a step reads (1008 + JP), zeros past the last delay.
+constexpr int mom_nbp(int K)
 {
-    const int n = kMomSegMax + 2 * K;
-    return n + (n >> 4) + 2;
+    return ((kMomSegMax + 2 * K > 1008 + mom_jp(K) ? kMomSegMax + 2 * K : 1008 + mom_jp(K)) + 7) / 8 * 8;
 }
+// FP16 coefficient row: reversed taps at offset 16, JP + 16 halves read, padded.
+constexpr int mom_cl(int K) { return mom_jp(K) + 32; }
 
 // Bytes of the moment kernel's int64 bins, rounded up to 128 so that the 16-byte column
 // records after them stay aligned.
@@ -92,9 +98,9 @@ inline int mom_lds_bytes(int K)
 {
     const int cols = 64 * kMomSetupWaves;
     int bytes = mom_u_bytes(K);
-    bytes += cols * 48 + kMomSetupWaves * 4 + 16;                  // column records
+    bytes += cols * 48 + kMomSetupWaves * 4 + 32;                  // column records, slots
     bytes += 2 * 4 * kPowCap * 8;                                  // z and x/y wall powers
-    bytes += kMom * (2 * K + 1 + 2 * kCfPad) * 4;                  // FP32 filter coefficients
+    bytes += 4 * kMom * mom_cl(K) * 2;                             // FP16 coefficient rows
     return bytes;
 }
 

@@ -948,13 +948,14 @@ DEV int col_qw(const MomCol &m, int iv)
 }
 
 struct MomLds {
-    long long *U;          // kMom x ustride bins (int64, then FP64 in place, then partial outputs)
-    MomCol *col;           // [kMomCols]
+    long long *U;          // kMom x ustride int64 bins; then the filter's partial tiles
+    MomCol *col;           // [kMomCols] column records; then the FP16 bins (hi, lo)
     int32_t *wtot;         // [kMomSetupWaves] images of each setup wave's chunk
     double *pzz;           // [4 kPowCap] z wall powers by (2 q + w), q in (-kPowCap, kPowCap)
     double *pxy;           // [4 kPowCap] x0, xL, y0, yL wall powers, kPowCap apart
-    float *cf;             // [kMom][2K + 1 + 2 kCfPad] FP32 filter coefficients, zero-padded
+    _Float16 *c16;         // [2 shifts][hi, lo][kMom][CL] FP16 coefficient rows (see the kernel)
     int32_t *item;         // [2] current and next item
+    uint32_t *bmax;        // [2] largest channel-0 bin of the item (FP32 bits), its records
 };
 
 DEV MomLds mom_carve(char *base, int K)
@@ -965,9 +966,10 @@ DEV MomLds mom_carve(char *base, int K)
     s.col = (MomCol *)p; p += kMomCols * sizeof(MomCol);
     s.pzz = (double *)p; p += 4 * kPowCap * 8;
     s.pxy = (double *)p; p += 4 * kPowCap * 8;
-    s.cf = (float *)p; p += (size_t)kMom * (2 * K + 1 + 2 * kCfPad) * 4;
+    s.c16 = (_Float16 *)p; p += (size_t)4 * kMom * mom_cl(K) * 2;
     s.wtot = (int32_t *)p; p += kMomSetupWaves * 4;
-    s.item = (int32_t *)p;
+    s.item = (int32_t *)p; p += 16;
+    s.bmax = (uint32_t *)p;  // 2 words
     return s;
 }
 
@@ -981,27 +983,19 @@ DEV void lds_add_u31(long long *p, double v)
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-// NS MFMA K-steps of the filter GEMM (see the kernel): step i feeds bins j = 4 (s0 + i) + kq
-// (kq = lane / 16) of output block b = lane % 16 of the tile, and coefficient row r = lane % 16.
-// ub points at this lane's bin of step 0 (padded layout: bin offsets 4 i + i / 4), ab at its
-// coefficient of step 0 (4 fewer per step; zeros pad both ends).  With MASK, the last step's
-// bins j >= J (J not a multiple of 4) are replaced by zero and read from bin J - 1.
-template <int NS, bool MASK, int J>
-DEV void mom_mfma_steps(const float *ub, const float *ab, int kq, f32x4_t &acc)
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+
+// 8 consecutive FP16 values from a 4-byte aligned LDS address (four dword reads).
+DEV f16x8_t lds_f16x8_a4(const _Float16 *p)
 {
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-        const float a = ab[-4 * i];
-        float bv;
-        if (MASK && i == NS - 1) {
-            const bool in = kq < (J & 3);
-            bv = ub[4 * i + (i >> 2) - (in ? 0 : kq - (J & 3) + 1)];
-            bv = in ? bv : 0.0f;
-        } else {
-            bv = ub[4 * i + (i >> 2)];
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
-    }
+    const uint32_t *q = (const uint32_t *)p;
+    typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+    u32x4_t v;
+    v[0] = q[0];
+    v[1] = q[1];
+    v[2] = q[2];
+    v[3] = q[3];
+    return __builtin_bit_cast(f16x8_t, v);
 }
 
 template <int KT>
@@ -1051,10 +1045,23 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
     // The index of the current item alternates between S.item[0] and S.item[1]: the last
     // wave fetches the next item at the start of the current one; its tables are filled
     // during the filter.
-    constexpr int CFS = 2 * K + 1 + 2 * kCfPad;  // coefficient row stride
-    for (int i = tid; i < kMom * CFS; i += kMomThreads) {
-        const int m = i / CFS, c = i - m * CFS - kCfPad;
-        S.cf[i] = (c >= 0 && c <= 2 * K) ? (float)P->coef[m * (2 * K + 1) + c] : 0.0f;
+    // FP16 coefficient rows of the filter (see there): row (sh, hl, m) holds at index i the
+    // reversed tap t = i + sh - 16 of channel m, c[m][2K - t] (zero outside [0, 2K]),
+    // scaled by 2^coef_exp, as hi = fp16(c) (hl = 0) and lo = fp16(c - hi) (hl = 1); the
+    // copy shifted by one (sh = 1) lets every lane read its 8 taps from a 4-byte boundary
+    constexpr int CL = mom_cl(K);
+    {
+        const float cscale = ldexpf(1.0f, P->coef_exp);
+        for (int i = tid; i < 2 * kMom * CL; i += kMomThreads) {
+            const int row = i / CL, idx = i - row * CL;
+            const int sh = row / kMom, m = row - sh * kMom;
+            const int t = idx + sh - 16;
+            const float c = (t >= 0 && t <= 2 * K) ? (float)(P->coef[m * (2 * K + 1) + 2 * K - t] * cscale) : 0.0f;
+            const _Float16 hi = (_Float16)c;
+            const _Float16 lo = (_Float16)(c - (float)hi);
+            S.c16[((sh * 2 + 0) * kMom + m) * CL + idx] = hi;
+            S.c16[((sh * 2 + 1) * kMom + m) * CL + idx] = lo;
+        }
     }
     if (tid == 0) S.item[0] = (int)atomicAdd(P->counter, 1u);
     __syncthreads();
@@ -1070,7 +1077,16 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
     for (int iter = 0;; ++iter) {
         const int item = uniform(S.item[iter & 1]);
         if (item >= P->n_items) break;
-        for (int i = tid; i < nU; i += kMomThreads) S.U[i] = 0;
+        {   // zero the bins, 16 bytes per store (nU is even)
+            typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+            u32x4_t *z = (u32x4_t *)S.U;
+            const u32x4_t zero = {0u, 0u, 0u, 0u};
+            for (int i = tid; i < nU / 2; i += kMomThreads) z[i] = zero;
+        }
+        if (tid == 0) {
+            S.bmax[0] = 0u;
+            S.bmax[1] = 0u;
+        }
         const ItemDev it = load_item(P, item);
         const ItemGeom G = item_geom(P, it, K);
         const double gk = 0.07957747154594767 * ldexp(1.0, G.escale);  // 2^e / (4 pi), exact scaling
@@ -1234,47 +1250,110 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             nxt_pow_stride = ni->pow_stride;
         }
 
-        // ---- bins to FP32 (the exact integer sums, rounded once) in the column-record area
-        float *Uf = (float *)S.col;
-        // channel m >= 1 minus channel 0 (the bias), rounded once: the sums are below 2^53, so
-        // the conversion to double is exact; one pad word per 16 bins (pad words are not read)
+        // ---- bins to FP16 pairs in the column-record area: V_m = U_m - U_0 for m >= 1 (the
+        //      bias), exact in int64 and in the double; scaled by 2^bexp so that |V| <= 2^13;
+        //      hi = fp16(V), lo = fp16(V - hi) (22 significant bits); zeros past the last delay.
+        //      Each record adds to bin i of channel m >= 1 a value within 1 of g (T_m + 1) and
+        //      to channel 0 one within 1 of g, so |V_m[i]| < U_0[i] + 2 (records in bin i): the
+        //      scale comes from max U_0 + 2 (records of the item).
+        constexpr int NB = kMomSegMax + 2 * K;
+        constexpr int NBP = mom_nbp(K);
         {
-            constexpr int nb = kMomSegMax + 2 * K;  // bins a channel can hold
-            for (int e = tid; e < kMom * nb; e += kMomThreads) {
-                const int m = e / nb, i = e - m * nb;
-                long long v = S.U[m * ustride + i];
-                if (m) v -= S.U[i];
-                Uf[m * ustride + i + (i >> 4)] = (float)(double)v;
+            long long mx = 0;
+            for (int i = tid; i < NB; i += kMomThreads) mx = max(mx, S.U[i]);
+            float fm = (float)mx;
+            uint32_t rc = rec_item;
+#pragma unroll
+            for (int dd = 32; dd >= 1; dd >>= 1) {
+                fm = fmaxf(fm, __shfl_xor(fm, dd, 64));
+                rc += __shfl_xor(rc, dd, 64);
+            }
+            if (lane == 0) {
+                if (fm > 0.0f) atomicMax(S.bmax, __float_as_uint(fm));
+                atomicAdd(S.bmax + 1, rc);
+            }
+        }
+        __syncthreads();
+        int bexp;
+        {
+            int E = 0;
+            // bound <= 2^E; the FP32 roundings may raise it by a few ulps, below 2^13 of margin
+            (void)frexpf(__uint_as_float(S.bmax[0]) + 2.0f * (float)S.bmax[1], &E);
+            bexp = 13 - E;
+        }
+        _Float16 *Uh = (_Float16 *)S.col, *Ul = Uh + kMom * NBP;
+        {
+            // work units (bin i, group of 3 channels); the bin sums are below 2^53, so the
+            // doubles are exact, and so is fma(U_m, 2^bexp, -U_0 2^bexp); one rounding to FP32
+            static_assert(kMom % 3 == 0, "channels in groups of 3");
+            const double bs = ldexp(1.0, bexp);
+            auto u64d = [](long long v) {  // exact for 0 <= v < 2^53
+                const unsigned long long u = (unsigned long long)v;
+                return fma((double)(uint32_t)(u >> 32), 4294967296.0, (double)(uint32_t)u);
+            };
+            auto put = [&](int e, float x) {
+                const _Float16 hi = (_Float16)x;
+                Uh[e] = hi;
+                Ul[e] = (_Float16)(x - (float)hi);
+            };
+            for (int w = tid; w < 3 * NB; w += kMomThreads) {
+                const int g = w / NB, i = w - g * NB;
+                // all four reads first (the stores below may alias them as far as the compiler
+                // knows, and would otherwise wait for each read in turn)
+                const long long v0 = S.U[i];
+                long long v[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) v[k] = S.U[(3 * g + k) * ustride + i];
+                const double u0s = u64d(v0) * bs;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int m = 3 * g + k;
+                    const double d = fma(u64d(v[k]), bs, -u0s);
+                    put(m * NBP + i, (float)(m ? d : u0s));
+                }
+            }
+            if constexpr (NBP > NB) {  // zeros past the last delay
+                for (int e = tid; e < kMom * (NBP - NB); e += kMomThreads) {
+                    const int m = e / (NBP - NB), i = NB + e - m * (NBP - NB);
+                    Uh[m * NBP + i] = (_Float16)0.0f;
+                    Ul[m * NBP + i] = (_Float16)0.0f;
+                }
             }
         }
         __syncthreads();
 
-        // ---- the filter as a GEMM on the matrix cores (v_mfma_f32_16x16x4f32):
-        //      OUT[r][b] = sum_m sum_j A_m[r][j] B_m[j][b], output sample 16 b + r,
-        //      A_m[r][j] = c_m[2K - (j - r)] (zero outside the band), B_m[j][b] = bin 16 b + j.
-        // Wave w takes the 16 output blocks of tile w % 4 (256 samples) and the tasks
-        // (channel, part of 8 K-steps) w / 4, w / 4 + 4, ...; the 4 waves of a tile are summed
-        // after.
+        // ---- the filter as a GEMM on the matrix cores, split FP16 products with FP32 sums
+        //      (v_mfma_f32_16x16x32_f16: hi*hi + hi*lo + lo*hi per step):
+        //      OUT[r][b] = sum_m sum_j A_m[r][j] B_m[j][b], output sample 16 b + r of a tile,
+        //      A_m[r][j] = c_m[2K - (j - r)] (zero outside the band), B_m[j][b] = bin 16 b + j,
+        //      j in [0, JP), 32 per step.  Lane l holds A[l % 16][8 (l / 16) + e] and
+        //      B[8 (l / 16) + e][l % 16], e < 8, and D[4 (l / 16) + v][l % 16] in acc[v].
+        // Wave w takes the 16 output blocks of tile w % 4 (256 samples) and the channels
+        // w / 4, w / 4 + 4, ...; the 4 waves of a tile are summed after.
         {
-            constexpr int J = 16 + 2 * K;                    // bins feeding one output block
-            constexpr int NS = (J + 3) / 4;                  // K-steps per channel
-            constexpr int PS = 8;                            // K-steps per task
-            constexpr int NPART = (NS + PS - 1) / PS;
-            constexpr int LS = NS - PS * (NPART - 1);        // K-steps of the last part
-            constexpr bool MASK = (J & 3) != 0;
+            constexpr int JP = mom_jp(K), NS = JP / 32;
             const int tile = wave & 3, r16 = lane & 15, kq = lane >> 4;
             f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
             // the next item's wall-power table entries: loads issued before the tasks, stored
             // after them (this item no longer reads the tables)
             double tv[3];
             if (fill) table_load(nxt_pow_offset, nxt_pow_stride, tid, tv);
-            for (int task = wave >> 2; task < kMom * NPART; task += 4) {
-                const int m = task / NPART, part = task - m * NPART;
-                const int s0 = part * PS;  // a multiple of 4: padded bin offsets split
-                const float *ub = Uf + m * ustride + 17 * (16 * tile + r16) + 4 * s0 + s0 / 4 + kq;
-                const float *ab = S.cf + m * CFS + kCfPad + 2 * K - 4 * s0 - kq + r16;
-                if (part < NPART - 1) mom_mfma_steps<PS, false, J>(ub, ab, kq, acc);
-                else mom_mfma_steps<LS, MASK, J>(ub, ab, kq, acc);
+            for (int m = wave >> 2; m < kMom; m += 4) {
+                const int bb = m * NBP + 256 * tile + 16 * r16 + 8 * kq;  // this lane's bins, step 0
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    // taps j - r = 32 s + 8 kq + e - r, stored at index + 16; odd starts read the
+                    // copy shifted by one
+                    const int t0 = 32 * s + 8 * kq - r16 + 16, sh = t0 & 1;
+                    const _Float16 *crow = S.c16 + ((sh * 2) * kMom + m) * CL + (t0 - sh);
+                    const f16x8_t ah = lds_f16x8_a4(crow);
+                    const f16x8_t al = lds_f16x8_a4(crow + kMom * CL);
+                    const f16x8_t bh = *(const f16x8_t *)(Uh + bb + 32 * s);
+                    const f16x8_t bl = *(const f16x8_t *)(Ul + bb + 32 * s);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, acc, 0, 0, 0);
+                }
             }
             if (fill) table_store(tid, tv);
             // the int64 bins are no longer read: their area takes the partial tiles
@@ -1286,7 +1365,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         {
             CRoomDev &R = *room_ptr(P, it.room);
             float *o = P->out + R.out_offset + (long)(it.mic - R.mic_offset) * G.rir_len + G.s0;
-            const double inv = ldexp(1.0, -G.escale);
+            const double inv = ldexp(1.0, -G.escale - bexp - P->coef_exp);
             const float *part = (const float *)S.U;
             for (int i = tid; i < G.Sn; i += kMomThreads) {
                 const int blk = i >> 4, row = i & 15, tl = blk >> 4, col = blk & 15;
