@@ -520,6 +520,19 @@ DEV double sqrt_normal(double a)
     return fma(e, hh, g);
 }
 
+// Square root of a normal positive double to within about one ulp: the first iteration
+// and one correction of sqrt_normal (which adds a second correction for correct rounding).
+DEV double sqrt_close(double a)
+{
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y, hh = y * 0.5;
+    const double r = fma(-hh, g, 0.5);
+    g = fma(g, r, g);
+    hh = fma(hh, r, hh);
+    const double e = fma(-g, g, a);
+    return fma(e, hh, g);
+}
+
 // One image of a column: distance (FP64, (dx^2 + dy^2) + dz^2), delay and its
 // integer / fractional split.  Returns whether the record belongs to the item
 // (delay in [nlo, nhi], order within the limit).
@@ -560,8 +573,10 @@ DEV bool image_eval(const ItemGeom &G, double rho2, int cord, int q, int w, int 
 // image_eval for the moment kernel's walk: the z image offset zw = +-sz is held per interval,
 // and the rounding-boundary test works on the fractional part: |fr + ec| > ethr, with
 // ec = half - 1/2 and ethr = 1/2 - 1e-12 H for an H at least tau + half of every image
-// that can become a record (a superset of image_eval's test; the exact quotient is the
-// definition's, so taking it more often changes nothing).
+// that can become a record (a superset of image_eval's test).  The distance first comes
+// from sqrt_close (about one ulp, so tau is off by far less than the test's margin); near
+// a boundary it is recomputed correctly rounded and tau taken as the definition's exact
+// quotient, so n0 is the definition's everywhere.
 DEV bool image_eval_z(const ItemGeom &G, double rho2, int cord, int q, int w, double zw, int order_mode,
                       double fs, double cs, double fsc, int split32, double half, double ec, double ethr,
                       int &n0, double &fr, double &d)
@@ -573,11 +588,13 @@ DEV bool image_eval_z(const ItemGeom &G, double rho2, int cord, int q, int w, do
     }
     const double Z = zw + (2.0 * (double)q) * G.Lz;
     const double dz = Z - G.rz;
-    d = sqrt_normal(rho2 + dz * dz);
+    const double d2 = rho2 + dz * dz;
+    d = sqrt_close(d2);
     double tau = d * fsc;
     double fl = floor(tau + half);
     fr = tau - fl;
     if (fabs(fr + ec) > ethr) {
+        d = sqrt_normal(d2);
         tau = d * fs / cs;
         fl = floor(tau + half);
         fr = tau - fl;
@@ -1115,13 +1132,10 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             if (lane == 0) S.wtot[wave] = T;
             if (cb == 0 && wave == kMomWaves - 1 && lane == 0) S.item[(iter + 1) & 1] = nxt_fetch;
             __syncthreads();
-            int base = 0, Tall = 0;
-#pragma unroll
-            for (int w = 0; w < kMomWaves; ++w) {
-                const int t = S.wtot[w];
-                base += w < wave ? t : 0;
-                Tall += t;
-            }
+            // the waves' totals: prefix over lanes 0..15 (one read each), then broadcast
+            const int wsum = wave_incl_scan_dpp(lane < kMomWaves ? S.wtot[lane] : 0);
+            const int Tall = __builtin_amdgcn_readlane(wsum, kMomWaves - 1);
+            const int base = wave ? __builtin_amdgcn_readlane(wsum, wave - 1) : 0;
             {
                 MomCol mc;
                 mc.rho2 = C.rho2;
