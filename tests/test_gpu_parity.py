@@ -147,6 +147,29 @@ def test_c3_precision_variants(H):
     assert res["split32"] >= res["fp32"]
 
 
+def test_absorbing_rooms_late_segments(H):
+    # Strongly absorbing walls (beta 0.02 .. 0.3, and one room with beta = 0) and long RIRs:
+    # in late segments nearly all records have gains far below the item's scale, so the
+    # filter's bin scale comes from the record count rather than the largest bin.
+    rng = np.random.default_rng(31)
+    rooms = []
+    for i in range(4):
+        L = np.array([rng.uniform(3, 6), rng.uniform(3, 5), rng.uniform(2.5, 3.5)])
+        beta = rng.uniform(0.02, 0.3, size=6) if i < 3 else np.zeros(6)
+        src = L * rng.uniform(0.2, 0.8, size=3)
+        mics = L * rng.uniform(0.2, 0.8, size=(2, 3))
+        rooms.append({"L": L, "beta": beta, "src": src, "mics": mics, "max_order": -1, "rir_len": 3000})
+    b = scenes.pack(rooms, 16000.0, scenes.C_SOUND, 81, ism.ORDER_INDEX_L1, "absorbing")
+    _say("absorbing rooms")
+    gpu, cnt = run(H, b)
+    ref, taps, rirs = oracle_batch(b)
+    assert np.all(np.isfinite(gpu))
+    err = rel_errors(b, gpu, ref, rirs)
+    _say(f"absorbing max err {err.max():.3e}")
+    assert err.max() <= TOL_FP32
+    assert cnt["taps"] == taps
+
+
 # ------------------------------------------------------------------ determinism
 def test_repeat_and_batched_vs_per_room_bitwise(H):
     import torch
