@@ -967,7 +967,7 @@ DEV int col_qw(const MomCol &m, int iv)
 struct MomLds {
     long long *U;          // kMom x ustride int64 bins; then the filter's partial tiles
     MomCol *col;           // [kMomCols] column records; then the FP16 bins (hi, lo)
-    int32_t *wtot;         // [kMomSetupWaves] images of each setup wave's chunk
+    int32_t *chunk;        // [1] next 64-column chunk of the item
     double *pzz;           // [4 kPowCap] z wall powers by (2 q + w), q in (-kPowCap, kPowCap)
     double *pxy;           // [4 kPowCap] x0, xL, y0, yL wall powers, kPowCap apart
     _Float16 *c16;         // [2 shifts][hi, lo][kMom][CL] FP16 coefficient rows (see the kernel)
@@ -984,7 +984,7 @@ DEV MomLds mom_carve(char *base, int K)
     s.pzz = (double *)p; p += 4 * kPowCap * 8;
     s.pxy = (double *)p; p += 4 * kPowCap * 8;
     s.c16 = (_Float16 *)p; p += (size_t)4 * kMom * mom_cl(K) * 2;
-    s.wtot = (int32_t *)p; p += kMomSetupWaves * 4;
+    s.chunk = (int32_t *)p; p += kMomSetupWaves * 4;
     s.item = (int32_t *)p; p += 16;
     s.bmax = (uint32_t *)p;  // 2 words
     return s;
@@ -1103,6 +1103,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         if (tid == 0) {
             S.bmax[0] = 0u;
             S.bmax[1] = 0u;
+            S.chunk[0] = 0;
         }
         const ItemDev it = load_item(P, item);
         const ItemGeom G = item_geom(P, it, K);
@@ -1120,54 +1121,53 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         if (wave == kMomWaves - 1 && lane == 0) nxt_fetch = (int)atomicAdd(P->counter, 1u);
         __syncthreads();  // bins zeroed, tables of this item complete
 
-        // ---- records: moments into the delay bins
-        for (int cb = 0; cb < G.ncols; cb += kMomCols) {
-            const int gc = wave * 64 + lane;
-            const MomColSetup C = mom_column(G, cb + gc, order_mode, S.pxy, kPowCap);
+        // ---- records: moments into the delay bins.  Each wave takes chunks of 64 columns
+        //      from a workgroup counter, sets them up (one per lane), writes their records
+        //      to its own 64 slots and walks their images; no workgroup barrier until the
+        //      item's columns are done, so waves never wait for each other's batches.
+        MomCol *wcol = S.col + 64 * wave;
+        for (;;) {
+            int ch = 0;
+            if (lane == 0) ch = atomicAdd(S.chunk, 1);
+            const int c0 = 64 * __builtin_amdgcn_readfirstlane(__shfl(ch, 0, 64));
+            if (c0 >= G.ncols) break;
+            const MomColSetup C = mom_column(G, c0 + lane, order_mode, S.pxy, kPowCap);
             __builtin_amdgcn_s_setprio(0);
             const int ctot = C.ctot;
             const int incl = wave_incl_scan_dpp(ctot);
-            const int T = __builtin_amdgcn_readlane(incl, 63);
+            const int Tall = __builtin_amdgcn_readlane(incl, 63);
             const int off = incl - ctot;
-            if (lane == 0) S.wtot[wave] = T;
-            if (cb == 0 && wave == kMomWaves - 1 && lane == 0) S.item[(iter + 1) & 1] = nxt_fetch;
-            __syncthreads();
-            // the waves' totals: prefix over lanes 0..15 (one read each), then broadcast
-            const int wsum = wave_incl_scan_dpp(lane < kMomWaves ? S.wtot[lane] : 0);
-            const int Tall = __builtin_amdgcn_readlane(wsum, kMomWaves - 1);
-            const int base = wave ? __builtin_amdgcn_readlane(wsum, wave - 1) : 0;
             {
                 MomCol mc;
                 mc.rho2 = C.rho2;
                 mc.bxy = C.bxy * gk;  // x/y wall powers times 2^e / (4 pi)
-                mc.start = base + off;
-                mc.end = base + off + ctot;
+                mc.start = off;
+                mc.end = off + ctot;
                 mc.len01 = (uint32_t)C.lens;
                 mc.len23 = (uint32_t)(C.lens >> 32);
                 mc.qw01 = (int32_t)(uint32_t)C.qws;
                 mc.qw23 = (int32_t)(uint32_t)(C.qws >> 32);
                 mc.cord = C.ord;
                 mc.pad = 0;
-                S.col[gc] = mc;
+                wcol[lane] = mc;  // read back by this wave only (LDS keeps a wave's order)
             }
-            __syncthreads();
 
-            // thread t takes the images [t n, (t + 1) n) of the batch: consecutive lanes
-            // sit in different columns, so their delays rarely coincide.  The walk state
-            // (column record, interval, z index, images left in the interval, z-power table
-            // index) stays in registers; the next record is read only when the column ends.
-            // The loop runs n times in every wave (scalar control); lanes past their last
-            // image idle.
-            const int n = __builtin_amdgcn_readfirstlane((Tall + kMomThreads - 1) / kMomThreads);
-            const int x0 = tid * n;
+            // lane t takes the images [t n, (t + 1) n) of the chunk: consecutive lanes sit in
+            // different columns, so their delays rarely coincide.  The walk state (column
+            // record, interval, z index, images left in the interval, z-power table index)
+            // stays in registers; the next record is read only when the column ends.  The
+            // loop runs n times in every wave (scalar control); lanes past their last image
+            // idle.
+            const int n = (Tall + 63) >> 6;
+            const int x0 = lane * n;
             const int cnt = max(0, min(n, Tall - x0));
             n_img += (uint32_t)cnt;
             if (cnt > 0) {
                 int c = 0;
 #pragma unroll
-                for (int st = kMomCols / 2; st >= 1; st >>= 1)
-                    if (S.col[c + st].start <= x0) c += st;
-                MomCol mc = S.col[c];
+                for (int st = 32; st >= 1; st >>= 1)
+                    if (wcol[c + st].start <= x0) c += st;
+                MomCol mc = wcol[c];
                 int loc = x0 - mc.start, iv = 0;
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
@@ -1179,16 +1179,6 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                 double zw = w ? -G.sz : G.sz;
                 int pz = 2 * (q + kPowCap) + w;  // S.pzz index of (q, w); |q| <= pmax < kPowCap
                 for (int k = 0; k < n; ++k) {
-                    // issue priority from the share of images left (3, 2, 1, 0 by quarters): a
-                    // wave that runs ahead yields to the others, so that the waves of a SIMD
-                    // finish together instead of the oldest first (the batch ends at a barrier)
-                    {
-                        const int left4 = 4 * (n - k);
-                        if (left4 > 3 * n) __builtin_amdgcn_s_setprio(3);
-                        else if (left4 > 2 * n) __builtin_amdgcn_s_setprio(2);
-                        else if (left4 > n) __builtin_amdgcn_s_setprio(1);
-                        else __builtin_amdgcn_s_setprio(0);
-                    }
                     if (k >= cnt) continue;
                     int n0;
                     double fr, d;
@@ -1232,7 +1222,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                         ++iv;
                         int l = iv < 4 ? col_len(mc, iv) : 0;
                         while (l == 0) {
-                            mc = S.col[++c];
+                            mc = wcol[++c];
                             iv = 0;
                             l = col_len(mc, 0);
                         }
@@ -1245,9 +1235,9 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                     }
                 }
             }
-            __builtin_amdgcn_s_setprio(0);
-            __syncthreads();  // the batch's column records are rewritten next
         }
+        if (wave == kMomWaves - 1 && lane == 0) S.item[(iter + 1) & 1] = nxt_fetch;
+        __syncthreads();  // every chunk of the item is binned
 
         n_rec += rec_item;
         n_taps += (unsigned long long)rec_item * (unsigned)(kmax - kmin + 1 - max(0, tL - tR)) - loss_item;
