@@ -243,6 +243,7 @@ int ism_build_plan(ism_handle *h, int n_rooms, const ism_room *rooms, const doub
         const ism_room &r = rooms[i];
         RoomDev &d = plan.rooms[i];
         std::memcpy(d.L, r.L, sizeof d.L);
+        for (int k = 0; k < 3; ++k) d.inv_L[k] = 1.0 / r.L[k];
         std::memcpy(d.beta, r.beta, sizeof d.beta);
         std::memcpy(d.src, r.src, sizeof d.src);
         d.rir_len = r.rir_len;

@@ -20,6 +20,7 @@ struct alignas(16) RoomDev {
     int64_t out_offset;
     int32_t pow_offset;  // wall-power tables at pow_tab[pow_offset + wall * pow_stride + e]
     int32_t pow_stride;  // exponents 0 .. pow_stride-1
+    double inv_L[3];     // 1 / L (index bounds, which carry a margin of one)
 };
 
 // One work item: output samples [s0, s1) of the RIR of microphone `mic`

@@ -344,6 +344,7 @@ struct ItemGeom {
     double Lx, Ly, Lz, sx, sy, sz, rx, ry, rz;
     double dlo2, dhi2;            // squared distance shell of the item's records
     double zeps;                  // margin of the column intervals' z bounds (in z-index units)
+    double inv2Lz;                // 1 / (2 Lz) (its rounding is inside the margin)
     const double *px0, *pz0, *pzL;
     int alo, blo;                 // first (x, y) image column indices
     float inv_nb;                 // 1 / nb
@@ -380,14 +381,16 @@ DEV ItemGeom item_geom(const LaunchDev *P, const ItemDev &it, int K)
     // distance shell of the records this segment needs (widened: every test below is exact);
     // n0 = floor(tau + half) puts tau in [n0 - half, n0 + 1 - half)
     const double half = P->lagrange ? 0.0 : 0.5;
-    const double dlo = fmax(0.0, ((double)G.nlo - half) * cs / fs * (1.0 - 1e-12) - 1e-12);
-    const double dhi = ((double)G.nhi + 1.0 - half) * cs / fs * (1.0 + 1e-12) + 1e-12;
+    const double csf = cs / fs;  // the margins cover its rounding
+    const double dlo = fmax(0.0, ((double)G.nlo - half) * csf * (1.0 - 1e-12) - 1e-12);
+    const double dhi = ((double)G.nhi + 1.0 - half) * csf * (1.0 + 1e-12) + 1e-12;
     G.dlo2 = dlo * dlo;
     G.dhi2 = dhi * dhi;
     // the column intervals' z bounds come from FP32 square roots (relative error below
     // 2^-22 with the FP32 rounding of the argument): widened by this margin in z-index
     // units they still hold every image of the shell
-    G.zeps = 1e-9 + 4e-7 * dhi * (0.5 / G.Lz);
+    G.inv2Lz = 0.5 * R.inv_L[2];
+    G.zeps = 1e-9 + 4e-7 * dhi * G.inv2Lz;
     // Fixed-point scale 2^e: no image is closer than the direct path and every
     // beta <= 1, so g <= 1/(4 pi max(dlo, |s - r|)) =: gb for every record of the
     // item, and |tap| <= g (|h| <= 1); e is the largest exponent with 2^e gb < 2^30.
@@ -399,8 +402,10 @@ DEV ItemGeom item_geom(const LaunchDev *P, const ItemDev &it, int K)
         (void)frexp(gb, &E);  // gb = m 2^E, m in [1/2, 1)
         G.escale = 30 - E;
     }
-    long alo = (long)floor((G.rx - dhi) / G.Lx) - 1, ahi = (long)ceil((G.rx + dhi) / G.Lx) + 1;
-    long blo = (long)floor((G.ry - dhi) / G.Ly) - 1, bhi = (long)ceil((G.ry + dhi) / G.Ly) + 1;
+    // image index bounds (with a margin of one, which also covers the reciprocal's rounding)
+    const double ilx = R.inv_L[0], ily = R.inv_L[1];
+    long alo = (long)floor((G.rx - dhi) * ilx) - 1, ahi = (long)ceil((G.rx + dhi) * ilx) + 1;
+    long blo = (long)floor((G.ry - dhi) * ily) - 1, bhi = (long)ceil((G.ry + dhi) * ily) + 1;
     if (G.N >= 0) {
         const long lim = P->order_mode == 0 ? 2L * G.N + 2 : (long)G.N + 1;
         alo = max(alo, -lim); ahi = min(ahi, lim);
@@ -465,7 +470,7 @@ DEV Column column_setup(const ItemGeom &G, int ci, int order_mode, const double 
     // shell and fails the delay test
     const double zb = (double)__builtin_amdgcn_sqrtf((float)(G.dhi2 - rho2));
     const double za = G.dlo2 > rho2 ? (double)__builtin_amdgcn_sqrtf((float)(G.dlo2 - rho2)) : 0.0;
-    const double inv2L = 0.5 / G.Lz;
+    const double inv2L = G.inv2Lz;
     int ni = 0;
     // interval slot ni (unrolled selects keep the slots in registers)
     auto put = [&](int qq, int ll, int ww) {
@@ -865,7 +870,7 @@ DEV MomColSetup mom_column(const ItemGeom &G, int ci, int order_mode, const doub
     const double zb = (double)__builtin_amdgcn_sqrtf((float)fmax(G.dhi2 - rho2, 0.0));
     const double za = (double)__builtin_amdgcn_sqrtf((float)fmax(G.dlo2 - rho2, 0.0));
     const bool hole = G.dlo2 > rho2;
-    const double inv2L = 0.5 / G.Lz;
+    const double inv2L = G.inv2Lz;
     uint32_t len[4];
     int qw[4];
 #pragma unroll
