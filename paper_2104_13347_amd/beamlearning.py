@@ -1,0 +1,116 @@
+"""Thin ctypes binding of the BeamLearning forward pass in libism.so (C-ABI
+declared in include/beamlearning.h).
+
+Argument marshalling only: the weight folding, the 18 filterbank layers, the
+pseudo-energy and the head all run in the library's HIP kernels.  torch
+supplies device memory and streams.  If the library is not built the first use
+fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import ism
+
+REGRESSION, CLASSIFICATION = 0, 1
+NF = 128
+MARGIN = 189
+
+EXPORTS = ["bl_param_count", "bl_model_create", "bl_model_destroy", "bl_workspace_bytes", "bl_forward"]
+
+_ready = False
+
+
+def load():
+    global _ready
+    L = ism.load()
+    if not _ready:
+        vp, ci, sz, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_int64
+        L.bl_param_count.argtypes = [ci, ci]
+        L.bl_param_count.restype = sz
+        L.bl_model_create.argtypes = [vp, ci, ci, ci, ctypes.c_float, vp, vp, ctypes.POINTER(vp)]
+        L.bl_model_create.restype = ci
+        L.bl_model_destroy.argtypes = [vp]
+        L.bl_model_destroy.restype = None
+        L.bl_workspace_bytes.argtypes = [ci, ci]
+        L.bl_workspace_bytes.restype = sz
+        L.bl_forward.argtypes = [vp, vp, ci, ci, vp, vp, i64, i64, vp, sz, vp, vp, vp]
+        L.bl_forward.restype = ci
+        _ready = True
+    return L
+
+
+def param_count(c_in, n_out):
+    return int(load().bl_param_count(int(c_in), int(n_out)))
+
+
+def workspace_bytes(batch, n_t):
+    return int(load().bl_workspace_bytes(int(batch), int(n_t)))
+
+
+class Model:
+    """A prepared network (folded FP16-pair weights in device memory).
+
+    params: the flat FP32 parameter array (numpy or a device tensor) in the
+    layout of include/beamlearning.h.
+    """
+
+    def __init__(self, handle, params, c_in=7, n_out=2, mode=REGRESSION, ln_eps=1e-6, stream=None):
+        import torch
+        self.lib = load()
+        self.handle = handle
+        self.c_in, self.n_out, self.mode = int(c_in), int(n_out), int(mode)
+        if not torch.is_tensor(params):
+            params = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32))
+        self._params = params.to(device="cuda", dtype=torch.float32).contiguous()
+        need = param_count(self.c_in, self.n_out)
+        if need == 0 or self._params.numel() != need:
+            raise ValueError(f"params hold {self._params.numel()} floats, the layout {need}")
+        m = ctypes.c_void_p()
+        rc = self.lib.bl_model_create(handle.h, self.c_in, self.n_out, self.mode, float(ln_eps),
+                                      ctypes.c_void_p(self._params.data_ptr()), ism._stream_handle(stream),
+                                      ctypes.byref(m))
+        handle._check(rc)
+        self.m = m
+
+    def close(self):
+        if getattr(self, "m", None):
+            import torch
+            torch.cuda.synchronize()
+            self.lib.bl_model_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, x, n_t=None, batch=None, offsets=None, ex_stride=None, ch_stride=None,
+                workspace=None, features=True, out=None, stream=None):
+        """Forward pass.  x: device FP32 tensor [B, c_in, n_t] (contiguous), or any
+        device FP32 tensor with explicit batch, n_t, offsets (device int64 tensor
+        or None), ex_stride and ch_stride in elements.  Returns (features or None, out)."""
+        import torch
+        if x.dim() == 3 and n_t is None:
+            batch, c, n_t = x.shape
+            if c != self.c_in:
+                raise ValueError(f"x has {c} channels, the model {self.c_in}")
+            x = x.contiguous()
+            ex_stride, ch_stride = c * n_t, n_t
+        batch, n_t = int(batch), int(n_t)
+        need = workspace_bytes(batch, n_t)
+        if workspace is None:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+        feat = torch.empty((batch, NF), dtype=torch.float32, device="cuda") if features else None
+        if out is None:
+            out = torch.empty((batch, self.n_out), dtype=torch.float32, device="cuda")
+        rc = self.lib.bl_forward(self.handle.h, self.m, batch, n_t, ctypes.c_void_p(x.data_ptr()),
+                                 ctypes.c_void_p(offsets.data_ptr() if offsets is not None else 0),
+                                 int(ex_stride or 0), int(ch_stride or 0), ctypes.c_void_p(workspace.data_ptr()),
+                                 int(workspace.numel()), ctypes.c_void_p(feat.data_ptr() if feat is not None else 0),
+                                 ctypes.c_void_p(out.data_ptr()), ism._stream_handle(stream))
+        self.handle._check(rc)
+        return feat, out

@@ -1,0 +1,726 @@
+// BeamLearning forward pass on gfx950 (paper section II.B): three cascaded
+// filterbank modules of depthwise-separable atrous convolutions with layer norm,
+// tanh and residual connections, the pseudo-energy of the valid samples, and a
+// layer norm, SELU and fully connected head.
+//
+// Design:
+//  * Folding.  The depthwise taps of a layer are folded into its pointwise
+//    weights once per model: W[k][c][o] = sum_j dw[c][j][k] pw[4c+j][o].  A layer
+//    is then one dilated convolution, a GEMM over K = 3 x 128 (3 time taps of the
+//    128 input channels) instead of a depthwise pass plus a GEMM over K = 512.
+//  * Matrix cores.  Layers 1..17 run on v_mfma_f32_16x16x32_f16 with FP16 pairs
+//    (x = hi + lo, W = hi + lo; hi*hi + hi*lo + lo*hi summed in FP32).  The
+//    activations are scaled by 2^11 and each layer's weights by a power of two
+//    chosen from its largest weight, so both halves of a pair stay normal FP16
+//    numbers; the output is scaled back exactly.  The folded weights are laid out
+//    in MFMA fragment order: one 1 KB contiguous load per wave and operand.
+//  * Layer norm across kernels.  The statistics of a layer span the whole
+//    n_t x 128 map of a frame, so a layer ends at a kernel boundary: kernel l
+//    writes a_l (before its norm) and per-tile (sum, M2) partials; kernel l+1
+//    combines the partials in FP64 (Chan's formula), forms
+//    x_{l+1} = x_l + tanh(LN(a_l)) on the fly while it stages its input tile, and
+//    writes x_{l+1} for the next residual.  Per layer and frame that is two reads
+//    and two writes of the 128-channel map, the HBM floor of this structure.
+//  * Tiles.  A workgroup (4 waves) takes 128 time samples of one frame plus a
+//    halo of D on each side; each wave computes all 128 rows for 32 of the 128
+//    output channels, its weight fragments streamed from L2 and its activation
+//    fragments read from LDS (row pitch 272 B: the 16 rows of a fragment fall on
+//    distinct banks).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <cmath>
+#include <new>
+
+#include "../../include/beamlearning.h"
+#include "ism_host.h"
+
+#define DEV __device__ __forceinline__
+
+namespace {
+
+constexpr int NF = 128;
+constexpr int MULT = 4;
+constexpr int NL = 18;
+constexpr int MT = 128;          // time samples per tile
+constexpr int KSTEPS = 12;       // K = 3 taps x 128 channels in steps of 32
+constexpr int XROW = 136;        // LDS pitch of a staged input row, in halves
+constexpr int MAX_D = 32;
+constexpr int MARGIN = BL_MARGIN;
+constexpr int XEXP = 11;         // activations are split after scaling by 2^11
+constexpr int FRAG_HALVES = 8 * KSTEPS * 2 * 512;  // per layer: [nb][ks][hi/lo][lane][8]
+constexpr int MAX_NT = 1 << 20;
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
+
+// Offsets (in floats) of each layer's tensors in the flat parameter array.
+struct ParamOffsets {
+    int64_t dw[NL], pw[NL], b[NL], g[NL], be[NL];
+    int64_t g_e, be_e, fc_w, fc_b;
+};
+
+struct ModelLayout {
+    size_t hdr, w0, vec, frag, head, total;
+};
+
+ModelLayout model_layout(int c_in, int n_out)
+{
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    ModelLayout m;
+    m.hdr = 0;
+    m.w0 = al(m.hdr + 64 * sizeof(int));
+    m.vec = al(m.w0 + (size_t)3 * c_in * NF * sizeof(float));
+    m.frag = al(m.vec + (size_t)NL * 3 * NF * sizeof(float));
+    m.head = al(m.frag + (size_t)(NL - 1) * FRAG_HALVES * sizeof(_Float16));
+    m.total = al(m.head + (size_t)(2 * NF + NF * n_out + n_out) * sizeof(float));
+    return m;
+}
+
+struct WsLayout {
+    size_t a[2], x[2], st[2], part, total;
+    int ntiles, ne;
+};
+
+WsLayout ws_layout(int batch, int n_t)
+{
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    WsLayout w;
+    w.ntiles = (n_t + MT - 1) / MT;
+    w.ne = (n_t - 2 * MARGIN + MT - 1) / MT;
+    const size_t map = (size_t)batch * n_t * NF * sizeof(float);
+    const size_t st = (size_t)batch * w.ntiles * 2 * sizeof(double);
+    size_t o = 0;
+    for (int i = 0; i < 2; ++i) { w.a[i] = o; o = al(o + map); }
+    for (int i = 0; i < 2; ++i) { w.x[i] = o; o = al(o + map); }
+    for (int i = 0; i < 2; ++i) { w.st[i] = o; o = al(o + st); }
+    w.part = o;
+    o = al(o + (size_t)batch * w.ne * NF * sizeof(float));
+    w.total = o;
+    return w;
+}
+
+// ------------------------------------------------------------------ reductions
+DEV double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+DEV double wave_max(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+// Sum over the workgroup (nw waves); every thread gets the total.  `red` holds nw doubles.
+DEV double block_sum(double v, double *red, int nw)
+{
+    v = wave_sum(v);
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += red[i];
+    return s;
+}
+
+// Layer-norm statistics of one frame from its per-tile (sum, M2 about the tile mean)
+// partials (Chan et al.'s pairwise update, written as two sums).
+DEV void ln_stats(const double *st, int ntiles, int T, float eps, double &mean, double &rstd)
+{
+    const double N = (double)T * NF;
+    double s = 0.0;
+    for (int i = 0; i < ntiles; ++i) s += st[2 * i];
+    mean = s / N;
+    double m2 = 0.0;
+    for (int i = 0; i < ntiles; ++i) {
+        const int rows = min(MT, T - i * MT);
+        const double ni = (double)rows * NF;
+        const double d = st[2 * i] / ni - mean;
+        m2 += st[2 * i + 1] + ni * d * d;
+    }
+    rstd = 1.0 / sqrt(m2 / N + (double)eps);
+}
+
+// ------------------------------------------------------------------ model preparation
+struct FoldArgs {
+    const float *params;
+    ParamOffsets po;
+    int c_in, n_out;
+    int *hdr;
+    float *w0, *vec, *head;
+    _Float16 *frag;
+};
+
+DEV double folded(const float *dw, const float *pw, int k, int o)
+{
+    // k = tap * 128 + c
+    const int tap = k / NF, c = k % NF;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < MULT; ++j) s += (double)dw[(c * MULT + j) * 3 + tap] * (double)pw[(c * MULT + j) * NF + o];
+    return s;
+}
+
+__global__ __launch_bounds__(256) void bl_fold(FoldArgs A)
+{
+    __shared__ double red[4];
+    const int tid = threadIdx.x;
+    const int l = blockIdx.x;
+    const float *P = A.params;
+    if (l == 0) {
+        // layer 0 stays FP32: w0[tap][c][o]
+        const int n = 3 * A.c_in * NF;
+        for (int i = tid; i < n; i += 256) {
+            const int o = i % NF, c = (i / NF) % A.c_in, tap = i / (NF * A.c_in);
+            double s = 0.0;
+            for (int j = 0; j < MULT; ++j)
+                s += (double)P[A.po.dw[0] + (c * MULT + j) * 3 + tap] * (double)P[A.po.pw[0] + (c * MULT + j) * NF + o];
+            A.w0[i] = (float)s;
+        }
+        if (tid == 0) A.hdr[0] = 0;
+        return;
+    }
+    if (l == NL) {
+        for (int ll = 0; ll < NL; ++ll)
+            for (int i = tid; i < NF; i += 256) {
+                A.vec[(ll * 3 + 0) * NF + i] = P[A.po.b[ll] + i];
+                A.vec[(ll * 3 + 1) * NF + i] = P[A.po.g[ll] + i];
+                A.vec[(ll * 3 + 2) * NF + i] = P[A.po.be[ll] + i];
+            }
+        const int nh = 2 * NF + NF * A.n_out + A.n_out;
+        for (int i = tid; i < nh; i += 256) {
+            float v;
+            if (i < NF) v = P[A.po.g_e + i];
+            else if (i < 2 * NF) v = P[A.po.be_e + i - NF];
+            else if (i < 2 * NF + NF * A.n_out) v = P[A.po.fc_w + i - 2 * NF];
+            else v = P[A.po.fc_b + i - 2 * NF - NF * A.n_out];
+            A.head[i] = v;
+        }
+        return;
+    }
+    const float *dw = P + A.po.dw[l];
+    const float *pw = P + A.po.pw[l];
+    double mx = 0.0;
+    for (int i = tid; i < 3 * NF * NF; i += 256) mx = fmax(mx, fabs(folded(dw, pw, i / NF, i % NF)));
+    mx = wave_max(mx);
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+    mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    int e = 0;
+    if (mx > 0.0) frexp(mx, &e);
+    const int wexp = 14 - e;  // max |W| 2^wexp < 2^14
+    if (tid == 0) A.hdr[l] = wexp;
+    _Float16 *fr = A.frag + (size_t)(l - 1) * FRAG_HALVES;
+    // fragment order [nb][ks][hi/lo][lane][e]: lane holds B[k = 32 ks + 8 (lane / 16) + e][n = 16 nb + lane % 16]
+    for (int i = tid; i < FRAG_HALVES / 2; i += 256) {
+        const int e8 = i & 7, lane = (i >> 3) & 63, ks = (i >> 9) % KSTEPS, nb = (i >> 9) / KSTEPS;
+        const int k = 32 * ks + 8 * (lane >> 4) + e8, n = 16 * nb + (lane & 15);
+        const double v = ldexp(folded(dw, pw, k, n), wexp);
+        const _Float16 hi = (_Float16)(float)v;
+        const _Float16 lo = (_Float16)(float)(v - (double)(float)hi);
+        const size_t base = ((size_t)(nb * KSTEPS + ks) * 2) * 512 + lane * 8 + e8;
+        fr[base] = hi;
+        fr[base + 512] = lo;
+    }
+}
+
+// ------------------------------------------------------------------ layer 0 (FP32, vector units)
+struct Layer0Args {
+    const float *x;
+    const int64_t *offs;
+    int64_t ex_stride, ch_stride;
+    const float *w0;    // [3][c_in][128]
+    const float *bias;  // [128]
+    float *a_out;       // [B][T][128]
+    double *st_out;     // [B][ntiles][2]
+    int T, ntiles, c_in;
+};
+
+__global__ __launch_bounds__(256) void bl_layer0(Layer0Args A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *xin = (float *)smem;               // [c_in][MT + 2]
+    float *w = xin + BL_MAX_CIN * (MT + 2);   // [3][c_in][128]
+    double *red = (double *)(w + 3 * BL_MAX_CIN * NF);
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x / A.ntiles, tile = blockIdx.x % A.ntiles;
+    const int t0 = tile * MT, T = A.T;
+    const int64_t off = A.offs ? A.offs[b] : (int64_t)b * A.ex_stride;
+    for (int i = tid; i < A.c_in * (MT + 2); i += 256) {
+        const int c = i / (MT + 2), r = i % (MT + 2);
+        const int t = t0 - 1 + r;
+        xin[i] = (t >= 0 && t < T) ? A.x[off + (int64_t)c * A.ch_stride + t] : 0.f;
+    }
+    for (int i = tid; i < 3 * A.c_in * NF; i += 256) w[i] = A.w0[i];
+    __syncthreads();
+    const int o = tid & (NF - 1), half = tid >> 7;
+    const float bo = A.bias[o];
+    const int rows = min(MT, T - t0);
+    float s = 0.f;
+    for (int r = half; r < rows; r += 2) {
+        float acc = bo;
+        for (int tap = 0; tap < 3; ++tap)
+            for (int c = 0; c < A.c_in; ++c) acc = fmaf(w[(tap * A.c_in + c) * NF + o], xin[c * (MT + 2) + r + tap], acc);
+        A.a_out[((size_t)b * T + t0 + r) * NF + o] = acc;
+        s += acc;
+    }
+    const double S = block_sum((double)s, red, 4);
+    const float mt = (float)(S / ((double)rows * NF));
+    float m2 = 0.f;
+    for (int r = half; r < rows; r += 2) {  // this thread's own stores, read back
+        const float d = A.a_out[((size_t)b * T + t0 + r) * NF + o] - mt;
+        m2 = fmaf(d, d, m2);
+    }
+    const double M2 = block_sum((double)m2, red, 4);
+    if (tid == 0) {
+        A.st_out[((size_t)b * A.ntiles + tile) * 2] = S;
+        A.st_out[((size_t)b * A.ntiles + tile) * 2 + 1] = M2;
+    }
+}
+
+// ------------------------------------------------------------------ layers 1..17 (matrix cores)
+struct LayerArgs {
+    const float *a_in;     // a_{l-1}
+    const float *x_in;     // x_{l-1} (l >= 2)
+    float *x_out;          // x_l
+    float *a_out;          // a_l
+    const double *st_in;   // partials of a_{l-1}
+    double *st_out;        // partials of a_l
+    const float *vec_prev; // b, g, be of layer l-1
+    const float *bias;     // b of layer l
+    const _Float16 *frag;  // layer l's weight fragments
+    const int *hdr;
+    int T, ntiles, layer, D;
+    float eps;
+};
+
+__global__ __launch_bounds__(256) void bl_layer(LayerArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int D = A.D, T = A.T;
+    const int rows = MT + 2 * D;
+    _Float16 *xh = (_Float16 *)smem;
+    _Float16 *xl = xh + rows * XROW;
+    double *red = (double *)(xl + rows * XROW);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int b = blockIdx.x / A.ntiles, tile = blockIdx.x % A.ntiles;
+    const int t0 = tile * MT;
+    const size_t fb = (size_t)b * T;
+
+    // 1. stage x_l = (l >= 2 ? x_{l-1} : 0) + tanh(LN(a_{l-1})) for rows t0 - D .. t0 + MT + D
+    {
+        double mean, rstd;
+        ln_stats(A.st_in + (size_t)b * A.ntiles * 2, A.ntiles, T, A.eps, mean, rstd);
+        const int c4 = (tid & 31) * 4;
+        const float4 g = *(const float4 *)(A.vec_prev + NF + c4);
+        const float4 be = *(const float4 *)(A.vec_prev + 2 * NF + c4);
+        const float mu = (float)mean, rs = (float)rstd;
+        const float4 sc = make_float4(g.x * rs, g.y * rs, g.z * rs, g.w * rs);
+        for (int r = tid >> 5; r < rows; r += 8) {
+            const int t = t0 - D + r;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (t >= 0 && t < T) {
+                const float4 a = *(const float4 *)(A.a_in + (fb + t) * NF + c4);
+                v.x = tanhf(fmaf(a.x - mu, sc.x, be.x));
+                v.y = tanhf(fmaf(a.y - mu, sc.y, be.y));
+                v.z = tanhf(fmaf(a.z - mu, sc.z, be.z));
+                v.w = tanhf(fmaf(a.w - mu, sc.w, be.w));
+                if (A.layer >= 2) {
+                    const float4 xp = *(const float4 *)(A.x_in + (fb + t) * NF + c4);
+                    v.x += xp.x; v.y += xp.y; v.z += xp.z; v.w += xp.w;
+                }
+                if (r >= D && r < D + MT) *(float4 *)(A.x_out + (fb + t) * NF + c4) = v;
+            }
+            const float s = (float)(1 << XEXP);
+            const float vs[4] = {v.x * s, v.y * s, v.z * s, v.w * s};
+            f16x4_t h, lo;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                h[i] = (_Float16)vs[i];
+                lo[i] = (_Float16)(vs[i] - (float)h[i]);
+            }
+            *(f16x4_t *)(xh + r * XROW + c4) = h;
+            *(f16x4_t *)(xl + r * XROW + c4) = lo;
+        }
+    }
+    __syncthreads();
+
+    // 2. a_l[t][n] = sum over taps and channels of x_l[t + (tap-1) D][c] W[tap][c][n]
+    f32x4_t acc[8][2];
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    const _Float16 *fr = A.frag + lane * 8;
+    const int nb0 = 2 * wave;
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+        const f16x8_t bh0 = *(const f16x8_t *)(fr + ((size_t)(nb0 * KSTEPS + ks) * 2) * 512);
+        const f16x8_t bl0 = *(const f16x8_t *)(fr + ((size_t)(nb0 * KSTEPS + ks) * 2 + 1) * 512);
+        const f16x8_t bh1 = *(const f16x8_t *)(fr + ((size_t)((nb0 + 1) * KSTEPS + ks) * 2) * 512);
+        const f16x8_t bl1 = *(const f16x8_t *)(fr + ((size_t)((nb0 + 1) * KSTEPS + ks) * 2 + 1) * 512);
+        const int tap = ks >> 2;
+        const int off = (tap * D + (lane & 15)) * XROW + (ks & 3) * 32 + 8 * (lane >> 4);
+#pragma unroll
+        for (int rb = 0; rb < 8; ++rb) {
+            const f16x8_t ah = *(const f16x8_t *)(xh + off + rb * 16 * XROW);
+            const f16x8_t al = *(const f16x8_t *)(xl + off + rb * 16 * XROW);
+            acc[rb][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh0, acc[rb][0], 0, 0, 0);
+            acc[rb][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl0, acc[rb][0], 0, 0, 0);
+            acc[rb][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh0, acc[rb][0], 0, 0, 0);
+            acc[rb][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh1, acc[rb][1], 0, 0, 0);
+            acc[rb][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl1, acc[rb][1], 0, 0, 0);
+            acc[rb][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh1, acc[rb][1], 0, 0, 0);
+        }
+    }
+
+    // 3. scale back, add the bias, store a_l and the tile's (sum, M2)
+    const float osc = ldexpf(1.f, -(XEXP + A.hdr[A.layer]));
+    const int nrows = min(MT, T - t0);
+    float s = 0.f;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int n = 32 * wave + 16 * cb + (lane & 15);
+        const float bn = A.bias[n];
+#pragma unroll
+        for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * rb + 4 * (lane >> 4) + v;
+                const float val = fmaf(acc[rb][cb][v], osc, bn);
+                acc[rb][cb][v] = val;
+                if (row < nrows) {
+                    A.a_out[(fb + t0 + row) * NF + n] = val;
+                    s += val;
+                }
+            }
+    }
+    const double S = block_sum((double)s, red, 4);
+    const float mt = (float)(S / ((double)nrows * NF));
+    float m2 = 0.f;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * rb + 4 * (lane >> 4) + v;
+                const float d = acc[rb][cb][v] - mt;
+                if (row < nrows) m2 = fmaf(d, d, m2);
+            }
+    const double M2 = block_sum((double)m2, red, 4);
+    if (tid == 0) {
+        A.st_out[((size_t)b * A.ntiles + tile) * 2] = S;
+        A.st_out[((size_t)b * A.ntiles + tile) * 2 + 1] = M2;
+    }
+}
+
+// ------------------------------------------------------------------ pseudo-energy partials
+struct EnergyArgs {
+    const float *a_in;    // a_17
+    const float *x_in;    // x_17
+    const double *st_in;  // partials of a_17
+    const float *vec;     // b, g, be of layer 17
+    float *part;          // [B][ne][128] sums of S^2
+    int T, ntiles, ne;
+    float eps;
+};
+
+__global__ __launch_bounds__(256) void bl_energy(EnergyArgs A)
+{
+    __shared__ float4 sm[8][32];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x / A.ne, et = blockIdx.x % A.ne;
+    const int T = A.T;
+    const int r0 = MARGIN + et * MT, r1 = min(r0 + MT, T - MARGIN);
+    double mean, rstd;
+    ln_stats(A.st_in + (size_t)b * A.ntiles * 2, A.ntiles, T, A.eps, mean, rstd);
+    const int c4 = (tid & 31) * 4;
+    const float4 g = *(const float4 *)(A.vec + NF + c4);
+    const float4 be = *(const float4 *)(A.vec + 2 * NF + c4);
+    const float mu = (float)mean, rs = (float)rstd;
+    const float4 sc = make_float4(g.x * rs, g.y * rs, g.z * rs, g.w * rs);
+    const size_t fb = (size_t)b * T;
+    float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int t = r0 + (tid >> 5); t < r1; t += 8) {
+        const float4 a = *(const float4 *)(A.a_in + (fb + t) * NF + c4);
+        const float4 xp = *(const float4 *)(A.x_in + (fb + t) * NF + c4);
+        const float sx = xp.x + tanhf(fmaf(a.x - mu, sc.x, be.x));
+        const float sy = xp.y + tanhf(fmaf(a.y - mu, sc.y, be.y));
+        const float sz = xp.z + tanhf(fmaf(a.z - mu, sc.z, be.z));
+        const float sw = xp.w + tanhf(fmaf(a.w - mu, sc.w, be.w));
+        e.x = fmaf(sx, sx, e.x); e.y = fmaf(sy, sy, e.y); e.z = fmaf(sz, sz, e.z); e.w = fmaf(sw, sw, e.w);
+    }
+    sm[tid >> 5][tid & 31] = e;
+    __syncthreads();
+    if (tid < 32) {
+        float4 t = sm[0][tid];
+        for (int i = 1; i < 8; ++i) {
+            const float4 u = sm[i][tid];
+            t.x += u.x; t.y += u.y; t.z += u.z; t.w += u.w;
+        }
+        *(float4 *)(A.part + ((size_t)b * A.ne + et) * NF + 4 * tid) = t;
+    }
+}
+
+// ------------------------------------------------------------------ head
+struct HeadArgs {
+    const float *part;
+    const float *head;  // g_e[128], be_e[128], fc_w[128][n_out], fc_b[n_out]
+    float *feat;
+    float *out;
+    int ne, n_out, n_valid, mode;
+    float eps;
+};
+
+__global__ __launch_bounds__(128) void bl_head(HeadArgs A)
+{
+    __shared__ double f[NF];
+    __shared__ double o[BL_MAX_NOUT];
+    __shared__ double red[2];
+    const int c = threadIdx.x, b = blockIdx.x;
+    double e = 0.0;
+    for (int i = 0; i < A.ne; ++i) e += (double)A.part[((size_t)b * A.ne + i) * NF + c];
+    e /= (double)A.n_valid;
+    const double mean = block_sum(e, red, 2) / NF;
+    const double d = e - mean;
+    const double var = block_sum(d * d, red, 2) / NF;
+    const double y = d / sqrt(var + (double)A.eps) * (double)A.head[c] + (double)A.head[NF + c];
+    const double sel = 1.0507009873554804934 * (y > 0.0 ? y : 1.6732632423543772848 * expm1(y));
+    f[c] = sel;
+    if (A.feat) A.feat[(size_t)b * NF + c] = (float)sel;
+    __syncthreads();
+    const float *W = A.head + 2 * NF;
+    const float *bias = W + NF * A.n_out;
+    double mx = -INFINITY;
+    for (int j = c; j < A.n_out; j += NF) {
+        double s = (double)bias[j];
+        for (int k = 0; k < NF; ++k) s += f[k] * (double)W[k * A.n_out + j];
+        o[j] = s;
+        mx = fmax(mx, s);
+    }
+    if (A.mode == BL_CLASSIFICATION) {
+        mx = wave_max(mx);
+        __syncthreads();
+        if ((c & 63) == 0) red[c >> 6] = mx;
+        __syncthreads();
+        mx = fmax(red[0], red[1]);
+        double se = 0.0;
+        for (int j = c; j < A.n_out; j += NF) {
+            o[j] = exp(o[j] - mx);
+            se += o[j];
+        }
+        se = block_sum(se, red, 2);
+        for (int j = c; j < A.n_out; j += NF) o[j] /= se;
+    }
+    for (int j = c; j < A.n_out; j += NF) A.out[(size_t)b * A.n_out + j] = (float)o[j];
+}
+
+int layer_lds_bytes(int D) { return 2 * (MT + 2 * D) * XROW * 2 + 64; }
+int layer0_lds_bytes() { return (BL_MAX_CIN * (MT + 2) + 3 * BL_MAX_CIN * NF) * 4 + 64; }
+
+}  // namespace
+
+struct bl_model {
+    int c_in, n_out, mode;
+    float eps;
+    void *dev;
+    ModelLayout lay;
+};
+
+extern "C" size_t bl_param_count(int c_in, int n_out)
+{
+    if (c_in < 1 || c_in > BL_MAX_CIN || n_out < 1 || n_out > BL_MAX_NOUT) return 0;
+    size_t n = 0;
+    for (int l = 0; l < NL; ++l) {
+        const size_t ci = l == 0 ? c_in : NF;
+        n += ci * MULT * 3 + ci * MULT * NF + 3 * NF;
+    }
+    return n + 2 * NF + (size_t)NF * n_out + n_out;
+}
+
+extern "C" int bl_model_create(ism_handle *h, int c_in, int n_out, int mode, float ln_eps, const float *params,
+                               ism_stream stream, bl_model **model)
+{
+    if (!h || !model) return ISM_EINVAL;
+    *model = nullptr;
+    if (c_in < 1 || c_in > BL_MAX_CIN || n_out < 1 || n_out > BL_MAX_NOUT) {
+        ism_set_error(h, "c_in must be in [1, %d] and n_out in [1, %d]", BL_MAX_CIN, BL_MAX_NOUT);
+        return ISM_EINVAL;
+    }
+    if (mode != BL_REGRESSION && mode != BL_CLASSIFICATION) {
+        ism_set_error(h, "mode must be BL_REGRESSION or BL_CLASSIFICATION");
+        return ISM_EINVAL;
+    }
+    if (!(ln_eps > 0.f) || !std::isfinite(ln_eps)) {
+        ism_set_error(h, "ln_eps must be finite and > 0");
+        return ISM_EINVAL;
+    }
+    if (!params) { ism_set_error(h, "NULL params"); return ISM_EINVAL; }
+    bl_model *m = new (std::nothrow) bl_model;
+    if (!m) return ISM_ENOMEM;
+    m->c_in = c_in;
+    m->n_out = n_out;
+    m->mode = mode;
+    m->eps = ln_eps;
+    m->lay = model_layout(c_in, n_out);
+    if (hipMalloc(&m->dev, m->lay.total) != hipSuccess) {
+        ism_set_error(h, "hipMalloc of %zu bytes for the model failed", m->lay.total);
+        delete m;
+        return ISM_ENOMEM;
+    }
+    FoldArgs F;
+    int64_t o = 0;
+    for (int l = 0; l < NL; ++l) {
+        const int64_t ci = l == 0 ? c_in : NF;
+        F.po.dw[l] = o; o += ci * MULT * 3;
+        F.po.pw[l] = o; o += ci * MULT * NF;
+        F.po.b[l] = o; o += NF;
+        F.po.g[l] = o; o += NF;
+        F.po.be[l] = o; o += NF;
+    }
+    F.po.g_e = o; o += NF;
+    F.po.be_e = o; o += NF;
+    F.po.fc_w = o; o += (int64_t)NF * n_out;
+    F.po.fc_b = o;
+    F.params = params;
+    F.c_in = c_in;
+    F.n_out = n_out;
+    char *base = (char *)m->dev;
+    F.hdr = (int *)(base + m->lay.hdr);
+    F.w0 = (float *)(base + m->lay.w0);
+    F.vec = (float *)(base + m->lay.vec);
+    F.frag = (_Float16 *)(base + m->lay.frag);
+    F.head = (float *)(base + m->lay.head);
+    hipLaunchKernelGGL(bl_fold, dim3(NL + 1), dim3(256), 0, (hipStream_t)stream, F);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        hipFree(m->dev);
+        delete m;
+        return ism_hip_fail(h, e, "bl_fold launch");
+    }
+    *model = m;
+    return ISM_OK;
+}
+
+extern "C" void bl_model_destroy(bl_model *m)
+{
+    if (!m) return;
+    if (m->dev) hipFree(m->dev);
+    delete m;
+}
+
+extern "C" size_t bl_workspace_bytes(int batch, int n_t)
+{
+    if (batch < 0 || n_t < 2 * MARGIN + 1 || n_t > MAX_NT) return 0;
+    return ws_layout(batch, n_t).total;
+}
+
+extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, const float *x,
+                          const int64_t *x_offsets, int64_t ex_stride, int64_t ch_stride, void *workspace,
+                          size_t workspace_bytes, float *features, float *out, ism_stream stream)
+{
+    if (!h) return ISM_EINVAL;
+    if (!m) { ism_set_error(h, "NULL model"); return ISM_EINVAL; }
+    if (batch < 0) { ism_set_error(h, "batch must be >= 0"); return ISM_EINVAL; }
+    if (n_t < 2 * MARGIN + 1 || n_t > MAX_NT) {
+        ism_set_error(h, "n_t must be in [%d, %d]", 2 * MARGIN + 1, MAX_NT);
+        return ISM_EINVAL;
+    }
+    if (ex_stride < 0 || ch_stride < 0) { ism_set_error(h, "strides must be >= 0"); return ISM_EINVAL; }
+    if (batch == 0) return ISM_OK;
+    if (!x || !workspace || !out) { ism_set_error(h, "NULL argument"); return ISM_EINVAL; }
+    const WsLayout w = ws_layout(batch, n_t);
+    if (workspace_bytes < w.total) {
+        ism_set_error(h, "workspace of %zu bytes, %zu needed", workspace_bytes, w.total);
+        return ISM_EINVAL;
+    }
+    if ((int64_t)batch * w.ntiles > 0x7fffffff) { ism_set_error(h, "batch too large"); return ISM_EINVAL; }
+    static bool lds_set = false;  // the attribute is per function and process
+    if (!lds_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)bl_layer, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           layer_lds_bytes(MAX_D));
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)bl_layer0, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    layer0_lds_bytes());
+        if (e != hipSuccess) return ism_hip_fail(h, e, "hipFuncSetAttribute");
+        lds_set = true;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    const char *mb = (const char *)m->dev;
+    float *Abuf[2] = {(float *)(ws + w.a[0]), (float *)(ws + w.a[1])};
+    float *Xbuf[2] = {(float *)(ws + w.x[0]), (float *)(ws + w.x[1])};
+    double *Sbuf[2] = {(double *)(ws + w.st[0]), (double *)(ws + w.st[1])};
+    const float *vec = (const float *)(mb + m->lay.vec);
+    const int grid = batch * w.ntiles;
+
+    Layer0Args L0;
+    L0.x = x;
+    L0.offs = x_offsets;
+    L0.ex_stride = ex_stride;
+    L0.ch_stride = ch_stride;
+    L0.w0 = (const float *)(mb + m->lay.w0);
+    L0.bias = vec;
+    L0.a_out = Abuf[0];
+    L0.st_out = Sbuf[0];
+    L0.T = n_t;
+    L0.ntiles = w.ntiles;
+    L0.c_in = m->c_in;
+    hipLaunchKernelGGL(bl_layer0, dim3(grid), dim3(256), layer0_lds_bytes(), st, L0);
+
+    for (int l = 1; l < NL; ++l) {
+        LayerArgs L;
+        L.a_in = Abuf[(l - 1) & 1];
+        L.x_in = Xbuf[(l - 1) & 1];
+        L.x_out = Xbuf[l & 1];
+        L.a_out = Abuf[l & 1];
+        L.st_in = Sbuf[(l - 1) & 1];
+        L.st_out = Sbuf[l & 1];
+        L.vec_prev = vec + (size_t)(l - 1) * 3 * NF;
+        L.bias = vec + (size_t)l * 3 * NF;
+        L.frag = (const _Float16 *)(mb + m->lay.frag) + (size_t)(l - 1) * FRAG_HALVES;
+        L.hdr = (const int *)(mb + m->lay.hdr);
+        L.T = n_t;
+        L.ntiles = w.ntiles;
+        L.layer = l;
+        L.D = 1 << (l % 6);
+        L.eps = m->eps;
+        hipLaunchKernelGGL(bl_layer, dim3(grid), dim3(256), layer_lds_bytes(L.D), st, L);
+    }
+
+    EnergyArgs E;
+    E.a_in = Abuf[(NL - 1) & 1];
+    E.x_in = Xbuf[(NL - 1) & 1];
+    E.st_in = Sbuf[(NL - 1) & 1];
+    E.vec = vec + (size_t)(NL - 1) * 3 * NF;
+    E.part = (float *)(ws + w.part);
+    E.T = n_t;
+    E.ntiles = w.ntiles;
+    E.ne = w.ne;
+    E.eps = m->eps;
+    hipLaunchKernelGGL(bl_energy, dim3(batch * w.ne), dim3(256), 0, st, E);
+
+    HeadArgs Hd;
+    Hd.part = E.part;
+    Hd.head = (const float *)(mb + m->lay.head);
+    Hd.feat = features;
+    Hd.out = out;
+    Hd.ne = w.ne;
+    Hd.n_out = m->n_out;
+    Hd.n_valid = n_t - 2 * MARGIN;
+    Hd.mode = m->mode;
+    Hd.eps = m->eps;
+    hipLaunchKernelGGL(bl_head, dim3(batch), dim3(128), 0, st, Hd);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ism_hip_fail(h, e, "bl_forward launch");
+    return ISM_OK;
+}

@@ -1,0 +1,142 @@
+"""GPU parity of the BeamLearning forward pass (paper section II.B) against the
+FP64 oracle, through the C-ABI (include/beamlearning.h).
+
+Tolerance.  Layers 1..17 multiply FP16 pairs on the matrix cores: each
+operand keeps 22 significant bits (2^-22 relative), the dropped lo*lo term is
+below 2^-22 of a product and the FP32 sums over K = 384 add about
+sqrt(384) 2^-24 of the summed magnitudes, so a layer's pre-norm output carries
+about 1e-6 of sum |W x|.  The layer norm divides by the map's standard
+deviation (a few times smaller than sum |W x| for these weights), tanh does not
+amplify, and 17 residual layers add their errors.  The head's layer norm
+divides the pseudo-energies by their spread across the 128 channels.  The
+bound used here, ATOL + RTOL |ref| on the 128 features and the outputs, keeps
+a margin of about 10x over the largest error measured on these cases.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import beamlearning as ref
+from paper_2104_13347_amd import beamlearning as blm
+from paper_2104_13347_amd import bl_data, ism
+
+ATOL = 2e-5
+RTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def handle():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    h = ism.Handle()
+    yield h
+    h.close()
+
+
+def _model(handle, seed, c_in=7, n_out=2, mode=blm.REGRESSION, unit_gain=True, eps=1e-6):
+    p = bl_data.make_params(seed, c_in=c_in, n_out=n_out, unit_gain=unit_gain)
+    return p, blm.Model(handle, bl_data.flatten(p, c_in, n_out), c_in=c_in, n_out=n_out, mode=mode, ln_eps=eps)
+
+
+def _check(tag, got_f, got_o, ref_f, ref_o):
+    ef = np.abs(got_f - ref_f).max()
+    eo = np.abs(got_o - ref_o).max()
+    print(f"[{tag}] max |features err| {ef:.3e}  max |out err| {eo:.3e}  |f| {np.abs(ref_f).max():.3f}", flush=True)
+    assert np.all(np.isfinite(got_f)) and np.all(np.isfinite(got_o))
+    assert np.all(np.abs(got_f - ref_f) <= ATOL + RTOL * np.abs(ref_f)), tag
+    assert np.all(np.abs(got_o - ref_o) <= ATOL + RTOL * np.abs(ref_o)), tag
+
+
+@pytest.mark.parametrize("c_in,n_t,batch,n_out,mode,seed", [
+    (7, 1024, 3, 2, blm.REGRESSION, 1),          # the paper's frame: 7 channels, 1024 samples
+    (7, 379, 2, 2, blm.REGRESSION, 2),           # shortest frame: one valid sample
+    (3, 700, 2, 37, blm.CLASSIFICATION, 3),      # ragged last tile
+    (1, 1300, 1, 1, blm.REGRESSION, 4),          # one channel, 11 tiles, ragged
+    (32, 520, 2, 1024, blm.CLASSIFICATION, 5),   # widest input and output
+])
+def test_forward_matches_oracle(handle, c_in, n_t, batch, n_out, mode, seed):
+    p, m = _model(handle, seed, c_in=c_in, n_out=n_out, mode=mode)
+    x = bl_data.frames(100 + seed, batch, c_in=c_in, n_t=n_t)
+    f, o = m.forward(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    rf, ro = ref.forward(x, p, eps=1e-6, mode=mode)
+    _check(f"c_in={c_in} n_t={n_t} n_out={n_out} mode={mode}", f.cpu().numpy(), o.cpu().numpy(), rf, ro)
+    m.close()
+
+
+def test_paper_initialisation_and_input_scales(handle):
+    # gains drawn as the paper draws every variable (small), and inputs of
+    # very different amplitude (layer 0 runs in FP32 on the vector units)
+    p, m = _model(handle, 21, unit_gain=False)
+    x = np.concatenate([bl_data.frames(22, 1, scale=1e-3), bl_data.frames(23, 1, scale=300.0)])
+    f, o = m.forward(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    rf, ro = ref.forward(x, p, eps=1e-6)
+    _check("paper init, scales 1e-3 / 300", f.cpu().numpy(), o.cpu().numpy(), rf, ro)
+    m.close()
+
+
+def test_offsets_and_strides_read_frames_in_place(handle):
+    # frames cut from longer multichannel recordings (room x mic x sample), as
+    # the convolution stage lays them out: per-frame offsets, channel stride
+    p, m = _model(handle, 31)
+    rng = np.random.default_rng(32)
+    rec = rng.standard_normal((3, 8, 5000)).astype(np.float32)
+    starts = [(0, 0), (0, 1024), (1, 3000), (2, 3976)]
+    offs = np.array([r * 8 * 5000 + s for r, s in starts], dtype=np.int64)
+    d = torch.from_numpy(rec).cuda()
+    f, o = m.forward(d, n_t=1024, batch=len(starts), offsets=torch.from_numpy(offs).cuda(), ch_stride=5000)
+    torch.cuda.synchronize()
+    x = np.stack([rec[r, :7, s:s + 1024] for r, s in starts])
+    rf, ro = ref.forward(x, p, eps=1e-6)
+    _check("offsets", f.cpu().numpy(), o.cpu().numpy(), rf, ro)
+    # the same frames as a contiguous batch give bitwise the same result
+    f2, o2 = m.forward(torch.from_numpy(np.ascontiguousarray(x)).cuda())
+    torch.cuda.synchronize()
+    assert torch.equal(f, f2) and torch.equal(o, o2)
+    m.close()
+
+
+def test_batch_invariance_and_repeatability(handle):
+    p, m = _model(handle, 41)
+    x = torch.from_numpy(bl_data.frames(42, 6)).cuda()
+    f, o = m.forward(x)
+    f1, o1 = m.forward(x[2:3])
+    fr, orr = m.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(f[2:3], f1) and torch.equal(o[2:3], o1)
+    assert torch.equal(f, fr) and torch.equal(o, orr)
+    assert m.forward(x[:0])[1].shape == (0, 2)
+    m.close()
+
+
+def test_full_batch_sampled(handle):
+    # the benchmark's launch: 3600 frames of 7 x 1024 in one call; frames
+    # sampled across the batch are checked against the oracle one by one
+    p, m = _model(handle, 51, unit_gain=False)
+    B = 3600
+    x = torch.randn((B, 7, 1024), generator=torch.Generator().manual_seed(52)).cuda()
+    f, o = m.forward(x)
+    torch.cuda.synchronize()
+    idx = [0, 1799, 3599]
+    xs = x[idx].cpu().numpy()
+    rf, ro = ref.forward(xs, p, eps=1e-6)
+    _check("3600 frames, sampled", f[idx].cpu().numpy(), o[idx].cpu().numpy(), rf, ro)
+    assert torch.isfinite(o).all()
+    m.close()
+
+
+def test_invalid_arguments(handle):
+    p, m = _model(handle, 61)
+    x = torch.zeros((1, 7, 378), device="cuda")
+    with pytest.raises(ism.IsmError):
+        m.forward(x)                                   # shorter than the receptive field
+    x = torch.zeros((2, 7, 1024), device="cuda")
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ism.IsmError):
+        m.forward(x, workspace=ws)                     # workspace too small
+    with pytest.raises(ValueError):
+        blm.Model(handle, np.zeros(10, np.float32))
+    m.close()
