@@ -170,6 +170,67 @@ def bench_c4(H, torch):
     return res
 
 
+def bench_beamlearning(H, torch):
+    """BeamLearning forward pass (section II.B) over 3600 frames of 7 x 1024 samples, the size of
+    the paper's 3600-localisation test set, cut on the device from the recordings of the
+    convolution stage (256 rooms, 8 mics, 1 s at 16 kHz; 15 frames per room, 7 of the 8
+    channels) through per-frame offsets.  Weights drawn as the paper initialises them.  The
+    paper times its inference one frame at a time, so the one-frame latency is reported too."""
+    from paper_2104_13347_amd import beamlearning as blm, bl_data, ism, scenes
+    b = scenes.c4()
+    rooms = ism.rooms_array(b)
+    rirs = torch.empty(int(b["out_size"]), dtype=torch.float32, device="cuda")
+    H.rir_batch(b, out=rirs, rooms=rooms)
+    y = H.convolve_batch(rirs, b["out_offset"], b["rir_len"], 8, torch.from_numpy(b["x"]).cuda(), 16000,
+                         snr_db=b["snr_db"], z=torch.from_numpy(b["z"]).cuda())
+    B, NT, CIN = 3600, 1024, 7
+    idx = np.arange(B)
+    offs = torch.from_numpy((idx // 15) * 8 * 16000 + (idx % 15) * NT).to(torch.int64).cuda()
+    model = blm.Model(H, bl_data.flatten(bl_data.make_params(2104), CIN, 2), c_in=CIN, n_out=2)
+    ws = torch.empty(blm.workspace_bytes(B, NT), dtype=torch.uint8, device="cuda")
+    out = torch.empty((B, 2), dtype=torch.float32, device="cuda")
+    run = lambda: model.forward(y, n_t=NT, batch=B, offsets=offs, ch_stride=16000, workspace=ws,
+                                features=False, out=out)
+    ms = _time_it(torch, run, reps=5)
+    ws1 = torch.empty(blm.workspace_bytes(1, NT), dtype=torch.uint8, device="cuda")
+    out1 = torch.empty((1, 2), dtype=torch.float32, device="cuda")
+    one = lambda: model.forward(y, n_t=NT, batch=1, offsets=offs[:1], ch_stride=16000, workspace=ws1,
+                                features=False, out=out1)
+    lat = [_time_it(torch, one, reps=1) for _ in range(30)]
+    # algorithmic HBM bytes per frame: layer 0 reads the frame and writes a_0; layer 1 reads
+    # a_0 and writes x_1, a_1; layers 2..17 read a, x and write x, a; the pseudo-energy reads
+    # a_17 and x_17 on the valid samples
+    m = NT * 128 * 4
+    per_frame = CIN * NT * 4 + m + 3 * m + 16 * 4 * m + 2 * (NT - 2 * 189) * 128 * 4
+    gbs = B * per_frame / (ms / 1e3) / 1e9
+    model.close()
+    return {"workload": "3600 frames x 7 ch x 1024 samples cut from 256 rooms x 8 mics x 1 s recordings; "
+                        "18 filterbank layers + pseudo-energy + head, paper-initialised weights",
+            "ms": ms, "frames_per_s": B / (ms / 1e3), "us_per_frame": ms * 1e3 / B,
+            "batch1_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+            "paper_gtx1080ti_batch1_ms": 16.2e3 / 3600,
+            "algorithmic_bytes_per_frame": per_frame,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0}}
+
+
+def cpu_baseline_beamlearning(n_frames=2):
+    """The FP64 BeamLearning oracle on a bounded sample: n_frames frames of 7 x 1024."""
+    from oracle import beamlearning as ref
+    from paper_2104_13347_amd import bl_data
+    p = bl_data.make_params(2104)
+    x = bl_data.frames(7, n_frames)
+    t = time.perf_counter()
+    ref.forward(x, p)
+    s = (time.perf_counter() - t) / n_frames
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        cores = 1
+    return {"value": 1.0 / s, "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_frames} frames of 7 x 1024, numpy FP64 (BLAS threads for the pointwise products)"}
+
+
 def bench_c2(torch, n_requests):
     """Serving: Poisson arrivals of single-room requests (RT60 U[0.1,1.0] s, RIR RT60*fs, M in
     {4,8,16,32}).  First a saturated run (all requests at t=0) gives the sustainable rate; then
@@ -210,9 +271,10 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the serving, precision and convolution sections")
-    ap.add_argument("--extras", default="c3,c4,paper,c2",
+    ap.add_argument("--extras", default="c3,c4,paper,c2,beamlearning",
                     help="comma list of extra sections to run: c3 precision, c4 convolution, paper (the "
-                         "paper's 336 000-RIR room dataset), c2 serving")
+                         "paper's 336 000-RIR room dataset), c2 serving, beamlearning (the paper's network "
+                         "on frames of the convolution stage)")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="run only a plain device copy of this many bytes (HBM counter calibration)")
@@ -353,6 +415,11 @@ def main():
             res["extras"]["paper_room1_dataset"] = bench_paper(H, torch)
         if "c2" in extras:
             res["extras"]["c2_serving"] = bench_c2(torch, args.serve_requests)
+        if "beamlearning" in extras:
+            bl = bench_beamlearning(H, torch)
+            if not args.no_cpu_baseline:
+                bl["cpu_baseline"] = cpu_baseline_beamlearning()
+            res["extras"]["beamlearning_forward"] = bl
     H.close()
 
     if not args.no_cpu_baseline:

@@ -45,7 +45,7 @@ namespace {
 constexpr int NF = 128;
 constexpr int MULT = 4;
 constexpr int NL = 18;
-constexpr int MT = 128;          // time samples per tile
+constexpr int MT = 64;           // time samples per tile
 constexpr int KSTEPS = 12;       // K = 3 taps x 128 channels in steps of 32
 constexpr int XROW = 136;        // LDS pitch of a staged input row, in halves
 constexpr int MAX_D = 32;
@@ -133,21 +133,33 @@ DEV double block_sum(double v, double *red, int nw)
 }
 
 // Layer-norm statistics of one frame from its per-tile (sum, M2 about the tile mean)
-// partials (Chan et al.'s pairwise update, written as two sums).
+// partials (Chan et al.'s pairwise update, written as two sums), each sum spread over
+// the lanes of a wave; every wave computes them for itself.
 DEV void ln_stats(const double *st, int ntiles, int T, float eps, double &mean, double &rstd)
 {
+    const int lane = threadIdx.x & 63;
     const double N = (double)T * NF;
     double s = 0.0;
-    for (int i = 0; i < ntiles; ++i) s += st[2 * i];
-    mean = s / N;
+    for (int i = lane; i < ntiles; i += 64) s += st[2 * i];
+    mean = wave_sum(s) / N;
     double m2 = 0.0;
-    for (int i = 0; i < ntiles; ++i) {
+    for (int i = lane; i < ntiles; i += 64) {
         const int rows = min(MT, T - i * MT);
         const double ni = (double)rows * NF;
         const double d = st[2 * i] / ni - mean;
         m2 += st[2 * i + 1] + ni * d * d;
     }
-    rstd = 1.0 / sqrt(m2 / N + (double)eps);
+    rstd = 1.0 / sqrt(wave_sum(m2) / N + (double)eps);
+}
+
+// tanh(y) = sign(y) (1 - 2 r), r = 1 / (2^(2 log2(e) |y|) + 1), with the hardware exp2
+// and reciprocal (about one ulp each).  Absolute error below about 2e-7: near y = 0 it
+// is the rounding of 1 - 2r, for large |y| it shrinks with r.
+DEV float tanh_fast(float y)
+{
+    const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * fabsf(y));
+    const float t = fmaf(-2.f, __builtin_amdgcn_rcpf(e + 1.f), 1.f);
+    return copysignf(t, y);
 }
 
 // ------------------------------------------------------------------ model preparation
@@ -245,42 +257,68 @@ struct Layer0Args {
     int T, ntiles, c_in;
 };
 
-__global__ __launch_bounds__(256) void bl_layer0(Layer0Args A)
+// One thread per output channel and quarter of the tile's rows (its MT/4 outputs in
+// registers).  The folded weights and each channel's input window sit in LDS; the
+// window is read as 16-byte broadcasts, one channel at a time.
+constexpr int L0THREADS = 512;
+constexpr int L0XP = MT + 4;   // LDS pitch of an input channel: 16-byte aligned rows
+
+__global__ __launch_bounds__(L0THREADS) void bl_layer0(Layer0Args A)
 {
+    constexpr int R = MT / (L0THREADS / NF);  // rows per thread
     extern __shared__ __align__(16) unsigned char smem[];
-    float *xin = (float *)smem;               // [c_in][MT + 2]
-    float *w = xin + BL_MAX_CIN * (MT + 2);   // [3][c_in][128]
-    double *red = (double *)(w + 3 * BL_MAX_CIN * NF);
+    const int c_in = A.c_in;
+    float *xin = (float *)smem;          // [c_in][L0XP]: xin[c][p] holds sample t0 - 1 + p
+    float *wl = xin + c_in * L0XP;       // [3][c_in][128]
+    double *red = (double *)(wl + 3 * c_in * NF);
     const int tid = threadIdx.x;
     const int b = blockIdx.x / A.ntiles, tile = blockIdx.x % A.ntiles;
     const int t0 = tile * MT, T = A.T;
     const int64_t off = A.offs ? A.offs[b] : (int64_t)b * A.ex_stride;
-    for (int i = tid; i < A.c_in * (MT + 2); i += 256) {
-        const int c = i / (MT + 2), r = i % (MT + 2);
-        const int t = t0 - 1 + r;
-        xin[i] = (t >= 0 && t < T) ? A.x[off + (int64_t)c * A.ch_stride + t] : 0.f;
+    for (int i = tid; i < c_in * L0XP; i += L0THREADS) {
+        const int c = i / L0XP, p = i % L0XP;
+        const int t = t0 - 1 + p;
+        xin[i] = (p < MT + 2 && t >= 0 && t < T) ? A.x[off + (int64_t)c * A.ch_stride + t] : 0.f;
     }
-    for (int i = tid; i < 3 * A.c_in * NF; i += 256) w[i] = A.w0[i];
+    for (int i = tid; i < 3 * c_in * NF; i += L0THREADS) wl[i] = A.w0[i];
     __syncthreads();
-    const int o = tid & (NF - 1), half = tid >> 7;
-    const float bo = A.bias[o];
+    const int o = tid & (NF - 1), part = tid / NF;
     const int rows = min(MT, T - t0);
-    float s = 0.f;
-    for (int r = half; r < rows; r += 2) {
-        float acc = bo;
-        for (int tap = 0; tap < 3; ++tap)
-            for (int c = 0; c < A.c_in; ++c) acc = fmaf(w[(tap * A.c_in + c) * NF + o], xin[c * (MT + 2) + r + tap], acc);
-        A.a_out[((size_t)b * T + t0 + r) * NF + o] = acc;
-        s += acc;
+    const int r0 = part * R;
+    const float bo = A.bias[o];
+    float v[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = bo;
+#pragma unroll 1
+    for (int c = 0; c < c_in; ++c) {
+        const float w0 = wl[c * NF + o], w1 = wl[(c_in + c) * NF + o], w2 = wl[(2 * c_in + c) * NF + o];
+        float xs[R + 4];
+        const float4 *src = (const float4 *)(xin + c * L0XP + r0);
+#pragma unroll
+        for (int q = 0; q < R / 4 + 1; ++q) {
+            const float4 f = src[q];
+            xs[4 * q] = f.x; xs[4 * q + 1] = f.y; xs[4 * q + 2] = f.z; xs[4 * q + 3] = f.w;
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = fmaf(w2, xs[i + 2], fmaf(w1, xs[i + 1], fmaf(w0, xs[i], v[i])));
     }
-    const double S = block_sum((double)s, red, 4);
+    float *dst = A.a_out + ((size_t)b * T + t0 + r0) * NF + o;
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+        if (r0 + i < rows) {
+            dst[(size_t)i * NF] = v[i];
+            s += v[i];
+        }
+    const double S = block_sum((double)s, red, L0THREADS / 64);
     const float mt = (float)(S / ((double)rows * NF));
     float m2 = 0.f;
-    for (int r = half; r < rows; r += 2) {  // this thread's own stores, read back
-        const float d = A.a_out[((size_t)b * T + t0 + r) * NF + o] - mt;
-        m2 = fmaf(d, d, m2);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const float d = v[i] - mt;
+        if (r0 + i < rows) m2 = fmaf(d, d, m2);
     }
-    const double M2 = block_sum((double)m2, red, 4);
+    const double M2 = block_sum((double)m2, red, L0THREADS / 64);
     if (tid == 0) {
         A.st_out[((size_t)b * A.ntiles + tile) * 2] = S;
         A.st_out[((size_t)b * A.ntiles + tile) * 2 + 1] = M2;
@@ -303,7 +341,19 @@ struct LayerArgs {
     float eps;
 };
 
-__global__ __launch_bounds__(256) void bl_layer(LayerArgs A)
+constexpr int LWAVES = MT / 16;        // waves per layer workgroup: MT / 64 row blocks x 4 column groups
+constexpr int LTHREADS = 64 * LWAVES;
+
+DEV void load_b(f16x8_t (&bq)[4], const _Float16 *fr, int nb0, int ks)
+{
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+            bq[2 * cb + p] = *(const f16x8_t *)(fr + ((size_t)((nb0 + cb) * KSTEPS + ks) * 2 + p) * 512);
+}
+
+__global__ __launch_bounds__(LTHREADS) void bl_layer(LayerArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int D = A.D, T = A.T;
@@ -315,8 +365,13 @@ __global__ __launch_bounds__(256) void bl_layer(LayerArgs A)
     const int b = blockIdx.x / A.ntiles, tile = blockIdx.x % A.ntiles;
     const int t0 = tile * MT;
     const size_t fb = (size_t)b * T;
+    const float *__restrict__ a_in = A.a_in;
+    const float *__restrict__ x_in = A.x_in;
+    float *__restrict__ x_out = A.x_out;
+    const bool resid = A.layer >= 2;
 
-    // 1. stage x_l = (l >= 2 ? x_{l-1} : 0) + tanh(LN(a_{l-1})) for rows t0 - D .. t0 + MT + D
+    // 1. stage x_l = (l >= 2 ? x_{l-1} : 0) + tanh(LN(a_{l-1})) for rows t0 - D .. t0 + MT + D;
+    //    four rows' loads are issued before any of them is used
     {
         double mean, rstd;
         ln_stats(A.st_in + (size_t)b * A.ntiles * 2, A.ntiles, T, A.eps, mean, rstd);
@@ -325,98 +380,131 @@ __global__ __launch_bounds__(256) void bl_layer(LayerArgs A)
         const float4 be = *(const float4 *)(A.vec_prev + 2 * NF + c4);
         const float mu = (float)mean, rs = (float)rstd;
         const float4 sc = make_float4(g.x * rs, g.y * rs, g.z * rs, g.w * rs);
-        for (int r = tid >> 5; r < rows; r += 8) {
-            const int t = t0 - D + r;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (t >= 0 && t < T) {
-                const float4 a = *(const float4 *)(A.a_in + (fb + t) * NF + c4);
-                v.x = tanhf(fmaf(a.x - mu, sc.x, be.x));
-                v.y = tanhf(fmaf(a.y - mu, sc.y, be.y));
-                v.z = tanhf(fmaf(a.z - mu, sc.z, be.z));
-                v.w = tanhf(fmaf(a.w - mu, sc.w, be.w));
-                if (A.layer >= 2) {
-                    const float4 xp = *(const float4 *)(A.x_in + (fb + t) * NF + c4);
-                    v.x += xp.x; v.y += xp.y; v.z += xp.z; v.w += xp.w;
-                }
-                if (r >= D && r < D + MT) *(float4 *)(A.x_out + (fb + t) * NF + c4) = v;
-            }
-            const float s = (float)(1 << XEXP);
-            const float vs[4] = {v.x * s, v.y * s, v.z * s, v.w * s};
-            f16x4_t h, lo;
+        constexpr int RS = LTHREADS / 32;  // rows per pass
+        constexpr int U = 4;
+        for (int rb = tid >> 5; rb < rows; rb += RS * U) {
+            float4 av[U], xv[U];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                h[i] = (_Float16)vs[i];
-                lo[i] = (_Float16)(vs[i] - (float)h[i]);
+            for (int u = 0; u < U; ++u) {
+                const int r = rb + RS * u, t = t0 - D + r;
+                const bool ok = r < rows && t >= 0 && t < T;
+                av[u] = ok ? *(const float4 *)(a_in + (fb + t) * NF + c4) : make_float4(0.f, 0.f, 0.f, 0.f);
+                xv[u] = ok && resid ? *(const float4 *)(x_in + (fb + t) * NF + c4) : make_float4(0.f, 0.f, 0.f, 0.f);
             }
-            *(f16x4_t *)(xh + r * XROW + c4) = h;
-            *(f16x4_t *)(xl + r * XROW + c4) = lo;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int r = rb + RS * u, t = t0 - D + r;
+                if (r < rows) {
+                    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (t >= 0 && t < T) {
+                        v.x = xv[u].x + tanh_fast(fmaf(av[u].x - mu, sc.x, be.x));
+                        v.y = xv[u].y + tanh_fast(fmaf(av[u].y - mu, sc.y, be.y));
+                        v.z = xv[u].z + tanh_fast(fmaf(av[u].z - mu, sc.z, be.z));
+                        v.w = xv[u].w + tanh_fast(fmaf(av[u].w - mu, sc.w, be.w));
+                        if (r >= D && r < D + MT) *(float4 *)(x_out + (fb + t) * NF + c4) = v;
+                    }
+                    const float s = (float)(1 << XEXP);
+                    const float vs[4] = {v.x * s, v.y * s, v.z * s, v.w * s};
+                    f16x4_t h, lo;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        h[i] = (_Float16)vs[i];
+                        lo[i] = (_Float16)(vs[i] - (float)h[i]);
+                    }
+                    *(f16x4_t *)(xh + r * XROW + c4) = h;
+                    *(f16x4_t *)(xl + r * XROW + c4) = lo;
+                }
+            }
         }
     }
     __syncthreads();
 
-    // 2. a_l[t][n] = sum over taps and channels of x_l[t + (tap-1) D][c] W[tap][c][n]
-    f32x4_t acc[8][2];
+    // 2. a_l[t][n] = sum over taps and channels of x_l[t + (tap-1) D][c] W[tap][c][n]; this
+    //    wave: rows 64 rh .. 64 rh + 63, columns 32 cg .. 32 cg + 31.  The weight fragments
+    //    of step ks + 1 are loaded while step ks runs.
+    const int rh = wave >> 2, cg = wave & 3;
+    f32x4_t acc[4][2];
 #pragma unroll
-    for (int rb = 0; rb < 8; ++rb)
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     const _Float16 *fr = A.frag + lane * 8;
-    const int nb0 = 2 * wave;
-    for (int ks = 0; ks < KSTEPS; ++ks) {
-        const f16x8_t bh0 = *(const f16x8_t *)(fr + ((size_t)(nb0 * KSTEPS + ks) * 2) * 512);
-        const f16x8_t bl0 = *(const f16x8_t *)(fr + ((size_t)(nb0 * KSTEPS + ks) * 2 + 1) * 512);
-        const f16x8_t bh1 = *(const f16x8_t *)(fr + ((size_t)((nb0 + 1) * KSTEPS + ks) * 2) * 512);
-        const f16x8_t bl1 = *(const f16x8_t *)(fr + ((size_t)((nb0 + 1) * KSTEPS + ks) * 2 + 1) * 512);
-        const int tap = ks >> 2;
-        const int off = (tap * D + (lane & 15)) * XROW + (ks & 3) * 32 + 8 * (lane >> 4);
+    const int nb0 = 2 * cg;
+    f16x8_t bq[4], bn[4];
+    load_b(bq, fr, nb0, 0);
+    const int rowl = 64 * rh + (lane & 15);
 #pragma unroll
-        for (int rb = 0; rb < 8; ++rb) {
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+        if (ks + 1 < KSTEPS) load_b(bn, fr, nb0, ks + 1);
+        const int tap = ks >> 2;
+        const int off = (tap * D + rowl) * XROW + (ks & 3) * 32 + 8 * (lane >> 4);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
             const f16x8_t ah = *(const f16x8_t *)(xh + off + rb * 16 * XROW);
             const f16x8_t al = *(const f16x8_t *)(xl + off + rb * 16 * XROW);
-            acc[rb][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh0, acc[rb][0], 0, 0, 0);
-            acc[rb][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl0, acc[rb][0], 0, 0, 0);
-            acc[rb][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh0, acc[rb][0], 0, 0, 0);
-            acc[rb][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh1, acc[rb][1], 0, 0, 0);
-            acc[rb][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl1, acc[rb][1], 0, 0, 0);
-            acc[rb][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh1, acc[rb][1], 0, 0, 0);
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bq[2 * cb], acc[rb][cb], 0, 0, 0);
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bq[2 * cb + 1], acc[rb][cb], 0, 0, 0);
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bq[2 * cb], acc[rb][cb], 0, 0, 0);
+            }
+        }
+        if (ks + 1 < KSTEPS) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bq[i] = bn[i];
         }
     }
 
     // 3. scale back, add the bias, store a_l and the tile's (sum, M2)
     const float osc = ldexpf(1.f, -(XEXP + A.hdr[A.layer]));
     const int nrows = min(MT, T - t0);
+    float *__restrict__ a_out = A.a_out;
     float s = 0.f;
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
-        const int n = 32 * wave + 16 * cb + (lane & 15);
-        const float bn = A.bias[n];
+        const float bn_ = A.bias[32 * cg + 16 * cb + (lane & 15)];
 #pragma unroll
-        for (int rb = 0; rb < 8; ++rb)
+        for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = 16 * rb + 4 * (lane >> 4) + v;
-                const float val = fmaf(acc[rb][cb][v], osc, bn);
-                acc[rb][cb][v] = val;
-                if (row < nrows) {
-                    A.a_out[(fb + t0 + row) * NF + n] = val;
-                    s += val;
-                }
-            }
+            for (int v = 0; v < 4; ++v) acc[rb][cb][v] = fmaf(acc[rb][cb][v], osc, bn_);
     }
-    const double S = block_sum((double)s, red, 4);
+    float *dst = a_out + (fb + t0 + 64 * rh + 4 * (lane >> 4)) * NF + 32 * cg + (lane & 15);
+    if (nrows == MT) {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    dst[(16 * rb + v) * NF + 16 * cb] = acc[rb][cb][v];
+                    s += acc[rb][cb][v];
+                }
+    } else {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (64 * rh + 16 * rb + 4 * (lane >> 4) + v < nrows) {
+                        dst[(16 * rb + v) * NF + 16 * cb] = acc[rb][cb][v];
+                        s += acc[rb][cb][v];
+                    }
+    }
+    const double S = block_sum((double)s, red, LWAVES);
     const float mt = (float)(S / ((double)nrows * NF));
     float m2 = 0.f;
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-        for (int rb = 0; rb < 8; ++rb)
+        for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = 16 * rb + 4 * (lane >> 4) + v;
+                const int row = 64 * rh + 16 * rb + 4 * (lane >> 4) + v;
                 const float d = acc[rb][cb][v] - mt;
                 if (row < nrows) m2 = fmaf(d, d, m2);
             }
-    const double M2 = block_sum((double)m2, red, 4);
+    const double M2 = block_sum((double)m2, red, LWAVES);
     if (tid == 0) {
         A.st_out[((size_t)b * A.ntiles + tile) * 2] = S;
         A.st_out[((size_t)b * A.ntiles + tile) * 2 + 1] = M2;
@@ -449,15 +537,28 @@ __global__ __launch_bounds__(256) void bl_energy(EnergyArgs A)
     const float mu = (float)mean, rs = (float)rstd;
     const float4 sc = make_float4(g.x * rs, g.y * rs, g.z * rs, g.w * rs);
     const size_t fb = (size_t)b * T;
+    const float *__restrict__ a_in = A.a_in;
+    const float *__restrict__ x_in = A.x_in;
     float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int t = r0 + (tid >> 5); t < r1; t += 8) {
-        const float4 a = *(const float4 *)(A.a_in + (fb + t) * NF + c4);
-        const float4 xp = *(const float4 *)(A.x_in + (fb + t) * NF + c4);
-        const float sx = xp.x + tanhf(fmaf(a.x - mu, sc.x, be.x));
-        const float sy = xp.y + tanhf(fmaf(a.y - mu, sc.y, be.y));
-        const float sz = xp.z + tanhf(fmaf(a.z - mu, sc.z, be.z));
-        const float sw = xp.w + tanhf(fmaf(a.w - mu, sc.w, be.w));
-        e.x = fmaf(sx, sx, e.x); e.y = fmaf(sy, sy, e.y); e.z = fmaf(sz, sz, e.z); e.w = fmaf(sw, sw, e.w);
+    constexpr int U = 4;
+    for (int tb = r0 + (tid >> 5); tb < r1; tb += 8 * U) {
+        float4 av[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = tb + 8 * u;
+            const bool ok = t < r1;
+            av[u] = ok ? *(const float4 *)(a_in + (fb + t) * NF + c4) : make_float4(0.f, 0.f, 0.f, 0.f);
+            xv[u] = ok ? *(const float4 *)(x_in + (fb + t) * NF + c4) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (tb + 8 * u < r1) {
+                const float sx = xv[u].x + tanh_fast(fmaf(av[u].x - mu, sc.x, be.x));
+                const float sy = xv[u].y + tanh_fast(fmaf(av[u].y - mu, sc.y, be.y));
+                const float sz = xv[u].z + tanh_fast(fmaf(av[u].z - mu, sc.z, be.z));
+                const float sw = xv[u].w + tanh_fast(fmaf(av[u].w - mu, sc.w, be.w));
+                e.x = fmaf(sx, sx, e.x); e.y = fmaf(sy, sy, e.y); e.z = fmaf(sz, sz, e.z); e.w = fmaf(sw, sw, e.w);
+            }
     }
     sm[tid >> 5][tid & 31] = e;
     __syncthreads();
@@ -524,8 +625,7 @@ __global__ __launch_bounds__(128) void bl_head(HeadArgs A)
     for (int j = c; j < A.n_out; j += NF) A.out[(size_t)b * A.n_out + j] = (float)o[j];
 }
 
-int layer_lds_bytes(int D) { return 2 * (MT + 2 * D) * XROW * 2 + 64; }
-int layer0_lds_bytes() { return (BL_MAX_CIN * (MT + 2) + 3 * BL_MAX_CIN * NF) * 4 + 64; }
+int layer_lds_bytes(int D) { return 2 * (MT + 2 * D) * XROW * 2 + 8 * LWAVES; }
 
 }  // namespace
 
@@ -648,9 +748,6 @@ extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, 
     if (!lds_set) {
         hipError_t e = hipFuncSetAttribute((const void *)bl_layer, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            layer_lds_bytes(MAX_D));
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void *)bl_layer0, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    layer0_lds_bytes());
         if (e != hipSuccess) return ism_hip_fail(h, e, "hipFuncSetAttribute");
         lds_set = true;
     }
@@ -675,7 +772,8 @@ extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, 
     L0.T = n_t;
     L0.ntiles = w.ntiles;
     L0.c_in = m->c_in;
-    hipLaunchKernelGGL(bl_layer0, dim3(grid), dim3(256), layer0_lds_bytes(), st, L0);
+    const int l0_lds = (m->c_in * L0XP + 3 * m->c_in * NF) * 4 + 8 * (L0THREADS / 64);
+    hipLaunchKernelGGL(bl_layer0, dim3(grid), dim3(L0THREADS), l0_lds, st, L0);
 
     for (int l = 1; l < NL; ++l) {
         LayerArgs L;
@@ -694,7 +792,7 @@ extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, 
         L.layer = l;
         L.D = 1 << (l % 6);
         L.eps = m->eps;
-        hipLaunchKernelGGL(bl_layer, dim3(grid), dim3(256), layer_lds_bytes(L.D), st, L);
+        hipLaunchKernelGGL(bl_layer, dim3(grid), dim3(LTHREADS), layer_lds_bytes(L.D), st, L);
     }
 
     EnergyArgs E;
