@@ -45,7 +45,18 @@ namespace {
 constexpr int NF = 128;
 constexpr int MULT = 4;
 constexpr int NL = 18;
-constexpr int MT = 64;           // time samples per tile
+#ifndef BL_MT
+#define BL_MT 64
+#endif
+#ifndef BL_PREFETCH
+#define BL_PREFETCH 1
+#endif
+constexpr int MT = BL_MT;        // time samples per tile
+constexpr int BPF = BL_PREFETCH; // weight-fragment steps loaded ahead of the one in use
+#ifndef BL_CHUNK
+#define BL_CHUNK 0
+#endif
+constexpr int CHUNK = BL_CHUNK;  // frames per pass through the 18 layers (0: the whole batch)
 constexpr int KSTEPS = 12;       // K = 3 taps x 128 channels in steps of 32
 constexpr int XROW = 136;        // LDS pitch of a staged input row, in halves
 constexpr int MAX_D = 32;
@@ -102,6 +113,16 @@ WsLayout ws_layout(int batch, int n_t)
     o = al(o + (size_t)batch * w.ne * NF * sizeof(float));
     w.total = o;
     return w;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Renumber them so that each XCD
+// takes one contiguous range of (frame, tile) blocks: the neighbouring tiles of a frame,
+// which read each other's halo rows, then share that XCD's L2.
+DEV int xcd_block()
+{
+    const int n = gridDim.x, i = blockIdx.x;
+    const int per = n >> 3, rem = n & 7, x = i & 7, k = i >> 3;
+    return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
 }
 
 // ------------------------------------------------------------------ reductions
@@ -249,7 +270,7 @@ __global__ __launch_bounds__(256) void bl_fold(FoldArgs A)
 struct Layer0Args {
     const float *x;
     const int64_t *offs;
-    int64_t ex_stride, ch_stride;
+    int64_t base, ex_stride, ch_stride;
     const float *w0;    // [3][c_in][128]
     const float *bias;  // [128]
     float *a_out;       // [B][T][128]
@@ -272,9 +293,10 @@ __global__ __launch_bounds__(L0THREADS) void bl_layer0(Layer0Args A)
     float *wl = xin + c_in * L0XP;       // [3][c_in][128]
     double *red = (double *)(wl + 3 * c_in * NF);
     const int tid = threadIdx.x;
-    const int b = blockIdx.x / A.ntiles, tile = blockIdx.x % A.ntiles;
+    const int blk = xcd_block();
+    const int b = blk / A.ntiles, tile = blk % A.ntiles;
     const int t0 = tile * MT, T = A.T;
-    const int64_t off = A.offs ? A.offs[b] : (int64_t)b * A.ex_stride;
+    const int64_t off = A.offs ? A.offs[b] : A.base + (int64_t)b * A.ex_stride;
     for (int i = tid; i < c_in * L0XP; i += L0THREADS) {
         const int c = i / L0XP, p = i % L0XP;
         const int t = t0 - 1 + p;
@@ -362,7 +384,8 @@ __global__ __launch_bounds__(LTHREADS) void bl_layer(LayerArgs A)
     _Float16 *xl = xh + rows * XROW;
     double *red = (double *)(xl + rows * XROW);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int b = blockIdx.x / A.ntiles, tile = blockIdx.x % A.ntiles;
+    const int blk = xcd_block();
+    const int b = blk / A.ntiles, tile = blk % A.ntiles;
     const int t0 = tile * MT;
     const size_t fb = (size_t)b * T;
     const float *__restrict__ a_in = A.a_in;
@@ -430,12 +453,14 @@ __global__ __launch_bounds__(LTHREADS) void bl_layer(LayerArgs A)
         for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     const _Float16 *fr = A.frag + lane * 8;
     const int nb0 = 2 * cg;
-    f16x8_t bq[4], bn[4];
-    load_b(bq, fr, nb0, 0);
+    f16x8_t bq[BPF + 1][4];  // ring of weight fragments: step ks in slot ks % (BPF + 1)
+#pragma unroll
+    for (int i = 0; i < BPF; ++i) load_b(bq[i], fr, nb0, i);
     const int rowl = 64 * rh + (lane & 15);
 #pragma unroll
     for (int ks = 0; ks < KSTEPS; ++ks) {
-        if (ks + 1 < KSTEPS) load_b(bn, fr, nb0, ks + 1);
+        if (ks + BPF < KSTEPS) load_b(bq[(ks + BPF) % (BPF + 1)], fr, nb0, ks + BPF);
+        const f16x8_t *bc = bq[ks % (BPF + 1)];
         const int tap = ks >> 2;
         const int off = (tap * D + rowl) * XROW + (ks & 3) * 32 + 8 * (lane >> 4);
 #pragma unroll
@@ -444,14 +469,10 @@ __global__ __launch_bounds__(LTHREADS) void bl_layer(LayerArgs A)
             const f16x8_t al = *(const f16x8_t *)(xl + off + rb * 16 * XROW);
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bq[2 * cb], acc[rb][cb], 0, 0, 0);
-                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bq[2 * cb + 1], acc[rb][cb], 0, 0, 0);
-                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bq[2 * cb], acc[rb][cb], 0, 0, 0);
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bc[2 * cb], acc[rb][cb], 0, 0, 0);
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bc[2 * cb + 1], acc[rb][cb], 0, 0, 0);
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bc[2 * cb], acc[rb][cb], 0, 0, 0);
             }
-        }
-        if (ks + 1 < KSTEPS) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) bq[i] = bn[i];
         }
     }
 
@@ -526,7 +547,8 @@ __global__ __launch_bounds__(256) void bl_energy(EnergyArgs A)
 {
     __shared__ float4 sm[8][32];
     const int tid = threadIdx.x;
-    const int b = blockIdx.x / A.ne, et = blockIdx.x % A.ne;
+    const int blk = xcd_block();
+    const int b = blk / A.ne, et = blk % A.ne;
     const int T = A.T;
     const int r0 = MARGIN + et * MT, r1 = min(r0 + MT, T - MARGIN);
     double mean, rstd;
@@ -721,7 +743,7 @@ extern "C" void bl_model_destroy(bl_model *m)
 extern "C" size_t bl_workspace_bytes(int batch, int n_t)
 {
     if (batch < 0 || n_t < 2 * MARGIN + 1 || n_t > MAX_NT) return 0;
-    return ws_layout(batch, n_t).total;
+    return ws_layout(CHUNK > 0 && batch > CHUNK ? CHUNK : batch, n_t).total;
 }
 
 extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, const float *x,
@@ -738,12 +760,13 @@ extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, 
     if (ex_stride < 0 || ch_stride < 0) { ism_set_error(h, "strides must be >= 0"); return ISM_EINVAL; }
     if (batch == 0) return ISM_OK;
     if (!x || !workspace || !out) { ism_set_error(h, "NULL argument"); return ISM_EINVAL; }
-    const WsLayout w = ws_layout(batch, n_t);
+    const int chunk = CHUNK > 0 && batch > CHUNK ? CHUNK : batch;
+    const WsLayout w = ws_layout(chunk, n_t);
     if (workspace_bytes < w.total) {
         ism_set_error(h, "workspace of %zu bytes, %zu needed", workspace_bytes, w.total);
         return ISM_EINVAL;
     }
-    if ((int64_t)batch * w.ntiles > 0x7fffffff) { ism_set_error(h, "batch too large"); return ISM_EINVAL; }
+    if ((int64_t)chunk * w.ntiles > 0x7fffffff) { ism_set_error(h, "batch too large"); return ISM_EINVAL; }
     static bool lds_set = false;  // the attribute is per function and process
     if (!lds_set) {
         hipError_t e = hipFuncSetAttribute((const void *)bl_layer, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -758,66 +781,70 @@ extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, 
     float *Xbuf[2] = {(float *)(ws + w.x[0]), (float *)(ws + w.x[1])};
     double *Sbuf[2] = {(double *)(ws + w.st[0]), (double *)(ws + w.st[1])};
     const float *vec = (const float *)(mb + m->lay.vec);
-    const int grid = batch * w.ntiles;
+    for (int c0 = 0; c0 < batch; c0 += chunk) {
+        const int nb = batch - c0 < chunk ? batch - c0 : chunk;
+        const int grid = nb * w.ntiles;
 
-    Layer0Args L0;
-    L0.x = x;
-    L0.offs = x_offsets;
-    L0.ex_stride = ex_stride;
-    L0.ch_stride = ch_stride;
-    L0.w0 = (const float *)(mb + m->lay.w0);
-    L0.bias = vec;
-    L0.a_out = Abuf[0];
-    L0.st_out = Sbuf[0];
-    L0.T = n_t;
-    L0.ntiles = w.ntiles;
-    L0.c_in = m->c_in;
-    const int l0_lds = (m->c_in * L0XP + 3 * m->c_in * NF) * 4 + 8 * (L0THREADS / 64);
-    hipLaunchKernelGGL(bl_layer0, dim3(grid), dim3(L0THREADS), l0_lds, st, L0);
+        Layer0Args L0;
+        L0.x = x;
+        L0.offs = x_offsets ? x_offsets + c0 : nullptr;
+        L0.base = (int64_t)c0 * ex_stride;
+        L0.ex_stride = ex_stride;
+        L0.ch_stride = ch_stride;
+        L0.w0 = (const float *)(mb + m->lay.w0);
+        L0.bias = vec;
+        L0.a_out = Abuf[0];
+        L0.st_out = Sbuf[0];
+        L0.T = n_t;
+        L0.ntiles = w.ntiles;
+        L0.c_in = m->c_in;
+        const int l0_lds = (m->c_in * L0XP + 3 * m->c_in * NF) * 4 + 8 * (L0THREADS / 64);
+        hipLaunchKernelGGL(bl_layer0, dim3(grid), dim3(L0THREADS), l0_lds, st, L0);
 
-    for (int l = 1; l < NL; ++l) {
-        LayerArgs L;
-        L.a_in = Abuf[(l - 1) & 1];
-        L.x_in = Xbuf[(l - 1) & 1];
-        L.x_out = Xbuf[l & 1];
-        L.a_out = Abuf[l & 1];
-        L.st_in = Sbuf[(l - 1) & 1];
-        L.st_out = Sbuf[l & 1];
-        L.vec_prev = vec + (size_t)(l - 1) * 3 * NF;
-        L.bias = vec + (size_t)l * 3 * NF;
-        L.frag = (const _Float16 *)(mb + m->lay.frag) + (size_t)(l - 1) * FRAG_HALVES;
-        L.hdr = (const int *)(mb + m->lay.hdr);
-        L.T = n_t;
-        L.ntiles = w.ntiles;
-        L.layer = l;
-        L.D = 1 << (l % 6);
-        L.eps = m->eps;
-        hipLaunchKernelGGL(bl_layer, dim3(grid), dim3(LTHREADS), layer_lds_bytes(L.D), st, L);
+        for (int l = 1; l < NL; ++l) {
+            LayerArgs L;
+            L.a_in = Abuf[(l - 1) & 1];
+            L.x_in = Xbuf[(l - 1) & 1];
+            L.x_out = Xbuf[l & 1];
+            L.a_out = Abuf[l & 1];
+            L.st_in = Sbuf[(l - 1) & 1];
+            L.st_out = Sbuf[l & 1];
+            L.vec_prev = vec + (size_t)(l - 1) * 3 * NF;
+            L.bias = vec + (size_t)l * 3 * NF;
+            L.frag = (const _Float16 *)(mb + m->lay.frag) + (size_t)(l - 1) * FRAG_HALVES;
+            L.hdr = (const int *)(mb + m->lay.hdr);
+            L.T = n_t;
+            L.ntiles = w.ntiles;
+            L.layer = l;
+            L.D = 1 << (l % 6);
+            L.eps = m->eps;
+            hipLaunchKernelGGL(bl_layer, dim3(grid), dim3(LTHREADS), layer_lds_bytes(L.D), st, L);
+        }
+
+        EnergyArgs E;
+        E.a_in = Abuf[(NL - 1) & 1];
+        E.x_in = Xbuf[(NL - 1) & 1];
+        E.st_in = Sbuf[(NL - 1) & 1];
+        E.vec = vec + (size_t)(NL - 1) * 3 * NF;
+        E.part = (float *)(ws + w.part);
+        E.T = n_t;
+        E.ntiles = w.ntiles;
+        E.ne = w.ne;
+        E.eps = m->eps;
+        hipLaunchKernelGGL(bl_energy, dim3(nb * w.ne), dim3(256), 0, st, E);
+
+        HeadArgs Hd;
+        Hd.part = E.part;
+        Hd.head = (const float *)(mb + m->lay.head);
+        Hd.feat = features ? features + (size_t)c0 * NF : nullptr;
+        Hd.out = out + (size_t)c0 * m->n_out;
+        Hd.ne = w.ne;
+        Hd.n_out = m->n_out;
+        Hd.n_valid = n_t - 2 * MARGIN;
+        Hd.mode = m->mode;
+        Hd.eps = m->eps;
+        hipLaunchKernelGGL(bl_head, dim3(nb), dim3(128), 0, st, Hd);
     }
-
-    EnergyArgs E;
-    E.a_in = Abuf[(NL - 1) & 1];
-    E.x_in = Xbuf[(NL - 1) & 1];
-    E.st_in = Sbuf[(NL - 1) & 1];
-    E.vec = vec + (size_t)(NL - 1) * 3 * NF;
-    E.part = (float *)(ws + w.part);
-    E.T = n_t;
-    E.ntiles = w.ntiles;
-    E.ne = w.ne;
-    E.eps = m->eps;
-    hipLaunchKernelGGL(bl_energy, dim3(batch * w.ne), dim3(256), 0, st, E);
-
-    HeadArgs Hd;
-    Hd.part = E.part;
-    Hd.head = (const float *)(mb + m->lay.head);
-    Hd.feat = features;
-    Hd.out = out;
-    Hd.ne = w.ne;
-    Hd.n_out = m->n_out;
-    Hd.n_valid = n_t - 2 * MARGIN;
-    Hd.mode = m->mode;
-    Hd.eps = m->eps;
-    hipLaunchKernelGGL(bl_head, dim3(batch), dim3(128), 0, st, Hd);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ism_hip_fail(h, e, "bl_forward launch");
     return ISM_OK;
