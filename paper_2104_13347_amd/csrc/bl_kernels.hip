@@ -375,88 +375,80 @@ DEV void load_b(f16x8_t (&bq)[4], const _Float16 *fr, int nb0, int ks)
             bq[2 * cb + p] = *(const f16x8_t *)(fr + ((size_t)((nb0 + cb) * KSTEPS + ks) * 2 + p) * 512);
 }
 
-__global__ __launch_bounds__(LTHREADS) void bl_layer(LayerArgs A)
+// Stage x_l = (l >= 2 ? x_{l-1} : 0) + tanh(LN(a_{l-1})) for rows t0 - D .. t0 + MT + D of
+// frame b into LDS as the scaled FP16 split (hi in xh, lo in xl), and write the tile's own
+// rows of x_l to HBM.  256 threads (ptid); four rows' loads are issued before any is used.
+DEV void stage_tile(const LayerArgs &A, int b, int tile, _Float16 *xh, _Float16 *xl, int ptid)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
     const int D = A.D, T = A.T;
     const int rows = MT + 2 * D;
-    _Float16 *xh = (_Float16 *)smem;
-    _Float16 *xl = xh + rows * XROW;
-    double *red = (double *)(xl + rows * XROW);
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int blk = xcd_block();
-    const int b = blk / A.ntiles, tile = blk % A.ntiles;
     const int t0 = tile * MT;
     const size_t fb = (size_t)b * T;
     const float *__restrict__ a_in = A.a_in;
     const float *__restrict__ x_in = A.x_in;
     float *__restrict__ x_out = A.x_out;
     const bool resid = A.layer >= 2;
-
-    // 1. stage x_l = (l >= 2 ? x_{l-1} : 0) + tanh(LN(a_{l-1})) for rows t0 - D .. t0 + MT + D;
-    //    four rows' loads are issued before any of them is used
-    {
-        double mean, rstd;
-        ln_stats(A.st_in + (size_t)b * A.ntiles * 2, A.ntiles, T, A.eps, mean, rstd);
-        const int c4 = (tid & 31) * 4;
-        const float4 g = *(const float4 *)(A.vec_prev + NF + c4);
-        const float4 be = *(const float4 *)(A.vec_prev + 2 * NF + c4);
-        const float mu = (float)mean, rs = (float)rstd;
-        const float4 sc = make_float4(g.x * rs, g.y * rs, g.z * rs, g.w * rs);
-        constexpr int RS = LTHREADS / 32;  // rows per pass
-        constexpr int U = 4;
-        for (int rb = tid >> 5; rb < rows; rb += RS * U) {
-            float4 av[U], xv[U];
+    double mean, rstd;
+    ln_stats(A.st_in + (size_t)b * A.ntiles * 2, A.ntiles, T, A.eps, mean, rstd);
+    const int c4 = (ptid & 31) * 4;
+    const float4 g = *(const float4 *)(A.vec_prev + NF + c4);
+    const float4 be = *(const float4 *)(A.vec_prev + 2 * NF + c4);
+    const float mu = (float)mean, rs = (float)rstd;
+    const float4 sc = make_float4(g.x * rs, g.y * rs, g.z * rs, g.w * rs);
+    constexpr int RS = 256 / 32;  // rows per pass
+    constexpr int U = 4;
+    for (int rb = ptid >> 5; rb < rows; rb += RS * U) {
+        float4 av[U], xv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int r = rb + RS * u, t = t0 - D + r;
-                const bool ok = r < rows && t >= 0 && t < T;
-                av[u] = ok ? *(const float4 *)(a_in + (fb + t) * NF + c4) : make_float4(0.f, 0.f, 0.f, 0.f);
-                xv[u] = ok && resid ? *(const float4 *)(x_in + (fb + t) * NF + c4) : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
+        for (int u = 0; u < U; ++u) {
+            const int r = rb + RS * u, t = t0 - D + r;
+            const bool ok = r < rows && t >= 0 && t < T;
+            av[u] = ok ? *(const float4 *)(a_in + (fb + t) * NF + c4) : make_float4(0.f, 0.f, 0.f, 0.f);
+            xv[u] = ok && resid ? *(const float4 *)(x_in + (fb + t) * NF + c4) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int r = rb + RS * u, t = t0 - D + r;
-                if (r < rows) {
-                    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (t >= 0 && t < T) {
-                        v.x = xv[u].x + tanh_fast(fmaf(av[u].x - mu, sc.x, be.x));
-                        v.y = xv[u].y + tanh_fast(fmaf(av[u].y - mu, sc.y, be.y));
-                        v.z = xv[u].z + tanh_fast(fmaf(av[u].z - mu, sc.z, be.z));
-                        v.w = xv[u].w + tanh_fast(fmaf(av[u].w - mu, sc.w, be.w));
-                        if (r >= D && r < D + MT) *(float4 *)(x_out + (fb + t) * NF + c4) = v;
-                    }
-                    const float s = (float)(1 << XEXP);
-                    const float vs[4] = {v.x * s, v.y * s, v.z * s, v.w * s};
-                    f16x4_t h, lo;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        h[i] = (_Float16)vs[i];
-                        lo[i] = (_Float16)(vs[i] - (float)h[i]);
-                    }
-                    *(f16x4_t *)(xh + r * XROW + c4) = h;
-                    *(f16x4_t *)(xl + r * XROW + c4) = lo;
+        for (int u = 0; u < U; ++u) {
+            const int r = rb + RS * u, t = t0 - D + r;
+            if (r < rows) {
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (t >= 0 && t < T) {
+                    v.x = xv[u].x + tanh_fast(fmaf(av[u].x - mu, sc.x, be.x));
+                    v.y = xv[u].y + tanh_fast(fmaf(av[u].y - mu, sc.y, be.y));
+                    v.z = xv[u].z + tanh_fast(fmaf(av[u].z - mu, sc.z, be.z));
+                    v.w = xv[u].w + tanh_fast(fmaf(av[u].w - mu, sc.w, be.w));
+                    if (r >= D && r < D + MT) *(float4 *)(x_out + (fb + t) * NF + c4) = v;
                 }
+                const float s = (float)(1 << XEXP);
+                const float vs[4] = {v.x * s, v.y * s, v.z * s, v.w * s};
+                f16x4_t h, lo;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    h[i] = (_Float16)vs[i];
+                    lo[i] = (_Float16)(vs[i] - (float)h[i]);
+                }
+                *(f16x4_t *)(xh + r * XROW + c4) = h;
+                *(f16x4_t *)(xl + r * XROW + c4) = lo;
             }
         }
     }
-    __syncthreads();
+}
 
-    // 2. a_l[t][n] = sum over taps and channels of x_l[t + (tap-1) D][c] W[tap][c][n]; this
-    //    wave: rows 64 rh .. 64 rh + 63, columns 32 cg .. 32 cg + 31.  The weight fragments
-    //    of step ks + 1 are loaded while step ks runs.
-    const int rh = wave >> 2, cg = wave & 3;
-    f32x4_t acc[4][2];
+// a_l[t][n] = sum over taps and channels of x_l[t + (tap-1) D][c] W[tap][c][n] for the MT = 64
+// rows of a staged tile and the 32 output channels of column group cg (one wave).  The
+// weight fragments of step ks + BPF are loaded while step ks runs.
+DEV void gemm_tile(const LayerArgs &A, const _Float16 *xh, const _Float16 *xl, int cg, int lane,
+                   f32x4_t (&acc)[4][2])
+{
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     const _Float16 *fr = A.frag + lane * 8;
-    const int nb0 = 2 * cg;
+    const int nb0 = 2 * cg, D = A.D;
     f16x8_t bq[BPF + 1][4];  // ring of weight fragments: step ks in slot ks % (BPF + 1)
 #pragma unroll
     for (int i = 0; i < BPF; ++i) load_b(bq[i], fr, nb0, i);
-    const int rowl = 64 * rh + (lane & 15);
+    const int rowl = lane & 15;
 #pragma unroll
     for (int ks = 0; ks < KSTEPS; ++ks) {
         if (ks + BPF < KSTEPS) load_b(bq[(ks + BPF) % (BPF + 1)], fr, nb0, ks + BPF);
@@ -475,11 +467,15 @@ __global__ __launch_bounds__(LTHREADS) void bl_layer(LayerArgs A)
             }
         }
     }
+}
 
-    // 3. scale back, add the bias, store a_l and the tile's (sum, M2)
-    const float osc = ldexpf(1.f, -(XEXP + A.hdr[A.layer]));
+// Scale back, add the bias and store the wave's 64 x 32 block of a_l; returns the wave's
+// sum over the valid rows (every lane).
+DEV float store_tile(const LayerArgs &A, int b, int tile, int cg, int lane, f32x4_t (&acc)[4][2])
+{
+    const int T = A.T, t0 = tile * MT;
     const int nrows = min(MT, T - t0);
-    float *__restrict__ a_out = A.a_out;
+    const float osc = ldexpf(1.f, -(XEXP + A.hdr[A.layer]));
     float s = 0.f;
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
@@ -489,7 +485,7 @@ __global__ __launch_bounds__(LTHREADS) void bl_layer(LayerArgs A)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[rb][cb][v] = fmaf(acc[rb][cb][v], osc, bn_);
     }
-    float *dst = a_out + (fb + t0 + 64 * rh + 4 * (lane >> 4)) * NF + 32 * cg + (lane & 15);
+    float *__restrict__ dst = A.a_out + ((size_t)b * T + t0 + 4 * (lane >> 4)) * NF + 32 * cg + (lane & 15);
     if (nrows == MT) {
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
@@ -507,13 +503,17 @@ __global__ __launch_bounds__(LTHREADS) void bl_layer(LayerArgs A)
             for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    if (64 * rh + 16 * rb + 4 * (lane >> 4) + v < nrows) {
+                    if (16 * rb + 4 * (lane >> 4) + v < nrows) {
                         dst[(16 * rb + v) * NF + 16 * cb] = acc[rb][cb][v];
                         s += acc[rb][cb][v];
                     }
     }
-    const double S = block_sum((double)s, red, LWAVES);
-    const float mt = (float)(S / ((double)nrows * NF));
+    return s;
+}
+
+// Sum of squared deviations from `mean` over the valid rows of the wave's block.
+DEV float m2_tile(int nrows, int lane, float mean, const f32x4_t (&acc)[4][2])
+{
     float m2 = 0.f;
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
@@ -521,10 +521,31 @@ __global__ __launch_bounds__(LTHREADS) void bl_layer(LayerArgs A)
         for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = 64 * rh + 16 * rb + 4 * (lane >> 4) + v;
-                const float d = acc[rb][cb][v] - mt;
-                if (row < nrows) m2 = fmaf(d, d, m2);
+                const float d = acc[rb][cb][v] - mean;
+                if (16 * rb + 4 * (lane >> 4) + v < nrows) m2 = fmaf(d, d, m2);
             }
+    return m2;
+}
+
+// One tile per workgroup (4 waves): stage, barrier, GEMM, store, tile statistics.
+__global__ __launch_bounds__(LTHREADS) void bl_layer(LayerArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int rows = MT + 2 * A.D;
+    _Float16 *xh = (_Float16 *)smem;
+    _Float16 *xl = xh + rows * XROW;
+    double *red = (double *)(xl + rows * XROW);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int blk = xcd_block();
+    const int b = blk / A.ntiles, tile = blk % A.ntiles;
+    stage_tile(A, b, tile, xh, xl, tid);
+    __syncthreads();
+    f32x4_t acc[4][2];
+    gemm_tile(A, xh, xl, wave, lane, acc);
+    const int nrows = min(MT, A.T - tile * MT);
+    const float s = store_tile(A, b, tile, wave, lane, acc);
+    const double S = block_sum((double)s, red, LWAVES);
+    const float m2 = m2_tile(nrows, lane, (float)(S / ((double)nrows * NF)), acc);
     const double M2 = block_sum((double)m2, red, LWAVES);
     if (tid == 0) {
         A.st_out[((size_t)b * A.ntiles + tile) * 2] = S;

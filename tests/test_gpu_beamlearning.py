@@ -140,3 +140,20 @@ def test_invalid_arguments(handle):
     with pytest.raises(ValueError):
         blm.Model(handle, np.zeros(10, np.float32))
     m.close()
+
+
+def test_large_ragged_batch_equals_single_frames(handle):
+    # 64 frames of 1000 samples (1024 tiles, the last of each frame ragged) in one call
+    # equal each frame run alone, bitwise; sampled frames against the oracle
+    p, m = _model(handle, 71)
+    x = bl_data.frames(72, 64, n_t=1000)
+    xd = torch.from_numpy(x).cuda()
+    f, o = m.forward(xd)
+    singles = [m.forward(xd[i:i + 1]) for i in range(64)]
+    torch.cuda.synchronize()
+    assert torch.equal(f, torch.cat([s[0] for s in singles]))
+    assert torch.equal(o, torch.cat([s[1] for s in singles]))
+    idx = [0, 33, 63]
+    rf, ro = ref.forward(x[idx], p, eps=1e-6)
+    _check("64 x 1000, sampled", f[idx].cpu().numpy(), o[idx].cpu().numpy(), rf, ro)
+    m.close()
