@@ -21,11 +21,11 @@
 //    x_{l+1} = x_l + tanh(LN(a_l)) on the fly while it stages its input tile, and
 //    writes x_{l+1} for the next residual.  Per layer and frame that is two reads
 //    and two writes of the 128-channel map, the HBM floor of this structure.
-//  * Tiles.  A workgroup (4 waves) takes 128 time samples of one frame plus a
-//    halo of D on each side; each wave computes all 128 rows for 32 of the 128
-//    output channels, its weight fragments streamed from L2 and its activation
-//    fragments read from LDS (row pitch 272 B: the 16 rows of a fragment fall on
-//    distinct banks).
+//  * Tiles.  A workgroup (4 waves) takes 64 time samples of one frame plus a halo of D
+//    on each side; each wave computes the 64 rows for 32 of the 128 output channels, its
+//    weight fragments streamed from L2 and its activation fragments read from LDS (row
+//    pitch 272 B: the 16 rows of a fragment fall on distinct banks).  Workgroups are
+//    renumbered so that each XCD runs a contiguous range of tiles (halo rows in its L2).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -53,6 +53,9 @@ constexpr int NL = 18;
 #endif
 constexpr int MT = BL_MT;        // time samples per tile
 constexpr int BPF = BL_PREFETCH; // weight-fragment steps loaded ahead of the one in use
+#ifndef BL_STAGE_U
+#define BL_STAGE_U 4
+#endif
 #ifndef BL_CHUNK
 #define BL_CHUNK 0
 #endif
@@ -396,7 +399,7 @@ DEV void stage_tile(const LayerArgs &A, int b, int tile, _Float16 *xh, _Float16 
     const float mu = (float)mean, rs = (float)rstd;
     const float4 sc = make_float4(g.x * rs, g.y * rs, g.z * rs, g.w * rs);
     constexpr int RS = 256 / 32;  // rows per pass
-    constexpr int U = 4;
+    constexpr int U = BL_STAGE_U;
     for (int rb = ptid >> 5; rb < rows; rb += RS * U) {
         float4 av[U], xv[U];
 #pragma unroll
