@@ -73,7 +73,11 @@ size_t bl_param_count(int c_in, int n_out);
  *   c_in: 1..BL_MAX_CIN input channels; n_out: 1..BL_MAX_NOUT outputs;
  *   mode: BL_REGRESSION or BL_CLASSIFICATION; ln_eps: the layer norms' eps (> 0).
  *   params: device FP32 array, read by the queued kernel only (it may be freed
- *   once that work is done).  *model receives the model; bl_model_destroy frees it.
+ *   once that work is done).  *model receives the model; bl_model_destroy frees it
+ *   (after waiting for the device).  The model lives on the device that is current
+ *   at creation and is ready once the work queued on `stream` has finished: a
+ *   forward pass on another stream must be ordered after it (an event, or a
+ *   stream or device synchronisation).
  * ISM_EINVAL for sizes out of range or non-finite eps, ISM_ENOMEM if the
  * allocation fails.
  */
@@ -89,10 +93,13 @@ size_t bl_workspace_bytes(int batch, int n_t);
  *   x: device FP32; frame b, channel c, sample n at
  *      x[off_b + c * ch_stride + n], off_b = x_offsets[b] if x_offsets is not
  *      NULL (a device int64 array of batch entries), else b * ex_stride.  Frames
- *      may overlap (read only).
+ *      may overlap (read only).  Every such element, for b < batch, c < c_in and
+ *      n < n_t, must lie inside the caller's allocation: the library cannot check
+ *      device offsets.
  *   n_t: frame length, 2*BL_MARGIN + 1 .. 1 << 20.
  *   workspace: device, at least bl_workspace_bytes(batch, n_t) bytes, owned by
  *      the caller; its contents on entry do not matter.  The call allocates nothing.
+ *      Calls that share a workspace must not run concurrently.
  *   features: device FP32 batch x 128 (f above), or NULL.
  *   out: device FP32 batch x n_out.
  * batch = 0 queues nothing.  ISM_EINVAL for a NULL pointer, n_t out of range,

@@ -74,6 +74,8 @@ class Model:
                                       ctypes.byref(m))
         handle._check(rc)
         self.m = m
+        # the folding kernel ran on `stream`; forward passes may use other streams
+        torch.cuda.synchronize()
 
     def close(self):
         if getattr(self, "m", None):

@@ -760,6 +760,7 @@ extern "C" int bl_model_create(ism_handle *h, int c_in, int n_out, int mode, flo
 extern "C" void bl_model_destroy(bl_model *m)
 {
     if (!m) return;
+    hipDeviceSynchronize();  // forward passes may still read the model
     if (m->dev) hipFree(m->dev);
     delete m;
 }
@@ -791,13 +792,11 @@ extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, 
         return ISM_EINVAL;
     }
     if ((int64_t)chunk * w.ntiles > 0x7fffffff) { ism_set_error(h, "batch too large"); return ISM_EINVAL; }
-    static bool lds_set = false;  // the attribute is per function and process
-    if (!lds_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)bl_layer, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           layer_lds_bytes(MAX_D));
-        if (e != hipSuccess) return ism_hip_fail(h, e, "hipFuncSetAttribute");
-        lds_set = true;
-    }
+    // the layer kernel's LDS can exceed the 64 KB default (set on every call: cheap, and
+    // valid whichever device is current)
+    hipError_t ea = hipFuncSetAttribute((const void *)bl_layer, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        layer_lds_bytes(MAX_D));
+    if (ea != hipSuccess) return ism_hip_fail(h, ea, "hipFuncSetAttribute");
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)workspace;
     const char *mb = (const char *)m->dev;
