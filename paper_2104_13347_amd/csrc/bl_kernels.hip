@@ -45,17 +45,15 @@ namespace {
 constexpr int NF = 128;
 constexpr int MULT = 4;
 constexpr int NL = 18;
-#ifndef BL_MT
-#define BL_MT 64
-#endif
+// Build constants (measured choices; alternatives in the design notes)
 #ifndef BL_PREFETCH
 #define BL_PREFETCH 1
 #endif
-constexpr int MT = BL_MT;        // time samples per tile
-constexpr int BPF = BL_PREFETCH; // weight-fragment steps loaded ahead of the one in use
 #ifndef BL_STAGE_U
 #define BL_STAGE_U 4
 #endif
+constexpr int MT = 64;           // time samples per tile: one wave covers the tile's 64 rows
+constexpr int BPF = BL_PREFETCH; // weight-fragment steps loaded ahead of the one in use
 #ifndef BL_CHUNK
 #define BL_CHUNK 0
 #endif
@@ -366,7 +364,7 @@ struct LayerArgs {
     float eps;
 };
 
-constexpr int LWAVES = MT / 16;        // waves per layer workgroup: MT / 64 row blocks x 4 column groups
+constexpr int LWAVES = 4;              // waves per layer workgroup: one per 32 output channels
 constexpr int LTHREADS = 64 * LWAVES;
 
 DEV void load_b(f16x8_t (&bq)[4], const _Float16 *fr, int nb0, int ks)
