@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/ism.h"
@@ -226,6 +227,27 @@ static double item_cost(const ism_room &r, double fs, double c, int K, int s0, i
     return recs * (2.0 * K + 1.0) + 30.0 * cols + 1.0;
 }
 
+// Threads for the host passes over a plan's items (large batches only).
+static int host_threads(size_t n)
+{
+    if (n < (1u << 18)) return 1;
+    const unsigned hc = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(8u, hc ? hc : 1u));
+}
+
+// Runs f(lo, hi) over [0, n) split into nt contiguous ranges, one thread each.
+template <class F>
+static void parallel_ranges(size_t n, int nt, F f)
+{
+    if (nt <= 1) { f((size_t)0, n); return; }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) {
+        const size_t lo = n * t / nt, hi = n * (t + 1) / nt;
+        th.emplace_back([=] { f(lo, hi); });
+    }
+    for (auto &x : th) x.join();
+}
+
 int ism_build_plan(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics, double fs,
                    double c, int fd_taps, int seg_len, Plan &plan)
 {
@@ -238,7 +260,9 @@ int ism_build_plan(ism_handle *h, int n_rooms, const ism_room *rooms, const doub
     plan.est_taps = 0.0;
     plan.est_records = 0.0;
     int64_t pow_total = 0;
-    std::vector<float> cost;
+    // a unit is one (room, output segment); its items are the room's microphones
+    std::vector<int32_t> unit_first(n_rooms + 1, 0);
+    int64_t n_units = 0, n_items = 0;
     for (int i = 0; i < n_rooms; ++i) {
         const ism_room &r = rooms[i];
         RoomDev &d = plan.rooms[i];
@@ -268,38 +292,57 @@ int ism_build_plan(ism_handle *h, int n_rooms, const ism_room *rooms, const doub
         d.pow_offset = (int32_t)pow_total;
         pow_total += 6LL * d.pow_stride;
         plan.n_mics_total = std::max<int64_t>(plan.n_mics_total, (int64_t)r.mic_offset + r.n_mics);
-        for (int m = 0; m < r.n_mics; ++m) {
-            for (int s0 = 0; s0 < r.rir_len; s0 += seg_len) {
-                const int s1 = std::min(s0 + seg_len, r.rir_len);
-                ItemDev it{i, r.mic_offset + m, s0, s1, d.pow_offset, d.pow_stride, {0, 0}};
-                plan.items.push_back(it);
-                const double cst = item_cost(r, fs, c, K, s0, s1);
-                cost.push_back((float)cst);
-                plan.est_taps += (cst - 1.0) > 0 ? cst : 0.0;
-                plan.seg_max = std::max(plan.seg_max, s1 - s0);
-            }
+        const int64_t nseg = ((int64_t)r.rir_len + seg_len - 1) / seg_len;
+        n_units += nseg;
+        n_items += nseg * r.n_mics;
+        if (n_units > INT32_MAX / 2 || n_items > INT32_MAX / 2) {
+            ism_set_error(h, "too many work items");
+            return ISM_ENOMEM;
+        }
+        unit_first[i + 1] = (int32_t)n_units;
+        plan.seg_max = std::max(plan.seg_max, std::min(seg_len, r.rir_len));
+    }
+    plan.pow_total = pow_total;
+    // longest-first order: counting sort of the units on a log2 cost key (1/16 octave
+    // buckets); a unit's items (its microphones) stay together
+    const int NB = 64 * 16;
+    std::vector<int32_t> bucket(n_units);
+    std::vector<int64_t> hist(NB + 1, 0);
+    for (int i = 0; i < n_rooms; ++i) {
+        const ism_room &r = rooms[i];
+        for (int32_t u = unit_first[i]; u < unit_first[i + 1]; ++u) {
+            const int s0 = (u - unit_first[i]) * seg_len, s1 = std::min(s0 + seg_len, r.rir_len);
+            const double cst = item_cost(r, fs, c, K, s0, s1);
+            plan.est_taps += (cst - 1.0) > 0 ? cst * r.n_mics : 0.0;
+            int bk = (int)std::floor(std::log2(std::max(1.0f, (float)cst)) * 16.0);
+            bk = std::min(std::max(bk, 0), NB - 1);
+            bucket[u] = NB - 1 - bk;
+            hist[bucket[u] + 1] += r.n_mics;
         }
     }
-    if (plan.items.size() > (size_t)INT32_MAX / 2) {
-        ism_set_error(h, "too many work items");
-        return ISM_ENOMEM;
-    }
     plan.est_records = plan.est_taps / (2.0 * K + 1.0);
-    plan.pow_total = pow_total;
-    // longest-first order: counting sort on a log2 cost key (1/16 octave buckets)
-    const int NB = 64 * 16;
-    std::vector<int> bucket(plan.items.size());
-    std::vector<int64_t> hist(NB + 1, 0);
-    for (size_t i = 0; i < plan.items.size(); ++i) {
-        int b = (int)std::floor(std::log2(std::max(1.0f, cost[i])) * 16.0);
-        b = std::min(std::max(b, 0), NB - 1);
-        bucket[i] = NB - 1 - b;
-        hist[bucket[i] + 1]++;
-    }
-    for (int b = 0; b < NB; ++b) hist[b + 1] += hist[b];
-    std::vector<ItemDev> sorted(plan.items.size());
-    for (size_t i = 0; i < plan.items.size(); ++i) sorted[hist[bucket[i]]++] = plan.items[i];
-    plan.items.swap(sorted);
+    for (int bk = 0; bk < NB; ++bk) hist[bk + 1] += hist[bk];
+    // first item of each unit in the sorted order (stable within a bucket)
+    std::vector<int32_t> unit_pos(n_units);
+    for (int i = 0; i < n_rooms; ++i)
+        for (int32_t u = unit_first[i]; u < unit_first[i + 1]; ++u) {
+            unit_pos[u] = (int32_t)hist[bucket[u]];
+            hist[bucket[u]] += rooms[i].n_mics;
+        }
+    plan.items.resize(n_items);
+    ItemDev *out = plan.items.data();
+    parallel_ranges((size_t)n_rooms, host_threads((size_t)n_items), [&](size_t lo, size_t hi) {
+        for (size_t i = lo; i < hi; ++i) {
+            const ism_room &r = rooms[i];
+            const RoomDev &d = plan.rooms[i];
+            for (int32_t u = unit_first[i]; u < unit_first[i + 1]; ++u) {
+                const int s0 = (u - unit_first[i]) * seg_len, s1 = std::min(s0 + seg_len, r.rir_len);
+                ItemDev *it = out + unit_pos[u];
+                for (int m = 0; m < r.n_mics; ++m)
+                    it[m] = ItemDev{(int32_t)i, r.mic_offset + m, s0, s1, d.pow_offset, d.pow_stride, {0, 0}};
+            }
+        }
+    });
     return ISM_OK;
 }
 
@@ -470,7 +513,15 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
     if (n_coef) std::memcpy(hb + off_coef, h->coef.data(), sizeof(double) * n_coef);
     std::memcpy(hb + off_rooms, plan.rooms.data(), sizeof(RoomDev) * n_rooms);
     std::memcpy(hb + off_mics, mics, sizeof(double) * 3 * plan.n_mics_total);
-    std::memcpy(hb + off_items, plan.items.data(), sizeof(ItemDev) * n_items);
+    {   // the item table is the bulk of the upload: copy it on several threads when large
+        char *dst = hb + off_items;
+        const char *src = (const char *)plan.items.data();
+        const size_t bytes = sizeof(ItemDev) * (size_t)n_items;
+        parallel_ranges(bytes / 4096 + 1, host_threads((size_t)n_items), [&](size_t lo, size_t hi) {
+            const size_t b0 = std::min(bytes, lo * 4096), b1 = std::min(bytes, hi * 4096);
+            if (b1 > b0) std::memcpy(dst + b0, src + b0, b1 - b0);
+        });
+    }
 
     int per_cu = 0;
     hipError_t e = hipSuccess;
