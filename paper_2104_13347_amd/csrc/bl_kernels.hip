@@ -161,6 +161,19 @@ DEV void ln_stats(const double *st, int ntiles, int T, float eps, double &mean, 
 {
     const int lane = threadIdx.x & 63;
     const double N = (double)T * NF;
+    if (ntiles <= 64) {  // one load round: lane i holds tile i's partials
+        const double si = lane < ntiles ? st[2 * lane] : 0.0;
+        const double mi = lane < ntiles ? st[2 * lane + 1] : 0.0;
+        mean = wave_sum(si) / N;
+        double m2 = 0.0;
+        if (lane < ntiles) {
+            const double ni = (double)min(MT, T - lane * MT) * NF;
+            const double d = si / ni - mean;
+            m2 = mi + ni * d * d;
+        }
+        rstd = 1.0 / sqrt(wave_sum(m2) / N + (double)eps);
+        return;
+    }
     double s = 0.0;
     for (int i = lane; i < ntiles; i += 64) s += st[2 * i];
     mean = wave_sum(s) / N;
@@ -436,9 +449,18 @@ DEV void stage_tile(const LayerArgs &A, int b, int tile, _Float16 *xh, _Float16 
 
 // a_l[t][n] = sum over taps and channels of x_l[t + (tap-1) D][c] W[tap][c][n] for the MT = 64
 // rows of a staged tile and the 32 output channels of column group cg (one wave).  The
-// weight fragments of step ks + BPF are loaded while step ks runs.
+// weight fragments sit in a ring of P + 1 steps: step ks in slot ks % (P + 1), step ks + P
+// loaded while step ks runs.  preload_b fills the first P slots.
+template <int P>
+DEV void preload_b(f16x8_t (&bq)[P + 1][4], const LayerArgs &A, int cg, int lane)
+{
+#pragma unroll
+    for (int i = 0; i < P; ++i) load_b(bq[i], A.frag + lane * 8, 2 * cg, i);
+}
+
+template <int P>
 DEV void gemm_tile(const LayerArgs &A, const _Float16 *xh, const _Float16 *xl, int cg, int lane,
-                   f32x4_t (&acc)[4][2])
+                   f16x8_t (&bq)[P + 1][4], f32x4_t (&acc)[4][2])
 {
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
@@ -446,14 +468,11 @@ DEV void gemm_tile(const LayerArgs &A, const _Float16 *xh, const _Float16 *xl, i
         for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     const _Float16 *fr = A.frag + lane * 8;
     const int nb0 = 2 * cg, D = A.D;
-    f16x8_t bq[BPF + 1][4];  // ring of weight fragments: step ks in slot ks % (BPF + 1)
-#pragma unroll
-    for (int i = 0; i < BPF; ++i) load_b(bq[i], fr, nb0, i);
     const int rowl = lane & 15;
 #pragma unroll
     for (int ks = 0; ks < KSTEPS; ++ks) {
-        if (ks + BPF < KSTEPS) load_b(bq[(ks + BPF) % (BPF + 1)], fr, nb0, ks + BPF);
-        const f16x8_t *bc = bq[ks % (BPF + 1)];
+        if (ks + P < KSTEPS) load_b(bq[(ks + P) % (P + 1)], fr, nb0, ks + P);
+        const f16x8_t *bc = bq[ks % (P + 1)];
         const int tap = ks >> 2;
         const int off = (tap * D + rowl) * XROW + (ks & 3) * 32 + 8 * (lane >> 4);
 #pragma unroll
@@ -528,9 +547,13 @@ DEV float m2_tile(int nrows, int lane, float mean, const f32x4_t (&acc)[4][2])
     return m2;
 }
 
-// One tile per workgroup (4 waves): stage, barrier, GEMM, store, tile statistics.
+// One tile per workgroup (4 waves): stage, barrier, GEMM, store, tile statistics.  The
+// low-latency form (at most one workgroup per CU, small batches) issues the first 7 steps'
+// weight-fragment loads before staging, so their latency hides behind it.
+template <bool LOWLAT>
 __global__ __launch_bounds__(LTHREADS) void bl_layer(LayerArgs A)
 {
+    constexpr int P = LOWLAT ? 7 : BPF;
     extern __shared__ __align__(16) unsigned char smem[];
     const int rows = MT + 2 * A.D;
     _Float16 *xh = (_Float16 *)smem;
@@ -539,10 +562,13 @@ __global__ __launch_bounds__(LTHREADS) void bl_layer(LayerArgs A)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int blk = xcd_block();
     const int b = blk / A.ntiles, tile = blk % A.ntiles;
+    f16x8_t bq[P + 1][4];
+    if (LOWLAT) preload_b<P>(bq, A, wave, lane);
     stage_tile(A, b, tile, xh, xl, tid);
     __syncthreads();
+    if (!LOWLAT) preload_b<P>(bq, A, wave, lane);
     f32x4_t acc[4][2];
-    gemm_tile(A, xh, xl, wave, lane, acc);
+    gemm_tile<P>(A, xh, xl, wave, lane, bq, acc);
     const int nrows = min(MT, A.T - tile * MT);
     const float s = store_tile(A, b, tile, wave, lane, acc);
     const double S = block_sum((double)s, red, LWAVES);
@@ -792,8 +818,11 @@ extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, 
     if ((int64_t)chunk * w.ntiles > 0x7fffffff) { ism_set_error(h, "batch too large"); return ISM_EINVAL; }
     // the layer kernel's LDS can exceed the 64 KB default (set on every call: cheap, and
     // valid whichever device is current)
-    hipError_t ea = hipFuncSetAttribute((const void *)bl_layer, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t ea = hipFuncSetAttribute((const void *)bl_layer<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         layer_lds_bytes(MAX_D));
+    if (ea == hipSuccess)
+        ea = hipFuncSetAttribute((const void *)bl_layer<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 layer_lds_bytes(MAX_D));
     if (ea != hipSuccess) return ism_hip_fail(h, ea, "hipFuncSetAttribute");
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)workspace;
@@ -839,7 +868,10 @@ extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, 
             L.layer = l;
             L.D = 1 << (l % 6);
             L.eps = m->eps;
-            hipLaunchKernelGGL(bl_layer, dim3(grid), dim3(LTHREADS), layer_lds_bytes(L.D), st, L);
+            if (grid <= h->n_cu)  // at most one workgroup per CU: latency-bound
+                hipLaunchKernelGGL(bl_layer<true>, dim3(grid), dim3(LTHREADS), layer_lds_bytes(L.D), st, L);
+            else
+                hipLaunchKernelGGL(bl_layer<false>, dim3(grid), dim3(LTHREADS), layer_lds_bytes(L.D), st, L);
         }
 
         EnergyArgs E;
