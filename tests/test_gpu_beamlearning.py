@@ -55,6 +55,7 @@ def _check(tag, got_f, got_o, ref_f, ref_o):
     (3, 700, 2, 37, blm.CLASSIFICATION, 3),      # ragged last tile
     (1, 1300, 1, 1, blm.REGRESSION, 4),          # one channel, 11 tiles, ragged
     (32, 520, 2, 1024, blm.CLASSIFICATION, 5),   # widest input and output
+    (2, 4500, 1, 3, blm.REGRESSION, 6),          # 71 tiles: statistics over more than 64 partials
 ])
 def test_forward_matches_oracle(handle, c_in, n_t, batch, n_out, mode, seed):
     p, m = _model(handle, seed, c_in=c_in, n_out=n_out, mode=mode)
