@@ -239,6 +239,39 @@ def cpu_baseline_beamlearning(n_frames=2):
             "sample": f"{n_frames} frames of 7 x 1024, numpy FP64 (BLAS threads for the pointwise products)"}
 
 
+def bench_rt_fit(H, torch):
+    """Uniform-absorption fit (section III.A: homogeneous walls with a simulated reverberation
+    time of 0.5 s) for the paper's two simulated rooms: 30 bisection steps, each one 16 000-sample
+    RIR (Lagrange filter, 16 kHz) and its T30 on the GPU.  The first room's Sabine beta (the
+    dataset's default) is given for comparison."""
+    from paper_2104_13347_amd import scenes
+    res = {"workload": "paper rooms 7x10x3.7 m and 5x5x4 m, target T30 0.5 s, mic at the array centre, "
+                       "source 2 m away, 16 kHz, 16000 samples, fd_taps 8, 30 bisection steps"}
+    rooms = {"room1_7x10x3.7": ([7.0, 10.0, 3.7], [4.0, 6.0, 1.5], [6.0, 6.0, 1.5]),
+             "room2_5x5x4": ([5.0, 5.0, 4.0], [2.5, 2.5, 1.5], [4.5, 2.5, 1.5])}
+    for name, (L, mic, src) in rooms.items():
+        H.fit_beta(L, src, mic, 16000.0, 343.0, 8, 0.5, 16000, iters=4)  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        beta, rt = H.fit_beta(L, src, mic, 16000.0, 343.0, 8, 0.5, 16000, iters=30)
+        res[name] = {"beta": beta, "t30_s": rt, "fit_ms": (time.perf_counter() - t) * 1e3}
+    res["room1_sabine_beta"] = float(scenes.paper_room1()["beta"][0][0])
+    # the paper's workflow: fit the walls, then generate the room's 336 000 RIRs with them
+    from paper_2104_13347_amd import ism
+    b = scenes.paper_room1(beta=res["room1_7x10x3.7"]["beta"])
+    rooms_t = ism.rooms_array(b)
+    out = torch.empty(int(b["out_size"]), dtype=torch.float32, device="cuda")
+    L, mic, src = rooms["room1_7x10x3.7"]
+
+    def fit_and_generate():
+        beta, _ = H.fit_beta(L, src, mic, 16000.0, 343.0, 8, 0.5, 16000, iters=30)
+        H.rir_batch(b, out=out, rooms=rooms_t)
+    res["room1_fit_and_dataset_ms"] = _time_it(torch, fit_and_generate, reps=2)
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_c2(torch, n_requests):
     """Serving: Poisson arrivals of single-room requests (RT60 U[0.1,1.0] s, RIR RT60*fs, M in
     {4,8,16,32}).  First a saturated run (all requests at t=0) gives the sustainable rate; then
@@ -279,10 +312,10 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the serving, precision and convolution sections")
-    ap.add_argument("--extras", default="c3,c4,paper,c2,beamlearning",
+    ap.add_argument("--extras", default="c3,c4,paper,c2,beamlearning,rtfit",
                     help="comma list of extra sections to run: c3 precision, c4 convolution, paper (the "
                          "paper's 336 000-RIR room dataset), c2 serving, beamlearning (the paper's network "
-                         "on frames of the convolution stage)")
+                         "on frames of the convolution stage), rtfit (uniform-absorption fit for a target T30)")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="run only a plain device copy of this many bytes (HBM counter calibration)")
@@ -428,6 +461,8 @@ def main():
             if not args.no_cpu_baseline:
                 bl["cpu_baseline"] = cpu_baseline_beamlearning()
             res["extras"]["beamlearning_forward"] = bl
+        if "rtfit" in extras:
+            res["extras"]["rt_fit"] = bench_rt_fit(H, torch)
     H.close()
 
     if not args.no_cpu_baseline:

@@ -221,6 +221,32 @@ int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float *rirs,
                        int use_mfma, float *out, ism_stream stream);
 
 /*
+ * Reverberation time of an RIR and the uniform-absorption fit (paper section III.A:
+ * the simulated rooms get homogeneous wall absorption chosen so that their RIRs have
+ * the target reverberation time; the paper cites Lehmann and Johansson's prediction
+ * for it, which is not reproduced here: the fit measures the simulated RIR itself).
+ *
+ * ism_rir_t30: T30 of the device FP32 RIR rir[0 .. rir_len) (ISO 3382: Schroeder
+ *   backward-integrated energy in dB, least-squares line over the samples from the
+ *   first one 5 dB down to the first one 35 dB down, time for that line to fall
+ *   60 dB), written as one double to the device pointer t30; +inf when the decay
+ *   does not reach -35 dB within the RIR.  Queued on `stream`.
+ * ism_fit_beta: the uniform beta (all six walls) whose time-bounded RIR of rir_len
+ *   samples from src to mic (fd_taps filter, FP32 precision) has T30 = rt_target:
+ *   `iters` bisection steps on beta in [0, 1), T30 being increasing in beta.
+ *   work: device buffer of ism_rt_work_bytes(rir_len) bytes, owned by the caller.
+ *   *beta_out, *rt_out (host): the fitted beta and the T30 of its RIR.  Blocking: it
+ *   waits for `stream` after every step.  rir_len should cover the decay to -35 dB
+ *   (about 1.5 x rt_target x fs or more).  Validation as for ism_rir, plus
+ *   ISM_EINVAL for rt_target <= 0, iters outside [1, 60] or a short work buffer.
+ */
+size_t ism_rt_work_bytes(int rir_len);
+int ism_rir_t30(ism_handle *h, const float *rir, int rir_len, double fs, double *t30, ism_stream stream);
+int ism_fit_beta(ism_handle *h, const double L[3], const double src[3], const double mic[3], double fs, double c,
+                 int fd_taps, double rt_target, int rir_len, int iters, void *work, size_t work_bytes,
+                 double *beta_out, double *rt_out, ism_stream stream);
+
+/*
  * Serving engine: continuous batching of single-room requests (the dataset
  * generator of section II.A run as a service, for requests of uneven room size,
  * RIR length and microphone count arriving at any time).

@@ -14,7 +14,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libism.so")
-SOURCES = ["ism_kernels.hip", "ism_api.cpp", "ism_conv.hip", "ism_serve.cpp", "bl_kernels.hip"]
+SOURCES = ["ism_kernels.hip", "ism_api.cpp", "ism_conv.hip", "ism_serve.cpp", "bl_kernels.hip", "ism_rtfit.hip"]
 ARCH = os.environ.get("ISM_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -25,6 +25,7 @@ EXPORTS = [
     "ism_rir_batch", "ism_batch_plan_stats", "ism_last_counts", "ism_set_tuning", "ism_get_tuning",
     "ism_autotune", "ism_convolve_batch", "ism_server_create", "ism_server_destroy", "ism_server_submit",
     "ism_server_poll", "ism_server_copy_result", "ism_server_release", "ism_server_stats", "ism_server_last_error", "ism_server_replay",
+    "ism_rt_work_bytes", "ism_rir_t30", "ism_fit_beta",
 ]
 
 ROOM_DTYPE = np.dtype([("L", np.float64, 3), ("beta", np.float64, 6), ("src", np.float64, 3),
@@ -99,6 +100,12 @@ def load():
     L.ism_server_last_error.restype = ctypes.c_char_p
     L.ism_server_replay.argtypes = [vp, ci, vp, dp, dp, cd, cd, ci, dp, dp]
     L.ism_server_replay.restype = ci
+    L.ism_rt_work_bytes.argtypes = [ci]
+    L.ism_rt_work_bytes.restype = ctypes.c_size_t
+    L.ism_rir_t30.argtypes = [vp, vp, ci, cd, vp, vp]
+    L.ism_rir_t30.restype = ci
+    L.ism_fit_beta.argtypes = [vp, dp, dp, dp, cd, cd, ci, cd, ci, ci, vp, ctypes.c_size_t, dp, dp, vp]
+    L.ism_fit_beta.restype = ci
     _lib = L
     return L
 
@@ -254,6 +261,31 @@ class Handle:
                                          ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
         self._check(rc)
         return out
+
+
+    # -- reverberation time
+    def rir_t30(self, rir, fs, stream=None):
+        """T30 (s) of a device FP32 RIR tensor (+inf if its decay does not reach -35 dB)."""
+        import torch
+        rir = rir.contiguous()
+        t = torch.empty(1, dtype=torch.float64, device="cuda")
+        self._check(self.lib.ism_rir_t30(self.h, ctypes.c_void_p(rir.data_ptr()), int(rir.numel()), float(fs),
+                                         ctypes.c_void_p(t.data_ptr()), _stream_handle(stream)))
+        return float(t.cpu()[0])
+
+    def fit_beta(self, L, src, mic, fs, c, fd_taps, rt_target, rir_len, iters=30, stream=None):
+        """Uniform beta whose simulated RIR (src -> mic) has T30 = rt_target.  Returns (beta, T30)."""
+        import torch
+        work = torch.empty(int(self.lib.ism_rt_work_bytes(int(rir_len))), dtype=torch.uint8, device="cuda")
+        L_ = np.ascontiguousarray(L, dtype=np.float64)
+        s_ = np.ascontiguousarray(src, dtype=np.float64)
+        m_ = np.ascontiguousarray(mic, dtype=np.float64)
+        beta, rt = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.ism_fit_beta(self.h, _dptr(L_), _dptr(s_), _dptr(m_), float(fs), float(c), int(fd_taps),
+                                          float(rt_target), int(rir_len), int(iters),
+                                          ctypes.c_void_p(work.data_ptr()), int(work.numel()),
+                                          ctypes.byref(beta), ctypes.byref(rt), _stream_handle(stream)))
+        return beta.value, rt.value
 
 
 SERVER_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}

@@ -130,7 +130,7 @@ def torus_sources(rng, center, n, R=2.0, dR=0.5, dphi_deg=7.0):
                                           r * np.sin(ph)], axis=1)
 
 
-def paper_room1(n_sources=48000, seed=2109, fs=16000.0, c=C_SOUND, fd_taps=8):
+def paper_room1(n_sources=48000, seed=2109, fs=16000.0, c=C_SOUND, fd_taps=8, beta=None):
     """The paper's first training room (section II.A and the dataset description): every source
     position is one entry of the batch, with the 7-microphone array; RIRs up to the
     reverberation time.  The paper names no sampling rate: 16 kHz here.  Reflection
@@ -138,7 +138,8 @@ def paper_room1(n_sources=48000, seed=2109, fs=16000.0, c=C_SOUND, fd_taps=8):
     rng = np.random.default_rng(seed)
     L = np.array([7.0, 10.0, 3.7])
     rt = 0.5
-    beta, _ = sabine_beta(L, rt, c)
+    if beta is None:  # a caller may pass a fitted coefficient instead of Sabine's
+        beta, _ = sabine_beta(L, rt, c)
     center = np.array([4.0, 6.0, 1.5])
     mics = uma8_array(center)
     src = torus_sources(rng, center, n_sources)

@@ -1,0 +1,63 @@
+"""GPU parity of the reverberation-time estimate and the uniform-absorption fit
+(paper section III.A) against the FP64 oracle (oracle/rt_fit.py), through the C-ABI.
+
+Tolerance.  The T30 estimate is a regression over thousands of samples of a
+decay computed in FP64 from the RIR; on the same samples both sides agree to
+rounding (1e-9 relative).  The fitted beta follows bisection decisions on T30
+values computed from the GPU's FP32 RIR and the oracle's FP64 RIR, which differ
+by about 1e-7 of the peak; both sides take the same decisions unless a step's
+T30 lands within that of the target, so beta agrees to the bisection width
+(2^-21 after 20 steps) with a margin.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import rt_fit as ref
+from paper_2104_13347_amd import ism
+
+FS = 8000.0
+L, SRC, MIC = [4.0, 5.0, 3.0], [1.2, 1.5, 1.4], [2.9, 3.6, 1.6]
+
+
+@pytest.fixture(scope="module")
+def handle():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    h = ism.Handle()
+    yield h
+    h.close()
+
+
+@pytest.mark.parametrize("T", [0.2, 0.9])
+def test_t30_exponential_decay(handle, T):
+    n = np.arange(int(3 * T * FS))
+    h = (np.exp(-3 * math.log(10) / T * n / FS) * np.random.default_rng(2).choice([-1.0, 1.0], n.size)).astype(np.float32)
+    got = handle.rir_t30(torch.from_numpy(h).cuda(), FS)
+    want = ref.t30(h.astype(np.float64), FS)
+    print(f"[exp decay T={T}] gpu {got:.9f} oracle {want:.9f}", flush=True)
+    assert abs(got - want) <= 1e-9 * want and abs(got - T) <= 1e-5 * T
+
+
+def test_t30_of_simulated_rir_and_short_decay(handle):
+    out = handle.rir(L, [0.8] * 6, SRC, [MIC], FS, 343.0, -1, 4800, 8)
+    torch.cuda.synchronize()
+    got = handle.rir_t30(out[0], FS)
+    want = ref.t30(out[0].cpu().numpy().astype(np.float64), FS)
+    print(f"[simulated RIR] gpu {got:.9f} oracle {want:.9f}", flush=True)
+    assert abs(got - want) <= 1e-9 * want
+    short = torch.from_numpy(np.exp(-np.arange(200) / 1000.0).astype(np.float32)).cuda()
+    assert handle.rir_t30(short, FS) == math.inf
+
+
+def test_fit_beta_matches_oracle(handle):
+    rt_target, n = 0.25, int(2.5 * 0.25 * FS)
+    beta, rt = handle.fit_beta(L, SRC, MIC, FS, 343.0, 8, rt_target, n, iters=20)
+    rb, rr = ref.fit_beta(L, SRC, MIC, FS, 343.0, 8, rt_target, n, iters=20)
+    print(f"[fit] gpu beta {beta:.7f} T30 {rt:.6f}  oracle beta {rb:.7f} T30 {rr:.6f}", flush=True)
+    assert abs(beta - rb) <= 1e-5
+    assert abs(rt - rr) <= 1e-4 * rr and abs(rt - rt_target) <= 1e-3
