@@ -304,31 +304,64 @@ int ism_build_plan(ism_handle *h, int n_rooms, const ism_room *rooms, const doub
     }
     plan.pow_total = pow_total;
     // longest-first order: counting sort of the units on a log2 cost key (1/16 octave
-    // buckets); a unit's items (its microphones) stay together
+    // buckets); a unit's items (its microphones) stay together.  Threads take contiguous
+    // room ranges with their own histograms; their cursors are laid out bucket by bucket
+    // in thread order, which gives the order of the sequential stable sort.
     const int NB = 64 * 16;
+    const int nt = host_threads((size_t)n_items);
     std::vector<int32_t> bucket(n_units);
-    std::vector<int64_t> hist(NB + 1, 0);
-    for (int i = 0; i < n_rooms; ++i) {
-        const ism_room &r = rooms[i];
-        for (int32_t u = unit_first[i]; u < unit_first[i + 1]; ++u) {
-            const int s0 = (u - unit_first[i]) * seg_len, s1 = std::min(s0 + seg_len, r.rir_len);
-            const double cst = item_cost(r, fs, c, K, s0, s1);
-            plan.est_taps += (cst - 1.0) > 0 ? cst * r.n_mics : 0.0;
-            int bk = (int)std::floor(std::log2(std::max(1.0f, (float)cst)) * 16.0);
-            bk = std::min(std::max(bk, 0), NB - 1);
-            bucket[u] = NB - 1 - bk;
-            hist[bucket[u] + 1] += r.n_mics;
+    std::vector<int64_t> th_hist((size_t)nt * NB, 0);
+    std::vector<double> th_taps(nt, 0.0);
+    auto room_range = [&](int t, int &lo, int &hi) {
+        lo = (int)((int64_t)n_rooms * t / nt);
+        hi = (int)((int64_t)n_rooms * (t + 1) / nt);
+    };
+    parallel_ranges((size_t)nt, nt, [&](size_t t0, size_t t1) {
+        for (size_t t = t0; t < t1; ++t) {
+            int lo, hi;
+            room_range((int)t, lo, hi);
+            int64_t *hist = th_hist.data() + t * NB;
+            double taps = 0.0;
+            for (int i = lo; i < hi; ++i) {
+                const ism_room &r = rooms[i];
+                for (int32_t u = unit_first[i]; u < unit_first[i + 1]; ++u) {
+                    const int s0 = (u - unit_first[i]) * seg_len, s1 = std::min(s0 + seg_len, r.rir_len);
+                    const double cst = item_cost(r, fs, c, K, s0, s1);
+                    taps += (cst - 1.0) > 0 ? cst * r.n_mics : 0.0;
+                    int bk = (int)std::floor(std::log2(std::max(1.0f, (float)cst)) * 16.0);
+                    bk = std::min(std::max(bk, 0), NB - 1);
+                    bucket[u] = NB - 1 - bk;
+                    hist[bucket[u]] += r.n_mics;
+                }
+            }
+            th_taps[t] = taps;
         }
-    }
+    });
+    for (int t = 0; t < nt; ++t) plan.est_taps += th_taps[t];
     plan.est_records = plan.est_taps / (2.0 * K + 1.0);
-    for (int bk = 0; bk < NB; ++bk) hist[bk + 1] += hist[bk];
-    // first item of each unit in the sorted order (stable within a bucket)
+    {   // exclusive offsets: bucket-major, thread-minor
+        int64_t run = 0;
+        for (int bk = 0; bk < NB; ++bk)
+            for (int t = 0; t < nt; ++t) {
+                const int64_t v = th_hist[(size_t)t * NB + bk];
+                th_hist[(size_t)t * NB + bk] = run;
+                run += v;
+            }
+    }
+    // first item of each unit in the sorted order
     std::vector<int32_t> unit_pos(n_units);
-    for (int i = 0; i < n_rooms; ++i)
-        for (int32_t u = unit_first[i]; u < unit_first[i + 1]; ++u) {
-            unit_pos[u] = (int32_t)hist[bucket[u]];
-            hist[bucket[u]] += rooms[i].n_mics;
+    parallel_ranges((size_t)nt, nt, [&](size_t t0, size_t t1) {
+        for (size_t t = t0; t < t1; ++t) {
+            int lo, hi;
+            room_range((int)t, lo, hi);
+            int64_t *cur = th_hist.data() + t * NB;
+            for (int i = lo; i < hi; ++i)
+                for (int32_t u = unit_first[i]; u < unit_first[i + 1]; ++u) {
+                    unit_pos[u] = (int32_t)cur[bucket[u]];
+                    cur[bucket[u]] += rooms[i].n_mics;
+                }
         }
+    });
     plan.items.resize(n_items);
     ItemDev *out = plan.items.data();
     parallel_ranges((size_t)n_rooms, host_threads((size_t)n_items), [&](size_t lo, size_t hi) {

@@ -2,7 +2,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/ism.h"
@@ -10,9 +12,26 @@
 
 namespace ism {
 
+// Allocator whose value-less construct leaves trivially constructible elements
+// uninitialised: resizing the item table writes nothing, its threaded fill is the only pass.
+template <class T>
+struct DefaultInitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = DefaultInitAlloc<U>;
+    };
+    DefaultInitAlloc() = default;
+    template <class U>
+    DefaultInitAlloc(const DefaultInitAlloc<U> &) noexcept {}
+    template <class U>
+    void construct(U *p) noexcept { ::new ((void *)p) U; }
+    template <class U, class... Args>
+    void construct(U *p, Args &&...args) { ::new ((void *)p) U(std::forward<Args>(args)...); }
+};
+
 struct Plan {
     std::vector<RoomDev> rooms;
-    std::vector<ItemDev> items;
+    std::vector<ItemDev, DefaultInitAlloc<ItemDev>> items;
     int64_t n_mics_total = 0;
     int64_t pow_total = 0;
     int seg_max = 0;
