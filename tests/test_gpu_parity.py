@@ -147,6 +147,20 @@ def test_c3_precision_variants(H):
     assert res["split32"] >= res["fp32"]
 
 
+def test_c3_all_rooms_sampled(H):
+    # the 48 kHz workload in its benchmark launch (64 rooms x 16 mics, 72 000 samples,
+    # 127 taps); one microphone of every room (a different one per room) against the oracle
+    b = scenes.c3()
+    gpu, _ = run(H, b)
+    rirs = [(r, r % 16) for r in range(64)]
+    _say("c3 all rooms: oracle")
+    ref, _, _ = oracle_batch(b, rirs, nthreads=min(16, os.cpu_count() or 1))
+    err = rel_errors(b, gpu, ref, rirs)
+    _say(f"c3 all rooms: max err {err.max():.3e} (room {int(err.argmax())})")
+    assert err.max() <= TOL_FP32
+    assert np.all(np.isfinite(gpu))
+
+
 def test_absorbing_rooms_late_segments(H):
     # Strongly absorbing walls (beta 0.02 .. 0.3, and one room with beta = 0) and long RIRs:
     # in late segments nearly all records have gains far below the item's scale, so the
