@@ -180,19 +180,17 @@ __global__ __launch_bounds__(64, 4) void conv_mfma(const float *__restrict__ x, 
     const int i = lane & 31;           // A row / B column within a tile
     const int kk0 = (lane >> 5) * 8;   // first K index of this lane's eight
     const uint32_t *xr32 = (const uint32_t *)xring;
-    // one step: Y_t += T_s H_{t - s} for the 16 output blocks t0 .. t0 + 15
-    auto step = [&](int s) {
-        // A fragments of T_s for K steps 0 and 1: x[X - e], X = 32 s + i - 16 ks - kk0, e = 0..7
+    // one step: Y_t += T_s H_{t - s} for the 16 output blocks t0 .. t0 + 15.  The A
+    // fragments of T_s are x[X - e], X = 32 s + i - 16 ks - kk0, e = 0..7: ring entry
+    // p = (-X) mod 128 for ks = 0 and p + 16 for ks = 1 (the ring is stored twice, so no
+    // wrap); read as the dwords w = p / 2 .. w + 4 and realigned by 16 (p mod 2) bits.
+    auto step = [&](int s, int w, uint32_t sh) {
         bf16x8_t a[2];
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-            const int X = CB * s + i - 16 * ks - kk0;
-            const int p = (-X) & (XR - 1);               // ring entry of e = 0
-            const int w = p >> 1;
-            const uint32_t sh = (uint32_t)(p & 1) * 16u;
             uint32_t d[5];
 #pragma unroll
-            for (int k = 0; k < 5; ++k) d[k] = xr32[w + k];
+            for (int k = 0; k < 5; ++k) d[k] = xr32[w + 8 * ks + k];
             u32x4_t v;
 #pragma unroll
             for (int k = 0; k < 4; ++k) v[k] = __builtin_amdgcn_alignbit(d[k + 1], d[k], sh);
@@ -215,16 +213,32 @@ __global__ __launch_bounds__(64, 4) void conv_mfma(const float *__restrict__ x, 
                 acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], __builtin_bit_cast(bf16x8_t, bv[ks][nt]),
                                                                    acc[nt], 0, 0, 0);
     };
+    auto ring_entry = [&](int s) { return (-(CB * s + i - kk0)) & (XR - 1); };
+    // Step u = s_start + 1 + 4 k + j enters source block u at ring entry (-32 u - lane) mod 128
+    // and reads T_u from entry (-(32 u + i - kk0)) mod 128: both depend on j only (four steps
+    // make one lap of the ring), so they are computed once.  Lanes below 32 store, and for
+    // them the two entries coincide.
+    int pj[PD];
+#pragma unroll
+    for (int j = 0; j < PD; ++j) pj[j] = ring_entry(s_start + 1 + j);
     auto advance = [&](int u, int j) {
         __syncthreads();   // the previous step's ring reads precede these writes
         store_block(t0 - u, hq[j]);
-        store_x(u, xq[j]);
+        if (lane < 32) {
+            const int X = CB * u + lane;
+            const uint16_t bv = (X >= 0 && X < src_len) ? f2bf(xq[j]) : (uint16_t)0;
+            xring[pj[j]] = bv;
+            xring[pj[j] + XR] = bv;
+        }
         hq[j] = load_block(t0 - u - PD);
         xq[j] = load_x(u + PD);
         __syncthreads();
-        step(u);
+        step(u, pj[j] >> 1, (uint32_t)(pj[j] & 1) * 16u);
     };
-    step(s_start);
+    {
+        const int p0 = ring_entry(s_start);
+        step(s_start, p0 >> 1, (uint32_t)(p0 & 1) * 16u);
+    }
     int u0 = s_start + 1;
     for (; u0 + PD - 1 <= s_end; u0 += PD) {   // whole groups: no branch inside
 #pragma unroll
