@@ -93,7 +93,13 @@ constexpr int XR = 128;   // source ring length (samples)
 constexpr int CRS = 40;   // RIR ring row stride (u16): 80 B rows keep the eight microphones' 16-B
                           // reads of one step on eight different bank groups
 
-__global__ __launch_bounds__(64, 4) void conv_mfma(const float *__restrict__ x, int src_len, int out_len,
+#ifndef CONV_PD
+#define CONV_PD 4  // steps of global prefetch (a multiple of 4: the source-ring entries repeat every 4 steps)
+#endif
+#ifndef CONV_MIN_WAVES
+#define CONV_MIN_WAVES 4
+#endif
+__global__ __launch_bounds__(64, CONV_MIN_WAVES) void conv_mfma(const float *__restrict__ x, int src_len, int out_len,
                                                 const uint16_t *__restrict__ hb,
                                                 const ConvRoom *__restrict__ rooms,
                                                 float *__restrict__ y, double *__restrict__ psum,
@@ -162,7 +168,7 @@ __global__ __launch_bounds__(64, 4) void conv_mfma(const float *__restrict__ x, 
         for (int tl = 0; tl < CG; ++tl) store_block(t0 - s_start + tl, h0[tl]);
     }
     // prefetch queue: the blocks entering the rings at step u sit in slot (u - s_start - 1) % PD
-    constexpr int PD = 4;
+    constexpr int PD = CONV_PD;
     float xq[PD];
     uint2 hq[PD];
 #pragma unroll
