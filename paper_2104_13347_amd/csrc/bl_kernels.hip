@@ -52,7 +52,11 @@ constexpr int NL = 18;
 #ifndef BL_STAGE_U
 #define BL_STAGE_U 4
 #endif
-constexpr int MT = 64;           // time samples per tile: one wave covers the tile's 64 rows
+#ifndef BL_RB
+#define BL_RB 4
+#endif
+constexpr int RB = BL_RB;        // 16-row blocks per wave: each wave covers all rows of its tile
+constexpr int MT = 16 * RB;      // time samples per tile
 constexpr int BPF = BL_PREFETCH; // weight-fragment steps loaded ahead of the one in use
 #ifndef BL_CHUNK
 #define BL_CHUNK 0
@@ -460,10 +464,10 @@ DEV void preload_b(f16x8_t (&bq)[P + 1][4], const LayerArgs &A, int cg, int lane
 
 template <int P>
 DEV void gemm_tile(const LayerArgs &A, const _Float16 *xh, const _Float16 *xl, int cg, int lane,
-                   f16x8_t (&bq)[P + 1][4], f32x4_t (&acc)[4][2])
+                   f16x8_t (&bq)[P + 1][4], f32x4_t (&acc)[RB][2])
 {
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     const _Float16 *fr = A.frag + lane * 8;
@@ -476,7 +480,7 @@ DEV void gemm_tile(const LayerArgs &A, const _Float16 *xh, const _Float16 *xl, i
         const int tap = ks >> 2;
         const int off = (tap * D + rowl) * XROW + (ks & 3) * 32 + 8 * (lane >> 4);
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
+        for (int rb = 0; rb < RB; ++rb) {
             const f16x8_t ah = *(const f16x8_t *)(xh + off + rb * 16 * XROW);
             const f16x8_t al = *(const f16x8_t *)(xl + off + rb * 16 * XROW);
 #pragma unroll
@@ -491,7 +495,7 @@ DEV void gemm_tile(const LayerArgs &A, const _Float16 *xh, const _Float16 *xl, i
 
 // Scale back, add the bias and store the wave's 64 x 32 block of a_l; returns the wave's
 // sum over the valid rows (every lane).
-DEV float store_tile(const LayerArgs &A, int b, int tile, int cg, int lane, f32x4_t (&acc)[4][2])
+DEV float store_tile(const LayerArgs &A, int b, int tile, int cg, int lane, f32x4_t (&acc)[RB][2])
 {
     const int T = A.T, t0 = tile * MT;
     const int nrows = min(MT, T - t0);
@@ -501,7 +505,7 @@ DEV float store_tile(const LayerArgs &A, int b, int tile, int cg, int lane, f32x
     for (int cb = 0; cb < 2; ++cb) {
         const float bn_ = A.bias[32 * cg + 16 * cb + (lane & 15)];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[rb][cb][v] = fmaf(acc[rb][cb][v], osc, bn_);
     }
@@ -510,7 +514,7 @@ DEV float store_tile(const LayerArgs &A, int b, int tile, int cg, int lane, f32x
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     dst[(16 * rb + v) * NF + 16 * cb] = acc[rb][cb][v];
@@ -520,7 +524,7 @@ DEV float store_tile(const LayerArgs &A, int b, int tile, int cg, int lane, f32x
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                     if (16 * rb + 4 * (lane >> 4) + v < nrows) {
@@ -532,13 +536,13 @@ DEV float store_tile(const LayerArgs &A, int b, int tile, int cg, int lane, f32x
 }
 
 // Sum of squared deviations from `mean` over the valid rows of the wave's block.
-DEV float m2_tile(int nrows, int lane, float mean, const f32x4_t (&acc)[4][2])
+DEV float m2_tile(int nrows, int lane, float mean, const f32x4_t (&acc)[RB][2])
 {
     float m2 = 0.f;
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const float d = acc[rb][cb][v] - mean;
@@ -567,7 +571,7 @@ __global__ __launch_bounds__(LTHREADS) void bl_layer(LayerArgs A)
     stage_tile(A, b, tile, xh, xl, tid);
     __syncthreads();
     if (!LOWLAT) preload_b<P>(bq, A, wave, lane);
-    f32x4_t acc[4][2];
+    f32x4_t acc[RB][2];
     gemm_tile<P>(A, xh, xl, wave, lane, bq, acc);
     const int nrows = min(MT, A.T - tile * MT);
     const float s = store_tile(A, b, tile, wave, lane, acc);
