@@ -238,7 +238,9 @@ int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float *rirs,
  *   *beta_out, *rt_out (host): the fitted beta and the T30 of its RIR.  Blocking: it
  *   waits for `stream` after every step.  rir_len should cover the decay to -35 dB
  *   (about 1.5 x rt_target x fs or more).  Validation as for ism_rir, plus
- *   ISM_EINVAL for rt_target <= 0, iters outside [1, 60] or a short work buffer.
+ *   ISM_EINVAL for rt_target <= 0, iters outside [1, 60] or a short work buffer;
+ *   ISM_EDOMAIN (beta_out and rt_out still written) when the final T30 misses the
+ *   target by more than 1 % (an RIR too short for the decay, or too few steps).
  */
 size_t ism_rt_work_bytes(int rir_len);
 int ism_rir_t30(ism_handle *h, const float *rir, int rir_len, double fs, double *t30, ism_stream stream);

@@ -185,5 +185,10 @@ extern "C" int ism_fit_beta(ism_handle *h, const double L[3], const double src[3
     if (rc) return rc;
     *beta_out = beta;
     *rt_out = rt;
+    if (!(std::fabs(rt - rt_target) <= 0.01 * rt_target)) {
+        ism_set_error(h, "target T30 %.4g s not reached: T30 %.4g s at beta %.6g after %d steps (rir_len too short "
+                      "for the decay, or fewer steps than the target needs)", rt_target, rt, beta, iters);
+        return ISM_EDOMAIN;
+    }
     return ISM_OK;
 }

@@ -61,3 +61,11 @@ def test_fit_beta_matches_oracle(handle):
     print(f"[fit] gpu beta {beta:.7f} T30 {rt:.6f}  oracle beta {rb:.7f} T30 {rr:.6f}", flush=True)
     assert abs(beta - rb) <= 1e-5
     assert abs(rt - rr) <= 1e-4 * rr and abs(rt - rt_target) <= 1e-3
+
+
+def test_fit_beta_reports_an_unreachable_target(handle):
+    # 200 samples cannot hold a 0.25 s decay down to -35 dB: every step sees +inf
+    with pytest.raises(ism.IsmError) as e:
+        handle.fit_beta(L, SRC, MIC, FS, 343.0, 8, 0.25, 200, iters=10)
+    assert e.value.code == ism.ISM_EDOMAIN
+
