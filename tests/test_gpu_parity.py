@@ -147,6 +147,25 @@ def test_c3_precision_variants(H):
     assert res["split32"] >= res["fp32"]
 
 
+def test_autotune_picks_a_candidate_and_keeps_results(H):
+    # the autotuner times each segment length on the batch and keeps the fastest; the batch
+    # then runs with it, and its RIRs still meet the bar against the oracle
+    import torch
+    b = scenes.c1(n_rooms=12)
+    best = H.autotune(b, candidates=[256, 512, 1024])
+    torch.cuda.synchronize()
+    _say(f"autotune best seg_len {best}")
+    assert best in (256, 512, 1024)
+    assert H.get_tuning()["seg_len"] == best
+    out = H.rir_batch(b)
+    torch.cuda.synchronize()
+    gpu = out.cpu().numpy()
+    rirs = [(r, r % 8) for r in range(12)]
+    ref, _, _ = oracle_batch(b, rirs)
+    assert rel_errors(b, gpu, ref, rirs).max() <= TOL_FP32
+    H.set_tuning(seg_len=1024)
+
+
 def test_c3_all_rooms_sampled(H):
     # the 48 kHz workload in its benchmark launch (64 rooms x 16 mics, 72 000 samples,
     # 127 taps); one microphone of every room (a different one per room) against the oracle
