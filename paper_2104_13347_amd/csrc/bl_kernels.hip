@@ -26,12 +26,16 @@
 //    weight fragments streamed from L2 and its activation fragments read from LDS (row
 //    pitch 272 B: the 16 rows of a fragment fall on distinct banks).  Workgroups are
 //    renumbered so that each XCD runs a contiguous range of tiles (halo rows in its L2).
+//    Batches too small to fill the chip take 16- or 32-row tiles instead (more, shorter
+//    workgroups); the layer-norm partials are per 16 rows in every form, so the tile
+//    height changes the schedule, not a single bit of the result.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
 
+#include <atomic>
 #include <cmath>
 #include <new>
 
@@ -52,16 +56,16 @@ constexpr int NL = 18;
 #ifndef BL_STAGE_U
 #define BL_STAGE_U 4
 #endif
-#ifndef BL_RB
-#define BL_RB 4
+#ifndef BL_LOWLAT_U
+#define BL_LOWLAT_U 4
 #endif
-constexpr int RB = BL_RB;        // 16-row blocks per wave: each wave covers all rows of its tile
-constexpr int MT = 16 * RB;      // time samples per tile
+constexpr int SB = 16;           // rows per layer-norm partial (the finest tile height)
 constexpr int BPF = BL_PREFETCH; // weight-fragment steps loaded ahead of the one in use
 #ifndef BL_CHUNK
 #define BL_CHUNK 0
 #endif
 constexpr int CHUNK = BL_CHUNK;  // frames per pass through the 18 layers (0: the whole batch)
+constexpr int MT0 = 64;         // time samples per layer-0 tile
 constexpr int KSTEPS = 12;       // K = 3 taps x 128 channels in steps of 32
 constexpr int XROW = 136;        // LDS pitch of a staged input row, in halves
 constexpr int MAX_D = 32;
@@ -99,17 +103,19 @@ ModelLayout model_layout(int c_in, int n_out)
 
 struct WsLayout {
     size_t a[2], x[2], st[2], part, total;
-    int ntiles, ne;
+    int nst, ne;
 };
+
+int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 WsLayout ws_layout(int batch, int n_t)
 {
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     WsLayout w;
-    w.ntiles = (n_t + MT - 1) / MT;
-    w.ne = (n_t - 2 * MARGIN + MT - 1) / MT;
+    w.nst = cdiv(n_t, SB);
+    w.ne = cdiv(n_t - 2 * MARGIN, MT0);
     const size_t map = (size_t)batch * n_t * NF * sizeof(float);
-    const size_t st = (size_t)batch * w.ntiles * 2 * sizeof(double);
+    const size_t st = (size_t)batch * w.nst * 2 * sizeof(double);
     size_t o = 0;
     for (int i = 0; i < 2; ++i) { w.a[i] = o; o = al(o + map); }
     for (int i = 0; i < 2; ++i) { w.x[i] = o; o = al(o + map); }
@@ -138,6 +144,40 @@ DEV double wave_sum(double v)
     return v;
 }
 
+// Wave totals of RB per-lane values at the cost of about one: at the xor-32 step the two
+// halves of the wave each keep half of the values (and at xor 16 half again), sending the
+// partner only what it keeps.  Every kept value sees the same additions, in the same
+// order, as in wave_sum, so lane l returns exactly wave_sum(v[rb]) for rb = l / (64 / RB).
+template <int RB>
+DEV double wave_sum_split(const float (&s)[RB])
+{
+    static_assert(RB == 1 || RB == 2 || RB == 4, "RB is 1, 2 or 4");
+    const int lane = threadIdx.x & 63;
+    double k;
+    int m0 = 32;
+    if constexpr (RB == 1) {
+        k = (double)s[0];
+    } else if constexpr (RB == 2) {
+        const bool hi = lane & 32;
+        k = (double)(hi ? s[1] : s[0]);
+        k += __shfl_xor((double)(hi ? s[0] : s[1]), 32, 64);
+        m0 = 16;
+    } else {
+        const bool hi = lane & 32;
+        double k0 = (double)(hi ? s[2] : s[0]), k1 = (double)(hi ? s[3] : s[1]);
+        k0 += __shfl_xor((double)(hi ? s[0] : s[2]), 32, 64);
+        k1 += __shfl_xor((double)(hi ? s[1] : s[3]), 32, 64);
+        const bool h16 = lane & 16;
+        k = h16 ? k1 : k0;
+        k += __shfl_xor(h16 ? k0 : k1, 16, 64);
+        m0 = 8;
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        if (m <= m0) k += __shfl_xor(k, m, 64);
+    return k;
+}
+
 DEV double wave_max(double v)
 {
 #pragma unroll
@@ -158,33 +198,42 @@ DEV double block_sum(double v, double *red, int nw)
     return s;
 }
 
-// Layer-norm statistics of one frame from its per-tile (sum, M2 about the tile mean)
-// partials (Chan et al.'s pairwise update, written as two sums), each sum spread over
-// the lanes of a wave; every wave computes them for itself.
-DEV void ln_stats(const double *st, int ntiles, int T, float eps, double &mean, double &rstd)
+// Layer-norm statistics of one frame from its per-block (sum, M2 about the block mean)
+// partials, one per SB rows (Chan et al.'s pairwise update, written as two sums), each sum
+// spread over the lanes of a wave; every wave computes them for itself.  The partials are
+// per SB rows whatever the tile height of the kernels that wrote them, so a frame's
+// statistics, and with them its result, do not depend on the batch it runs in.
+//
+// One load round (nst <= 64): lane i holds partial i (si, mi; zero beyond nst).
+DEV void ln_stats_lanes(double si, double mi, int nst, int T, float eps, double &mean, double &rstd)
 {
     const int lane = threadIdx.x & 63;
     const double N = (double)T * NF;
-    if (ntiles <= 64) {  // one load round: lane i holds tile i's partials
-        const double si = lane < ntiles ? st[2 * lane] : 0.0;
-        const double mi = lane < ntiles ? st[2 * lane + 1] : 0.0;
-        mean = wave_sum(si) / N;
-        double m2 = 0.0;
-        if (lane < ntiles) {
-            const double ni = (double)min(MT, T - lane * MT) * NF;
-            const double d = si / ni - mean;
-            m2 = mi + ni * d * d;
-        }
-        rstd = 1.0 / sqrt(wave_sum(m2) / N + (double)eps);
+    mean = wave_sum(si) / N;
+    double m2 = 0.0;
+    if (lane < nst) {
+        const double ni = (double)min(SB, T - lane * SB) * NF;
+        const double d = si / ni - mean;
+        m2 = mi + ni * d * d;
+    }
+    rstd = 1.0 / sqrt(wave_sum(m2) / N + (double)eps);
+}
+
+DEV void ln_stats(const double *st, int nst, int T, float eps, double &mean, double &rstd)
+{
+    const int lane = threadIdx.x & 63;
+    if (nst <= 64) {
+        const bool ok = lane < nst;
+        ln_stats_lanes(ok ? st[2 * lane] : 0.0, ok ? st[2 * lane + 1] : 0.0, nst, T, eps, mean, rstd);
         return;
     }
+    const double N = (double)T * NF;
     double s = 0.0;
-    for (int i = lane; i < ntiles; i += 64) s += st[2 * i];
+    for (int i = lane; i < nst; i += 64) s += st[2 * i];
     mean = wave_sum(s) / N;
     double m2 = 0.0;
-    for (int i = lane; i < ntiles; i += 64) {
-        const int rows = min(MT, T - i * MT);
-        const double ni = (double)rows * NF;
+    for (int i = lane; i < nst; i += 64) {
+        const double ni = (double)min(SB, T - i * SB) * NF;
         const double d = st[2 * i] / ni - mean;
         m2 += st[2 * i + 1] + ni * d * d;
     }
@@ -292,39 +341,41 @@ struct Layer0Args {
     const float *w0;    // [3][c_in][128]
     const float *bias;  // [128]
     float *a_out;       // [B][T][128]
-    double *st_out;     // [B][ntiles][2]
-    int T, ntiles, c_in;
+    double *st_out;     // [B][nst][2]
+    int T, ntiles, nst, c_in;
 };
 
-// One thread per output channel and quarter of the tile's rows (its MT/4 outputs in
-// registers).  The folded weights and each channel's input window sit in LDS; the
-// window is read as 16-byte broadcasts, one channel at a time.
+// One thread per output channel and 16-row block of the tile (its 16 outputs in
+// registers): block p is computed by waves 2p and 2p + 1, which also give its layer-norm
+// partial.  The folded weights and each channel's input window sit in LDS; the window
+// is read as 16-byte broadcasts, one channel at a time.
 constexpr int L0THREADS = 512;
-constexpr int L0XP = MT + 4;   // LDS pitch of an input channel: 16-byte aligned rows
+constexpr int L0XP = MT0 + 4;  // LDS pitch of an input channel: 16-byte aligned rows
 
 __global__ __launch_bounds__(L0THREADS) void bl_layer0(Layer0Args A)
 {
-    constexpr int R = MT / (L0THREADS / NF);  // rows per thread
+    constexpr int R = MT0 / (L0THREADS / NF);  // rows per thread
+    static_assert(R == SB, "one 16-row block per group of 128 threads");
     extern __shared__ __align__(16) unsigned char smem[];
     const int c_in = A.c_in;
     float *xin = (float *)smem;          // [c_in][L0XP]: xin[c][p] holds sample t0 - 1 + p
     float *wl = xin + c_in * L0XP;       // [3][c_in][128]
-    double *red = (double *)(wl + 3 * c_in * NF);
-    const int tid = threadIdx.x;
+    double *red = (double *)(wl + 3 * c_in * NF);  // [2][8]
+    const int tid = threadIdx.x, wave = tid >> 6;
     const int blk = xcd_block();
     const int b = blk / A.ntiles, tile = blk % A.ntiles;
-    const int t0 = tile * MT, T = A.T;
+    const int t0 = tile * MT0, T = A.T;
     const int64_t off = A.offs ? A.offs[b] : A.base + (int64_t)b * A.ex_stride;
     for (int i = tid; i < c_in * L0XP; i += L0THREADS) {
         const int c = i / L0XP, p = i % L0XP;
         const int t = t0 - 1 + p;
-        xin[i] = (p < MT + 2 && t >= 0 && t < T) ? A.x[off + (int64_t)c * A.ch_stride + t] : 0.f;
+        xin[i] = (p < MT0 + 2 && t >= 0 && t < T) ? A.x[off + (int64_t)c * A.ch_stride + t] : 0.f;
     }
     for (int i = tid; i < 3 * c_in * NF; i += L0THREADS) wl[i] = A.w0[i];
     __syncthreads();
     const int o = tid & (NF - 1), part = tid / NF;
-    const int rows = min(MT, T - t0);
     const int r0 = part * R;
+    const int nr = min(R, T - t0 - r0);  // valid rows of this block (<= 0 past the frame)
     const float bo = A.bias[o];
     float v[R];
 #pragma unroll
@@ -346,22 +397,28 @@ __global__ __launch_bounds__(L0THREADS) void bl_layer0(Layer0Args A)
     float s = 0.f;
 #pragma unroll
     for (int i = 0; i < R; ++i)
-        if (r0 + i < rows) {
+        if (i < nr) {
             dst[(size_t)i * NF] = v[i];
             s += v[i];
         }
-    const double S = block_sum((double)s, red, L0THREADS / 64);
-    const float mt = (float)(S / ((double)rows * NF));
+    const double ws = wave_sum((double)s);
+    if ((tid & 63) == 0) red[wave] = ws;
+    __syncthreads();
+    const double S = red[2 * part] + red[2 * part + 1];
+    const float mt = nr > 0 ? (float)(S / ((double)nr * NF)) : 0.f;
     float m2 = 0.f;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const float d = v[i] - mt;
-        if (r0 + i < rows) m2 = fmaf(d, d, m2);
+        if (i < nr) m2 = fmaf(d, d, m2);
     }
-    const double M2 = block_sum((double)m2, red, L0THREADS / 64);
-    if (tid == 0) {
-        A.st_out[((size_t)b * A.ntiles + tile) * 2] = S;
-        A.st_out[((size_t)b * A.ntiles + tile) * 2 + 1] = M2;
+    const double wm = wave_sum((double)m2);
+    if ((tid & 63) == 0) red[8 + wave] = wm;
+    __syncthreads();
+    if (o == 0 && nr > 0) {
+        double *so = A.st_out + ((size_t)b * A.nst + tile * (MT0 / SB) + part) * 2;
+        so[0] = S;
+        so[1] = red[8 + 2 * part] + red[8 + 2 * part + 1];
     }
 }
 
@@ -377,7 +434,7 @@ struct LayerArgs {
     const float *bias;     // b of layer l
     const _Float16 *frag;  // layer l's weight fragments
     const int *hdr;
-    int T, ntiles, layer, D;
+    int T, ntiles, nst, layer, D;
     float eps;
 };
 
@@ -395,7 +452,9 @@ DEV void load_b(f16x8_t (&bq)[4], const _Float16 *fr, int nb0, int ks)
 
 // Stage x_l = (l >= 2 ? x_{l-1} : 0) + tanh(LN(a_{l-1})) for rows t0 - D .. t0 + MT + D of
 // frame b into LDS as the scaled FP16 split (hi in xh, lo in xl), and write the tile's own
-// rows of x_l to HBM.  256 threads (ptid); four rows' loads are issued before any is used.
+// rows of x_l to HBM.  256 threads (ptid), 8 rows per pass; U passes' loads are issued
+// before any is used.
+template <int MT, int U>
 DEV void stage_tile(const LayerArgs &A, int b, int tile, _Float16 *xh, _Float16 *xl, int ptid)
 {
     const int D = A.D, T = A.T;
@@ -407,14 +466,13 @@ DEV void stage_tile(const LayerArgs &A, int b, int tile, _Float16 *xh, _Float16 
     float *__restrict__ x_out = A.x_out;
     const bool resid = A.layer >= 2;
     double mean, rstd;
-    ln_stats(A.st_in + (size_t)b * A.ntiles * 2, A.ntiles, T, A.eps, mean, rstd);
+    ln_stats(A.st_in + (size_t)b * A.nst * 2, A.nst, T, A.eps, mean, rstd);
     const int c4 = (ptid & 31) * 4;
     const float4 g = *(const float4 *)(A.vec_prev + NF + c4);
     const float4 be = *(const float4 *)(A.vec_prev + 2 * NF + c4);
     const float mu = (float)mean, rs = (float)rstd;
     const float4 sc = make_float4(g.x * rs, g.y * rs, g.z * rs, g.w * rs);
     constexpr int RS = 256 / 32;  // rows per pass
-    constexpr int U = BL_STAGE_U;
     for (int rb = ptid >> 5; rb < rows; rb += RS * U) {
         float4 av[U], xv[U];
 #pragma unroll
@@ -451,10 +509,10 @@ DEV void stage_tile(const LayerArgs &A, int b, int tile, _Float16 *xh, _Float16 
     }
 }
 
-// a_l[t][n] = sum over taps and channels of x_l[t + (tap-1) D][c] W[tap][c][n] for the MT = 64
-// rows of a staged tile and the 32 output channels of column group cg (one wave).  The
-// weight fragments sit in a ring of P + 1 steps: step ks in slot ks % (P + 1), step ks + P
-// loaded while step ks runs.  preload_b fills the first P slots.
+// a_l[t][n] = sum over taps and channels of x_l[t + (tap-1) D][c] W[tap][c][n] for the
+// 16 RB rows of a staged tile and the 32 output channels of column group cg (one wave).
+// The weight fragments sit in a ring of P + 1 steps: step ks in slot ks % (P + 1), step
+// ks + P loaded while step ks runs.  preload_b fills the first P slots.
 template <int P>
 DEV void preload_b(f16x8_t (&bq)[P + 1][4], const LayerArgs &A, int cg, int lane)
 {
@@ -462,7 +520,7 @@ DEV void preload_b(f16x8_t (&bq)[P + 1][4], const LayerArgs &A, int cg, int lane
     for (int i = 0; i < P; ++i) load_b(bq[i], A.frag + lane * 8, 2 * cg, i);
 }
 
-template <int P>
+template <int P, int RB>
 DEV void gemm_tile(const LayerArgs &A, const _Float16 *xh, const _Float16 *xl, int cg, int lane,
                    f16x8_t (&bq)[P + 1][4], f32x4_t (&acc)[RB][2])
 {
@@ -493,14 +551,15 @@ DEV void gemm_tile(const LayerArgs &A, const _Float16 *xh, const _Float16 *xl, i
     }
 }
 
-// Scale back, add the bias and store the wave's 64 x 32 block of a_l; returns the wave's
-// sum over the valid rows (every lane).
-DEV float store_tile(const LayerArgs &A, int b, int tile, int cg, int lane, f32x4_t (&acc)[RB][2])
+// Scale back, add the bias and store the wave's 16 RB x 32 block of a_l; s[rb] gets the
+// lane's sum over the valid rows of 16-row block rb.
+template <int RB>
+DEV void store_tile(const LayerArgs &A, int b, int tile, int cg, int lane, f32x4_t (&acc)[RB][2], float (&s)[RB])
 {
+    constexpr int MT = 16 * RB;
     const int T = A.T, t0 = tile * MT;
     const int nrows = min(MT, T - t0);
     const float osc = ldexpf(1.f, -(XEXP + A.hdr[A.layer]));
-    float s = 0.f;
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
         const float bn_ = A.bias[32 * cg + 16 * cb + (lane & 15)];
@@ -510,6 +569,8 @@ DEV float store_tile(const LayerArgs &A, int b, int tile, int cg, int lane, f32x
             for (int v = 0; v < 4; ++v) acc[rb][cb][v] = fmaf(acc[rb][cb][v], osc, bn_);
     }
     float *__restrict__ dst = A.a_out + ((size_t)b * T + t0 + 4 * (lane >> 4)) * NF + 32 * cg + (lane & 15);
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) s[rb] = 0.f;
     if (nrows == MT) {
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
@@ -518,7 +579,7 @@ DEV float store_tile(const LayerArgs &A, int b, int tile, int cg, int lane, f32x
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     dst[(16 * rb + v) * NF + 16 * cb] = acc[rb][cb][v];
-                    s += acc[rb][cb][v];
+                    s[rb] += acc[rb][cb][v];
                 }
     } else {
 #pragma unroll
@@ -529,58 +590,88 @@ DEV float store_tile(const LayerArgs &A, int b, int tile, int cg, int lane, f32x
                 for (int v = 0; v < 4; ++v)
                     if (16 * rb + 4 * (lane >> 4) + v < nrows) {
                         dst[(16 * rb + v) * NF + 16 * cb] = acc[rb][cb][v];
-                        s += acc[rb][cb][v];
+                        s[rb] += acc[rb][cb][v];
                     }
     }
-    return s;
 }
 
-// Sum of squared deviations from `mean` over the valid rows of the wave's block.
-DEV float m2_tile(int nrows, int lane, float mean, const f32x4_t (&acc)[RB][2])
+// Sums of squared deviations from each 16-row block's mean over its valid rows.
+template <int RB>
+DEV void m2_tile(int nrows, int lane, const float (&mean)[RB], const f32x4_t (&acc)[RB][2], float (&m2)[RB])
 {
-    float m2 = 0.f;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) m2[rb] = 0.f;
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float d = acc[rb][cb][v] - mean;
-                if (16 * rb + 4 * (lane >> 4) + v < nrows) m2 = fmaf(d, d, m2);
+                const float d = acc[rb][cb][v] - mean[rb];
+                if (16 * rb + 4 * (lane >> 4) + v < nrows) m2[rb] = fmaf(d, d, m2[rb]);
             }
-    return m2;
 }
 
-// One tile per workgroup (4 waves): stage, barrier, GEMM, store, tile statistics.  The
-// low-latency form (at most one workgroup per CU, small batches) issues the first 7 steps'
-// weight-fragment loads before staging, so their latency hides behind it.
-template <bool LOWLAT>
+// One tile of 16 RB rows per workgroup (4 waves): stage, barrier, GEMM, store, and the
+// layer-norm partial of each 16-row block (a fixed-order sum over the four waves, so the
+// same for every RB).  The low-latency form (at most one workgroup per CU, small batches)
+// issues the first 7 steps' weight-fragment loads before staging, so their latency hides
+// behind it, and stages in fewer, wider passes.
+template <bool LOWLAT, int RB>
 __global__ __launch_bounds__(LTHREADS) void bl_layer(LayerArgs A)
 {
+    constexpr int MT = 16 * RB;
     constexpr int P = LOWLAT ? 7 : BPF;
+    constexpr int U = LOWLAT ? BL_LOWLAT_U : BL_STAGE_U;
     extern __shared__ __align__(16) unsigned char smem[];
     const int rows = MT + 2 * A.D;
     _Float16 *xh = (_Float16 *)smem;
     _Float16 *xl = xh + rows * XROW;
-    double *red = (double *)(xl + rows * XROW);
+    double *red = (double *)(xl + rows * XROW);  // [2][LWAVES][RB]
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int blk = xcd_block();
     const int b = blk / A.ntiles, tile = blk % A.ntiles;
     f16x8_t bq[P + 1][4];
     if (LOWLAT) preload_b<P>(bq, A, wave, lane);
-    stage_tile(A, b, tile, xh, xl, tid);
+    stage_tile<MT, U>(A, b, tile, xh, xl, tid);
     __syncthreads();
     if (!LOWLAT) preload_b<P>(bq, A, wave, lane);
     f32x4_t acc[RB][2];
-    gemm_tile<P>(A, xh, xl, wave, lane, bq, acc);
+    gemm_tile<P, RB>(A, xh, xl, wave, lane, bq, acc);
     const int nrows = min(MT, A.T - tile * MT);
-    const float s = store_tile(A, b, tile, wave, lane, acc);
-    const double S = block_sum((double)s, red, LWAVES);
-    const float m2 = m2_tile(nrows, lane, (float)(S / ((double)nrows * NF)), acc);
-    const double M2 = block_sum((double)m2, red, LWAVES);
-    if (tid == 0) {
-        A.st_out[((size_t)b * A.ntiles + tile) * 2] = S;
-        A.st_out[((size_t)b * A.ntiles + tile) * 2 + 1] = M2;
+    float s[RB];
+    store_tile<RB>(A, b, tile, wave, lane, acc, s);
+    constexpr int LPB = 64 / RB;  // lanes per 16-row block in wave_sum_split's result
+    {
+        const double w = wave_sum_split<RB>(s);
+        if (lane % LPB == 0) red[wave * RB + lane / LPB] = w;
+    }
+    __syncthreads();
+    float mean[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        double S = 0.0;
+        for (int w = 0; w < LWAVES; ++w) S += red[w * RB + rb];
+        const int nr = min(16, nrows - 16 * rb);
+        mean[rb] = nr > 0 ? (float)(S / ((double)nr * NF)) : 0.f;
+    }
+    float m2[RB];
+    m2_tile<RB>(nrows, lane, mean, acc, m2);
+    double *red2 = red + LWAVES * RB;
+    {
+        const double w = wave_sum_split<RB>(m2);
+        if (lane % LPB == 0) red2[wave * RB + lane / LPB] = w;
+    }
+    __syncthreads();
+    if (tid < RB && 16 * tid < nrows) {
+        double S = 0.0, M2 = 0.0;
+        for (int w = 0; w < LWAVES; ++w) {
+            S += red[w * RB + tid];
+            M2 += red2[w * RB + tid];
+        }
+        double *so = A.st_out + ((size_t)b * A.nst + tile * RB + tid) * 2;
+        so[0] = S;
+        so[1] = M2;
     }
 }
 
@@ -591,7 +682,7 @@ struct EnergyArgs {
     const double *st_in;  // partials of a_17
     const float *vec;     // b, g, be of layer 17
     float *part;          // [B][ne][128] sums of S^2
-    int T, ntiles, ne;
+    int T, nst, ne;
     float eps;
 };
 
@@ -602,9 +693,9 @@ __global__ __launch_bounds__(256) void bl_energy(EnergyArgs A)
     const int blk = xcd_block();
     const int b = blk / A.ne, et = blk % A.ne;
     const int T = A.T;
-    const int r0 = MARGIN + et * MT, r1 = min(r0 + MT, T - MARGIN);
+    const int r0 = MARGIN + et * MT0, r1 = min(r0 + MT0, T - MARGIN);
     double mean, rstd;
-    ln_stats(A.st_in + (size_t)b * A.ntiles * 2, A.ntiles, T, A.eps, mean, rstd);
+    ln_stats(A.st_in + (size_t)b * A.nst * 2, A.nst, T, A.eps, mean, rstd);
     const int c4 = (tid & 31) * 4;
     const float4 g = *(const float4 *)(A.vec + NF + c4);
     const float4 be = *(const float4 *)(A.vec + 2 * NF + c4);
@@ -663,6 +754,7 @@ __global__ __launch_bounds__(128) void bl_head(HeadArgs A)
     __shared__ double red[2];
     const int c = threadIdx.x, b = blockIdx.x;
     double e = 0.0;
+#pragma unroll 8
     for (int i = 0; i < A.ne; ++i) e += (double)A.part[((size_t)b * A.ne + i) * NF + c];
     e /= (double)A.n_valid;
     const double mean = block_sum(e, red, 2) / NF;
@@ -678,6 +770,7 @@ __global__ __launch_bounds__(128) void bl_head(HeadArgs A)
     double mx = -INFINITY;
     for (int j = c; j < A.n_out; j += NF) {
         double s = (double)bias[j];
+#pragma unroll 16
         for (int k = 0; k < NF; ++k) s += f[k] * (double)W[k * A.n_out + j];
         o[j] = s;
         mx = fmax(mx, s);
@@ -699,7 +792,25 @@ __global__ __launch_bounds__(128) void bl_head(HeadArgs A)
     for (int j = c; j < A.n_out; j += NF) A.out[(size_t)b * A.n_out + j] = (float)o[j];
 }
 
-int layer_lds_bytes(int D) { return 2 * (MT + 2 * D) * XROW * 2 + 8 * LWAVES; }
+int layer_lds_bytes(int rb, int D) { return 2 * (16 * rb + 2 * D) * XROW * 2 + 2 * 8 * LWAVES * rb; }
+
+// The layer kernel's LDS can exceed the 64 KB default: raise each form's limit once per
+// device (the attribute is per device).
+int set_layer_lds_limits()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    static std::atomic<unsigned long long> done{0};
+    if (dev < 64 && (done.load() >> dev & 1ull)) return 0;
+    const void *fn[4] = {(const void *)bl_layer<false, 4>, (const void *)bl_layer<true, 4>,
+                         (const void *)bl_layer<true, 2>, (const void *)bl_layer<true, 1>};
+    const int rb[4] = {4, 4, 2, 1};
+    for (int i = 0; i < 4 && e == hipSuccess; ++i)
+        e = hipFuncSetAttribute(fn[i], hipFuncAttributeMaxDynamicSharedMemorySize, layer_lds_bytes(rb[i], MAX_D));
+    if (e == hipSuccess && dev < 64) done.fetch_or(1ull << dev);
+    return (int)e;
+}
 
 }  // namespace
 
@@ -819,15 +930,9 @@ extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, 
         ism_set_error(h, "workspace of %zu bytes, %zu needed", workspace_bytes, w.total);
         return ISM_EINVAL;
     }
-    if ((int64_t)chunk * w.ntiles > 0x7fffffff) { ism_set_error(h, "batch too large"); return ISM_EINVAL; }
-    // the layer kernel's LDS can exceed the 64 KB default (set on every call: cheap, and
-    // valid whichever device is current)
-    hipError_t ea = hipFuncSetAttribute((const void *)bl_layer<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        layer_lds_bytes(MAX_D));
-    if (ea == hipSuccess)
-        ea = hipFuncSetAttribute((const void *)bl_layer<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 layer_lds_bytes(MAX_D));
-    if (ea != hipSuccess) return ism_hip_fail(h, ea, "hipFuncSetAttribute");
+    if ((int64_t)chunk * w.nst > 0x7fffffff) { ism_set_error(h, "batch too large"); return ISM_EINVAL; }
+    const int ea = set_layer_lds_limits();
+    if (ea != 0) return ism_hip_fail(h, (hipError_t)ea, "hipFuncSetAttribute");
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)workspace;
     const char *mb = (const char *)m->dev;
@@ -837,7 +942,17 @@ extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, 
     const float *vec = (const float *)(mb + m->lay.vec);
     for (int c0 = 0; c0 < batch; c0 += chunk) {
         const int nb = batch - c0 < chunk ? batch - c0 : chunk;
-        const int grid = nb * w.ntiles;
+        const int nt0 = cdiv(n_t, MT0);
+        // Tile height of layers 1..17: the tallest whose grid still fits one workgroup per
+        // CU takes the low-latency form; larger batches take 64-row tiles at full occupancy.
+        int rb = 4;
+        bool lowlat = false;
+        for (int r = 1; r <= 4; r *= 2)
+            if ((int64_t)nb * cdiv(n_t, 16 * r) <= h->n_cu) {
+                rb = r;
+                lowlat = true;
+                break;
+            }
 
         Layer0Args L0;
         L0.x = x;
@@ -850,10 +965,11 @@ extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, 
         L0.a_out = Abuf[0];
         L0.st_out = Sbuf[0];
         L0.T = n_t;
-        L0.ntiles = w.ntiles;
+        L0.ntiles = nt0;
+        L0.nst = w.nst;
         L0.c_in = m->c_in;
-        const int l0_lds = (m->c_in * L0XP + 3 * m->c_in * NF) * 4 + 8 * (L0THREADS / 64);
-        hipLaunchKernelGGL(bl_layer0, dim3(grid), dim3(L0THREADS), l0_lds, st, L0);
+        const int l0_lds = (m->c_in * L0XP + 3 * m->c_in * NF) * 4 + 2 * 8 * (L0THREADS / 64);
+        hipLaunchKernelGGL(bl_layer0, dim3(nb * nt0), dim3(L0THREADS), l0_lds, st, L0);
 
         for (int l = 1; l < NL; ++l) {
             LayerArgs L;
@@ -868,14 +984,17 @@ extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, 
             L.frag = (const _Float16 *)(mb + m->lay.frag) + (size_t)(l - 1) * FRAG_HALVES;
             L.hdr = (const int *)(mb + m->lay.hdr);
             L.T = n_t;
-            L.ntiles = w.ntiles;
+            L.ntiles = cdiv(n_t, 16 * rb);
+            L.nst = w.nst;
             L.layer = l;
             L.D = 1 << (l % 6);
             L.eps = m->eps;
-            if (grid <= h->n_cu)  // at most one workgroup per CU: latency-bound
-                hipLaunchKernelGGL(bl_layer<true>, dim3(grid), dim3(LTHREADS), layer_lds_bytes(L.D), st, L);
-            else
-                hipLaunchKernelGGL(bl_layer<false>, dim3(grid), dim3(LTHREADS), layer_lds_bytes(L.D), st, L);
+            const dim3 grid(nb * L.ntiles), blk(LTHREADS);
+            const int lds = layer_lds_bytes(rb, L.D);
+            if (!lowlat) hipLaunchKernelGGL((bl_layer<false, 4>), grid, blk, lds, st, L);
+            else if (rb == 4) hipLaunchKernelGGL((bl_layer<true, 4>), grid, blk, lds, st, L);
+            else if (rb == 2) hipLaunchKernelGGL((bl_layer<true, 2>), grid, blk, lds, st, L);
+            else hipLaunchKernelGGL((bl_layer<true, 1>), grid, blk, lds, st, L);
         }
 
         EnergyArgs E;
@@ -885,7 +1004,7 @@ extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, 
         E.vec = vec + (size_t)(NL - 1) * 3 * NF;
         E.part = (float *)(ws + w.part);
         E.T = n_t;
-        E.ntiles = w.ntiles;
+        E.nst = w.nst;
         E.ne = w.ne;
         E.eps = m->eps;
         hipLaunchKernelGGL(bl_energy, dim3(nb * w.ne), dim3(256), 0, st, E);

@@ -113,6 +113,24 @@ def test_batch_invariance_and_repeatability(handle):
     m.close()
 
 
+@pytest.mark.parametrize("batch", [4, 6, 12])
+def test_every_tile_height_equals_single_frames(handle, batch):
+    # frames of 1000 samples on 256 CUs: a frame alone and a batch of 4 run layers 1..17
+    # in 16-row tiles, a batch of 6 in 32-row tiles and a batch of 12 in 64-row tiles
+    # (low-latency form); the layer-norm partials are per 16 rows in every form, so each
+    # frame's result is bitwise the same as when it runs alone
+    p, m = _model(handle, 81 + batch)
+    x = torch.from_numpy(bl_data.frames(90 + batch, batch, n_t=1000)).cuda()
+    f, o = m.forward(x)
+    singles = [m.forward(x[i:i + 1]) for i in range(batch)]
+    torch.cuda.synchronize()
+    assert torch.equal(f, torch.cat([s[0] for s in singles]))
+    assert torch.equal(o, torch.cat([s[1] for s in singles]))
+    rf, ro = ref.forward(x[-1:].cpu().numpy(), p, eps=1e-6)
+    _check(f"batch {batch} x 1000, last frame", f[-1:].cpu().numpy(), o[-1:].cpu().numpy(), rf, ro)
+    m.close()
+
+
 def test_full_batch_sampled(handle):
     # the benchmark's launch: 3600 frames of 7 x 1024 in one call; frames
     # sampled across the batch are checked against the oracle one by one
