@@ -102,6 +102,8 @@ size_t bl_workspace_bytes(int batch, int n_t);
  *      Calls that share a workspace must not run concurrently.
  *   features: device FP32 batch x 128 (f above), or NULL.
  *   out: device FP32 batch x n_out.
+ * A frame's features and outputs are bitwise the same whatever the batch it runs
+ * in (the launch shape changes with the batch size, the arithmetic does not).
  * batch = 0 queues nothing.  ISM_EINVAL for a NULL pointer, n_t out of range,
  * a negative stride or a workspace that is too small.
  */

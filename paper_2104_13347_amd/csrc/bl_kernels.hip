@@ -16,7 +16,7 @@
 //    in MFMA fragment order: one 1 KB contiguous load per wave and operand.
 //  * Layer norm across kernels.  The statistics of a layer span the whole
 //    n_t x 128 map of a frame, so a layer ends at a kernel boundary: kernel l
-//    writes a_l (before its norm) and per-tile (sum, M2) partials; kernel l+1
+//    writes a_l (before its norm) and (sum, M2) partials per 16 rows; kernel l+1
 //    combines the partials in FP64 (Chan's formula), forms
 //    x_{l+1} = x_l + tanh(LN(a_l)) on the fly while it stages its input tile, and
 //    writes x_{l+1} for the next residual.  Per layer and frame that is two reads
