@@ -795,7 +795,9 @@ __global__ __launch_bounds__(128) void bl_head(HeadArgs A)
 int layer_lds_bytes(int rb, int D) { return 2 * (16 * rb + 2 * D) * XROW * 2 + 2 * 8 * LWAVES * rb; }
 
 // The layer kernel's LDS can exceed the 64 KB default: raise each form's limit once per
-// device (the attribute is per device).
+// device (the attribute is per device).  A device reset in the process clears the
+// attribute but not this cache; the next launch above 64 KB then fails, and bl_forward
+// reports it as ISM_EDEVICE.
 int set_layer_lds_limits()
 {
     int dev = 0;
