@@ -231,9 +231,9 @@ def test_brute_force_tiny_rooms():
 
 # ---------------------------------------------------------------- the paper's workload statement
 def test_paper_classroom_image_count_and_order():
-    # Section II.A: a 7 x 10 x 3.70 m classroom with a 0.5 s reverberation time needs reflections
-    # "up to the 60th order" and more than 80000 image sources per RIR.  Count the images whose
-    # delay is below 0.5 s for the array position of section III.A.
+    # Section II.A: for a 7 x 10 x 3.70 m classroom with a 0.5 s reverberation time the paper
+    # states reflection orders reaching 60 and over 80 000 image sources per RIR.  Count the
+    # images whose delay is below 0.5 s for the array position of section III.A.
     fs, c, T = 16000.0, 343.0, 0.5
     L = (7.0, 10.0, 3.7)
     mic, src = (4.0, 6.0, 1.5), (5.2, 7.6, 1.5)
