@@ -371,7 +371,12 @@ __global__ __launch_bounds__(L0THREADS) void bl_layer0(Layer0Args A)
         const int t = t0 - 1 + p;
         xin[i] = (p < MT0 + 2 && t >= 0 && t < T) ? A.x[off + (int64_t)c * A.ch_stride + t] : 0.f;
     }
-    for (int i = tid; i < 3 * c_in * NF; i += L0THREADS) wl[i] = A.w0[i];
+    {
+        // 16-byte copies (the weights and wl are 16-byte aligned; 3 c_in NF is a multiple of 4)
+        const float4 *__restrict__ w4 = (const float4 *)A.w0;
+        float4 *wl4 = (float4 *)wl;
+        for (int i = tid; i < 3 * c_in * NF / 4; i += L0THREADS) wl4[i] = w4[i];
+    }
     __syncthreads();
     const int o = tid & (NF - 1), part = tid / NF;
     const int r0 = part * R;
