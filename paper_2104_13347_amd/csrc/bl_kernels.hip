@@ -752,12 +752,22 @@ struct HeadArgs {
     float eps;
 };
 
+constexpr int HEAD_SMALL = 16;  // outputs up to which the dot products run on all 128 threads
+
 __global__ __launch_bounds__(128) void bl_head(HeadArgs A)
 {
     __shared__ double f[NF];
     __shared__ double o[BL_MAX_NOUT];
     __shared__ double red[2];
+    __shared__ double part[2 * HEAD_SMALL];
     const int c = threadIdx.x, b = blockIdx.x;
+    const float *W = A.head + 2 * NF;
+    const float *bias = W + NF * A.n_out;
+    const bool small = A.n_out <= HEAD_SMALL;
+    // small heads: thread c holds input channel c's weights, loaded before the reductions
+    double wv[HEAD_SMALL];
+#pragma unroll
+    for (int j = 0; j < HEAD_SMALL; ++j) wv[j] = small && j < A.n_out ? (double)W[c * A.n_out + j] : 0.0;
     double e = 0.0;
 #pragma unroll 8
     for (int i = 0; i < A.ne; ++i) e += (double)A.part[((size_t)b * A.ne + i) * NF + c];
@@ -769,17 +779,28 @@ __global__ __launch_bounds__(128) void bl_head(HeadArgs A)
     const double sel = 1.0507009873554804934 * (y > 0.0 ? y : 1.6732632423543772848 * expm1(y));
     f[c] = sel;
     if (A.feat) A.feat[(size_t)b * NF + c] = (float)sel;
-    __syncthreads();
-    const float *W = A.head + 2 * NF;
-    const float *bias = W + NF * A.n_out;
-    double mx = -INFINITY;
-    for (int j = c; j < A.n_out; j += NF) {
-        double s = (double)bias[j];
+    if (small) {
+        // o[j] = bias[j] + sum over c of f[c] W[c][j]: a wave sum per output, then the two waves
+#pragma unroll
+        for (int j = 0; j < HEAD_SMALL; ++j)
+            if (j < A.n_out) {
+                const double w = wave_sum(sel * wv[j]);
+                if ((c & 63) == 0) part[2 * j + (c >> 6)] = w;
+            }
+        __syncthreads();
+        if (c < A.n_out) o[c] = (double)bias[c] + (part[2 * c] + part[2 * c + 1]);
+    } else {
+        __syncthreads();
+        for (int j = c; j < A.n_out; j += NF) {
+            double s = (double)bias[j];
 #pragma unroll 16
-        for (int k = 0; k < NF; ++k) s += f[k] * (double)W[k * A.n_out + j];
-        o[j] = s;
-        mx = fmax(mx, s);
+            for (int k = 0; k < NF; ++k) s += f[k] * (double)W[k * A.n_out + j];
+            o[j] = s;
+        }
     }
+    __syncthreads();
+    double mx = -INFINITY;
+    for (int j = c; j < A.n_out; j += NF) mx = fmax(mx, o[j]);
     if (A.mode == BL_CLASSIFICATION) {
         mx = wave_max(mx);
         __syncthreads();

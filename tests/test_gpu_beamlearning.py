@@ -56,6 +56,8 @@ def _check(tag, got_f, got_o, ref_f, ref_o):
     (1, 1300, 1, 1, blm.REGRESSION, 4),          # one channel, 11 tiles, ragged
     (32, 520, 2, 1024, blm.CLASSIFICATION, 5),   # widest input and output
     (2, 4500, 1, 3, blm.REGRESSION, 6),          # 71 tiles: statistics over more than 64 partials
+    (4, 800, 2, 16, blm.CLASSIFICATION, 7),      # largest head whose dot products span all threads
+    (5, 600, 1, 17, blm.CLASSIFICATION, 8),      # smallest head with one thread per output
 ])
 def test_forward_matches_oracle(handle, c_in, n_t, batch, n_out, mode, seed):
     p, m = _model(handle, seed, c_in=c_in, n_out=n_out, mode=mode)
