@@ -133,6 +133,23 @@ def test_every_tile_height_equals_single_frames(handle, batch):
     m.close()
 
 
+@pytest.mark.parametrize("batch", [40, 50])
+def test_shortest_frames_in_64_row_tiles_equal_single_frames(handle, batch):
+    # frames of 379 samples (one valid output sample; the last 64-row tile holds 59 rows)
+    # on 256 CUs: a batch of 40 runs 64-row tiles in the low-latency form, a batch of 50
+    # at full occupancy; each frame alone runs 16-row tiles
+    p, m = _model(handle, 101 + batch)
+    x = torch.from_numpy(bl_data.frames(110 + batch, batch, n_t=379)).cuda()
+    f, o = m.forward(x)
+    singles = [m.forward(x[i:i + 1]) for i in range(batch)]
+    torch.cuda.synchronize()
+    assert torch.equal(f, torch.cat([s[0] for s in singles]))
+    assert torch.equal(o, torch.cat([s[1] for s in singles]))
+    rf, ro = ref.forward(x[:1].cpu().numpy(), p, eps=1e-6)
+    _check(f"batch {batch} x 379, first frame", f[:1].cpu().numpy(), o[:1].cpu().numpy(), rf, ro)
+    m.close()
+
+
 def test_full_batch_sampled(handle):
     # the benchmark's launch: 3600 frames of 7 x 1024 in one call; frames
     # sampled across the batch are checked against the oracle one by one
