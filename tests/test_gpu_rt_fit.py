@@ -63,6 +63,17 @@ def test_fit_beta_matches_oracle(handle):
     assert abs(rt - rr) <= 1e-4 * rr and abs(rt - rt_target) <= 1e-3
 
 
+def test_fit_beta_paper_room_at_full_size(handle):
+    # the benchmark's fit: the paper's 7 x 10 x 3.7 m room, target T30 0.5 s, 16 kHz,
+    # 16 000 samples, 30 steps (section III.A); the oracle takes a few seconds
+    Lp, mic, src = [7.0, 10.0, 3.7], [4.0, 6.0, 1.5], [6.0, 6.0, 1.5]
+    beta, rt = handle.fit_beta(Lp, src, mic, 16000.0, 343.0, 8, 0.5, 16000, iters=30)
+    rb, rr = ref.fit_beta(Lp, src, mic, 16000.0, 343.0, 8, 0.5, 16000, iters=30)
+    print(f"[paper room fit] gpu beta {beta:.9f} T30 {rt:.9f}  oracle beta {rb:.9f} T30 {rr:.9f}", flush=True)
+    assert abs(beta - rb) <= 1e-6
+    assert abs(rt - rr) <= 1e-6 * rr and abs(rt - 0.5) <= 1e-4
+
+
 def test_fit_beta_reports_an_unreachable_target(handle):
     # 200 samples cannot hold a 0.25 s decay down to -35 dB: every step sees +inf
     with pytest.raises(ism.IsmError) as e:
