@@ -204,6 +204,14 @@ def bench_beamlearning(H, torch):
     one = lambda: model.forward(y, n_t=NT, batch=1, offsets=offs[:1], ch_stride=16000, workspace=ws1,
                                 features=False, out=out1)
     lat = [_time_it(torch, one, reps=1) for _ in range(30)]
+    # small batches (16- and 32-row tiles below 256 workgroups per layer): p50 per call
+    ws16 = torch.empty(blm.workspace_bytes(16, NT), dtype=torch.uint8, device="cuda")
+    out16 = torch.empty((16, 2), dtype=torch.float32, device="cuda")
+    small = {}
+    for nb in (2, 4, 8, 16):
+        call = lambda: model.forward(y, n_t=NT, batch=nb, offsets=offs[:nb], ch_stride=16000, workspace=ws16,
+                                     features=False, out=out16[:nb])
+        small[str(nb)] = float(np.median([_time_it(torch, call, reps=1) for _ in range(15)]))
     # algorithmic HBM bytes per frame: layer 0 reads the frame and writes a_0; layer 1 reads
     # a_0 and writes x_1, a_1; layers 2..17 read a, x and write x, a; the pseudo-energy reads
     # a_17 and x_17 on the valid samples
@@ -216,6 +224,7 @@ def bench_beamlearning(H, torch):
             "ms": ms, "frames_per_s": B / (ms / 1e3), "us_per_frame": ms * 1e3 / B,
             "pipeline_ms": pipe_ms,  # RIRs (256 rooms x 8 mics) + convolution + forward pass
             "batch1_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+            "small_batch_p50_ms": small,
             "paper_gtx1080ti_batch1_ms": 16.2e3 / 3600,
             "algorithmic_bytes_per_frame": per_frame,
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0}}
