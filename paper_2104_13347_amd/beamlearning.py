@@ -109,6 +109,10 @@ class Model:
         feat = torch.empty((batch, NF), dtype=torch.float32, device="cuda") if features else None
         if out is None:
             out = torch.empty((batch, self.n_out), dtype=torch.float32, device="cuda")
+        elif (out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous()
+              or out.numel() < batch * self.n_out):
+            raise ValueError(f"out must be a contiguous CUDA float32 tensor of at least {batch} x {self.n_out} "
+                             f"elements")
         rc = self.lib.bl_forward(self.handle.h, self.m, batch, n_t, ctypes.c_void_p(x.data_ptr()),
                                  ctypes.c_void_p(offsets.data_ptr() if offsets is not None else 0),
                                  int(ex_stride or 0), int(ch_stride or 0), ctypes.c_void_p(workspace.data_ptr()),

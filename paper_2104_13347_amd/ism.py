@@ -173,6 +173,13 @@ class Handle:
         return {"seg_len": a.value, "wg_per_cu": b.value, "graphs": c.value}
 
     # -- RIRs
+    @staticmethod
+    def _check_out(out, n):
+        """A caller-supplied output must hold n contiguous float32 elements on the device."""
+        import torch
+        if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous() or out.numel() < n:
+            raise ValueError(f"out must be a contiguous CUDA float32 tensor of at least {n} elements")
+
     def rir(self, L, beta, src, mics, fs, c, max_order, rir_len, fd_taps,
             order_mode=ORDER_INDEX_L1, precision=PREC_FP32, out=None, stream=None):
         """One room: returns (or fills) a float32 device tensor [M, rir_len]."""
@@ -184,6 +191,8 @@ class Handle:
         M = mics.shape[0]
         if out is None:
             out = torch.empty((M, int(rir_len)), dtype=torch.float32, device="cuda")
+        else:
+            self._check_out(out, M * max(int(rir_len), 0))
         rc = self.lib.ism_rir(self.h, _dptr(L), _dptr(beta), _dptr(src), int(M), _dptr(mics), float(fs),
                               float(c), int(max_order), int(order_mode), int(rir_len), int(fd_taps),
                               int(precision), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
@@ -198,6 +207,8 @@ class Handle:
         mics = np.ascontiguousarray(batch["mics"], dtype=np.float64)
         if out is None:
             out = torch.empty(int(batch["out_size"]), dtype=torch.float32, device="cuda")
+        else:
+            self._check_out(out, int(batch["out_size"]))
         rc = self.lib.ism_rir_batch(self.h, len(rooms), rooms.ctypes.data_as(ctypes.c_void_p), _dptr(mics),
                                     float(batch["fs"]), float(batch["c"]), int(batch["fd_taps"]),
                                     int(batch["order_mode"]), int(precision), ctypes.c_void_p(out.data_ptr()),
@@ -229,6 +240,8 @@ class Handle:
         mics = np.ascontiguousarray(batch["mics"], dtype=np.float64)
         if out is None:
             out = torch.empty(int(batch["out_size"]), dtype=torch.float32, device="cuda")
+        else:
+            self._check_out(out, int(batch["out_size"]))
         cand = list(candidates or [])
         carr = (ctypes.c_int * max(1, len(cand)))(*cand)
         best = ctypes.c_int()
@@ -249,6 +262,8 @@ class Handle:
         ln = np.ascontiguousarray(rir_len, dtype=np.int32)
         if out is None:
             out = torch.empty((R, int(M), int(out_len)), dtype=torch.float32, device="cuda")
+        else:
+            self._check_out(out, R * int(M) * max(int(out_len), 0))
         snr_p = None
         if snr_db is not None:
             snr = np.ascontiguousarray(snr_db, dtype=np.float32)

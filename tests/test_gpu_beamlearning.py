@@ -177,6 +177,10 @@ def test_invalid_arguments(handle):
         m.forward(x, workspace=ws)                     # workspace too small
     with pytest.raises(ValueError):
         blm.Model(handle, np.zeros(10, np.float32))
+    with pytest.raises(ValueError):
+        m.forward(x, out=torch.empty((1, 2), device="cuda"))                     # too small for 2 frames
+    with pytest.raises(ValueError):
+        m.forward(x, out=torch.empty((2, 2), dtype=torch.float64, device="cuda"))  # wrong type
     m.close()
 
 

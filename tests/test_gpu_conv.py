@@ -103,3 +103,23 @@ def test_conv_argument_errors(H):
         H.convolve_batch(d, [0], [0], 8, torch.zeros((1, 4), device="cuda"), 4)
     with pytest.raises(ism.IsmError):   # MFMA path takes 8 microphones
         H.convolve_batch(d, [0], [2], 2, torch.zeros((1, 4), device="cuda"), 4, use_mfma=True)
+
+
+def test_caller_outputs_are_checked(H):
+    # a caller-supplied output that is too small, of another type or not contiguous is
+    # refused before any launch
+    import torch
+    L, beta, src, mic = [5.0, 4.0, 3.0], [0.9] * 6, [1.0, 1.2, 1.1], [[3.0, 2.5, 1.6]]
+    with pytest.raises(ValueError):
+        H.rir(L, beta, src, mic, 16000.0, 343.0, 2, 512, 81, out=torch.empty(511, device="cuda"))
+    with pytest.raises(ValueError):
+        H.rir(L, beta, src, mic, 16000.0, 343.0, 2, 512, 81, out=torch.empty(512, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        H.rir(L, beta, src, mic, 16000.0, 343.0, 2, 512, 81, out=torch.empty((512, 2), device="cuda")[:, 0])
+    d = torch.zeros(16, device="cuda")
+    with pytest.raises(ValueError):
+        H.convolve_batch(d, [0], [4], 1, torch.zeros((1, 4), device="cuda"), 4, use_mfma=False,
+                         out=torch.empty(3, device="cuda"))
+    out = H.rir(L, beta, src, mic, 16000.0, 343.0, 2, 512, 81, out=torch.empty(512, device="cuda"))
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all() and out.abs().max() > 0
