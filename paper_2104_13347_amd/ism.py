@@ -180,6 +180,13 @@ class Handle:
         if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous() or out.numel() < n:
             raise ValueError(f"out must be a contiguous CUDA float32 tensor of at least {n} elements")
 
+    @staticmethod
+    def _check_in(t, name, n=0):
+        """A device input must be contiguous float32 (and hold at least n elements)."""
+        import torch
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() < n:
+            raise ValueError(f"{name} must be a contiguous CUDA float32 tensor" + (f" of at least {n} elements" if n else ""))
+
     def rir(self, L, beta, src, mics, fs, c, max_order, rir_len, fd_taps,
             order_mode=ORDER_INDEX_L1, precision=PREC_FP32, out=None, stream=None):
         """One room: returns (or fills) a float32 device tensor [M, rir_len]."""
@@ -260,6 +267,10 @@ class Handle:
         R = int(src.shape[0])
         off = np.ascontiguousarray(rir_offset, dtype=np.int64)
         ln = np.ascontiguousarray(rir_len, dtype=np.int32)
+        self._check_in(src, "src")
+        self._check_in(rirs, "rirs", int((off + int(M) * ln.astype(np.int64)).max()) if off.size else 0)
+        if z is not None:
+            self._check_in(z, "z", R * int(M) * max(int(out_len), 0))
         if out is None:
             out = torch.empty((R, int(M), int(out_len)), dtype=torch.float32, device="cuda")
         else:
@@ -283,6 +294,7 @@ class Handle:
         """T30 (s) of a device FP32 RIR tensor (+inf if its decay does not reach -35 dB)."""
         import torch
         rir = rir.contiguous()
+        self._check_in(rir, "rir")
         t = torch.empty(1, dtype=torch.float64, device="cuda")
         self._check(self.lib.ism_rir_t30(self.h, ctypes.c_void_p(rir.data_ptr()), int(rir.numel()), float(fs),
                                          ctypes.c_void_p(t.data_ptr()), _stream_handle(stream)))

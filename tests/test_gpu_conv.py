@@ -120,6 +120,12 @@ def test_caller_outputs_are_checked(H):
     with pytest.raises(ValueError):
         H.convolve_batch(d, [0], [4], 1, torch.zeros((1, 4), device="cuda"), 4, use_mfma=False,
                          out=torch.empty(3, device="cuda"))
+    with pytest.raises(ValueError):     # rirs shorter than offset + M x rir_len
+        H.convolve_batch(d, [0], [9], 2, torch.zeros((1, 4), device="cuda"), 4, use_mfma=False)
+    with pytest.raises(ValueError):     # source of another type
+        H.convolve_batch(d, [0], [4], 1, torch.zeros((1, 4), dtype=torch.float64, device="cuda"), 4, use_mfma=False)
+    with pytest.raises(ValueError):
+        H.rir_t30(torch.ones(64, dtype=torch.float64, device="cuda"), 16000.0)
     out = H.rir(L, beta, src, mic, 16000.0, 343.0, 2, 512, 81, out=torch.empty(512, device="cuda"))
     torch.cuda.synchronize()
     assert torch.isfinite(out).all() and out.abs().max() > 0
