@@ -96,6 +96,10 @@ class Model:
         device FP32 tensor with explicit batch, n_t, offsets (device int64 tensor
         or None), ex_stride and ch_stride in elements.  Returns (features or None, out)."""
         import torch
+        if x.dtype != torch.float32 or not x.is_cuda:
+            raise ValueError("x must be a CUDA float32 tensor")
+        if offsets is not None and (offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous()):
+            raise ValueError("offsets must be a contiguous CUDA int64 tensor")
         if x.dim() == 3 and n_t is None:
             batch, c, n_t = x.shape
             if c != self.c_in:

@@ -181,6 +181,8 @@ def test_invalid_arguments(handle):
         m.forward(x, out=torch.empty((1, 2), device="cuda"))                     # too small for 2 frames
     with pytest.raises(ValueError):
         m.forward(x, out=torch.empty((2, 2), dtype=torch.float64, device="cuda"))  # wrong type
+    with pytest.raises(ValueError):
+        m.forward(x.double())                                                    # frames of another type
     m.close()
 
 
