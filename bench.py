@@ -408,8 +408,11 @@ def main():
             "note": "FP64 flops counted by rocprofv3 per launch / this run's launch time; VALU issue "
                     "fraction = VALU wave-instructions x 4 cycles / (1024 SIMDs x kernel cycles)"}
 
-    # plain: the same kernels launched once per room, host loop, one stream
+    # plain: the same kernels launched once per room, host loop, one stream, launched directly
+    # (no graph capture: a graph is keyed to the upload size, which changes from room to room)
     if not args.no_plain:
+        saved_tuning = H.get_tuning()
+        H.set_tuning(graphs=0)
         M = int(batch["n_mics"][0])
         mics_all = batch["mics"]
         for r in range(min(8, args.rooms)):   # warm-up
@@ -424,6 +427,7 @@ def main():
                   -1, L, batch["fd_taps"], out=out[o:o + M * L].view(M, L))
         torch.cuda.synchronize()
         plain_s = time.perf_counter() - t0
+        H.set_tuning(graphs=saved_tuning["graphs"])
         res["rirs_per_s_plain"] = n_rirs / plain_s
         res["taps_per_s_plain"] = taps / plain_s
         res["batched_vs_plain"] = rirs_batched / res["rirs_per_s_plain"]

@@ -64,7 +64,8 @@ class Model:
         self.c_in, self.n_out, self.mode = int(c_in), int(n_out), int(mode)
         if not torch.is_tensor(params):
             params = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32))
-        self._params = params.to(device="cuda", dtype=torch.float32).contiguous()
+        with ism._on(stream):   # the folding kernel reads the copy on `stream`
+            self._params = params.to(device="cuda", dtype=torch.float32).contiguous()
         need = param_count(self.c_in, self.n_out)
         if need == 0 or self._params.numel() != need:
             raise ValueError(f"params hold {self._params.numel()} floats, the layout {need}")
@@ -90,6 +91,40 @@ class Model:
         except Exception:
             pass
 
+    def _check_extent(self, x, n_t, batch, offsets, ex_stride, ch_stride):
+        """Explicit frame layout: every element the kernels read, frame b < batch, channel
+        c < c_in, sample n < n_t at off_b + c * ch_stride + n, must lie in x (contiguous).
+        Device offsets are read back once per offsets tensor (its address and torch's version
+        counter) to check them; a tensor rewritten outside torch keeps its old check."""
+        if n_t is None or batch is None or ch_stride is None:
+            raise ValueError("n_t, batch and ch_stride are required with an explicit frame layout")
+        if offsets is None and ex_stride is None:
+            raise ValueError("either offsets or ex_stride is required with an explicit frame layout")
+        batch, n_t, ch_stride = int(batch), int(n_t), int(ch_stride)
+        if batch < 0 or n_t < 1 or ch_stride < 0 or (ex_stride is not None and int(ex_stride) < 0):
+            raise ValueError("batch, strides and offsets must be non-negative and n_t >= 1")
+        if batch == 0:
+            return
+        if not x.is_contiguous():
+            raise ValueError("x must be contiguous with an explicit frame layout (offsets index its storage)")
+        span = (self.c_in - 1) * ch_stride + n_t   # elements of one frame from its offset
+        if offsets is None:
+            hi = (batch - 1) * int(ex_stride) + span
+            if hi > x.numel():
+                raise ValueError(f"frames reach element {hi} of x, which holds {x.numel()}")
+            return
+        if offsets.numel() < batch:
+            raise ValueError(f"offsets holds {offsets.numel()} entries for {batch} frames")
+        key = (offsets.data_ptr(), offsets._version, batch)
+        cache = getattr(self, "_off_range", None)
+        if cache is None or cache[0] != key:
+            o = offsets[:batch]
+            lo, hi = int(o.min().item()), int(o.max().item())
+            self._off_range = cache = (key, lo, hi)
+        lo, hi = cache[1], cache[2]
+        if lo < 0 or hi + span > x.numel():
+            raise ValueError(f"frame offsets in [{lo}, {hi}] reach past the {x.numel()} elements of x")
+
     def forward(self, x, n_t=None, batch=None, offsets=None, ex_stride=None, ch_stride=None,
                 workspace=None, features=True, out=None, stream=None):
         """Forward pass.  x: device FP32 tensor [B, c_in, n_t] (contiguous), or any
@@ -104,19 +139,24 @@ class Model:
             batch, c, n_t = x.shape
             if c != self.c_in:
                 raise ValueError(f"x has {c} channels, the model {self.c_in}")
-            x = x.contiguous()
+            with ism._on(stream):
+                x = x.contiguous()
             ex_stride, ch_stride = c * n_t, n_t
+            offsets = None
+        else:
+            self._check_extent(x, n_t, batch, offsets, ex_stride, ch_stride)
         batch, n_t = int(batch), int(n_t)
-        need = workspace_bytes(batch, n_t)
-        if workspace is None:
-            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
-        feat = torch.empty((batch, NF), dtype=torch.float32, device="cuda") if features else None
-        if out is None:
-            out = torch.empty((batch, self.n_out), dtype=torch.float32, device="cuda")
-        elif (out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous()
-              or out.numel() < batch * self.n_out):
+        if out is not None and (out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous()
+                                or out.numel() < batch * self.n_out):
             raise ValueError(f"out must be a contiguous CUDA float32 tensor of at least {batch} x {self.n_out} "
                              f"elements")
+        need = workspace_bytes(batch, n_t)
+        with ism._on(stream):
+            if workspace is None:
+                workspace = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+            feat = torch.empty((batch, NF), dtype=torch.float32, device="cuda") if features else None
+            if out is None:
+                out = torch.empty((batch, self.n_out), dtype=torch.float32, device="cuda")
         rc = self.lib.bl_forward(self.handle.h, self.m, batch, n_t, ctypes.c_void_p(x.data_ptr()),
                                  ctypes.c_void_p(offsets.data_ptr() if offsets is not None else 0),
                                  int(ex_stride or 0), int(ch_stride or 0), ctypes.c_void_p(workspace.data_ptr()),

@@ -136,6 +136,15 @@ def _stream_handle(stream):
     return ctypes.c_void_p(int(stream.cuda_stream))
 
 
+def _on(stream):
+    """Context in which temporaries (outputs, workspaces, contiguous copies) are allocated and
+    written on the stream the library queues its work on, so the caching allocator orders
+    their reuse after that work."""
+    import contextlib
+    import torch
+    return contextlib.nullcontext() if stream is None else torch.cuda.stream(stream)
+
+
 class Handle:
     """Owns an ism_handle (device buffers, pinned staging, tuning state, graphs)."""
 
@@ -197,7 +206,8 @@ class Handle:
         mics = np.ascontiguousarray(np.atleast_2d(mics), dtype=np.float64)
         M = mics.shape[0]
         if out is None:
-            out = torch.empty((M, int(rir_len)), dtype=torch.float32, device="cuda")
+            with _on(stream):
+                out = torch.empty((M, int(rir_len)), dtype=torch.float32, device="cuda")
         else:
             self._check_out(out, M * max(int(rir_len), 0))
         rc = self.lib.ism_rir(self.h, _dptr(L), _dptr(beta), _dptr(src), int(M), _dptr(mics), float(fs),
@@ -213,7 +223,8 @@ class Handle:
             rooms = rooms_array(batch)
         mics = np.ascontiguousarray(batch["mics"], dtype=np.float64)
         if out is None:
-            out = torch.empty(int(batch["out_size"]), dtype=torch.float32, device="cuda")
+            with _on(stream):
+                out = torch.empty(int(batch["out_size"]), dtype=torch.float32, device="cuda")
         else:
             self._check_out(out, int(batch["out_size"]))
         rc = self.lib.ism_rir_batch(self.h, len(rooms), rooms.ctypes.data_as(ctypes.c_void_p), _dptr(mics),
@@ -246,7 +257,8 @@ class Handle:
         rooms = rooms_array(batch)
         mics = np.ascontiguousarray(batch["mics"], dtype=np.float64)
         if out is None:
-            out = torch.empty(int(batch["out_size"]), dtype=torch.float32, device="cuda")
+            with _on(stream):
+                out = torch.empty(int(batch["out_size"]), dtype=torch.float32, device="cuda")
         else:
             self._check_out(out, int(batch["out_size"]))
         cand = list(candidates or [])
@@ -272,7 +284,8 @@ class Handle:
         if z is not None:
             self._check_in(z, "z", R * int(M) * max(int(out_len), 0))
         if out is None:
-            out = torch.empty((R, int(M), int(out_len)), dtype=torch.float32, device="cuda")
+            with _on(stream):
+                out = torch.empty((R, int(M), int(out_len)), dtype=torch.float32, device="cuda")
         else:
             self._check_out(out, R * int(M) * max(int(out_len), 0))
         snr_p = None
@@ -293,17 +306,20 @@ class Handle:
     def rir_t30(self, rir, fs, stream=None):
         """T30 (s) of a device FP32 RIR tensor (+inf if its decay does not reach -35 dB)."""
         import torch
-        rir = rir.contiguous()
-        self._check_in(rir, "rir")
-        t = torch.empty(1, dtype=torch.float64, device="cuda")
-        self._check(self.lib.ism_rir_t30(self.h, ctypes.c_void_p(rir.data_ptr()), int(rir.numel()), float(fs),
-                                         ctypes.c_void_p(t.data_ptr()), _stream_handle(stream)))
-        return float(t.cpu()[0])
+        with _on(stream):
+            rir = rir.contiguous()
+            self._check_in(rir, "rir")
+            t = torch.empty(1, dtype=torch.float64, device="cuda")
+            self._check(self.lib.ism_rir_t30(self.h, ctypes.c_void_p(rir.data_ptr()), int(rir.numel()), float(fs),
+                                             ctypes.c_void_p(t.data_ptr()), _stream_handle(stream)))
+            # the copy to the host runs on the stream that wrote t
+            return float(t.cpu()[0])
 
     def fit_beta(self, L, src, mic, fs, c, fd_taps, rt_target, rir_len, iters=30, stream=None):
         """Uniform beta whose simulated RIR (src -> mic) has T30 = rt_target.  Returns (beta, T30)."""
         import torch
-        work = torch.empty(int(self.lib.ism_rt_work_bytes(int(rir_len))), dtype=torch.uint8, device="cuda")
+        with _on(stream):
+            work = torch.empty(int(self.lib.ism_rt_work_bytes(int(rir_len))), dtype=torch.uint8, device="cuda")
         L_ = np.ascontiguousarray(L, dtype=np.float64)
         s_ = np.ascontiguousarray(src, dtype=np.float64)
         m_ = np.ascontiguousarray(mic, dtype=np.float64)
@@ -368,7 +384,8 @@ class Server:
     def result(self, ticket, M, rir_len, stream=None):
         """Copy a finished result into a new device tensor [M, rir_len]."""
         import torch
-        out = torch.empty((M, rir_len), dtype=torch.float32, device="cuda")
+        with _on(stream):
+            out = torch.empty((M, rir_len), dtype=torch.float32, device="cuda")
         self._check(self.lib.ism_server_copy_result(self.s, ctypes.c_uint64(ticket), ctypes.c_void_p(out.data_ptr()),
                                                     _stream_handle(stream)))
         return out

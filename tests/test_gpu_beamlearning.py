@@ -12,6 +12,8 @@ divides the pseudo-energies by their spread across the 128 channels.  The
 bound used here, ATOL + RTOL |ref| on the 128 features and the outputs, keeps
 a margin of about 10x over the largest error measured on these cases.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -201,3 +203,48 @@ def test_large_ragged_batch_equals_single_frames(handle):
     rf, ro = ref.forward(x[idx], p, eps=1e-6)
     _check("64 x 1000, sampled", f[idx].cpu().numpy(), o[idx].cpu().numpy(), rf, ro)
     m.close()
+
+
+def test_explicit_layout_is_checked_before_launch(handle):
+    # an explicit frame layout that would read past x, or leaves a stride or the frame
+    # count open, is refused on the host (the kernels cannot check device offsets)
+    p, m = _model(handle, 41, c_in=3, n_out=2)
+    x = torch.zeros(3 * 1000, device="cuda")
+    with pytest.raises(ValueError):          # ch_stride missing
+        m.forward(x, n_t=1000, batch=1, ex_stride=3000)
+    with pytest.raises(ValueError):          # neither offsets nor ex_stride
+        m.forward(x, n_t=1000, batch=1, ch_stride=1000)
+    with pytest.raises(ValueError):          # second frame past the end
+        m.forward(x, n_t=1000, batch=2, ex_stride=3000, ch_stride=1000)
+    with pytest.raises(ValueError):          # fewer offsets than frames
+        m.forward(x, n_t=1000, batch=2, offsets=torch.zeros(1, dtype=torch.int64, device="cuda"), ch_stride=1000)
+    with pytest.raises(ValueError):          # an offset past the end
+        m.forward(x, n_t=1000, batch=1, offsets=torch.tensor([1], dtype=torch.int64, device="cuda"), ch_stride=1000)
+    with pytest.raises(ValueError):          # a negative offset
+        m.forward(x, n_t=500, batch=1, offsets=torch.tensor([-1], dtype=torch.int64, device="cuda"), ch_stride=1000)
+    # exactly the extent of x is accepted
+    f, o = m.forward(x, n_t=1000, batch=1, ex_stride=3000, ch_stride=1000)
+    torch.cuda.synchronize()
+    assert torch.isfinite(o).all()
+    m.close()
+
+
+def test_side_stream_equals_default_stream(handle):
+    # a forward pass and a T30 queued on a non-current stream give the default-stream
+    # results: temporaries are allocated and written on that stream and t30 is read after it
+    p, m = _model(handle, 43, c_in=7, n_out=2)
+    x = torch.from_numpy(bl_data.frames(44, 5, n_t=900)).cuda()
+    f0, o0 = m.forward(x)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    f1, o1 = m.forward(x, stream=s)
+    s.synchronize()
+    assert torch.equal(f0, f1) and torch.equal(o0, o1)
+    m.close()
+    rir = handle.rir([4.0, 5.0, 3.0], [0.8] * 6, [1.2, 1.5, 1.4], [[2.9, 3.6, 1.6]], 8000.0, 343.0, -1, 4000, 9)[0]
+    torch.cuda.synchronize()
+    t_def = handle.rir_t30(rir, 8000.0)
+    s.wait_stream(torch.cuda.current_stream())
+    t_side = handle.rir_t30(rir[::1], 8000.0, stream=s)
+    assert t_def == t_side and math.isfinite(t_def)

@@ -346,3 +346,32 @@ def test_brute_force_tiny_rooms_lagrange():
             ref = _brute_force_lagrange_rir(b["L"][i], b["beta"][i], b["src"][i], mic, b["fs"], b["c"], 48)
             got, _ = oracle.rir(b["L"][i], b["beta"][i], b["src"][i], mic, b["fs"], b["c"], -1, 0, 48, 8)
             assert np.max(np.abs(got - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+def test_rir_list_equals_per_rir_oracle_on_a_ragged_batch():
+    # the threaded batch driver (output offsets, microphone offsets, RIR lengths, a subset of
+    # (room, mic) pairs in any order) gives each RIR exactly as the one-RIR call does
+    b = scenes.tiny(seed=21, n_rooms=3, M=3, rir_len=64, taps=9)
+    b = scenes.subset(b, [2, 0, 1])
+    lens = [40, 64, 23]
+    rooms = []
+    for i in range(3):
+        o, M = b["mic_offset"][i], b["n_mics"][i]
+        rooms.append({"L": b["L"][i], "beta": b["beta"][i], "src": b["src"][i], "mics": b["mics"][o:o + M],
+                      "max_order": -1, "rir_len": lens[i]})
+    rooms[1]["mics"] = rooms[1]["mics"][:2]            # a room with fewer microphones
+    b = scenes.pack(rooms, b["fs"], b["c"], b["fd_taps"], b["order_mode"], "ragged")
+    pairs = [(1, 1), (0, 2), (2, 0), (0, 0), (1, 0)]   # a subset, out of order
+    out, taps = oracle.rir_list(b, pairs, nthreads=3)
+    total = 0
+    covered = np.zeros(out.size, dtype=bool)
+    for r, m in pairs:
+        o, L = int(b["out_offset"][r]), int(b["rir_len"][r])
+        mic = b["mics"][b["mic_offset"][r] + m]
+        ref, st = oracle.rir(b["L"][r], b["beta"][r], b["src"][r], mic, b["fs"], b["c"], -1, 0, L, b["fd_taps"])
+        got = out[o + m * L:o + (m + 1) * L]
+        assert np.array_equal(got, ref), (r, m)
+        covered[o + m * L:o + (m + 1) * L] = True
+        total += st["taps"]
+    assert taps == total
+    assert np.all(out[~covered] == 0.0)                # RIRs not asked for stay untouched
