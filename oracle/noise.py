@@ -23,9 +23,9 @@ implements one counter-based generator from its published definition:
 The library's convention (include/ism.h, ism_normal_deviates): the deviates of
 room r, microphone m, samples 4j .. 4j+3 come from the Philox output words
 (x0, x1, x2, x3) of counter (j, m, r, 0) and key (seed mod 2^32, seed >> 32);
-a word x becomes the uniform ((x >> 8) + 1/2) 2^-24 (24 bits, exact in FP32);
-(x0, x1) give samples 4j, 4j+1 (cos, sin) and (x2, x3) samples 4j+2, 4j+3.
-The deviates are therefore bounded by sqrt(50 ln 2) = 5.89 in magnitude.
+a word x becomes the uniform ((x >> 9) + 1/2) 2^-23 (23 bits and the half: exact
+in FP32); (x0, x1) give samples 4j, 4j+1 (cos, sin) and (x2, x3) samples 4j+2,
+4j+3.  The deviates are therefore bounded by sqrt(48 ln 2) = 5.77 in magnitude.
 """
 from __future__ import annotations
 
@@ -55,12 +55,13 @@ def philox4x32_10(ctr, key):
 
 
 def uniforms(words):
-    """24-bit uniforms in (0, 1) from 32-bit words: ((x >> 8) + 1/2) 2^-24, exact in FP64."""
-    return ((np.asarray(words, dtype=np.uint64) >> np.uint64(8)).astype(np.float64) + 0.5) * 2.0 ** -24
+    """Uniforms in (0, 1) from 32-bit words: ((x >> 9) + 1/2) 2^-23 (exact in FP64 and FP32)."""
+    return ((np.asarray(words, dtype=np.uint64) >> np.uint64(9)).astype(np.float64) + 0.5) * 2.0 ** -23
 
 
 def box_muller(u1, u2):
-    """Box-Muller pair (cos, sin) of standard normals from uniforms u1 in (0, 1], u2 in [0, 1)."""
+    """Box-Muller pair (cos, sin) of standard normals from uniforms u1 in (0, 1], u2 in [0, 1)
+    (the open interval (0, 1) here)."""
     rad = np.sqrt(-2.0 * np.log(u1))
     return rad * np.cos(2.0 * np.pi * u2), rad * np.sin(2.0 * np.pi * u2)
 

@@ -65,7 +65,7 @@ def test_deviates_are_standard_normal_and_independent():
     s = noise.deviates(2109, 7, 1, n)[0]
     assert abs(np.corrcoef(z[0], o)[0, 1]) < 5.0 / np.sqrt(n)
     assert abs(np.corrcoef(z[0], s)[0, 1]) < 5.0 / np.sqrt(n)
-    assert np.abs(z).max() <= np.sqrt(50.0 * np.log(2.0)) + 1e-12
+    assert np.abs(z).max() <= np.sqrt(48.0 * np.log(2.0)) + 1e-12
 
 
 def test_deviates_prefix_and_tail_probability():
