@@ -9,6 +9,7 @@ fails loudly; there is no fallback.
 from __future__ import annotations
 
 import ctypes
+import weakref
 
 import numpy as np
 
@@ -94,8 +95,9 @@ class Model:
     def _check_extent(self, x, n_t, batch, offsets, ex_stride, ch_stride):
         """Explicit frame layout: every element the kernels read, frame b < batch, channel
         c < c_in, sample n < n_t at off_b + c * ch_stride + n, must lie in x (contiguous).
-        Device offsets are read back once per offsets tensor (its address and torch's version
-        counter) to check them; a tensor rewritten outside torch keeps its old check."""
+        Device offsets are read back to check them, once per offsets tensor object (held by a
+        weak reference, so a new tensor that reuses a freed one's memory is read again) and
+        torch's version counter of it; a tensor rewritten outside torch keeps its old check."""
         if n_t is None or batch is None or ch_stride is None:
             raise ValueError("n_t, batch and ch_stride are required with an explicit frame layout")
         if offsets is None and ex_stride is None:
@@ -115,13 +117,13 @@ class Model:
             return
         if offsets.numel() < batch:
             raise ValueError(f"offsets holds {offsets.numel()} entries for {batch} frames")
-        key = (offsets.data_ptr(), offsets._version, batch)
+        key = (offsets._version, batch)
         cache = getattr(self, "_off_range", None)
-        if cache is None or cache[0] != key:
+        if cache is None or cache[0]() is not offsets or cache[1] != key:
             o = offsets[:batch]
             lo, hi = int(o.min().item()), int(o.max().item())
-            self._off_range = cache = (key, lo, hi)
-        lo, hi = cache[1], cache[2]
+            self._off_range = cache = (weakref.ref(offsets), key, lo, hi)
+        lo, hi = cache[2], cache[3]
         if lo < 0 or hi + span > x.numel():
             raise ValueError(f"frame offsets in [{lo}, {hi}] reach past the {x.numel()} elements of x")
 

@@ -72,3 +72,39 @@ def test_forward_validation(handle):
     vp = ctypes.c_void_p
     rc = lib.bl_forward(handle.h, None, 1, 1024, vp(4096), None, 0, 0, vp(4096), 1 << 30, None, vp(4096), None)
     assert rc == ism.ISM_EINVAL and "model" in handle.lib.ism_last_error(handle.h).decode()
+
+
+def test_offset_check_is_per_tensor_object():
+    # the host check of an explicit frame layout reads the offsets again for every new
+    # offsets tensor, even one at the address of a freed tensor that passed, and after an
+    # in-place change of the same tensor (CPU tensors stand in for device ones: the check
+    # only reads them)
+    import types
+    import torch
+    fake = types.SimpleNamespace(c_in=3)
+    x = torch.zeros(3 * 1000)
+    check = lambda off, n_t=1000: blm.Model._check_extent(fake, x, n_t, 1, off, None, 1000)
+    ok = torch.tensor([0], dtype=torch.int64)
+    check(ok)
+    with pytest.raises(ValueError):
+        check(torch.tensor([1], dtype=torch.int64))
+    for _ in range(4):      # fresh tensors, often at a reused address
+        good = torch.tensor([0], dtype=torch.int64)
+        check(good, n_t=500)
+        del good
+        with pytest.raises(ValueError):
+            check(torch.tensor([-1], dtype=torch.int64), n_t=500)
+    ok.fill_(1)             # in place: torch's version counter moves
+    with pytest.raises(ValueError):
+        check(ok)
+    # a new tensor object at the very address of one that passed, with the same version
+    # counter (0) but other contents
+    import numpy as np
+    buf = np.zeros(1, dtype=np.int64)
+    t1 = torch.from_numpy(buf)
+    check(t1, n_t=500)
+    buf[0] = -1
+    t2 = torch.from_numpy(buf)
+    assert t2.data_ptr() == t1.data_ptr() and t2._version == t1._version
+    with pytest.raises(ValueError):
+        check(t2, n_t=500)
