@@ -31,6 +31,11 @@ METRIC = "image-source taps/s + RIRs/s (batched vs plain, same GPU); p50/p99 RIR
 # (4 flops), two multiplies, and 4 for an accurate (compensated) accumulation
 FLOPS_PER_TAP = 12
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+# what each precision mode computes in: FP64 geometry and delay split throughout; the default
+# evaluates FP64 Chebyshev moments, sums them exactly in 64-bit integer bins and runs the filter on
+# the matrix cores over FP16 pairs (hi*hi + hi*lo + lo*hi) with FP32 sums
+DTYPES = ["f64+int64+f16pair-mfma", "f64+f16-lut+int64", "f32-split+int64+f16pair-mfma", "f64+f32-atomic",
+          "f64+f32+int64"]
 
 
 def kernel_source_hash():
@@ -62,30 +67,67 @@ def measured_traffic(kernel):
     return d.get("hbm_bytes_per_launch") if d else None
 
 
-def cpu_baseline(batch, budget_s=12.0):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def rir_errors(batch, gpu, ref, rirs):
+    """max |gpu - oracle| / max |oracle| of each listed (room, mic) RIR (flat batch layout)."""
+    errs = []
+    for r, m in rirs:
+        L = int(batch["rir_len"][r])
+        o = int(batch["out_offset"][r]) + m * L
+        g, f = gpu[o:o + L].astype(np.float64), ref[o:o + L]
+        errs.append(float(np.abs(g - f).max() / max(np.abs(f).max(), 1e-300)))
+    return np.array(errs)
+
+
+def cpu_baseline(batch, gpu=None, budget_s=12.0, total_taps=None):
+    """The FP64 oracle on the host cores (threads over RIRs) on a bounded random sample of the
+    batch's rooms; with `gpu` (the batch's GPU output, host copy) the sample's RIRs are also
+    compared with it, so the headline run carries its own error against the oracle."""
     import oracle
     nthreads = os.cpu_count() or 1
     R = len(batch["rir_len"])
     rng = np.random.default_rng(99)
     order = rng.permutation(R)
+    ref = np.zeros(int(batch["out_size"]))
     taps = 0
-    rirs = 0
+    done = []
     t0 = time.perf_counter()
     used = 0
     for i in range(0, R, 4):
         rooms = order[i:i + 4]
         lst = [(int(r), m) for r in rooms for m in range(int(batch["n_mics"][r]))]
-        _, t = oracle.rir_list(batch, lst, nthreads=nthreads)
+        _, t = oracle.rir_list(batch, lst, nthreads=nthreads, out=ref)
         taps += t
-        rirs += len(lst)
+        done += lst
         used += len(rooms)
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": taps / dt, "unit": "taps/s", "cores": nthreads, "kind": "oracle",
-            "rirs_per_s": rirs / dt,
-            "sample": f"{used} random rooms of the 1024-room batch, all 8 mics ({rirs} RIRs, {taps} taps), "
-                      f"FP64 oracle, {nthreads} threads over RIRs, {dt:.1f} s"}
+    # single-core rate on the first two RIRs of the sample
+    t1 = time.perf_counter()
+    _, t_one = oracle.rir_list(batch, done[:2], nthreads=1)
+    one_core = t_one / (time.perf_counter() - t1)
+    res = {"value": taps / dt, "unit": "taps/s", "cores": nthreads, "kind": "oracle",
+           "cpu_model": cpu_model(), "single_core_taps_per_s": one_core,
+           "rirs_per_s": len(done) / dt,
+           "sample": f"{used} random rooms of the 1024-room batch, all 8 mics ({len(done)} RIRs, {taps} taps), "
+                     f"FP64 oracle, {nthreads} threads over RIRs, {dt:.1f} s"}
+    if total_taps:
+        res["full_batch_s_extrapolated"] = total_taps / res["value"]
+    if gpu is not None:
+        e = rir_errors(batch, gpu, ref, done)
+        res["gpu_vs_oracle"] = {"rirs": len(done), "max_err_over_peak": float(e.max()),
+                                "median_err_over_peak": float(np.median(e)), "bar": 1e-5}
+    return res
 
 
 def _time_it(torch, fn, reps=3):
@@ -102,19 +144,33 @@ def _time_it(torch, fn, reps=3):
     return float(np.median(ts))
 
 
-def bench_c3(H, torch):
-    """64 rooms 20x15x8 m, 48 kHz, 72000 samples, 16 mics, 127 taps: throughput per precision mode
-    (errors against the FP64 oracle are checked in the tests)."""
+def bench_c3(H, torch, with_errors=True):
+    """64 rooms 20x15x8 m, 48 kHz, 72000 samples, 16 mics, 127 taps: throughput per precision mode,
+    and each mode's error against the FP64 oracle on a sample of RIRs (every microphone of rooms
+    0 and 37, computed once on the host cores)."""
     from paper_2104_13347_amd import ism, scenes
     b = scenes.c3()
     rooms = ism.rooms_array(b)
     out = torch.empty(int(b["out_size"]), dtype=torch.float32, device="cuda")
     res = {"workload": "64 rooms 20x15x8 m, per-wall beta U[0.85,0.95], 48 kHz, 72000 samples, 16 mics, 127 taps"}
+    sample = [(r, m) for r in (0, 37) for m in range(16)]
+    ref = None
+    if with_errors:
+        import oracle
+        ref = np.zeros(int(b["out_size"]))
+        oracle.rir_list(b, sample, out=ref)
+        res["error_sample"] = "all 16 mics of rooms 0 and 37 (32 RIRs), FP64 oracle"
+    bars = {"fp32": 1e-5, "fp32_direct": 1e-5, "fp16_lut": 2e-3, "fp32_split": None}
     for prec, name in [(ism.PREC_FP32, "fp32"), (ism.PREC_FP32_DIRECT, "fp32_direct"), (ism.PREC_FP16_LUT, "fp16_lut"),
                        (ism.PREC_FP32_SPLIT, "fp32_split")]:
         ms = _time_it(torch, lambda: H.rir_batch(b, precision=prec, out=out, rooms=rooms))
         taps = H.last_counts()["taps"]
         res[name] = {"ms": ms, "taps_per_s": taps / (ms / 1e3), "rirs_per_s": 64 * 16 / (ms / 1e3), "taps": taps}
+        if ref is not None:
+            e = rir_errors(b, out.cpu().numpy(), ref, sample)
+            res[name]["max_err_over_peak"] = float(e.max())
+            res[name]["median_err_over_peak"] = float(np.median(e))
+            res[name]["bar"] = bars[name]
     return res
 
 
@@ -144,12 +200,12 @@ def bench_c4(H, torch):
     """256 rooms (1024-room distribution, seed 2108), 8 mics: RIR batch on the GPU, then convolution
     with 1 s white-noise sources and sensor noise at SNR U[0,30] dB."""
     from paper_2104_13347_amd import ism, scenes
-    b = scenes.c4()
+    b = scenes.c4(with_z=False)
     rooms = ism.rooms_array(b)
     rirs = torch.empty(int(b["out_size"]), dtype=torch.float32, device="cuda")
     x = torch.from_numpy(b["x"]).cuda()
-    z = torch.from_numpy(b["z"]).cuda()
     y = torch.empty((256, 8, 16000), dtype=torch.float32, device="cuda")
+    seed = b["noise_seed"]
     lens = b["rir_len"]
     offs = b["out_offset"]
     rir_ms = _time_it(torch, lambda: H.rir_batch(b, out=rirs, rooms=rooms))
@@ -157,16 +213,24 @@ def bench_c4(H, torch):
     for L in lens:   # algorithmic MACs: sum over n < 16000 of min(n + 1, L)
         L = int(L)
         flops += 2.0 * 8 * (L * 16000 - L * (L - 1) / 2.0)
-    res = {"workload": "256 rooms x 8 mics, RIR 0.8*RT60*fs, 1 s N(0,1) source at 16 kHz, SNR U[0,30] dB",
+    res = {"workload": "256 rooms x 8 mics, RIR 0.8*RT60*fs, 1 s N(0,1) source at 16 kHz, SNR U[0,30] dB, "
+                       "sensor noise drawn on the device (Philox4x32-10 + Box-Muller)",
            "rir_batch_ms": rir_ms, "algorithmic_flops": flops}
     for mfma, name in [(True, "bf16_mfma"), (False, "fp32_direct")]:
-        ms = _time_it(torch, lambda: H.convolve_batch(rirs, offs, lens, 8, x, 16000, snr_db=b["snr_db"], z=z,
-                                                      use_mfma=mfma, out=y))
-        tf = flops / (ms / 1e3) / 1e12
-        res[name] = {"ms": ms, "tflops": tf,
-                     "peak_tflops": 2500.0 if mfma else FP32_VECTOR_PEAK_TFLOPS,
-                     "frac": tf / (2500.0 if mfma else FP32_VECTOR_PEAK_TFLOPS)}
-    res["pipeline_ms"] = rir_ms + res["bf16_mfma"]["ms"]
+        ms = _time_it(torch, lambda: H.convolve_batch(rirs, offs, lens, 8, x, 16000, snr_db=b["snr_db"],
+                                                      noise_seed=seed, use_mfma=mfma, out=y))
+        ms_clean = _time_it(torch, lambda: H.convolve_batch(rirs, offs, lens, 8, x, 16000, use_mfma=mfma, out=y))
+        tf = flops / (ms_clean / 1e3) / 1e12
+        peak = 2500.0 if mfma else FP32_VECTOR_PEAK_TFLOPS
+        res[name] = {"ms_with_noise": ms, "ms_convolution_only": ms_clean, "tflops": tf,
+                     "peak_tflops": peak, "frac": tf / peak,
+                     "path_tflops": flops / (ms / 1e3) / 1e12, "path_frac": flops / (ms / 1e3) / 1e12 / peak}
+    res["noise_pass_ms"] = res["bf16_mfma"]["ms_with_noise"] - res["bf16_mfma"]["ms_convolution_only"]
+
+    def pipeline():   # RIRs, convolution and device-drawn noise
+        H.rir_batch(b, out=rirs, rooms=rooms)
+        H.convolve_batch(rirs, offs, lens, 8, x, 16000, snr_db=b["snr_db"], noise_seed=seed, out=y)
+    res["pipeline_ms"] = _time_it(torch, pipeline)
     return res
 
 
@@ -177,12 +241,12 @@ def bench_beamlearning(H, torch):
     channels) through per-frame offsets.  Weights drawn as the paper initialises them.  The
     paper times its inference one frame at a time, so the one-frame latency is reported too."""
     from paper_2104_13347_amd import beamlearning as blm, bl_data, ism, scenes
-    b = scenes.c4()
+    b = scenes.c4(with_z=False)
     rooms = ism.rooms_array(b)
     rirs = torch.empty(int(b["out_size"]), dtype=torch.float32, device="cuda")
     H.rir_batch(b, out=rirs, rooms=rooms)
     y = H.convolve_batch(rirs, b["out_offset"], b["rir_len"], 8, torch.from_numpy(b["x"]).cuda(), 16000,
-                         snr_db=b["snr_db"], z=torch.from_numpy(b["z"]).cuda())
+                         snr_db=b["snr_db"], noise_seed=b["noise_seed"])
     B, NT, CIN = 3600, 1024, 7
     idx = np.arange(B)
     offs = torch.from_numpy((idx // 15) * 8 * 16000 + (idx % 15) * NT).to(torch.int64).cuda()
@@ -192,11 +256,12 @@ def bench_beamlearning(H, torch):
     run = lambda: model.forward(y, n_t=NT, batch=B, offsets=offs, ch_stride=16000, workspace=ws,
                                 features=False, out=out)
     ms = _time_it(torch, run, reps=5)
-    xs, zs = torch.from_numpy(b["x"]).cuda(), torch.from_numpy(b["z"]).cuda()
+    xs = torch.from_numpy(b["x"]).cuda()
 
     def pipeline():  # RIRs of the 256 rooms, their recordings, then the network on 3600 frames
         H.rir_batch(b, out=rirs, rooms=rooms)
-        H.convolve_batch(rirs, b["out_offset"], b["rir_len"], 8, xs, 16000, snr_db=b["snr_db"], z=zs, out=y)
+        H.convolve_batch(rirs, b["out_offset"], b["rir_len"], 8, xs, 16000, snr_db=b["snr_db"],
+                         noise_seed=b["noise_seed"], out=y)
         run()
     pipe_ms = _time_it(torch, pipeline, reps=3)
     ws1 = torch.empty(blm.workspace_bytes(1, NT), dtype=torch.uint8, device="cuda")
@@ -250,34 +315,40 @@ def cpu_baseline_beamlearning(n_frames=2):
 
 def bench_rt_fit(H, torch):
     """Uniform-absorption fit (section III.A: homogeneous walls with a simulated reverberation
-    time of 0.5 s) for the paper's two simulated rooms: 30 bisection steps, each one 16 000-sample
-    RIR (Lagrange filter, 16 kHz) and its T30 on the GPU.  The first room's Sabine beta (the
-    dataset's default) is given for comparison."""
-    from paper_2104_13347_amd import scenes
-    res = {"workload": "paper rooms 7x10x3.7 m and 5x5x4 m, target T30 0.5 s, mic at the array centre, "
-                       "source 2 m away, 16 kHz, 16000 samples, fd_taps 8, 30 bisection steps"}
-    rooms = {"room1_7x10x3.7": ([7.0, 10.0, 3.7], [4.0, 6.0, 1.5], [6.0, 6.0, 1.5]),
-             "room2_5x5x4": ([5.0, 5.0, 4.0], [2.5, 2.5, 1.5], [4.5, 2.5, 1.5])}
-    for name, (L, mic, src) in rooms.items():
-        H.fit_beta(L, src, mic, 16000.0, 343.0, 8, 0.5, 16000, iters=30)  # warm-up (same steps as the timed fit: fewer miss the 1 % bar)
+    time of 0.5 s) for the paper's two simulated rooms, then each room's 336 000-RIR dataset with
+    the fitted walls.  Room-level fit: the mean T30 of the RIRs from the first 8 torus sources of
+    the room's dataset to the 7 array microphones (56 RIRs of 16 000 samples per step, Lagrange
+    filter, 16 kHz, 30 bisection steps).  The single-pair fit (array centre, one source 2 m away)
+    and Sabine's coefficient are given for comparison."""
+    from paper_2104_13347_amd import ism, scenes
+    res = {"workload": "paper rooms 7x10x3.7 m and 5x5x4 m, target T30 0.5 s; room-level fit on the mean T30 of "
+                       "8 torus sources x 7 mics (16 kHz, 16000 samples, fd_taps 8, 30 bisection steps), then the "
+                       "room's 48000-source x 7-mic dataset (8000 samples) with the fitted beta"}
+    rooms = {"room1_7x10x3.7": (scenes.paper_room1, [7.0, 10.0, 3.7], [4.0, 6.0, 1.5], [6.0, 6.0, 1.5]),
+             "room2_5x5x4": (scenes.paper_room2, [5.0, 5.0, 4.0], [2.5, 2.5, 1.5], [4.5, 2.5, 1.5])}
+    for name, (scene, L, mic, src) in rooms.items():
+        probe = scene(n_sources=8)
+        srcs, mics = probe["src"], probe["mics"][:7]
+        H.fit_beta_mean(L, srcs, mics, 16000.0, 343.0, 8, 0.5, 16000, iters=30)   # warm-up, same steps
         torch.cuda.synchronize()
         t = time.perf_counter()
-        beta, rt = H.fit_beta(L, src, mic, 16000.0, 343.0, 8, 0.5, 16000, iters=30)
-        res[name] = {"beta": beta, "t30_s": rt, "fit_ms": (time.perf_counter() - t) * 1e3}
-    res["room1_sabine_beta"] = float(scenes.paper_room1()["beta"][0][0])
-    # the paper's workflow: fit the walls, then generate the room's 336 000 RIRs with them
-    from paper_2104_13347_amd import ism
-    b = scenes.paper_room1(beta=res["room1_7x10x3.7"]["beta"])
-    rooms_t = ism.rooms_array(b)
-    out = torch.empty(int(b["out_size"]), dtype=torch.float32, device="cuda")
-    L, mic, src = rooms["room1_7x10x3.7"]
-
-    def fit_and_generate():
-        beta, _ = H.fit_beta(L, src, mic, 16000.0, 343.0, 8, 0.5, 16000, iters=30)
-        H.rir_batch(b, out=out, rooms=rooms_t)
-    res["room1_fit_and_dataset_ms"] = _time_it(torch, fit_and_generate, reps=2)
-    del out
-    torch.cuda.empty_cache()
+        beta, rt = H.fit_beta_mean(L, srcs, mics, 16000.0, 343.0, 8, 0.5, 16000, iters=30)
+        fit_ms = (time.perf_counter() - t) * 1e3
+        b1, rt1 = H.fit_beta(L, src, mic, 16000.0, 343.0, 8, 0.5, 16000, iters=30)
+        b = scene(beta=beta)
+        rooms_t = ism.rooms_array(b)
+        out = torch.empty(int(b["out_size"]), dtype=torch.float32, device="cuda")
+        ms = _time_it(torch, lambda: H.rir_batch(b, out=out, rooms=rooms_t), reps=2)
+        cnt = H.last_counts()
+        n_rirs = int(b["n_mics"].sum())
+        res[name] = {"beta_room_fit": beta, "mean_t30_s": rt, "room_fit_ms": fit_ms,
+                     "beta_single_pair_fit": b1, "single_pair_t30_s": rt1,
+                     "beta_sabine": float(scene(n_sources=1)["beta"][0][0]),
+                     "dataset": {"rirs": n_rirs, "ms": ms, "rirs_per_s": n_rirs / (ms / 1e3),
+                                 "taps_per_s": cnt["taps"] / (ms / 1e3), "taps": cnt["taps"],
+                                 "output_bytes": int(b["out_size"]) * 4}}
+        del out
+        torch.cuda.empty_cache()
     return res
 
 
@@ -313,7 +384,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--rooms", type=int, default=1024)
     ap.add_argument("--precision", type=int, default=0)
-    ap.add_argument("--seg-len", type=int, default=0)
+    ap.add_argument("--seg-len", type=int, default=0, help="fixed segment length (no autotuning)")
+    ap.add_argument("--no-autotune", action="store_true", help="launch with the default tuning")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ablation", action="store_true",
@@ -357,6 +429,14 @@ def main():
         H.set_tuning(seg_len=args.seg_len)
     out = torch.empty(int(batch["out_size"]), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
+    tune_s = None
+    if not args.seg_len and not args.no_autotune:
+        # one-time set-up before the warm-up: the batch's shape bucket is tuned on its first launch
+        H.set_autotune(True)
+        t = time.perf_counter()
+        H.rir_batch(batch, precision=args.precision, out=out, rooms=rooms)
+        torch.cuda.synchronize()
+        tune_s = time.perf_counter() - t
 
     for _ in range(args.warmup):
         H.rir_batch(batch, precision=args.precision, out=out, rooms=rooms)
@@ -373,6 +453,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     launch_ms = [a.elapsed_time(b) for a, b in evs]
+    gpu_out = out.cpu().numpy() if not args.no_cpu_baseline else None   # headline result, for its error
     ms_per_step = wall * 1e3 / args.steps
     taps = counts["taps"]
     value = taps / (ms_per_step / 1e3)
@@ -381,13 +462,13 @@ def main():
 
     res = {"metric": METRIC, "value": value, "unit": "taps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "vs_baseline": None, "dtype": DTYPES[args.precision], "data": "synthetic",
            "config": {"workload": "c1: 1024 seeded shoebox rooms x 8 mics, 16 kHz, RIR 0.8*RT60*fs, "
                                   "81-tap Hann-windowed sinc, time-bounded image sets",
                       "rooms": args.rooms, "rirs": n_rirs, "taps_per_step": taps,
                       "records_per_step": counts["records"], "images_tested_per_step": counts["images"],
                       "precision": ["fp32", "fp16_lut", "fp32_split", "fp32_atomic", "fp32_direct"][args.precision],
-                      "tuning": H.get_tuning()},
+                      "tuning": dict(H.get_tuning(), tuning_s=tune_s)},
            "rirs_per_s_batched": rirs_batched}
 
     # roofline of the segment kernel (the launch is one graph: upload + prologue + segments)
@@ -396,23 +477,34 @@ def main():
     traffic = measured_traffic(kernel)
     res["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                        "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
-                       "kernel": kernel, "launch_ms": k_ms,
+                       "basis": "algorithmic: 12 flops per tap of the direct per-tap method (the work the "
+                                "output represents), not the instructions this kernel issues; see 'executed'",
+                       "kernel": kernel, "launch_ms": k_ms, "launch_ms_min": float(np.min(launch_ms)),
+                       "launch_ms_median": float(np.median(launch_ms)),
                        "flops_per_tap": FLOPS_PER_TAP, "taps_per_launch": taps}
     # what the kernel executes (committed counters of the same source), beside the nominal rate
     cc = committed_counters(kernel)
     if cc and "executed" in cc:
         ex = cc["executed"]
-        res["roofline"]["executed"] = {
-            "fp64_tflops": ex["fp64_flops_per_launch"] / (k_ms / 1e3) / 1e12, "fp64_peak_tflops": 78.6,
-            "valu_issue_fraction": ex["valu_issue_fraction"],
-            "note": "FP64 flops counted by rocprofv3 per launch / this run's launch time; VALU issue "
-                    "fraction = VALU wave-instructions x 4 cycles / (1024 SIMDs x kernel cycles)"}
+        e = {"fp64_tflops": ex["fp64_flops_per_launch"] / (k_ms / 1e3) / 1e12, "fp64_peak_tflops": 78.6,
+             "fp64_frac": ex["fp64_flops_per_launch"] / (k_ms / 1e3) / 1e12 / 78.6,
+             "valu_issue_fraction": ex["valu_issue_fraction"],
+             "note": "FP64 flops counted by rocprofv3 per launch / this run's launch time; VALU issue "
+                     "fraction = VALU wave-instructions x 4 cycles / (1024 SIMDs x kernel cycles)"}
+        for k in ("fp32_flops_per_launch", "lds_busy_fraction", "lds_bank_conflict_share", "wait_fraction",
+                  "profile_kernel_ms", "source_hash"):
+            if k in ex:
+                e[k] = ex[k]
+        if "fp32_flops_per_launch" in ex:
+            e["fp32_tflops"] = ex["fp32_flops_per_launch"] / (k_ms / 1e3) / 1e12
+        res["roofline"]["executed"] = e
 
     # plain: the same kernels launched once per room, host loop, one stream, launched directly
     # (no graph capture: a graph is keyed to the upload size, which changes from room to room)
     if not args.no_plain:
         saved_tuning = H.get_tuning()
         H.set_tuning(graphs=0)
+        H.set_autotune(False)   # the batch's tuned segment length, no tuning inside the timed loop
         M = int(batch["n_mics"][0])
         mics_all = batch["mics"]
         for r in range(min(8, args.rooms)):   # warm-up
@@ -428,6 +520,7 @@ def main():
         torch.cuda.synchronize()
         plain_s = time.perf_counter() - t0
         H.set_tuning(graphs=saved_tuning["graphs"])
+        H.set_autotune(bool(saved_tuning["autotune"]))
         res["rirs_per_s_plain"] = n_rirs / plain_s
         res["taps_per_s_plain"] = taps / plain_s
         res["batched_vs_plain"] = rirs_batched / res["rirs_per_s_plain"]
@@ -462,7 +555,7 @@ def main():
     if extras:
         res["extras"] = {}
         if "c3" in extras:
-            res["extras"]["c3_precision"] = bench_c3(H, torch)
+            res["extras"]["c3_precision"] = bench_c3(H, torch, with_errors=not args.no_cpu_baseline)
         if "c4" in extras:
             res["extras"]["c4_convolution"] = bench_c4(H, torch)
         if "paper" in extras:
@@ -479,7 +572,9 @@ def main():
     H.close()
 
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(batch)
+        res["cpu_baseline"] = cpu_baseline(batch, gpu=gpu_out, total_taps=taps)
+        if "gpu_vs_oracle" in res["cpu_baseline"]:
+            res["config"]["max_err_over_peak"] = res["cpu_baseline"]["gpu_vs_oracle"]["max_err_over_peak"]
     print(json.dumps(res))
 
 

@@ -192,14 +192,37 @@ int ism_set_tuning(ism_handle *h, int seg_len, int wg_per_cu, int graphs);
 int ism_get_tuning(const ism_handle *h, int *seg_len, int *wg_per_cu, int *graphs);
 
 /*
- * Autotuner: times the batch with each candidate segment length (64-multiples
- * from the candidate list, or the built-in list if n_cand == 0) on `stream`,
- * keeps the fastest in the handle, and returns it in *best_seg_len (may be NULL).
- * out receives the batch result of the last candidate.  Synchronises `stream`.
+ * Autotuner of the batched launch (section II.A: the paper batches its RIR
+ * computation on the GPU; the launch shape is tuned per workload).  Knobs: the
+ * segment length (output samples per work item: 256, 512, 1024, and 2048 where the
+ * per-tap kernel runs; the moment kernel takes at most 1024, so longer candidates
+ * are never tried where it runs), and for the per-tap kernel the cap on resident
+ * single-wave workgroups per compute unit (0, 4, 8, 16) and the image order within a
+ * column chunk.  Coordinate search on the caller's batch: each candidate is launched
+ * once untimed and twice timed with HIP events on `stream` (the faster run counts).
+ * The winner is kept in the handle and in its cache under the batch's shape bucket
+ * (precision, fd_taps, order_mode, fs, ceil(log2 longest RIR), ceil(log2 most
+ * microphones)).  out receives the batch's result with the winning configuration.
+ * cand / n_cand: segment lengths to try instead of the built-in list (n_cand = 0).
+ * *best_seg_len (may be NULL): the chosen segment length.  Synchronises `stream`.
  */
 int ism_autotune(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics,
                  double fs, double c, int fd_taps, int order_mode, int precision, float *out,
                  ism_stream stream, const int *cand, int n_cand, int *best_seg_len);
+
+/*
+ * enable = 1: ism_rir_batch (and ism_rir) look up each batch's shape bucket in the
+ * handle's tuning cache; the first batch of a bucket not yet cached is tuned as by
+ * ism_autotune (that call then synchronises `stream` and takes several launches), later
+ * batches of the bucket launch with the cached configuration.  enable = 0 (default):
+ * every launch uses the handle's current tuning.
+ * ism_get_launch_tuning: the configuration the next launch uses, the autotune mode,
+ * the number of cached buckets, and the tuned time (ms) of the cache entry that matches
+ * the current configuration (0 if none).  Any pointer may be NULL.
+ */
+int ism_set_autotune(ism_handle *h, int enable);
+int ism_get_launch_tuning(const ism_handle *h, int *seg_len, int *wg_per_cu, int *interleave, int *autotune,
+                          int *n_tuned_buckets, float *last_tuned_ms);
 
 /*
  * Source convolution and sensor noise for a batch of rooms (paper section III.A:
@@ -209,16 +232,47 @@ int ism_autotune(ism_handle *h, int n_rooms, const ism_room *rooms, const double
  *   rir_offset, rir_len: host arrays of n_rooms entries.
  *   src: device FP32, n_rooms x src_len; out: device FP32, n_rooms x M x out_len.
  *   y[r][m][n] = sum_{j <= min(n, rir_len-1)} h[r][m][j] * x[r][n-j], n < out_len.
- *   snr_db: host, n_rooms entries, or NULL for no noise.  z: device FP32
- *   n_rooms x M x out_len standard normal deviates (required if snr_db != NULL):
- *   y += sigma_r * z, sigma_r^2 = mean over m,n of y^2 * 10^(-snr_db[r]/10).
- *   use_mfma: 1 = block-Toeplitz GEMM on MFMA, BF16 inputs, FP32 accumulation;
- *             0 = FP32 direct convolution on the vector units.
+ *   snr_db: host, n_rooms entries, or NULL for no noise.  With noise,
+ *   y += sigma_r * z, sigma_r^2 = mean over m,n of y^2 * 10^(-snr_db[r]/10), where
+ *   z[r][m][n] are the standard normal deviates that ism_normal_deviates writes for
+ *   (n_rooms, M, out_len, noise_seed): they are drawn inside the noise pass and never
+ *   stored.  r is the room's index within this call, so a caller that splits one
+ *   dataset over several calls gives each call its own seed.
+ *   use_mfma: 1 = block-Toeplitz GEMM on MFMA, BF16 inputs, FP32 accumulation
+ *             (M must be 8); 0 = FP32 direct convolution on the vector units.
+ *   Limits: 0 <= n_rooms <= 65535, 1 <= M <= 65535, rir_len in [1, 2^24],
+ *   src_len and out_len in [1, 2^28]; otherwise ISM_EINVAL before any device work.
+ *   Asynchronous on `stream`; the handle keeps a workspace (BF16 RIRs, power sums,
+ *   room table) that a later call may reuse once this call's work has finished.
  */
 int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float *rirs,
                        const int64_t *rir_offset, const int32_t *rir_len, const float *src,
-                       int src_len, int out_len, const float *snr_db, const float *z,
+                       int src_len, int out_len, const float *snr_db, uint64_t noise_seed,
                        int use_mfma, float *out, ism_stream stream);
+
+/*
+ * As ism_convolve_batch, with the noise deviates supplied by the caller: z is device
+ * FP32, n_rooms x M x out_len standard normal deviates, required if snr_db != NULL.
+ * The form that lets a test give the GPU and the reference the same numbers.
+ */
+int ism_convolve_batch_z(ism_handle *h, int n_rooms, int M, const float *rirs,
+                         const int64_t *rir_offset, const int32_t *rir_len, const float *src,
+                         int src_len, int out_len, const float *snr_db, const float *z,
+                         int use_mfma, float *out, ism_stream stream);
+
+/*
+ * Seeded standard normal deviates (the sensor noise of paper section III.A), written
+ * to the device FP32 array z[r][m][n], r < n_rooms, m < M, n < n_samples.  Generator:
+ * Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011) with key
+ * (seed mod 2^32, seed >> 32); samples 4j .. 4j+3 of (r, m) come from counter
+ * (j, m, r, 0), whose output words x0..x3 become uniforms ((x >> 9) + 1/2) 2^-23;
+ * Box-Muller (1958) turns (x0, x1) into samples 4j (cosine) and 4j+1 (sine), and
+ * (x2, x3) into 4j+2 and 4j+3.  FP32 arithmetic (logf, sqrtf, sincospif): each
+ * deviate is within a few FP32 ulps of its exact value, |z| <= sqrt(48 ln 2).
+ * Limits as for ism_convolve_batch (n_samples in place of out_len).  Asynchronous.
+ */
+int ism_normal_deviates(ism_handle *h, int n_rooms, int M, int n_samples, uint64_t seed, float *z,
+                        ism_stream stream);
 
 /*
  * Reverberation time of an RIR and the uniform-absorption fit (paper section III.A:
@@ -243,6 +297,21 @@ int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float *rirs,
  *   target by more than 1 % (an RIR too short for the decay, or too few steps).
  */
 size_t ism_rt_work_bytes(int rir_len);
+/*
+ * ism_fit_beta_mean: room-level form of ism_fit_beta (section III.A asks for the room's
+ *   reverberation time, not one pair's): the uniform beta whose RIRs from every source
+ *   srcs[i] (host, n_src x 3) to every microphone mics[m] (host, M x 3) have a mean T30
+ *   of rt_target.  Each bisection step is one batched launch of the n_src x M RIRs
+ *   (time-bounded, fd_taps filter, ISM_PREC_FP32) and one T30 per RIR; the mean is
+ *   summed on the host in RIR order (source-major) and is +inf when any decay does not
+ *   reach -35 dB.  work: device buffer of ism_rt_mean_work_bytes(n_src, M, rir_len)
+ *   bytes, owned by the caller.  Requires n_src x M <= 65535.  Blocking, errors and the
+ *   1 % check as for ism_fit_beta (ISM_EDOMAIN when the mean misses the target).
+ */
+size_t ism_rt_mean_work_bytes(int n_src, int M, int rir_len);
+int ism_fit_beta_mean(ism_handle *h, const double L[3], int n_src, const double *srcs, int M, const double *mics,
+                      double fs, double c, int fd_taps, double rt_target, int rir_len, int iters, void *work,
+                      size_t work_bytes, double *beta_out, double *rt_out, ism_stream stream);
 int ism_rir_t30(ism_handle *h, const float *rir, int rir_len, double fs, double *t30, ism_stream stream);
 int ism_fit_beta(ism_handle *h, const double L[3], const double src[3], const double mic[3], double fs, double c,
                  int fd_taps, double rt_target, int rir_len, int iters, void *work, size_t work_bytes,

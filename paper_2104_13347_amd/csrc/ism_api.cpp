@@ -633,6 +633,30 @@ extern "C" int ism_last_counts(ism_handle *h, int64_t counts[8])
     return ISM_OK;
 }
 
+static int tune_batch(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics, double fs, double c,
+                      int fd_taps, int order_mode, int precision, float *out, hipStream_t stream,
+                      const std::vector<int> &seg_cands, TuneVal &best);
+
+static TuneKey tune_key(int n_rooms, const ism_room *rooms, double fs, int fd_taps, int order_mode, int precision)
+{
+    int len = 1, nm = 1;
+    for (int i = 0; i < n_rooms; ++i) {
+        len = std::max(len, rooms[i].rir_len);
+        nm = std::max(nm, rooms[i].n_mics);
+    }
+    auto clog2 = [](int v) { int b = 0; while ((1LL << b) < v) ++b; return b; };
+    return TuneKey{precision, fd_taps, order_mode, (long long)std::llround(fs * 1e3), clog2(len), clog2(nm)};
+}
+
+static int rir_batch_impl(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics, double fs,
+                          double c, int fd_taps, int order_mode, int precision, float *out, hipStream_t stream)
+{
+    Plan &plan = h->plan;
+    int st = ism_build_plan(h, n_rooms, rooms, mics, fs, c, fd_taps, h->seg_len, plan);
+    if (st) return st;
+    return ism_run_plan(h, plan, mics, fs, c, fd_taps, order_mode, precision, out, stream, nullptr);
+}
+
 extern "C" int ism_rir_batch(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics,
                              double fs, double c, int fd_taps, int order_mode, int precision, float *out,
                              ism_stream stream)
@@ -648,9 +672,23 @@ extern "C" int ism_rir_batch(ism_handle *h, int n_rooms, const ism_room *rooms, 
     for (int i = 0; i < n_rooms; ++i)
         if ((st = ism_validate_room(h, i, rooms[i], mics))) return st;
     if (n_rooms == 0) return ISM_OK;
-    Plan &plan = h->plan;
-    if ((st = ism_build_plan(h, n_rooms, rooms, mics, fs, c, fd_taps, h->seg_len, plan))) return st;
-    return ism_run_plan(h, plan, mics, fs, c, fd_taps, order_mode, precision, out, (hipStream_t)stream, nullptr);
+    if (h->autotune && h->device >= 0) {
+        const TuneKey key = tune_key(n_rooms, rooms, fs, fd_taps, order_mode, precision);
+        auto hit = h->tune_cache.find(key);
+        if (hit == h->tune_cache.end()) {
+            TuneVal best{};
+            // the tuner leaves the batch's result (with the chosen configuration) in out
+            if ((st = tune_batch(h, n_rooms, rooms, mics, fs, c, fd_taps, order_mode, precision, out,
+                                 (hipStream_t)stream, {}, best)))
+                return st;
+            h->tune_cache[key] = best;
+            return ISM_OK;
+        }
+        h->seg_len = hit->second.seg_len;
+        h->wg_per_cu = hit->second.wg_per_cu;
+        h->interleave = hit->second.interleave;
+    }
+    return rir_batch_impl(h, n_rooms, rooms, mics, fs, c, fd_taps, order_mode, precision, out, (hipStream_t)stream);
 }
 
 extern "C" int ism_rir(ism_handle *h, const double L[3], const double beta[6], const double src[3], int M,
@@ -675,41 +713,138 @@ extern "C" int ism_rir(ism_handle *h, const double L[3], const double beta[6], c
 }
 
 // ------------------------------------------------------------------ autotuner
+// Launch configuration of a batch: segment length (output samples per work item; the
+// moment kernel takes at most kMomSegMax, so longer candidates are not tried where it
+// would otherwise run), and for the per-tap kernel (single-wave workgroups) the cap on
+// resident workgroups per CU and the enumeration order of a column chunk.  Coordinate
+// search: segment lengths first, then (per-tap kernel only) the occupancy cap, then the
+// order; each candidate runs once untimed (graph capture, caches) and twice timed, and the
+// fastest time counts.  The last launch uses the winner, so `out` holds its result.
+static bool moment_path(int fd_taps, int precision)
+{
+    const int K = half_length(fd_taps);
+    const bool compiled = fd_taps == kLagrangeTaps || K == 4 || K == 40 || K == 63;
+    return compiled && (precision == ISM_PREC_FP32 || precision == ISM_PREC_FP32_SPLIT);
+}
+
+static int tune_batch(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics, double fs, double c,
+                      int fd_taps, int order_mode, int precision, float *out, hipStream_t q,
+                      const std::vector<int> &seg_cands, TuneVal &best)
+{
+    const bool mom = moment_path(fd_taps, precision);
+    std::vector<int> segs = seg_cands;
+    if (segs.empty()) segs = mom ? std::vector<int>{256, 512, 1024} : std::vector<int>{256, 512, 1024, 2048};
+    std::vector<int> ok;
+    for (int sl : segs)
+        if (sl >= 64 && sl % 64 == 0 && sl <= (mom ? kMomSegMax : kSegMaxLimit)) ok.push_back(sl);
+    if (ok.empty()) {
+        ism_set_error(h, "no valid segment-length candidate (multiples of 64 up to %d)", mom ? kMomSegMax : kSegMaxLimit);
+        return ISM_EINVAL;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) { ism_set_error(h, "hipEventCreate failed"); return ISM_EDEVICE; }
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        ism_set_error(h, "hipEventCreate failed");
+        return ISM_EDEVICE;
+    }
+    const int s_seg = h->seg_len, s_wg = h->wg_per_cu, s_il = h->interleave;
+    best = TuneVal{s_seg, s_wg, s_il, 1e30f};
+    int st = ISM_OK;
+    auto trial = [&](int sl, int wg, int il) -> int {
+        h->seg_len = sl;
+        h->wg_per_cu = wg;
+        h->interleave = il;
+        int rc = rir_batch_impl(h, n_rooms, rooms, mics, fs, c, fd_taps, order_mode, precision, out, q);
+        if (rc) return rc;
+        float t = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            if (hipEventRecord(e0, q) != hipSuccess) return ISM_EDEVICE;
+            if ((rc = rir_batch_impl(h, n_rooms, rooms, mics, fs, c, fd_taps, order_mode, precision, out, q)))
+                return rc;
+            if (hipEventRecord(e1, q) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return ISM_EDEVICE;
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            t = std::min(t, ms);
+        }
+        if (t < best.ms) best = TuneVal{sl, wg, il, t};
+        return ISM_OK;
+    };
+    for (int sl : ok)
+        if ((st = trial(sl, s_wg, s_il))) break;
+    if (!st && !mom) {
+        const int caps[] = {0, 4, 8, 16};
+        const int sl = best.seg_len, il = best.interleave;
+        for (int wg : caps)
+            if (wg != s_wg && (st = trial(sl, wg, il))) break;
+        if (!st) st = trial(best.seg_len, best.wg_per_cu, 1 - best.interleave);
+    }
+    if (!st) {   // the winner's launch last: out holds its result
+        h->seg_len = best.seg_len;
+        h->wg_per_cu = best.wg_per_cu;
+        h->interleave = best.interleave;
+        st = rir_batch_impl(h, n_rooms, rooms, mics, fs, c, fd_taps, order_mode, precision, out, q);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) {
+        h->seg_len = s_seg;
+        h->wg_per_cu = s_wg;
+        h->interleave = s_il;
+        if (st == ISM_EDEVICE && h->last_error.empty()) ism_set_error(h, "HIP event call failed while tuning");
+    }
+    return st;
+}
+
 extern "C" int ism_autotune(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics, double fs,
                             double c, int fd_taps, int order_mode, int precision, float *out, ism_stream stream,
                             const int *cand, int n_cand, int *best_seg_len)
 {
     if (!h) return ISM_EINVAL;
-    static const int kDefault[] = {256, 512, 1024, 2048};
+    h->last_error.clear();
+    if (n_rooms < 1 || !rooms || !mics || !out || (n_cand > 0 && !cand)) {
+        ism_set_error(h, "NULL argument or empty batch");
+        return ISM_EINVAL;
+    }
+    int st = ism_validate_common(h, fs, c, fd_taps, order_mode, precision);
+    if (st) return st;
+    for (int i = 0; i < n_rooms; ++i)
+        if ((st = ism_validate_room(h, i, rooms[i], mics))) return st;
+    if (h->device < 0) { ism_set_error(h, "no HIP device"); return ISM_EDEVICE; }
     std::vector<int> cands;
     if (cand && n_cand > 0) cands.assign(cand, cand + n_cand);
-    else cands.assign(kDefault, kDefault + 4);
-    hipStream_t q = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        ism_set_error(h, "hipEventCreate failed");
-        return ISM_EDEVICE;
+    TuneVal best{};
+    if ((st = tune_batch(h, n_rooms, rooms, mics, fs, c, fd_taps, order_mode, precision, out, (hipStream_t)stream,
+                         cands, best)))
+        return st;
+    h->tune_cache[tune_key(n_rooms, rooms, fs, fd_taps, order_mode, precision)] = best;
+    if (best_seg_len) *best_seg_len = best.seg_len;
+    return ISM_OK;
+}
+
+extern "C" int ism_set_autotune(ism_handle *h, int enable)
+{
+    if (!h) return ISM_EINVAL;
+    if (enable < 0 || enable > 1) { ism_set_error(h, "enable must be 0 or 1"); return ISM_EINVAL; }
+    h->autotune = enable;
+    return ISM_OK;
+}
+
+extern "C" int ism_get_launch_tuning(const ism_handle *h, int *seg_len, int *wg_per_cu, int *interleave,
+                                     int *autotune, int *n_tuned_buckets, float *last_tuned_ms)
+{
+    if (!h) return ISM_EINVAL;
+    if (seg_len) *seg_len = h->seg_len;
+    if (wg_per_cu) *wg_per_cu = h->wg_per_cu;
+    if (interleave) *interleave = h->interleave;
+    if (autotune) *autotune = h->autotune;
+    if (n_tuned_buckets) *n_tuned_buckets = (int)h->tune_cache.size();
+    if (last_tuned_ms) {
+        *last_tuned_ms = 0.f;
+        for (const auto &kv : h->tune_cache)
+            if (kv.second.seg_len == h->seg_len && kv.second.wg_per_cu == h->wg_per_cu &&
+                kv.second.interleave == h->interleave)
+                *last_tuned_ms = kv.second.ms;
     }
-    const int saved = h->seg_len;
-    int best = saved;
-    float best_ms = 1e30f;
-    int st = ISM_OK;
-    for (int sl : cands) {
-        if (sl < 64 || sl > kSegMaxLimit || sl % 64) continue;
-        h->seg_len = sl;
-        // warm-up (graph capture, caches), then one timed run
-        if ((st = ism_rir_batch(h, n_rooms, rooms, mics, fs, c, fd_taps, order_mode, precision, out, stream))) break;
-        hipEventRecord(e0, q);
-        if ((st = ism_rir_batch(h, n_rooms, rooms, mics, fs, c, fd_taps, order_mode, precision, out, stream))) break;
-        hipEventRecord(e1, q);
-        if (hipEventSynchronize(e1) != hipSuccess) { st = ISM_EDEVICE; break; }
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_ms) { best_ms = ms; best = sl; }
-    }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    h->seg_len = st == ISM_OK ? best : saved;
-    if (best_seg_len) *best_seg_len = h->seg_len;
-    return st;
+    return ISM_OK;
 }

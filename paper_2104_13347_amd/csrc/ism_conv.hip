@@ -22,7 +22,10 @@
 //
 // Noise: every output tile writes the sum of y^2 of its samples (FP64,
 // fixed-order wave reduction); the noise kernel adds those partial sums in tile
-// order for its room, derives sigma, and adds sigma * z.
+// order for its room, derives sigma, and adds sigma * z.  z is either supplied by
+// the caller or drawn inside the noise pass from a counter-based generator
+// (Philox4x32-10 and the Box-Muller transform), so the seeded form reads y once,
+// writes it once and reads no deviates from memory.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -338,19 +341,119 @@ __global__ __launch_bounds__(256) void conv_direct(const float *__restrict__ rir
     if (tid == 0) psum[((int64_t)r * M + m) * tiles_per_room + tile] = red[0];
 }
 
-// ------------------------------------------------------------------ noise
+// ------------------------------------------------------------------ seeded deviates
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011): ten rounds on a 128-bit
+// counter under a 64-bit key.  Each round takes the two 64-bit products
+// w0 * 0xD2511F53 and w2 * 0xCD9E8D57 and forms (hi2 ^ w1 ^ k0, lo2, hi0 ^ w3 ^ k1,
+// lo0); the key is advanced by the Weyl increments 0x9E3779B9, 0xBB67AE85 after each
+// round (the bump after the tenth round is never used).
+DEV uint4 philox4x32_10(uint4 w, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = w.x * 0xD2511F53u, hi0 = __umulhi(w.x, 0xD2511F53u);
+        const uint32_t lo2 = w.z * 0xCD9E8D57u, hi2 = __umulhi(w.z, 0xCD9E8D57u);
+        w = make_uint4(hi2 ^ w.y ^ k0, lo2, hi0 ^ w.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return w;
+}
+
+// Box and Muller (1958): uniforms u1, u2 in (0, 1) give the independent standard
+// normals sqrt(-2 ln u1) cos(2 pi u2) and sqrt(-2 ln u1) sin(2 pi u2).  A 32-bit word
+// x becomes the uniform ((x >> 9) + 1/2) 2^-23 (exact in FP32), so |z| <= sqrt(48 ln 2).
+DEV float2 box_muller(uint32_t a, uint32_t b)
+{
+    const float u1 = ((float)(a >> 9) + 0.5f) * 0x1p-23f;
+    const float u2 = ((float)(b >> 9) + 0.5f) * 0x1p-23f;
+    const float rad = sqrtf(-2.0f * logf(u1));
+    float sn, cs;
+    sincospif(2.0f * u2, &sn, &cs);
+    return make_float2(rad * cs, rad * sn);
+}
+
+// The four deviates of samples 4j .. 4j+3 of room r, microphone m (the counter layout
+// of ism_normal_deviates): counter (j, m, r, 0); words (x0, x1) give samples 4j, 4j+1,
+// (x2, x3) samples 4j+2, 4j+3.
+DEV float4 deviates4(uint32_t j, uint32_t m, uint32_t r, uint32_t k0, uint32_t k1)
+{
+    const uint4 w = philox4x32_10(make_uint4(j, m, r, 0u), k0, k1);
+    const float2 a = box_muller(w.x, w.y), b = box_muller(w.z, w.w);
+    return make_float4(a.x, a.y, b.x, b.y);
+}
+
+// grid (chunks, rooms): z[r][m][n] for n < n_samples
+__global__ __launch_bounds__(256) void normal_deviates_kernel(float *__restrict__ z, int M, int n_samples,
+                                                              uint32_t k0, uint32_t k1)
+{
+    const int r = blockIdx.y;
+    const int nq = (n_samples + 3) >> 2;
+    float *zr = z + (int64_t)r * M * n_samples;
+    const bool vec = (n_samples & 3) == 0 && ((uintptr_t)z & 15) == 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)M * nq;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int m = (int)(t / nq), j = (int)(t - (int64_t)m * nq);
+        const float4 d = deviates4((uint32_t)j, (uint32_t)m, (uint32_t)r, k0, k1);
+        float *p = zr + (int64_t)m * n_samples + 4 * j;
+        if (vec) {
+            *(float4 *)p = d;
+        } else {
+            const float e[4] = {d.x, d.y, d.z, d.w};
+            for (int q = 0; q < 4 && 4 * j + q < n_samples; ++q) p[q] = e[q];
+        }
+    }
+}
+
+// per-room noise scale from the convolution's partial power sums (fixed order)
+DEV float room_sigma(const double *__restrict__ psum, int r, int n_parts, int64_t per_room, float snr_db)
+{
+    double P = 0.0;
+    for (int k = 0; k < n_parts; ++k) P += psum[(int64_t)r * n_parts + k];
+    P /= (double)per_room;
+    return (float)sqrt(P * pow(10.0, -(double)snr_db / 10.0));
+}
+
+// grid (chunks, rooms): y += sigma_r z with z drawn here (one Philox call per 4 samples)
+__global__ __launch_bounds__(256) void conv_noise_seeded(float *__restrict__ y, const double *__restrict__ psum,
+                                                         const ConvRoom *__restrict__ rooms, int n_parts, int M,
+                                                         int out_len, uint32_t k0, uint32_t k1)
+{
+    const int r = blockIdx.y;
+    __shared__ float sigma_s;
+    if (threadIdx.x == 0) sigma_s = room_sigma(psum, r, n_parts, (int64_t)M * out_len, rooms[r].snr_db);
+    __syncthreads();
+    const float sg = sigma_s;
+    const int nq = (out_len + 3) >> 2;
+    float *yr = y + (int64_t)r * M * out_len;
+    const bool vec = (out_len & 3) == 0 && ((uintptr_t)y & 15) == 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)M * nq;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int m = (int)(t / nq), j = (int)(t - (int64_t)m * nq);
+        const float4 d = deviates4((uint32_t)j, (uint32_t)m, (uint32_t)r, k0, k1);
+        float *p = yr + (int64_t)m * out_len + 4 * j;
+        if (vec) {
+            float4 v = *(float4 *)p;
+            v.x = fmaf(sg, d.x, v.x);
+            v.y = fmaf(sg, d.y, v.y);
+            v.z = fmaf(sg, d.z, v.z);
+            v.w = fmaf(sg, d.w, v.w);
+            *(float4 *)p = v;
+        } else {
+            const float e[4] = {d.x, d.y, d.z, d.w};
+            for (int q = 0; q < 4 && 4 * j + q < out_len; ++q) p[q] = fmaf(sg, e[q], p[q]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ noise (caller's deviates)
 // grid (chunks, rooms); psum holds n_parts partial sums of y^2 per room, in order.
 __global__ void conv_noise(float *__restrict__ y, const float *__restrict__ z, const double *__restrict__ psum,
                            const ConvRoom *__restrict__ rooms, int n_parts, int64_t per_room)
 {
     const int r = blockIdx.y;
     __shared__ float sigma_s;
-    if (threadIdx.x == 0) {
-        double P = 0.0;
-        for (int k = 0; k < n_parts; ++k) P += psum[(int64_t)r * n_parts + k];
-        P /= (double)per_room;
-        sigma_s = (float)sqrt(P * pow(10.0, -(double)rooms[r].snr_db / 10.0));
-    }
+    if (threadIdx.x == 0) sigma_s = room_sigma(psum, r, n_parts, per_room, rooms[r].snr_db);
     __syncthreads();
     const float sg = sigma_s;
     float *yr = y + (int64_t)r * per_room;
@@ -379,14 +482,16 @@ void ism_conv_release(ism_handle *h)
 
 static size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 
-extern "C" int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float *rirs, const int64_t *rir_offset,
-                                  const int32_t *rir_len, const float *src, int src_len, int out_len,
-                                  const float *snr_db, const float *z, int use_mfma, float *out, ism_stream stream)
+// noise: none (snr_db NULL), caller's deviates z, or deviates drawn from noise_seed
+static int convolve_impl(ism_handle *h, int n_rooms, int M, const float *rirs, const int64_t *rir_offset,
+                         const int32_t *rir_len, const float *src, int src_len, int out_len, const float *snr_db,
+                         const float *z, bool seeded, uint64_t noise_seed, int use_mfma, float *out,
+                         ism_stream stream)
 {
     if (!h) return ISM_EINVAL;
     h->last_error.clear();
-    if (n_rooms < 0 || M < 1 || src_len < 1 || out_len < 1) {
-        ism_set_error(h, "n_rooms >= 0, M >= 1, src_len >= 1 and out_len >= 1 required");
+    if (n_rooms < 0 || n_rooms > 65535 || M < 1 || M > 65535 || src_len < 1 || out_len < 1) {
+        ism_set_error(h, "0 <= n_rooms <= 65535, 1 <= M <= 65535, src_len >= 1 and out_len >= 1 required");
         return ISM_EINVAL;
     }
     if (n_rooms == 0) return ISM_OK;
@@ -394,7 +499,7 @@ extern "C" int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float
         ism_set_error(h, "NULL argument");
         return ISM_EINVAL;
     }
-    if (snr_db && !z) {
+    if (snr_db && !z && !seeded) {
         ism_set_error(h, "noise deviates z are required when snr_db is given");
         return ISM_EINVAL;
     }
@@ -493,7 +598,13 @@ extern "C" int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float
                            out, ps, dt_tiles);
         if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_direct launch");
     }
-    if (snr_db) {
+    if (snr_db && seeded) {
+        const int64_t quads = (int64_t)M * ((out_len + 3) / 4);
+        const int chunks = (int)std::min<int64_t>(256, (quads + 255) / 256);
+        hipLaunchKernelGGL(conv_noise_seeded, dim3(chunks, n_rooms), dim3(256), 0, q, out, ps, rm, (int)n_parts, M,
+                           out_len, (uint32_t)noise_seed, (uint32_t)(noise_seed >> 32));
+        if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_noise_seeded launch");
+    } else if (snr_db) {
         const int64_t per_room = (int64_t)M * out_len;
         const int chunks = (int)std::min<int64_t>(64, (per_room + 255) / 256);
         hipLaunchKernelGGL(conv_noise, dim3(chunks, n_rooms), dim3(256), 0, q, out, z, ps, rm, (int)n_parts, per_room);
@@ -501,5 +612,43 @@ extern "C" int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float
     }
     if ((e = hipEventRecord(C.ev, q)) != hipSuccess) return ism_hip_fail(h, e, "hipEventRecord");
     C.used = true;
+    return ISM_OK;
+}
+
+extern "C" int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float *rirs, const int64_t *rir_offset,
+                                  const int32_t *rir_len, const float *src, int src_len, int out_len,
+                                  const float *snr_db, uint64_t noise_seed, int use_mfma, float *out,
+                                  ism_stream stream)
+{
+    return convolve_impl(h, n_rooms, M, rirs, rir_offset, rir_len, src, src_len, out_len, snr_db, nullptr, true,
+                         noise_seed, use_mfma, out, stream);
+}
+
+extern "C" int ism_convolve_batch_z(ism_handle *h, int n_rooms, int M, const float *rirs, const int64_t *rir_offset,
+                                    const int32_t *rir_len, const float *src, int src_len, int out_len,
+                                    const float *snr_db, const float *z, int use_mfma, float *out, ism_stream stream)
+{
+    return convolve_impl(h, n_rooms, M, rirs, rir_offset, rir_len, src, src_len, out_len, snr_db, z, false, 0,
+                         use_mfma, out, stream);
+}
+
+extern "C" int ism_normal_deviates(ism_handle *h, int n_rooms, int M, int n_samples, uint64_t seed, float *z,
+                                   ism_stream stream)
+{
+    if (!h) return ISM_EINVAL;
+    h->last_error.clear();
+    if (n_rooms < 0 || M < 1 || n_samples < 1 || n_rooms > 65535 || (int64_t)n_samples > (1LL << 28)) {
+        ism_set_error(h, "0 <= n_rooms <= 65535, M >= 1 and 1 <= n_samples <= 2^28 required");
+        return ISM_EINVAL;
+    }
+    if (n_rooms == 0) return ISM_OK;
+    if (!z) { ism_set_error(h, "NULL argument"); return ISM_EINVAL; }
+    if (h->device < 0) { ism_set_error(h, "no HIP device"); return ISM_EDEVICE; }
+    const int64_t quads = (int64_t)M * ((n_samples + 3) / 4);
+    const int chunks = (int)std::min<int64_t>(256, (quads + 255) / 256);
+    hipLaunchKernelGGL(normal_deviates_kernel, dim3(chunks, n_rooms), dim3(256), 0, (hipStream_t)stream, z, M,
+                       n_samples, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ism_hip_fail(h, e, "normal_deviates launch");
     return ISM_OK;
 }

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <memory>
 #include <string>
 #include <utility>
@@ -66,6 +67,27 @@ struct Slot {
     GraphKey key;
 };
 
+// Autotuner cache: one launch configuration per shape bucket of a batch.
+struct TuneKey {
+    int precision, fd_taps, order_mode;
+    long long fs_mhz;   // sample rate in mHz
+    int len_bucket;     // ceil(log2(longest RIR))
+    int mic_bucket;     // ceil(log2(most microphones of a room))
+    bool operator<(const TuneKey &o) const
+    {
+        if (precision != o.precision) return precision < o.precision;
+        if (fd_taps != o.fd_taps) return fd_taps < o.fd_taps;
+        if (order_mode != o.order_mode) return order_mode < o.order_mode;
+        if (fs_mhz != o.fs_mhz) return fs_mhz < o.fs_mhz;
+        if (len_bucket != o.len_bucket) return len_bucket < o.len_bucket;
+        return mic_bucket < o.mic_bucket;
+    }
+};
+struct TuneVal {
+    int seg_len, wg_per_cu, interleave;
+    float ms;           // time of the winning configuration on the batch it was tuned on
+};
+
 struct ConvState;
 struct ServeState;
 
@@ -92,6 +114,8 @@ struct ism_handle {
     ism::ConvState *conv = nullptr;
     int coef_K = -1;                  // Chebyshev filter coefficients of the moment kernel, for coef_K
     std::vector<double> coef;
+    int autotune = 0;                 // 1: tune each new shape bucket on its first batch
+    std::map<ism::TuneKey, ism::TuneVal> tune_cache;
 };
 
 void ism_set_error(ism_handle *h, const char *fmt, ...);

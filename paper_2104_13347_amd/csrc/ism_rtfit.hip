@@ -10,7 +10,9 @@
 // (threshold crossings, then the regression sums).
 //
 // Fit: bisection on a uniform beta in [0, 1) (T30 increases with beta), one RIR from
-// the moment kernel and one T30 per step.
+// the moment kernel and one T30 per step.  Room-level fit: each step is one batched
+// launch of every (source, microphone) RIR of the room, one T30 workgroup per RIR, and
+// the mean of the T30s (summed on the host in RIR order).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -18,6 +20,7 @@
 
 #include <climits>
 #include <cmath>
+#include <vector>
 
 #include "../../include/ism.h"
 #include "ism_host.h"
@@ -52,9 +55,12 @@ __device__ __forceinline__ int rt_block_min(int v, int *red)
     return s;
 }
 
+// grid: one workgroup per RIR; RIR i is h[i * n .. (i + 1) n), its T30 goes to out[i]
 __global__ __launch_bounds__(RT_THREADS) void rt_t30_kernel(const float *__restrict__ h, int n, double fs,
                                                             double *__restrict__ out)
 {
+    h += (int64_t)blockIdx.x * n;
+    out += blockIdx.x;
     __shared__ double suf[RT_THREADS + 1];
     __shared__ double red[RT_THREADS / 64];
     __shared__ int redi[RT_THREADS / 64];
@@ -188,6 +194,91 @@ extern "C" int ism_fit_beta(ism_handle *h, const double L[3], const double src[3
     if (!(std::fabs(rt - rt_target) <= 0.01 * rt_target)) {
         ism_set_error(h, "target T30 %.4g s not reached: T30 %.4g s at beta %.6g after %d steps (rir_len too short "
                       "for the decay, or fewer steps than the target needs)", rt_target, rt, beta, iters);
+        return ISM_EDOMAIN;
+    }
+    return ISM_OK;
+}
+
+extern "C" size_t ism_rt_mean_work_bytes(int n_src, int M, int rir_len)
+{
+    if (n_src < 1 || M < 1 || rir_len < 1) return 0;
+    const size_t n = (size_t)n_src * (size_t)M;
+    return align256(n * (size_t)rir_len * sizeof(float)) + align256(n * sizeof(double));
+}
+
+extern "C" int ism_fit_beta_mean(ism_handle *h, const double L[3], int n_src, const double *srcs, int M,
+                                 const double *mics, double fs, double c, int fd_taps, double rt_target,
+                                 int rir_len, int iters, void *work, size_t work_bytes, double *beta_out,
+                                 double *rt_out, ism_stream stream)
+{
+    if (!h) return ISM_EINVAL;
+    h->last_error.clear();
+    if (!L || !srcs || !mics || !work || !beta_out || !rt_out) { ism_set_error(h, "NULL argument"); return ISM_EINVAL; }
+    if (n_src < 1 || M < 1 || (int64_t)n_src * M > 65535) {
+        ism_set_error(h, "n_src >= 1, M >= 1 and n_src * M <= 65535 required");
+        return ISM_EINVAL;
+    }
+    if (!(rt_target > 0.0) || !std::isfinite(rt_target)) {
+        ism_set_error(h, "rt_target must be finite and > 0");
+        return ISM_EINVAL;
+    }
+    if (iters < 1 || iters > 60) { ism_set_error(h, "iters must be in [1, 60]"); return ISM_EINVAL; }
+    if (rir_len < 1 || work_bytes < ism_rt_mean_work_bytes(n_src, M, rir_len)) {
+        ism_set_error(h, "rir_len < 1 or work of %zu bytes, %zu needed", work_bytes,
+                      ism_rt_mean_work_bytes(n_src, M, rir_len));
+        return ISM_EINVAL;
+    }
+    const int n = n_src * M;
+    hipStream_t st = (hipStream_t)stream;
+    float *rirs = (float *)work;
+    double *dev_rt = (double *)((char *)work + align256((size_t)n * rir_len * sizeof(float)));
+    std::vector<ism_room> rooms(n_src);
+    for (int i = 0; i < n_src; ++i) {
+        ism_room &r = rooms[i];
+        for (int k = 0; k < 3; ++k) {
+            r.L[k] = L[k];
+            r.src[k] = srcs[3 * i + k];
+        }
+        r.mic_offset = 0;
+        r.n_mics = M;
+        r.max_order = -1;
+        r.rir_len = rir_len;
+        r.out_offset = (int64_t)i * M * rir_len;
+    }
+    std::vector<double> rt(n);
+    auto trial = [&](double beta, double &mean) -> int {
+        for (ism_room &r : rooms)
+            for (int k = 0; k < 6; ++k) r.beta[k] = beta;
+        int rc = ism_rir_batch(h, n_src, rooms.data(), mics, fs, c, fd_taps, ISM_ORDER_INDEX_L1, ISM_PREC_FP32, rirs,
+                               stream);
+        if (rc) return rc;
+        hipLaunchKernelGGL(rt_t30_kernel, dim3(n), dim3(RT_THREADS), 0, st, rirs, rir_len, fs, dev_rt);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return ism_hip_fail(h, e, "rt_t30_kernel launch");
+        e = hipMemcpyAsync(rt.data(), dev_rt, sizeof(double) * n, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return ism_hip_fail(h, e, "T30 read-back");
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += rt[i];
+        mean = s / n;
+        return ISM_OK;
+    };
+    double lo = 0.0, hi = 1.0, mean = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        const int rc = trial(mid, mean);
+        if (rc) return rc;
+        if (mean < rt_target) lo = mid;
+        else hi = mid;
+    }
+    const double beta = 0.5 * (lo + hi);
+    const int rc = trial(beta, mean);
+    if (rc) return rc;
+    *beta_out = beta;
+    *rt_out = mean;
+    if (!(std::fabs(mean - rt_target) <= 0.01 * rt_target)) {
+        ism_set_error(h, "target mean T30 %.4g s not reached: %.4g s at beta %.6g after %d steps", rt_target, mean,
+                      beta, iters);
         return ISM_EDOMAIN;
     }
     return ISM_OK;

@@ -23,9 +23,9 @@ PREC_FP32, PREC_FP16_LUT, PREC_FP32_SPLIT, PREC_FP32_ATOMIC, PREC_FP32_DIRECT = 
 EXPORTS = [
     "ism_create", "ism_destroy", "ism_strerror", "ism_last_error", "ism_version", "ism_rir",
     "ism_rir_batch", "ism_batch_plan_stats", "ism_last_counts", "ism_set_tuning", "ism_get_tuning",
-    "ism_autotune", "ism_convolve_batch", "ism_server_create", "ism_server_destroy", "ism_server_submit",
+    "ism_autotune", "ism_set_autotune", "ism_get_launch_tuning", "ism_convolve_batch", "ism_convolve_batch_z", "ism_normal_deviates", "ism_server_create", "ism_server_destroy", "ism_server_submit",
     "ism_server_poll", "ism_server_copy_result", "ism_server_release", "ism_server_stats", "ism_server_last_error", "ism_server_replay",
-    "ism_rt_work_bytes", "ism_rir_t30", "ism_fit_beta",
+    "ism_rt_work_bytes", "ism_rir_t30", "ism_fit_beta", "ism_rt_mean_work_bytes", "ism_fit_beta_mean",
 ]
 
 ROOM_DTYPE = np.dtype([("L", np.float64, 3), ("beta", np.float64, 6), ("src", np.float64, 3),
@@ -80,8 +80,16 @@ def load():
     L.ism_autotune.argtypes = [vp, ci, vp, dp, cd, cd, ci, ci, ci, vp, vp, ctypes.POINTER(ci), ci,
                                ctypes.POINTER(ci)]
     L.ism_autotune.restype = ci
-    L.ism_convolve_batch.argtypes = [vp, ci, ci, vp, i64p, i32p, vp, ci, ci, fp, vp, ci, vp, vp]
+    L.ism_set_autotune.argtypes = [vp, ci]
+    L.ism_set_autotune.restype = ci
+    L.ism_get_launch_tuning.argtypes = [vp] + [ctypes.POINTER(ci)] * 5 + [fp]
+    L.ism_get_launch_tuning.restype = ci
+    L.ism_convolve_batch.argtypes = [vp, ci, ci, vp, i64p, i32p, vp, ci, ci, fp, ctypes.c_uint64, ci, vp, vp]
     L.ism_convolve_batch.restype = ci
+    L.ism_convolve_batch_z.argtypes = [vp, ci, ci, vp, i64p, i32p, vp, ci, ci, fp, vp, ci, vp, vp]
+    L.ism_convolve_batch_z.restype = ci
+    L.ism_normal_deviates.argtypes = [vp, ci, ci, ci, ctypes.c_uint64, vp, vp]
+    L.ism_normal_deviates.restype = ci
     L.ism_server_create.argtypes = [ci, ctypes.c_size_t, ci, ci, ctypes.POINTER(vp)]
     L.ism_server_create.restype = ci
     L.ism_server_destroy.argtypes = [vp]
@@ -106,6 +114,10 @@ def load():
     L.ism_rir_t30.restype = ci
     L.ism_fit_beta.argtypes = [vp, dp, dp, dp, cd, cd, ci, cd, ci, ci, vp, ctypes.c_size_t, dp, dp, vp]
     L.ism_fit_beta.restype = ci
+    L.ism_rt_mean_work_bytes.argtypes = [ci, ci, ci]
+    L.ism_rt_mean_work_bytes.restype = ctypes.c_size_t
+    L.ism_fit_beta_mean.argtypes = [vp, dp, ci, dp, ci, dp, cd, cd, ci, cd, ci, ci, vp, ctypes.c_size_t, dp, dp, vp]
+    L.ism_fit_beta_mean.restype = ci
     _lib = L
     return L
 
@@ -179,7 +191,15 @@ class Handle:
     def get_tuning(self):
         a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         self._check(self.lib.ism_get_tuning(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return {"seg_len": a.value, "wg_per_cu": b.value, "graphs": c.value}
+        v = [ctypes.c_int() for _ in range(5)]
+        ms = ctypes.c_float()
+        self._check(self.lib.ism_get_launch_tuning(self.h, *[ctypes.byref(x) for x in v], ctypes.byref(ms)))
+        return {"seg_len": a.value, "wg_per_cu": b.value, "graphs": c.value, "interleave": v[2].value,
+                "autotune": v[3].value, "tuned_buckets": v[4].value, "tuned_ms": ms.value}
+
+    def set_autotune(self, enable=True):
+        """Tune each new shape bucket on its first batch (ism_set_autotune)."""
+        self._check(self.lib.ism_set_autotune(self.h, int(bool(enable))))
 
     # -- RIRs
     @staticmethod
@@ -272,15 +292,19 @@ class Handle:
         return best.value
 
     # -- source convolution
-    def convolve_batch(self, rirs, rir_offset, rir_len, M, src, out_len, snr_db=None, z=None, use_mfma=True,
-                       out=None, stream=None):
-        """RIRs (flat device tensor) convolved with sources [R, src_len] (device), plus noise."""
+    def convolve_batch(self, rirs, rir_offset, rir_len, M, src, out_len, snr_db=None, z=None, noise_seed=None,
+                       use_mfma=True, out=None, stream=None):
+        """RIRs (flat device tensor) convolved with sources [R, src_len] (device), plus sensor noise
+        at snr_db (per room) when given: deviates z [R, M, out_len] from the caller
+        (ism_convolve_batch_z), or drawn on the device from noise_seed (ism_convolve_batch)."""
         import torch
         R = int(src.shape[0])
         off = np.ascontiguousarray(rir_offset, dtype=np.int64)
         ln = np.ascontiguousarray(rir_len, dtype=np.int32)
         self._check_in(src, "src")
         self._check_in(rirs, "rirs", int((off + int(M) * ln.astype(np.int64)).max()) if off.size else 0)
+        if snr_db is not None and (z is None) == (noise_seed is None):
+            raise ValueError("with snr_db give exactly one of z (deviates) and noise_seed")
         if z is not None:
             self._check_in(z, "z", R * int(M) * max(int(out_len), 0))
         if out is None:
@@ -292,15 +316,30 @@ class Handle:
         if snr_db is not None:
             snr = np.ascontiguousarray(snr_db, dtype=np.float32)
             snr_p = snr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
-        rc = self.lib.ism_convolve_batch(self.h, R, int(M), ctypes.c_void_p(rirs.data_ptr()),
-                                         off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                         ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                         ctypes.c_void_p(src.data_ptr()), int(src.shape[1]), int(out_len), snr_p,
-                                         ctypes.c_void_p(z.data_ptr() if z is not None else 0), int(bool(use_mfma)),
-                                         ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+        args = (self.h, R, int(M), ctypes.c_void_p(rirs.data_ptr()),
+                off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                ctypes.c_void_p(src.data_ptr()), int(src.shape[1]), int(out_len), snr_p)
+        tail = (int(bool(use_mfma)), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+        if z is not None:
+            rc = self.lib.ism_convolve_batch_z(*args, ctypes.c_void_p(z.data_ptr()), *tail)
+        else:
+            rc = self.lib.ism_convolve_batch(*args, int(noise_seed or 0) & 0xFFFFFFFFFFFFFFFF, *tail)
         self._check(rc)
         return out
 
+    def normal_deviates(self, n_rooms, M, n_samples, seed, out=None, stream=None):
+        """Seeded standard normal deviates [n_rooms, M, n_samples] (float32, device): the sensor
+        noise that convolve_batch draws for noise_seed = seed."""
+        import torch
+        if out is None:
+            with _on(stream):
+                out = torch.empty((int(n_rooms), int(M), int(n_samples)), dtype=torch.float32, device="cuda")
+        else:
+            self._check_out(out, int(n_rooms) * int(M) * int(n_samples))
+        self._check(self.lib.ism_normal_deviates(self.h, int(n_rooms), int(M), int(n_samples),
+                                                 int(seed) & 0xFFFFFFFFFFFFFFFF, ctypes.c_void_p(out.data_ptr()),
+                                                 _stream_handle(stream)))
+        return out
 
     # -- reverberation time
     def rir_t30(self, rir, fs, stream=None):
@@ -328,6 +367,25 @@ class Handle:
                                           float(rt_target), int(rir_len), int(iters),
                                           ctypes.c_void_p(work.data_ptr()), int(work.numel()),
                                           ctypes.byref(beta), ctypes.byref(rt), _stream_handle(stream)))
+        return beta.value, rt.value
+
+
+    def fit_beta_mean(self, L, srcs, mics, fs, c, fd_taps, rt_target, rir_len, iters=30, stream=None):
+        """Uniform beta whose RIRs from every source to every microphone have a mean T30 of
+        rt_target.  Returns (beta, mean T30)."""
+        import torch
+        srcs = np.ascontiguousarray(np.atleast_2d(srcs), dtype=np.float64)
+        mics = np.ascontiguousarray(np.atleast_2d(mics), dtype=np.float64)
+        n_src, M = srcs.shape[0], mics.shape[0]
+        nbytes = int(self.lib.ism_rt_mean_work_bytes(int(n_src), int(M), int(rir_len)))
+        with _on(stream):
+            work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+        L_ = np.ascontiguousarray(L, dtype=np.float64)
+        beta, rt = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.ism_fit_beta_mean(self.h, _dptr(L_), int(n_src), _dptr(srcs), int(M), _dptr(mics),
+                                               float(fs), float(c), int(fd_taps), float(rt_target), int(rir_len),
+                                               int(iters), ctypes.c_void_p(work.data_ptr()), int(work.numel()),
+                                               ctypes.byref(beta), ctypes.byref(rt), _stream_handle(stream)))
         return beta.value, rt.value
 
 

@@ -22,7 +22,10 @@ SNR), at the sizes of the five benchmark configurations:
 * ``paper_room1``  the paper's first training room: 7 x 10 x 3.7 m, RT 0.5 s,
           the 7-microphone array (centre + 6 on an 8 cm circle) at (4, 6, 1.5) m,
           sources uniform in the torus of central radius 2 m, +-0.5 m radially and
-          +-7 degrees in elevation around it (48 000 positions per room).
+          +-7 degrees in elevation around it (48 000 positions per room);
+* ``paper_room2``  the paper's second simulated room: 5 x 5 x 4 m, RT 0.5 s, the
+          same array centred at (2.5, 2.5, 1.5) m and the same torus (positions
+          within 0.1 m of a wall drawn again), 48 000 positions.
 
 Seeds default to 2104 + config index.  The paper's recordings are not
 available; white-noise sources stand in for them.
@@ -148,6 +151,30 @@ def paper_room1(n_sources=48000, seed=2109, fs=16000.0, c=C_SOUND, fd_taps=8, be
     return pack(rooms, fs, c, fd_taps, ORDER_INDEX_L1, "paper_room1")
 
 
+def paper_room2(n_sources=48000, seed=2110, fs=16000.0, c=C_SOUND, fd_taps=8, beta=None, wall_margin=0.1):
+    """The paper's second simulated room (section III.A): almost cubic, 5 x 5 x 4 m, reverberation
+    time 0.5 s, the same 7-microphone array and torus of sources.  The paper gives no array
+    position for this room: centred in the floor plan at 1.5 m (as in room 1).  The torus then
+    reaches the walls (2.5 m from the centre on the axes), so positions closer than wall_margin to
+    a wall are drawn again.  Sabine's coefficient unless a fitted beta is passed."""
+    rng = np.random.default_rng(seed)
+    L = np.array([5.0, 5.0, 4.0])
+    rt = 0.5
+    if beta is None:
+        beta, _ = sabine_beta(L, rt, c)
+    center = np.array([2.5, 2.5, 1.5])
+    mics = uma8_array(center)
+    src = np.empty((0, 3))
+    while len(src) < n_sources:
+        cand = torus_sources(rng, center, n_sources)
+        ok = np.all((cand > wall_margin) & (cand < L - wall_margin), axis=1)
+        src = np.concatenate([src, cand[ok]])
+    src = src[:n_sources]
+    rooms = [{"L": L, "beta": np.full(6, float(beta)), "src": src[i], "mics": mics, "max_order": -1,
+              "rir_len": int(round(rt * fs)), "rt60": rt} for i in range(n_sources)]
+    return pack(rooms, fs, c, fd_taps, ORDER_INDEX_L1, "paper_room2")
+
+
 def c0():
     room = {"L": (5.0, 4.0, 3.0), "beta": (0.7,) * 6, "src": (1.3, 2.1, 1.5),
             "mics": [(3.6, 1.7, 1.2)], "max_order": 10, "rir_len": 4096}
@@ -202,15 +229,18 @@ def c3(seed=2107, n_rooms=64, fs=48000.0, c=C_SOUND):
     return pack(rooms, fs, c, 127, ORDER_INDEX_L1, "c3")
 
 
-def c4(seed=2108, n_rooms=256, fs=16000.0, c=C_SOUND, src_len=16000):
+def c4(seed=2108, n_rooms=256, fs=16000.0, c=C_SOUND, src_len=16000, with_z=True):
     rng = np.random.default_rng(seed)
     rooms = [_shoebox_room(rng, 0.2, 0.8, 8, 0.8, fs, c) for _ in range(n_rooms)]
     batch = pack(rooms, fs, c, 81, ORDER_INDEX_L1, "c4")
     batch["x"] = rng.standard_normal((n_rooms, src_len)).astype(np.float32)
     batch["snr_db"] = rng.uniform(0.0, 30.0, size=n_rooms).astype(np.float32)
-    # standard normal sensor-noise deviates [room, mic, sample]; scaled to the drawn SNR
-    # by the convolution step
-    batch["z"] = rng.standard_normal((n_rooms, 8, src_len)).astype(np.float32)
+    # key of the sensor-noise generator when the deviates are drawn on the device
+    batch["noise_seed"] = seed
+    if with_z:
+        # host-drawn standard normal deviates [room, mic, sample] for the caller-supplied
+        # noise form; scaled to the drawn SNR by the convolution step
+        batch["z"] = rng.standard_normal((n_rooms, 8, src_len)).astype(np.float32)
     return batch
 
 

@@ -1,7 +1,14 @@
 """GPU parity of the source convolution + sensor noise (paper section III.A)
 against the FP64 oracle.  RIR inputs are seeded synthetic decaying-noise
 arrays (not outputs of the GPU path).  Bars: BF16 MFMA path relative RMS error
-<= 1e-2 per room; FP32 direct path max |err| <= 1e-5 x peak per room."""
+<= 1e-2 per room; FP32 direct path max |err| <= 1e-5 x peak per room.
+
+Seeded noise: the device's Philox4x32-10 / Box-Muller deviates against the
+oracle's (oracle/noise.py) within TOL_DEV (derived below); their moments and
+cross-channel correlations against the normal law; the seeded convolution
+bitwise equal to the caller-deviate form given the device deviates, and within
+the bars of the oracle given the oracle's own deviates; each room's SNR
+recovered from the added noise."""
 import sys
 
 import numpy as np
@@ -14,6 +21,9 @@ pytestmark = pytest.mark.gpu
 
 TOL_BF16_RMS = 1e-2
 TOL_FP32 = 1e-5
+# device deviates are FP32 logf / sqrtf / sincospif of exact uniforms: a few ulps of the
+# radius sqrt(-2 ln u1) <= sqrt(48 ln 2) = 5.77 each; 8 ulps of 5.77 = 2.8e-6
+TOL_DEV = 8 * 5.77 * 2.0 ** -24
 
 
 @pytest.fixture(scope="module")
@@ -26,21 +36,23 @@ def H():
     h.close()
 
 
-def _run(H, rirs, offs, lens, x, out_len, snr=None, z=None, mfma=True):
+def _run(H, rirs, offs, lens, x, out_len, snr=None, z=None, mfma=True, seed=None):
     import torch
     M = 8
     d_rirs = torch.from_numpy(rirs).cuda()
     d_x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
-    d_z = torch.from_numpy(np.ascontiguousarray(z, dtype=np.float32)).cuda() if z is not None else None
-    y = H.convolve_batch(d_rirs, offs, lens, M, d_x, out_len, snr_db=snr, z=d_z, use_mfma=mfma)
+    if z is not None and not torch.is_tensor(z):
+        z = torch.from_numpy(np.ascontiguousarray(z, dtype=np.float32)).cuda()
+    y = H.convolve_batch(d_rirs, offs, lens, M, d_x, out_len, snr_db=snr, z=z, noise_seed=seed, use_mfma=mfma)
     torch.cuda.synchronize()
     return y.cpu().numpy().astype(np.float64)
 
 
-def _oracle(rirs, offs, lens, x, out_len, r, snr=None, z=None):
+def _oracle(rirs, offs, lens, x, out_len, r, snr=None, z=None, zr=None):
+    # z: deviates of the whole batch [R, M, out_len]; zr: those of room r alone [M, out_len]
     L = int(lens[r])
     h = rirs[offs[r]:offs[r] + 8 * L].reshape(8, L).astype(np.float64)
-    zz = None if z is None else z[r].astype(np.float64)
+    zz = zr if zr is not None else (None if z is None else z[r].astype(np.float64))
     return oracle.conv_room(h, x[r].astype(np.float64), out_len, snr_db=None if snr is None else float(snr[r]), z=zz)
 
 
@@ -96,6 +108,100 @@ def test_conv_full_size_sampled(H):
         sys.stdout.write(f"c4 room {r} len {lens[r]} rel rms {rms:.3e}\n")
 
 
+@pytest.mark.parametrize("shape", [(3, 5, 1003), (2, 8, 16000), (1, 1, 1), (1, 2, 6)])
+def test_device_deviates_match_oracle(H, shape):
+    # ragged (n % 4 != 0, scalar tail) and aligned (float4 stores) sample counts
+    import torch
+    from oracle import noise
+    seed = 0x1234_5678_9ABC_DEF0
+    R, M, n = shape
+    got = H.normal_deviates(R, M, n, seed).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    err = 0.0
+    for r in range(R):
+        ref = noise.deviates(seed, r, M, n)
+        err = max(err, float(np.abs(got[r] - ref).max()))
+    sys.stdout.write(f"deviates {shape}: max|gpu - oracle| = {err:.2e} (bar {TOL_DEV:.2e})\n")
+    assert err <= TOL_DEV
+
+
+def test_device_deviates_moments():
+    # 8 channels x 2^20 samples: mean 0, variance 1, kurtosis 3, and no correlation between
+    # channels or between neighbouring samples (5-sigma bands of the sample statistics)
+    import torch
+    h = ism.Handle()
+    try:
+        n = 1 << 20
+        z = h.normal_deviates(1, 8, n, 2108)[0].double()
+        torch.cuda.synchronize()
+    finally:
+        h.close()
+    mean = z.mean(dim=1)
+    var = z.var(dim=1)
+    kurt = ((z - mean[:, None]) ** 4).mean(dim=1) / var ** 2
+    assert float(mean.abs().max()) <= 5.0 / np.sqrt(n)
+    assert float((var - 1.0).abs().max()) <= 5.0 * np.sqrt(2.0 / n)
+    assert float((kurt - 3.0).abs().max()) <= 5.0 * np.sqrt(96.0 / n)
+    zc = (z - mean[:, None]) / var.sqrt()[:, None]
+    corr = (zc @ zc.T) / n
+    off = corr - torch.diag(torch.diag(corr))
+    assert float(off.abs().max()) <= 5.0 / np.sqrt(n)
+    lag1 = (zc[:, 1:] * zc[:, :-1]).mean(dim=1)
+    assert float(lag1.abs().max()) <= 5.0 / np.sqrt(n)
+
+
+@pytest.mark.parametrize("mfma", [True, False])
+def test_conv_seeded_noise(H, mfma):
+    # the seeded form draws the same deviates as ism_normal_deviates: bitwise equal to the
+    # caller-deviate form given those; within the bars of the oracle given the oracle's own
+    # deviates; and the noise it adds has each room's SNR
+    import torch
+    from oracle import noise
+    lens = np.array([300, 800, 1])
+    rirs, offs = scenes.synthetic_rirs(lens, 8, seed=9)
+    rng = np.random.default_rng(10)
+    x = rng.standard_normal((3, 3000)).astype(np.float32)
+    out_len = 2502      # not a multiple of 4: scalar tails
+    snr = np.array([0.0, 17.25, 30.0], dtype=np.float32)
+    seed = 987654321
+    got = _run(H, rirs, offs, lens, x, out_len, snr=snr, mfma=mfma, seed=seed)
+    zdev = H.normal_deviates(3, 8, out_len, seed)
+    same = _run(H, rirs, offs, lens, x, out_len, snr=snr, z=zdev, mfma=mfma)
+    assert np.array_equal(got, same)
+    clean = _run(H, rirs, offs, lens, x, out_len, mfma=mfma)
+    for r in range(3):
+        zr = noise.deviates(seed, r, 8, out_len)
+        ref = _oracle(rirs, offs, lens, x, out_len, r, snr=snr, zr=zr)
+        _check(got[r], ref, mfma)
+        # SNR of the added noise: sigma by least squares of (noisy - clean) on the deviates,
+        # against the clean signal's mean power
+        d = (got[r] - clean[r]).ravel()
+        zz = zr.ravel()
+        sigma = float(d @ zz / (zz @ zz))
+        P = float(np.mean(clean[r] ** 2))
+        snr_hat = 10.0 * np.log10(P / sigma ** 2)
+        sys.stdout.write(f"room {r} mfma={mfma}: SNR {snr[r]:.4f} dB, recovered {snr_hat:.7f} dB\n")
+        # bar: sigma is rounded to FP32 once (2^-24 relative = 5.2e-7 dB), and each noisy sample
+        # once (averaging out in the least-squares sigma to well below that)
+        assert abs(snr_hat - float(snr[r])) <= 3e-6
+
+
+def test_conv_seeded_full_size(H):
+    # the 256-room workload with device noise: finite, four rooms against the oracle given
+    # the oracle's deviates for the same seed
+    from oracle import noise
+    b = scenes.c4(with_z=False)
+    lens = b["rir_len"]
+    rirs, offs = scenes.synthetic_rirs(lens, 8, seed=8)
+    got = _run(H, rirs, offs, lens, b["x"], 16000, snr=b["snr_db"], mfma=True, seed=b["noise_seed"])
+    assert np.all(np.isfinite(got))
+    for r in [0, 101, 255]:
+        ref = _oracle(rirs, offs, lens, b["x"], 16000, r, snr=b["snr_db"],
+                      zr=noise.deviates(b["noise_seed"], r, 8, 16000))
+        rms = _check(got[r], ref, True)
+        sys.stdout.write(f"c4 seeded room {r} len {lens[r]} rel rms {rms:.3e}\n")
+
+
 def test_conv_argument_errors(H):
     import torch
     d = torch.zeros(16, device="cuda")
@@ -103,6 +209,10 @@ def test_conv_argument_errors(H):
         H.convolve_batch(d, [0], [0], 8, torch.zeros((1, 4), device="cuda"), 4)
     with pytest.raises(ism.IsmError):   # MFMA path takes 8 microphones
         H.convolve_batch(d, [0], [2], 2, torch.zeros((1, 4), device="cuda"), 4, use_mfma=True)
+    with pytest.raises(ValueError):     # noise needs exactly one of z and noise_seed
+        H.convolve_batch(d, [0], [2], 1, torch.zeros((1, 4), device="cuda"), 4, snr_db=[10.0], use_mfma=False)
+    with pytest.raises(ism.IsmError):
+        H.normal_deviates(1, 0, 16, 1)
 
 
 def test_caller_outputs_are_checked(H):

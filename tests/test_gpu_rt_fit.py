@@ -80,3 +80,32 @@ def test_fit_beta_reports_an_unreachable_target(handle):
         handle.fit_beta(L, SRC, MIC, FS, 343.0, 8, 0.25, 200, iters=10)
     assert e.value.code == ism.ISM_EDOMAIN
 
+
+
+def test_fit_beta_mean_small_room_matches_oracle(handle):
+    # room-level fit (mean T30 over every source-microphone pair) against the oracle's
+    Ls, srcs, mics = [2.0, 2.5, 1.8], [[0.6, 0.7, 0.9], [1.4, 1.9, 0.5]], [[1.1, 1.2, 1.0], [1.15, 1.25, 1.0]]
+    beta, rt = handle.fit_beta_mean(Ls, srcs, mics, 4000.0, 343.0, 8, 0.1, 1000, iters=16)
+    rb, rr = ref.fit_beta_mean(Ls, srcs, mics, 4000.0, 343.0, 8, 0.1, 1000, iters=16)
+    print(f"[mean fit small] gpu beta {beta:.9f} T30 {rt:.9f}  oracle beta {rb:.9f} T30 {rr:.9f}", flush=True)
+    assert abs(beta - rb) <= 2.0 ** -16
+    assert abs(rt - rr) <= 1e-5 * rr and abs(rt - 0.1) <= 1e-3
+    # one pair: the same decisions as the single-pair fit
+    b1, _ = handle.fit_beta_mean(Ls, srcs[:1], mics[:1], 4000.0, 343.0, 8, 0.1, 1000, iters=16)
+    b2, _ = handle.fit_beta(Ls, srcs[0], mics[0], 4000.0, 343.0, 8, 0.1, 1000, iters=16)
+    assert b1 == b2
+
+
+@pytest.mark.parametrize("room", ["room1", "room2"])
+def test_fit_beta_mean_paper_rooms(handle, room):
+    # the paper's two simulated rooms (section III.A: homogeneous walls giving a reverberation
+    # time of 0.5 s): two torus sources of the dataset scene x the 7 array microphones, 16 kHz,
+    # 16 000 samples, 30 steps, against the oracle's room-level fit
+    from paper_2104_13347_amd import scenes
+    b = scenes.paper_room1(n_sources=2) if room == "room1" else scenes.paper_room2(n_sources=2)
+    Lr, srcs, mics = b["L"][0], b["src"], b["mics"][:7]
+    beta, rt = handle.fit_beta_mean(Lr, srcs, mics, 16000.0, 343.0, 8, 0.5, 16000, iters=30)
+    rb, rr = ref.fit_beta_mean(Lr, srcs, mics, 16000.0, 343.0, 8, 0.5, 16000, iters=30)
+    print(f"[mean fit {room}] gpu beta {beta:.9f} T30 {rt:.9f}  oracle beta {rb:.9f} T30 {rr:.9f}", flush=True)
+    assert abs(beta - rb) <= 1e-6
+    assert abs(rt - rr) <= 1e-6 * rr and abs(rt - 0.5) <= 1e-3
