@@ -352,29 +352,57 @@ def bench_rt_fit(H, torch):
     return res
 
 
-def bench_c2(torch, n_requests):
+def bench_c2(torch, n_requests, batched_taps_per_s=None):
     """Serving: Poisson arrivals of single-room requests (RT60 U[0.1,1.0] s, RIR RT60*fs, M in
-    {4,8,16,32}).  First a saturated run (all requests at t=0) gives the sustainable rate; then
-    arrivals at 0.7 of that rate give latency percentiles."""
+    {4,8,16,32}).  A saturated run (all requests at t=0) on the 8 GB engine gives the sustainable
+    rate; arrivals at 0.7 of it then run three times on each HBM budget (8 GB, 1 GB, and 32 MB,
+    where admission binds), giving p50/p99 latency per replay and served taps/s (exact device
+    counts).  The budget covers the output pool and every lane's staging slots."""
     from paper_2104_13347_amd import ism, scenes
     reqs, gaps, meta = scenes.c2(n_requests=n_requests)
     b = scenes.pack(reqs, meta["fs"], meta["c"], meta["fd_taps"], meta["order_mode"], "c2")
     n_rirs = int(b["n_mics"].sum())
-    S = ism.Server(n_lanes=4, hbm_budget_bytes=8 << 30, max_batch_rooms=64)
-    try:
-        lat0, wall0 = S.replay(b, np.zeros(n_requests))
-        rate = n_requests / wall0
-        lam = 0.7 * rate
-        lat, wall = S.replay(b, np.cumsum(gaps) / lam)
-        st = S.stats()
-    finally:
-        S.close()
-    return {"workload": f"{n_requests} requests, Poisson arrivals, RT60 U[0.1,1.0] s, M in {{4,8,16,32}}, 16 kHz",
-            "saturated": {"requests_per_s": rate, "rirs_per_s": n_rirs / wall0, "wall_s": wall0},
-            "poisson": {"lambda_per_s": lam, "p50_ms": float(np.percentile(lat, 50)),
-                        "p99_ms": float(np.percentile(lat, 99)), "rirs_per_s": n_rirs / wall, "wall_s": wall},
-            "lanes": 4, "hbm_budget_bytes": 8 << 30, "max_concurrent_batches": st["max_concurrent_batches"],
-            "batches": st["batches"]}
+    res = {"workload": f"{n_requests} requests, Poisson arrivals, RT60 U[0.1,1.0] s, M in {{4,8,16,32}}, 16 kHz",
+           "lanes": 4, "max_batch_rooms": 64, "replays_per_budget": 3}
+    lam = None
+    for name, budget in [("budget_8GiB", 8 << 30), ("budget_1GiB", 1 << 30), ("budget_32MiB", 32 << 20)]:
+        S = ism.Server(n_lanes=4, hbm_budget_bytes=budget, max_batch_rooms=64)
+        try:
+            c0 = S.counters()
+            lat0, wall0 = S.replay(b, np.zeros(n_requests))
+            c1 = S.counters()
+            entry = {"saturated": {"requests_per_s": n_requests / wall0, "rirs_per_s": n_rirs / wall0,
+                                   "taps_per_s": (c1["taps_done"] - c0["taps_done"]) / wall0, "wall_s": wall0}}
+            if lam is None:
+                lam = 0.7 * n_requests / wall0
+            reps = []
+            for _ in range(3):
+                a = S.counters()
+                lat, wall = S.replay(b, np.cumsum(gaps) / lam)
+                z = S.counters()
+                reps.append({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                             "rirs_per_s": n_rirs / wall, "taps_per_s": (z["taps_done"] - a["taps_done"]) / wall,
+                             "wall_s": wall, "admission_stalls": z["admission_stalls"] - a["admission_stalls"]})
+            p99 = [r["p99_ms"] for r in reps]
+            st, cn = S.stats(), S.counters()
+            entry["poisson"] = {
+                "lambda_per_s": lam, "replays": reps,
+                "p50_ms_median": float(np.median([r["p50_ms"] for r in reps])),
+                "p99_ms_median": float(np.median(p99)), "p99_ms_range": [float(min(p99)), float(max(p99))],
+                "served_taps_per_s_median": float(np.median([r["taps_per_s"] for r in reps]))}
+            if batched_taps_per_s:
+                entry["poisson"]["served_vs_batched_taps"] = entry["poisson"]["served_taps_per_s_median"] / \
+                    batched_taps_per_s
+                entry["saturated"]["served_vs_batched_taps"] = entry["saturated"]["taps_per_s"] / batched_taps_per_s
+            entry["memory"] = {"budget_bytes": cn["budget_bytes"], "pool_bytes": cn["pool_bytes"],
+                               "staging_bytes": cn["staging_bytes"], "pool_peak_bytes": cn["pool_peak_bytes"],
+                               "admission_stalls_total": cn["admission_stalls"]}
+            entry["max_concurrent_batches"] = st["max_concurrent_batches"]
+            entry["batches"] = st["batches"]
+            res[name] = entry
+        finally:
+            S.close()
+    return res
 
 
 def main():
@@ -561,7 +589,7 @@ def main():
         if "paper" in extras:
             res["extras"]["paper_room1_dataset"] = bench_paper(H, torch)
         if "c2" in extras:
-            res["extras"]["c2_serving"] = bench_c2(torch, args.serve_requests)
+            res["extras"]["c2_serving"] = bench_c2(torch, args.serve_requests, batched_taps_per_s=value)
         if "beamlearning" in extras:
             bl = bench_beamlearning(H, torch)
             if not args.no_cpu_baseline:

@@ -242,7 +242,7 @@ int ism_get_launch_tuning(const ism_handle *h, int *seg_len, int *wg_per_cu, int
  *             (M must be 8); 0 = FP32 direct convolution on the vector units.
  *   Limits: 0 <= n_rooms <= 65535, 1 <= M <= 65535, rir_len in [1, 2^24],
  *   src_len and out_len in [1, 2^28]; otherwise ISM_EINVAL before any device work.
- *   Asynchronous on `stream`; the handle keeps a workspace (BF16 RIRs, power sums,
+ *   Asynchronous on `stream`; the handle keeps a workspace (tile power sums,
  *   room table) that a later call may reuse once this call's work has finished.
  */
 int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float *rirs,
@@ -323,16 +323,20 @@ int ism_fit_beta(ism_handle *h, const double L[3], const double src[3], const do
  * RIR length and microphone count arriving at any time).
  *
  * ism_server_create: n_lanes streams (1..16), each with its own launch state;
- *   hbm_budget_bytes is allocated once as the output pool; a request is admitted,
- *   in strict FIFO order, when its output (M x rir_len floats) fits in the pool and
- *   a lane is free; up to max_batch_rooms admitted requests with equal fs, c,
- *   fd_taps, order_mode and precision form one batched launch.  Batches on
- *   different lanes run concurrently.  mock = 1 runs the scheduler without a
- *   device (batches complete after a host-side delay; outputs are NULL).
+ *   hbm_budget_bytes bounds all the device memory the engine holds: each lane's two
+ *   fixed staging slots (launch buffers; 64 KiB per room of a full batch, at most a
+ *   quarter of the budget over all lanes) and the output pool (the rest, allocated
+ *   once).  A request is admitted, in strict FIFO order, when its output
+ *   (M x rir_len floats) fits in the pool and a lane is free; up to max_batch_rooms
+ *   admitted requests with equal fs, c, fd_taps, order_mode and precision whose
+ *   launch buffer fits a slot form one batched launch.  Batches on different lanes
+ *   run concurrently.  mock = 1 runs the scheduler without a device (batches
+ *   complete after a host-side delay; outputs are NULL; no staging is reserved).
+ *   ISM_ENOMEM if the budget cannot hold the staging slots.
  * ism_server_submit: copies the room and its microphones (host), returns a ticket;
  *   room->mic_offset and room->out_offset are ignored.  Thread-safe.
- *   ISM_ENOMEM if the output can never fit the budget; validation errors as for
- *   ism_rir.
+ *   ISM_ENOMEM if the output can never fit the pool or its launch buffer a staging
+ *   slot; validation errors as for ism_rir.
  * ism_server_poll: *state = 0 queued, 1 running, 2 done, 3 failed; when done,
  *   *out_dev = device pointer to the M x rir_len result (owned by the engine until
  *   release) and *latency_ms = completion - submission (host clock at the
@@ -359,6 +363,14 @@ int ism_server_poll(ism_server *s, uint64_t ticket, int *state, float **out_dev,
 int ism_server_copy_result(ism_server *s, uint64_t ticket, float *dst, ism_stream stream);
 int ism_server_release(ism_server *s, uint64_t ticket);
 int ism_server_stats(ism_server *s, int64_t stats[8]);
+/*
+ * ism_server_counters: v[0] HBM budget, v[1] output pool bytes, v[2] staging bytes
+ * (two fixed launch-buffer slots per lane; the pool is the budget less these), v[3] peak
+ * pool bytes in use, v[4] admission stalls (requests that waited at the head of the queue
+ * for pool memory), v[5] taps and v[6] image records of finished batches (exact device
+ * counts, as ism_last_counts), v[7] RIRs done.
+ */
+int ism_server_counters(ism_server *s, int64_t v[8]);
 const char *ism_server_last_error(ism_server *s);
 int ism_server_replay(ism_server *s, int n, const ism_room *rooms, const double *mics, const double *arrival_s,
                       double fs, double c, int fd_taps, double *latency_ms, double *wall_s);

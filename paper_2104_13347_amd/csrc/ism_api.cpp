@@ -25,7 +25,7 @@ using namespace ism;
 namespace ism {
 struct KernelEntry { hipError_t (*fn)(const LaunchDev *, int, int, hipStream_t); const void *sym; };
 KernelEntry select_segment_kernel(int K, int variant);
-KernelEntry select_moment_kernel(int K);
+KernelEntry select_moment_kernel(int K, bool reduced);
 hipError_t launch_prologue(const LaunchDev *P, int n_rooms, hipStream_t st);
 }  // namespace ism
 
@@ -402,6 +402,11 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 static int ensure_slot(ism_handle *h, Slot &s, size_t bytes)
 {
     if (s.cap >= bytes) return ISM_OK;
+    if (h->staging_fixed) {
+        ism_set_error(h, "launch buffer of %zu bytes exceeds the fixed staging slot of %zu bytes", bytes,
+                      h->staging_fixed);
+        return ISM_ENOMEM;
+    }
     if (s.event && s.used) hipEventSynchronize(s.event);
     free_slot(s);
     size_t cap = std::max<size_t>(bytes + bytes / 4, 1 << 20);
@@ -413,6 +418,44 @@ static int ensure_slot(ism_handle *h, Slot &s, size_t bytes)
     if (e != hipSuccess) return ism_hip_fail(h, e, "hipEventCreate");
     s.cap = cap;
     return ISM_OK;
+}
+
+int ism_reserve_staging(ism_handle *h, size_t bytes)
+{
+    if (!h || bytes < 4096) return ISM_EINVAL;
+    if (h->device < 0) { ism_set_error(h, "no HIP device"); return ISM_EDEVICE; }
+    for (Slot &s : h->slots) {
+        if (s.event && s.used) hipEventSynchronize(s.event);
+        free_slot(s);
+        hipError_t e = hipHostMalloc(&s.host, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) { s.host = nullptr; ism_set_error(h, "pinned allocation failed"); return ISM_ENOMEM; }
+        e = hipMalloc(&s.dev, bytes);
+        if (e != hipSuccess) { s.dev = nullptr; ism_set_error(h, "device allocation failed"); return ISM_ENOMEM; }
+        e = hipEventCreateWithFlags(&s.event, hipEventDisableTiming);
+        if (e != hipSuccess) return ism_hip_fail(h, e, "hipEventCreate");
+        s.cap = bytes;
+    }
+    h->staging_fixed = bytes;
+    return ISM_OK;
+}
+
+// The launch buffer's layout (ism_run_plan): header | rooms | mics | items | coefficients |
+// counters | wall-power tables, each part 256-byte aligned.  The per-room term counts a
+// room's share of each part; the fixed part the header, the largest coefficient table, the
+// counters and the alignment padding of six parts.
+size_t ism_launch_fixed_bytes(int fd_taps)
+{
+    const int K = half_length(fd_taps);
+    return align_up(sizeof(LaunchDev), 256) + sizeof(double) * kMom * (2 * K + 1) + 256 + 6 * 256;
+}
+
+size_t ism_room_launch_bytes(const ism_room &r, double fs, double c, int fd_taps, int seg_len)
+{
+    const int K = half_length(fd_taps);
+    if (fd_taps == kLagrangeTaps) seg_len = std::min(seg_len, kMomSegMax);
+    const size_t nseg = ((size_t)std::max(r.rir_len, 1) + seg_len - 1) / seg_len;
+    return sizeof(RoomDev) + sizeof(double) * 3 * (size_t)r.n_mics + sizeof(ItemDev) * nseg * (size_t)r.n_mics +
+           sizeof(double) * 6 * (size_t)pow_stride_for(r, fs, c, K);
 }
 
 // Chebyshev coefficients of the moment kernel's filter: for each tap k in [-K, K],
@@ -472,9 +515,10 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
     int lds = 0, block = 64;
     int pow_max = 0;
     for (const RoomDev &r : plan.rooms) pow_max = std::max(pow_max, r.pow_stride);
-    const bool moments = (precision == ISM_PREC_FP32 || precision == ISM_PREC_FP32_SPLIT) &&
+    const bool reduced = precision == ISM_PREC_FP16_LUT;
+    const bool moments = (precision == ISM_PREC_FP32 || precision == ISM_PREC_FP32_SPLIT || reduced) &&
                          plan.seg_max <= kMomSegMax && pow_max <= kPowCap;
-    if (moments) ke = select_moment_kernel(K);
+    if (moments) ke = select_moment_kernel(K, reduced);
     if (ke.fn) {
         lds = mom_lds_bytes(K);
         block = 64 * kMomWaves;

@@ -114,6 +114,7 @@ struct ism_handle {
     ism::ConvState *conv = nullptr;
     int coef_K = -1;                  // Chebyshev filter coefficients of the moment kernel, for coef_K
     std::vector<double> coef;
+    size_t staging_fixed = 0;         // nonzero: both staging slots fixed at this capacity (no growth)
     int autotune = 0;                 // 1: tune each new shape bucket on its first batch
     std::map<ism::TuneKey, ism::TuneVal> tune_cache;
 };
@@ -126,5 +127,12 @@ int ism_build_plan(ism_handle *h, int n_rooms, const ism_room *rooms, const doub
                    int fd_taps, int seg_len, ism::Plan &plan);
 int ism_run_plan(ism_handle *h, const ism::Plan &plan, const double *mics, double fs, double c, int fd_taps,
                  int order_mode, int precision, float *out, hipStream_t stream, double *t_ms);
+// Device bytes of the launch buffer of a batch: a fixed part plus one term per room
+// (room record, microphones, work items, wall-power tables), for segments of seg_len.
+size_t ism_launch_fixed_bytes(int fd_taps);
+size_t ism_room_launch_bytes(const ism_room &r, double fs, double c, int fd_taps, int seg_len);
+// Allocates both staging slots of the handle at `bytes` each and fixes them there: a batch
+// whose launch buffer is larger then fails with ISM_ENOMEM instead of growing the slots.
+int ism_reserve_staging(ism_handle *h, size_t bytes);
 void ism_conv_release(ism_handle *h);
 void ism_serve_release(ism_handle *h);

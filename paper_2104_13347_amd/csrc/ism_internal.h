@@ -73,6 +73,7 @@ constexpr int kCols = 64;           // columns per enumeration chunk (one per la
 
 // Moment kernel: Chebyshev moments per delay bin, waves per workgroup, largest segment.
 constexpr int kMom = 9;
+constexpr int kMomRed = 6;          // terms of the reduced-precision form
 constexpr int kMomWaves = 16;       // waves per workgroup (one item per workgroup)
 constexpr int kMomSetupWaves = 16;  // waves that set up a batch of image columns, 64 each
 constexpr int kMomSegMax = 1024;

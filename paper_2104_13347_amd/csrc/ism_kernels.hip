@@ -1020,12 +1020,18 @@ DEV f16x8_t lds_f16x8_a4(const _Float16 *p)
     return __builtin_bit_cast(f16x8_t, v);
 }
 
-template <int KT>
+// RED = true: the reduced-precision form (ISM_PREC_FP16_LUT on this kernel): kMomRed = 6
+// Chebyshev terms (truncation below 1.3e-4 of max|h|), FP16 bins and FP16 coefficients
+// without their low halves, one matrix-core product per step; delays, distances and the
+// exact integer binning as in the full form.
+template <int KT, bool RED>
 __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__restrict__ P)
 {
     constexpr int K = KT;
+    constexpr int NM = RED ? kMomRed : kMom;   // moment channels
     static_assert(kMom * mom_ustride(KT) * 4 <= kMomCols * (int)sizeof(MomCol),
                   "the FP32 bins fit the column-record area");
+    static_assert(NM % 3 == 0 && NM <= kMom, "channels in groups of 3");
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = uniform(tid >> 6);
     const int ustride = mom_ustride(K);
@@ -1039,7 +1045,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
     const int kmin = lagrange ? -3 : -K, kmax = lagrange ? 4 : K;
     uint64_t n_taps = 0;
     uint32_t n_rec = 0, n_img = 0;
-    const int nU = kMom * ustride;
+    const int nU = NM * ustride;
 
     // wall-power tables of an item's room into LDS, one entry i < kTab per thread:
     // pzz[i = 2 (q + kPowCap) + w] = beta_z0^|q - w| beta_zL^|q|; pxy[i] = x0, xL, y0, yL
@@ -1214,7 +1220,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                         lds_add_u31(u, gs);
                         lds_add_u31(u + ustride, fma(gs, xx, gs));
 #pragma unroll
-                        for (int m = 2; m < kMom; ++m) {
+                        for (int m = 2; m < NM; ++m) {
                             const double tn = fma(x2, tc, -tp);
                             lds_add_u31(m < 7 ? u + m * ustride : u7 + (m - 7) * ustride, fma(gs, tn, gs));
                             tp = tc;
@@ -1294,7 +1300,6 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         {
             // work units (bin i, group of 3 channels); the bin sums are below 2^53, so the
             // doubles are exact, and so is fma(U_m, 2^bexp, -U_0 2^bexp); one rounding to FP32
-            static_assert(kMom % 3 == 0, "channels in groups of 3");
             const double bs = ldexp(1.0, bexp);
             auto u64d = [](long long v) {  // exact for 0 <= v < 2^53
                 const unsigned long long u = (unsigned long long)v;
@@ -1303,9 +1308,9 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             auto put = [&](int e, float x) {
                 const _Float16 hi = (_Float16)x;
                 Uh[e] = hi;
-                Ul[e] = (_Float16)(x - (float)hi);
+                if (!RED) Ul[e] = (_Float16)(x - (float)hi);
             };
-            for (int w = tid; w < 3 * NB; w += kMomThreads) {
+            for (int w = tid; w < (NM / 3) * NB; w += kMomThreads) {
                 const int g = w / NB, i = w - g * NB;
                 // all four reads first (the stores below may alias them as far as the compiler
                 // knows, and would otherwise wait for each read in turn)
@@ -1322,10 +1327,10 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                 }
             }
             if constexpr (NBP > NB) {  // zeros past the last delay
-                for (int e = tid; e < kMom * (NBP - NB); e += kMomThreads) {
+                for (int e = tid; e < NM * (NBP - NB); e += kMomThreads) {
                     const int m = e / (NBP - NB), i = NB + e - m * (NBP - NB);
                     Uh[m * NBP + i] = (_Float16)0.0f;
-                    Ul[m * NBP + i] = (_Float16)0.0f;
+                    if (!RED) Ul[m * NBP + i] = (_Float16)0.0f;
                 }
             }
         }
@@ -1347,7 +1352,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             // after them (this item no longer reads the tables)
             double tv[3];
             if (fill) table_load(nxt_pow_offset, nxt_pow_stride, tid, tv);
-            for (int m = wave >> 2; m < kMom; m += 4) {
+            for (int m = wave >> 2; m < NM; m += 4) {
                 const int bb = m * NBP + 256 * tile + 16 * r16 + 8 * kq;  // this lane's bins, step 0
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
@@ -1356,12 +1361,14 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                     const int t0 = 32 * s + 8 * kq - r16 + 16, sh = t0 & 1;
                     const _Float16 *crow = S.c16 + ((sh * 2) * kMom + m) * CL + (t0 - sh);
                     const f16x8_t ah = lds_f16x8_a4(crow);
-                    const f16x8_t al = lds_f16x8_a4(crow + kMom * CL);
                     const f16x8_t bh = *(const f16x8_t *)(Uh + bb + 32 * s);
-                    const f16x8_t bl = *(const f16x8_t *)(Ul + bb + 32 * s);
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, acc, 0, 0, 0);
+                    if (!RED) {
+                        const f16x8_t al = lds_f16x8_a4(crow + kMom * CL);
+                        const f16x8_t bl = *(const f16x8_t *)(Ul + bb + 32 * s);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, acc, 0, 0, 0);
+                    }
                 }
             }
             if (fill) table_store(tid, tv);
@@ -1435,22 +1442,23 @@ KernelEntry select_segment_kernel(int K, int variant)
     return {launch_t<0, VAR_FX>, sym_t<0, VAR_FX>()};
 }
 
-template <int KT>
+template <int KT, bool RED>
 static hipError_t launch_m(const LaunchDev *P, int grid, int lds, hipStream_t st)
 {
-    hipLaunchKernelGGL((ism_moments<KT>), dim3(grid), dim3(kMomThreads), lds, st, P);
+    hipLaunchKernelGGL((ism_moments<KT, RED>), dim3(grid), dim3(kMomThreads), lds, st, P);
     return hipGetLastError();
 }
 
-template <int KT>
-static const void *sym_m() { return reinterpret_cast<const void *>(&ism_moments<KT>); }
+template <int KT, bool RED>
+static const void *sym_m() { return reinterpret_cast<const void *>(&ism_moments<KT, RED>); }
 
-// Moment kernel for the compiled half-lengths; {nullptr, nullptr} otherwise.
-KernelEntry select_moment_kernel(int K)
+// Moment kernel for the compiled half-lengths (full or reduced precision); {nullptr,
+// nullptr} otherwise.
+KernelEntry select_moment_kernel(int K, bool reduced)
 {
-    if (K == 4) return {launch_m<4>, sym_m<4>()};
-    if (K == 40) return {launch_m<40>, sym_m<40>()};
-    if (K == 63) return {launch_m<63>, sym_m<63>()};
+    if (K == 4) return reduced ? KernelEntry{launch_m<4, true>, sym_m<4, true>()} : KernelEntry{launch_m<4, false>, sym_m<4, false>()};
+    if (K == 40) return reduced ? KernelEntry{launch_m<40, true>, sym_m<40, true>()} : KernelEntry{launch_m<40, false>, sym_m<40, false>()};
+    if (K == 63) return reduced ? KernelEntry{launch_m<63, true>, sym_m<63, true>()} : KernelEntry{launch_m<63, false>, sym_m<63, false>()};
     return {nullptr, nullptr};
 }
 

@@ -3,8 +3,11 @@
 // Requests arrive at any time (ism_server_submit, any thread).  A scheduler
 // thread owns everything else:
 //   * admission: strict FIFO; a request is admitted when its output fits in the
-//     engine's HBM pool (a first-fit sub-allocator over one allocation of the
-//     requested budget) and a lane is free;
+//     engine's HBM pool (a first-fit sub-allocator over one allocation) and a lane
+//     is free.  The budget covers everything the engine holds on the device: the
+//     output pool plus each lane's two fixed staging slots (launch buffers: room
+//     table, microphones, work items, wall-power tables); a batch also stops growing
+//     when its launch buffer would not fit a slot;
 //   * lanes: each lane is a stream with its own library handle (own staging
 //     slots); the requests admitted together become one batched launch
 //     (ism_rir_batch) on a free lane, while batches on other lanes are still
@@ -104,6 +107,7 @@ struct Request {
     double fs = 0, c = 0;
     int fd_taps = 0, order_mode = 0, precision = 0;
     size_t bytes = 0, off = 0;
+    size_t plan_bytes = 0;  // its share of a launch buffer
     int state = Q_QUEUED;
     int status = ISM_OK;
     int64_t tag = -1;  // replay index
@@ -114,6 +118,7 @@ struct Lane {
     ism_handle *h = nullptr;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    unsigned long long *counts = nullptr;  // pinned: the batch's work counters, copied after its launch
     bool busy = false;
     std::vector<uint64_t> batch;
     double mock_until = 0;
@@ -125,6 +130,8 @@ struct ism_server {
     int mock = 0;
     int max_batch = 64;
     double mock_taps_per_s = 2e12;
+    size_t budget = 0;
+    size_t slot_bytes = 0;   // each lane's two staging slots hold this many bytes each (0 in mock mode)
     Pool pool;
     char *base = nullptr;  // device pool
     std::vector<Lane> lanes;
@@ -141,6 +148,9 @@ struct ism_server {
     // statistics
     int64_t n_submitted = 0, n_done = 0, n_batches = 0, max_inflight_batches = 0;
     int64_t rirs_done = 0;
+    int64_t admission_stalls = 0;   // requests that waited at the queue head for pool memory
+    uint64_t stalled_ticket = 0;
+    int64_t taps_done = 0, records_done = 0;
     double busy_lane_time = 0;
     void loop();
 };
@@ -167,6 +177,10 @@ void ism_server::loop()
             else fin = hipEventQuery(L.done) == hipSuccess;
             if (!fin) continue;
             const double td = mock ? L.mock_until : t;
+            if (!mock && L.counts) {   // the counters were copied before the completion event
+                taps_done += (int64_t)L.counts[0];
+                records_done += (int64_t)L.counts[1];
+            }
             for (uint64_t tk : L.batch) {
                 auto it = reqs.find(tk);
                 if (it == reqs.end()) continue;
@@ -189,12 +203,21 @@ void ism_server::loop()
             const Request &head = reqs[pending.front()];
             const double fs = head.fs, c = head.c;
             const int taps = head.fd_taps, om = head.order_mode, pr = head.precision;
+            size_t plan = ism_launch_fixed_bytes(taps);
             while (!pending.empty() && (int)batch.size() < max_batch) {
                 Request &r = reqs[pending.front()];
                 if (r.fs != fs || r.c != c || r.fd_taps != taps || r.order_mode != om || r.precision != pr) break;
+                if (slot_bytes && plan + r.plan_bytes > slot_bytes) break;  // the launch buffer is full
                 size_t off;
-                if (!pool.alloc(r.bytes, &off)) break;  // strict FIFO: the head waits for memory
+                if (!pool.alloc(r.bytes, &off)) {  // strict FIFO: the head waits for memory
+                    if (stalled_ticket != r.ticket) {
+                        stalled_ticket = r.ticket;
+                        ++admission_stalls;
+                    }
+                    break;
+                }
                 r.off = off;
+                plan += r.plan_bytes;
                 batch.push_back(r.ticket);
                 pending.pop_front();
             }
@@ -220,6 +243,10 @@ void ism_server::loop()
                 lk.unlock();  // planning and launch without holding the lock
                 st = ism_rir_batch(L.h, (int)rooms.size(), rooms.data(), mics.data(), fs, c, taps, om, pr,
                                    (float *)base, L.stream);
+                if (st == ISM_OK && L.h->last_stats &&
+                    hipMemcpyAsync(L.counts, L.h->last_stats, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                   L.stream) != hipSuccess)
+                    st = ISM_EDEVICE;
                 if (st == ISM_OK && hipEventRecord(L.done, L.stream) != hipSuccess) st = ISM_EDEVICE;
                 lk.lock();
             }
@@ -257,7 +284,22 @@ extern "C" int ism_server_create(int n_lanes, size_t hbm_budget_bytes, int max_b
     if (!s) return ISM_ENOMEM;
     s->mock = mock ? 1 : 0;
     s->max_batch = max_batch_rooms;
-    s->pool.init(Pool::round(hbm_budget_bytes) - (mock ? 0 : 0));
+    s->budget = hbm_budget_bytes;
+    // staging: 64 KiB of launch buffer per room of a full batch, at most a quarter of the budget
+    // over all lanes' two slots, at least 16 KiB; rounded to the pool's granule
+    size_t staging = 0;
+    if (!s->mock) {
+        size_t sb = (size_t)max_batch_rooms << 16;
+        sb = std::min(sb, hbm_budget_bytes / (8 * (size_t)n_lanes));
+        sb = std::max<size_t>(Pool::round(sb), 16384);
+        s->slot_bytes = sb;
+        staging = 2 * (size_t)n_lanes * sb;
+        if (staging + 4096 > hbm_budget_bytes) {
+            delete s;
+            return ISM_ENOMEM;
+        }
+    }
+    s->pool.init((hbm_budget_bytes - staging) / 256 * 256);
     s->lanes.resize(n_lanes);
     if (!s->mock) {
         if (hipMalloc((void **)&s->base, s->pool.size) != hipSuccess) {
@@ -269,6 +311,12 @@ extern "C" int ism_server_create(int n_lanes, size_t hbm_budget_bytes, int max_b
             if (st == ISM_OK && hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess) st = ISM_EDEVICE;
             if (st == ISM_OK && hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) st = ISM_EDEVICE;
             if (st == ISM_OK) st = ism_set_tuning(L.h, 0, -1, 0);  // batch shapes vary: launch directly
+            if (st == ISM_OK) st = ism_reserve_staging(L.h, s->slot_bytes);
+            if (st == ISM_OK && hipHostMalloc((void **)&L.counts, 8 * sizeof(unsigned long long),
+                                              hipHostMallocDefault) != hipSuccess) {
+                L.counts = nullptr;
+                st = ISM_ENOMEM;
+            }
             if (st != ISM_OK) {
                 ism_server_destroy(s);
                 return st == ISM_EINVAL ? ISM_EDEVICE : st;
@@ -291,6 +339,7 @@ extern "C" void ism_server_destroy(ism_server *s)
         if (L.done) hipEventDestroy(L.done);
         if (L.stream) hipStreamDestroy(L.stream);
         if (L.h) ism_destroy(L.h);
+        if (L.counts) hipHostFree(L.counts);
     }
     if (s->base) hipFree(s->base);
     delete s;
@@ -317,7 +366,14 @@ static int submit_impl(ism_server *s, const ism_room *room, const double *mics, 
     const size_t bytes = sizeof(float) * (size_t)r.n_mics * (size_t)r.rir_len;
     if (Pool::round(bytes) > s->pool.size) {
         std::lock_guard<std::mutex> g(s->mu);
-        s->err = "request output exceeds the engine's HBM budget";
+        s->err = "request output exceeds the engine's output pool (HBM budget less the lanes' staging)";
+        return ISM_ENOMEM;
+    }
+    // the lanes launch with the library's default segment length (1024)
+    const size_t plan_bytes = ism_room_launch_bytes(r, fs, c, fd_taps, 1024);
+    if (s->slot_bytes && ism_launch_fixed_bytes(fd_taps) + plan_bytes > s->slot_bytes) {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->err = "request's launch buffer exceeds a lane's staging slot (raise the HBM budget or max_batch_rooms)";
         return ISM_ENOMEM;
     }
     Request q;
@@ -329,6 +385,7 @@ static int submit_impl(ism_server *s, const ism_room *room, const double *mics, 
     q.order_mode = order_mode;
     q.precision = precision;
     q.bytes = bytes;
+    q.plan_bytes = plan_bytes;
     q.tag = tag;
     q.t_submit = now_s();
     {
@@ -412,6 +469,21 @@ extern "C" int ism_server_stats(ism_server *s, int64_t st[8])
     st[5] = (int64_t)s->pool.peak;
     st[6] = (int64_t)s->pending.size();
     st[7] = s->rirs_done;
+    return ISM_OK;
+}
+
+extern "C" int ism_server_counters(ism_server *s, int64_t v[8])
+{
+    if (!s || !v) return ISM_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    v[0] = (int64_t)s->budget;
+    v[1] = (int64_t)s->pool.size;
+    v[2] = (int64_t)(2 * s->lanes.size() * s->slot_bytes);
+    v[3] = (int64_t)s->pool.peak;
+    v[4] = s->admission_stalls;
+    v[5] = s->taps_done;
+    v[6] = s->records_done;
+    v[7] = s->rirs_done;
     return ISM_OK;
 }
 

@@ -24,7 +24,7 @@ EXPORTS = [
     "ism_create", "ism_destroy", "ism_strerror", "ism_last_error", "ism_version", "ism_rir",
     "ism_rir_batch", "ism_batch_plan_stats", "ism_last_counts", "ism_set_tuning", "ism_get_tuning",
     "ism_autotune", "ism_set_autotune", "ism_get_launch_tuning", "ism_convolve_batch", "ism_convolve_batch_z", "ism_normal_deviates", "ism_server_create", "ism_server_destroy", "ism_server_submit",
-    "ism_server_poll", "ism_server_copy_result", "ism_server_release", "ism_server_stats", "ism_server_last_error", "ism_server_replay",
+    "ism_server_poll", "ism_server_copy_result", "ism_server_release", "ism_server_stats", "ism_server_counters", "ism_server_last_error", "ism_server_replay",
     "ism_rt_work_bytes", "ism_rir_t30", "ism_fit_beta", "ism_rt_mean_work_bytes", "ism_fit_beta_mean",
 ]
 
@@ -104,6 +104,8 @@ def load():
     L.ism_server_release.restype = ci
     L.ism_server_stats.argtypes = [vp, i64p]
     L.ism_server_stats.restype = ci
+    L.ism_server_counters.argtypes = [vp, i64p]
+    L.ism_server_counters.restype = ci
     L.ism_server_last_error.argtypes = [vp]
     L.ism_server_last_error.restype = ctypes.c_char_p
     L.ism_server_replay.argtypes = [vp, ci, vp, dp, dp, cd, cd, ci, dp, dp]
@@ -457,6 +459,13 @@ class Server:
         keys = ["submitted", "done", "batches", "max_concurrent_batches", "pool_bytes", "pool_peak_bytes",
                 "queued", "rirs_done"]
         return dict(zip(keys, [int(v) for v in st]))
+
+    def counters(self):
+        v = (ctypes.c_int64 * 8)()
+        self._check(self.lib.ism_server_counters(self.s, v))
+        keys = ["budget_bytes", "pool_bytes", "staging_bytes", "pool_peak_bytes", "admission_stalls", "taps_done",
+                "records_done", "rirs_done"]
+        return dict(zip(keys, [int(x) for x in v]))
 
     def replay(self, batch, arrival_s):
         """Submit the rooms of a scene batch at the given arrival times; returns (latencies ms, wall s)."""

@@ -82,9 +82,48 @@ def test_budget_bounds_pool_and_everything_completes(torch_cuda):
         b = scenes.pack(reqs, meta["fs"], meta["c"], meta["fd_taps"], meta["order_mode"], "c2")
         lat, wall = S.replay(b, np.cumsum(gaps) * 2e-4)
         st = S.stats()
-        sys.stdout.write(f"budget {budget} stats {st} wall {wall:.3f}s p50 {np.median(lat):.2f} ms\n")
+        cn = S.counters()
+        sys.stdout.write(f"budget {budget} stats {st} counters {cn} wall {wall:.3f}s p50 {np.median(lat):.2f} ms\n")
         assert st["done"] == 60
-        assert st["pool_peak_bytes"] <= budget
+        # the budget covers the output pool and every lane's staging slots
+        assert cn["pool_bytes"] + cn["staging_bytes"] <= budget and cn["staging_bytes"] > 0
+        assert st["pool_peak_bytes"] <= cn["pool_bytes"]
+        assert cn["admission_stalls"] > 0, "a budget of three largest outputs must make admission wait"
         assert np.all(lat > 0)
+        # served taps are the exact device counts: those of the same rooms in one batch
+        H = ism.Handle()
+        try:
+            H.rir_batch(b)
+            assert H.last_counts()["taps"] == cn["taps_done"]
+        finally:
+            H.close()
+    finally:
+        S.close()
+
+
+def test_launch_buffer_limits_the_batch(torch_cuda):
+    # a small budget gives small staging slots: batches stop growing at the slot, everything
+    # still completes, and a request whose launch buffer can never fit a slot is refused
+    reqs, gaps, meta = scenes.c2(n_requests=30, seed=7)
+    S = ism.Server(n_lanes=2, hbm_budget_bytes=16 << 20, max_batch_rooms=64)
+    try:
+        cn = S.counters()
+        assert cn["staging_bytes"] <= (16 << 20) // 4
+        b = scenes.pack(reqs, meta["fs"], meta["c"], meta["fd_taps"], meta["order_mode"], "c2")
+        lat, wall = S.replay(b, np.zeros(30))
+        st = S.stats()
+        assert st["done"] == 30 and np.all(lat > 0)
+    finally:
+        S.close()
+    S = ism.Server(n_lanes=16, hbm_budget_bytes=1 << 20, max_batch_rooms=1)
+    try:
+        # 16 lanes x 2 slots of 16 KiB; 256 microphones need more launch buffer than a slot
+        # (microphones and work items) while their 100-sample outputs fit the pool
+        L = [6.0, 5.0, 3.0]
+        g = np.stack(np.meshgrid(np.linspace(1.0, 5.0, 16), np.linspace(1.0, 4.0, 16), [1.5]), -1).reshape(-1, 3)
+        assert S.counters()["pool_bytes"] > 4 * 256 * 100
+        with pytest.raises(ism.IsmError) as e:
+            S.submit(L, [0.8] * 6, [0.5, 0.5, 2.5], g, 100, meta["fs"], meta["c"], meta["fd_taps"])
+        assert e.value.code == ism.ISM_ENOMEM
     finally:
         S.close()
