@@ -111,6 +111,23 @@ int bl_forward(ism_handle *h, const bl_model *model, int batch, int n_t, const f
                const int64_t *x_offsets, int64_t ex_stride, int64_t ch_stride, void *workspace,
                size_t workspace_bytes, float *features, float *out, ism_stream stream);
 
+/*
+ * bl_forward without allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid it).
+ * Arguments and results as for bl_forward, without the workspace: the workspace is a
+ * fixed device array of bl_noalloc_scratch_bytes() bytes (64 MiB) per GPU inside the
+ * library, held until the process ends, through which the batch passes as many frames
+ * at a time as it holds (the results equal bl_forward's bitwise).  The call allocates
+ * nothing.  Every call on one GPU shares that array: calls that overlap on a GPU (on
+ * different streams, or from different threads) race and must be serialised by the
+ * caller.  Call with the handle's device current.  ISM_EINVAL as for bl_forward, and
+ * when one frame's workspace exceeds the array (n_t above about 32 600 samples).
+ */
+size_t bl_noalloc_scratch_bytes(void);
+int bl_forward_noalloc(ism_handle *h, const bl_model *model, int batch, int n_t, const float *x,
+                       const int64_t *x_offsets, int64_t ex_stride, int64_t ch_stride, float *features,
+                       float *out, ism_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

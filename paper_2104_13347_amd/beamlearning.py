@@ -19,7 +19,8 @@ REGRESSION, CLASSIFICATION = 0, 1
 NF = 128
 MARGIN = 189
 
-EXPORTS = ["bl_param_count", "bl_model_create", "bl_model_destroy", "bl_workspace_bytes", "bl_forward"]
+EXPORTS = ["bl_param_count", "bl_model_create", "bl_model_destroy", "bl_workspace_bytes", "bl_forward",
+           "bl_noalloc_scratch_bytes", "bl_forward_noalloc"]
 
 _ready = False
 
@@ -39,6 +40,10 @@ def load():
         L.bl_workspace_bytes.restype = sz
         L.bl_forward.argtypes = [vp, vp, ci, ci, vp, vp, i64, i64, vp, sz, vp, vp, vp]
         L.bl_forward.restype = ci
+        L.bl_noalloc_scratch_bytes.argtypes = []
+        L.bl_noalloc_scratch_bytes.restype = sz
+        L.bl_forward_noalloc.argtypes = [vp, vp, ci, ci, vp, vp, i64, i64, vp, vp, vp]
+        L.bl_forward_noalloc.restype = ci
         _ready = True
     return L
 
@@ -128,10 +133,12 @@ class Model:
             raise ValueError(f"frame offsets in [{lo}, {hi}] reach past the {x.numel()} elements of x")
 
     def forward(self, x, n_t=None, batch=None, offsets=None, ex_stride=None, ch_stride=None,
-                workspace=None, features=True, out=None, stream=None):
+                workspace=None, features=True, out=None, stream=None, noalloc=False):
         """Forward pass.  x: device FP32 tensor [B, c_in, n_t] (contiguous), or any
         device FP32 tensor with explicit batch, n_t, offsets (device int64 tensor
-        or None), ex_stride and ch_stride in elements.  Returns (features or None, out)."""
+        or None), ex_stride and ch_stride in elements.  Returns (features or None, out).
+        noalloc=True calls bl_forward_noalloc (the library's fixed workspace; no
+        workspace argument)."""
         import torch
         if x.dtype != torch.float32 or not x.is_cuda:
             raise ValueError("x must be a CUDA float32 tensor")
@@ -152,13 +159,23 @@ class Model:
                                 or out.numel() < batch * self.n_out):
             raise ValueError(f"out must be a contiguous CUDA float32 tensor of at least {batch} x {self.n_out} "
                              f"elements")
+        if noalloc and workspace is not None:
+            raise ValueError("the no-allocation form takes no workspace")
         need = workspace_bytes(batch, n_t)
         with ism._on(stream):
-            if workspace is None:
+            if workspace is None and not noalloc:
                 workspace = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
             feat = torch.empty((batch, NF), dtype=torch.float32, device="cuda") if features else None
             if out is None:
                 out = torch.empty((batch, self.n_out), dtype=torch.float32, device="cuda")
+        if noalloc:
+            rc = self.lib.bl_forward_noalloc(self.handle.h, self.m, batch, n_t, ctypes.c_void_p(x.data_ptr()),
+                                             ctypes.c_void_p(offsets.data_ptr() if offsets is not None else 0),
+                                             int(ex_stride or 0), int(ch_stride or 0),
+                                             ctypes.c_void_p(feat.data_ptr() if feat is not None else 0),
+                                             ctypes.c_void_p(out.data_ptr()), ism._stream_handle(stream))
+            self.handle._check(rc)
+            return feat, out
         rc = self.lib.bl_forward(self.handle.h, self.m, batch, n_t, ctypes.c_void_p(x.data_ptr()),
                                  ctypes.c_void_p(offsets.data_ptr() if offsets is not None else 0),
                                  int(ex_stride or 0), int(ch_stride or 0), ctypes.c_void_p(workspace.data_ptr()),

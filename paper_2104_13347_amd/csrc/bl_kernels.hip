@@ -35,6 +35,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <new>
@@ -938,26 +939,13 @@ extern "C" size_t bl_workspace_bytes(int batch, int n_t)
     return ws_layout(CHUNK > 0 && batch > CHUNK ? CHUNK : batch, n_t).total;
 }
 
-extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, const float *x,
-                          const int64_t *x_offsets, int64_t ex_stride, int64_t ch_stride, void *workspace,
-                          size_t workspace_bytes, float *features, float *out, ism_stream stream)
+// The forward pass over `batch` frames, `chunk` frames per pass through the layers, with the
+// workspace laid out for `chunk` frames (arguments already checked).
+static int forward_impl(ism_handle *h, const bl_model *m, int batch, int chunk, int n_t, const float *x,
+                        const int64_t *x_offsets, int64_t ex_stride, int64_t ch_stride, void *workspace,
+                        float *features, float *out, ism_stream stream)
 {
-    if (!h) return ISM_EINVAL;
-    if (!m) { ism_set_error(h, "NULL model"); return ISM_EINVAL; }
-    if (batch < 0) { ism_set_error(h, "batch must be >= 0"); return ISM_EINVAL; }
-    if (n_t < 2 * MARGIN + 1 || n_t > MAX_NT) {
-        ism_set_error(h, "n_t must be in [%d, %d]", 2 * MARGIN + 1, MAX_NT);
-        return ISM_EINVAL;
-    }
-    if (ex_stride < 0 || ch_stride < 0) { ism_set_error(h, "strides must be >= 0"); return ISM_EINVAL; }
-    if (batch == 0) return ISM_OK;
-    if (!x || !workspace || !out) { ism_set_error(h, "NULL argument"); return ISM_EINVAL; }
-    const int chunk = CHUNK > 0 && batch > CHUNK ? CHUNK : batch;
     const WsLayout w = ws_layout(chunk, n_t);
-    if (workspace_bytes < w.total) {
-        ism_set_error(h, "workspace of %zu bytes, %zu needed", workspace_bytes, w.total);
-        return ISM_EINVAL;
-    }
     if ((int64_t)chunk * w.nst > 0x7fffffff) { ism_set_error(h, "batch too large"); return ISM_EINVAL; }
     const int ea = set_layer_lds_limits();
     if (ea != 0) return ism_hip_fail(h, (hipError_t)ea, "hipFuncSetAttribute");
@@ -1052,4 +1040,94 @@ extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, 
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ism_hip_fail(h, e, "bl_forward launch");
     return ISM_OK;
+}
+
+static int check_forward_args(ism_handle *h, const bl_model *m, int batch, int n_t, int64_t ex_stride,
+                              int64_t ch_stride)
+{
+    if (!m) { ism_set_error(h, "NULL model"); return ISM_EINVAL; }
+    if (batch < 0) { ism_set_error(h, "batch must be >= 0"); return ISM_EINVAL; }
+    if (n_t < 2 * MARGIN + 1 || n_t > MAX_NT) {
+        ism_set_error(h, "n_t must be in [%d, %d]", 2 * MARGIN + 1, MAX_NT);
+        return ISM_EINVAL;
+    }
+    if (ex_stride < 0 || ch_stride < 0) { ism_set_error(h, "strides must be >= 0"); return ISM_EINVAL; }
+    return ISM_OK;
+}
+
+extern "C" int bl_forward(ism_handle *h, const bl_model *m, int batch, int n_t, const float *x,
+                          const int64_t *x_offsets, int64_t ex_stride, int64_t ch_stride, void *workspace,
+                          size_t workspace_bytes, float *features, float *out, ism_stream stream)
+{
+    if (!h) return ISM_EINVAL;
+    int rc = check_forward_args(h, m, batch, n_t, ex_stride, ch_stride);
+    if (rc) return rc;
+    if (batch == 0) return ISM_OK;
+    if (!x || !workspace || !out) { ism_set_error(h, "NULL argument"); return ISM_EINVAL; }
+    const int chunk = CHUNK > 0 && batch > CHUNK ? CHUNK : batch;
+    const size_t need = ws_layout(chunk, n_t).total;
+    if (workspace_bytes < need) {
+        ism_set_error(h, "workspace of %zu bytes, %zu needed", workspace_bytes, need);
+        return ISM_EINVAL;
+    }
+    return forward_impl(h, m, batch, chunk, n_t, x, x_offsets, ex_stride, ch_stride, workspace, features, out,
+                        stream);
+}
+
+// ------------------------------------------------------------------ form without allocation
+// The workspace of bl_forward_noalloc: one file-scope device array per GPU, held until the
+// process ends.  Host code never passes the array's name to a kernel (in host code it is a
+// stand-in, not a device address): the entry point takes the device address of its copy
+// from hipGetSymbolAddress once per device, with that device current, and uses only that.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::atomic<void *> g_scratch_addr[kMaxDevices];
+
+static int scratch_address(ism_handle *h, void **p)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return ism_hip_fail(h, e, "hipGetDevice");
+    if (dev != h->device) {
+        ism_set_error(h, "call with the handle's device (%d) current, not %d", h->device, dev);
+        return ISM_EINVAL;
+    }
+    if (dev < 0 || dev >= kMaxDevices) { ism_set_error(h, "device index %d out of range", dev); return ISM_EINVAL; }
+    void *a = g_scratch_addr[dev].load(std::memory_order_acquire);
+    if (!a) {   // a race between threads only repeats the same query
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !a) return ism_hip_fail(h, e == hipSuccess ? hipErrorInvalidSymbol : e,
+                                                       "hipGetSymbolAddress of the workspace array");
+        g_scratch_addr[dev].store(a, std::memory_order_release);
+    }
+    *p = a;
+    return ISM_OK;
+}
+
+extern "C" size_t bl_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+extern "C" int bl_forward_noalloc(ism_handle *h, const bl_model *m, int batch, int n_t, const float *x,
+                                  const int64_t *x_offsets, int64_t ex_stride, int64_t ch_stride,
+                                  float *features, float *out, ism_stream stream)
+{
+    if (!h) return ISM_EINVAL;
+    h->last_error.clear();
+    int rc = check_forward_args(h, m, batch, n_t, ex_stride, ch_stride);
+    if (rc) return rc;
+    if (batch == 0) return ISM_OK;
+    if (!x || !out) { ism_set_error(h, "NULL argument"); return ISM_EINVAL; }
+    if (h->device < 0) { ism_set_error(h, "no HIP device"); return ISM_EDEVICE; }
+    // frames per pass: as many as the array holds (the results do not depend on it)
+    if (ws_layout(1, n_t).total > kScratchBytes) {
+        ism_set_error(h, "one frame of %d samples needs %zu bytes of workspace, more than the %zu of the "
+                      "no-allocation form (at most about %d samples)", n_t, ws_layout(1, n_t).total, kScratchBytes,
+                      (int)(kScratchBytes / ws_layout(1, 1024).total * 1024));
+        return ISM_EINVAL;
+    }
+    int chunk = (int)std::min<size_t>((size_t)batch, kScratchBytes / ws_layout(1, n_t).total);
+    while (chunk > 1 && ws_layout(chunk, n_t).total > kScratchBytes) --chunk;
+    void *ws = nullptr;
+    if ((rc = scratch_address(h, &ws))) return rc;
+    return forward_impl(h, m, batch, chunk, n_t, x, x_offsets, ex_stride, ch_stride, ws, features, out, stream);
 }
