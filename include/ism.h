@@ -140,8 +140,9 @@ int ism_version(void);
  *   max_order, order_mode: image set (see above).
  *   rir_len: samples per RIR; fd_taps: odd windowed-sinc length 2K+1 (<= 255), or
  *            8 for the 7th-order Lagrange filter (ISM_PREC_FP32 / _SPLIT only; segments of
- *            at most 1024 samples are planned for it; rooms whose RIR length needs wall
- *            exponents of 128 or more are rejected with ISM_EINVAL).
+ *            at most 1024 samples are planned for it; it runs on the moment kernel, or on
+ *            the per-tap kernel with FP32 coefficients for rooms whose RIR length needs
+ *            wall exponents of 128 or more).
  *   precision: ism_precision.
  *   out: device, M x rir_len floats, row-major, fully overwritten.
  */
@@ -242,8 +243,8 @@ int ism_get_launch_tuning(const ism_handle *h, int *seg_len, int *wg_per_cu, int
  *             (M must be 8); 0 = FP32 direct convolution on the vector units.
  *   Limits: 0 <= n_rooms <= 65535, 1 <= M <= 65535, rir_len in [1, 2^24],
  *   src_len and out_len in [1, 2^28]; otherwise ISM_EINVAL before any device work.
- *   Asynchronous on `stream`; the handle keeps a workspace (tile power sums,
- *   room table) that a later call may reuse once this call's work has finished.
+ *   Asynchronous on `stream`; the handle keeps a workspace (BF16 RIRs, tile power
+ *   sums, room table) that a later call may reuse once this call's work has finished.
  */
 int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float *rirs,
                        const int64_t *rir_offset, const int32_t *rir_len, const float *src,

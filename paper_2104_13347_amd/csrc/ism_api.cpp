@@ -528,9 +528,9 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
             h->coef_K = key;
         }
     } else if (lagrange) {
-        ism_set_error(h, "the Lagrange filter needs segments of at most %d samples and wall-exponent tables of "
-                      "at most %d entries (a room too small for its RIR length)", kMomSegMax, kPowCap);
-        return ISM_EINVAL;
+        // rooms whose wall-exponent tables exceed the moment kernel's: per-tap evaluation
+        ke = select_segment_kernel(K, VAR_LAG);
+        lds = seg_lds_bytes(plan.seg_max, K, VAR_LAG);
     } else {
         ke = select_segment_kernel(K, variant);
         lds = seg_lds_bytes(plan.seg_max, K, variant);

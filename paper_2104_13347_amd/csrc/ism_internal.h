@@ -35,7 +35,7 @@ struct alignas(16) ItemDev {
     int32_t pad[2];
 };
 
-enum Variant : int32_t { VAR_FX = 0, VAR_LUT = 1, VAR_F32ATOM = 2 };
+enum Variant : int32_t { VAR_FX = 0, VAR_LUT = 1, VAR_F32ATOM = 2, VAR_LAG = 3 };
 
 struct alignas(16) LaunchDev {
     double fs;

@@ -212,6 +212,27 @@ DEV void taps_fp32_ct(long long *acc64, float *acc32, float f, float a0, float a
     }
 }
 
+// 7th-order Lagrange interpolation on the per-tap kernel: taps k = -3..4 at n0 + k,
+// n0 = floor(tau), f = tau - n0 in [0, 1); the coefficient of node j = k + 3 at D = f + 3 is
+// prod_{i != j} (D - i) / (j - i), from prefix and suffix products of w_i = D - i (each
+// w_i = f + (3 - i) rounded once) and the node denominators prod_{i != j} (j - i).
+DEV void taps_lagrange(long long *acc64, float f, float gs)
+{
+    constexpr float inv_den[8] = {-1.0f / 5040.0f, 1.0f / 720.0f, -1.0f / 240.0f, 1.0f / 144.0f,
+                                  -1.0f / 144.0f, 1.0f / 240.0f, -1.0f / 720.0f, 1.0f / 5040.0f};
+    float w[8], pre[8], suf[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[i] = f + (float)(3 - i);
+    pre[0] = 1.0f;
+#pragma unroll
+    for (int i = 1; i < 8; ++i) pre[i] = pre[i - 1] * w[i - 1];
+    suf[7] = 1.0f;
+#pragma unroll
+    for (int i = 6; i >= 0; --i) suf[i] = suf[i + 1] * w[i + 1];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) lds_add_fx(acc64 + (j - 3), (pre[j] * suf[j]) * (inv_den[j] * gs));
+}
+
 // Runtime K: constants from an LDS table (uniform address, broadcast read).
 template <bool FX>
 DEV void taps_fp32_rt(long long *acc64, float *acc32, int K, const float2 *trig, float f, float a0, float a1,
@@ -527,13 +548,16 @@ DEV double sqrt_normal(double a)
 
 // Square root of a normal positive double to within about one ulp: the first iteration
 // and one correction of sqrt_normal (which adds a second correction for correct rounding).
-DEV double sqrt_close(double a)
+// The iteration also refines the reciprocal square root: *rinv = 2 hh = 1 / sqrt(a) to
+// about the square of the hardware estimate's relative error.
+DEV double sqrt_close(double a, double *rinv)
 {
     const double y = __builtin_amdgcn_rsq(a);
     double g = a * y, hh = y * 0.5;
     const double r = fma(-hh, g, 0.5);
     g = fma(g, r, g);
     hh = fma(hh, r, hh);
+    *rinv = hh + hh;
     const double e = fma(-g, g, a);
     return fma(e, hh, g);
 }
@@ -584,7 +608,7 @@ DEV bool image_eval(const ItemGeom &G, double rho2, int cord, int q, int w, int 
 // quotient, so n0 is the definition's everywhere.
 DEV bool image_eval_z(const ItemGeom &G, double rho2, int cord, int q, int w, double zw, int order_mode,
                       double fs, double cs, double fsc, int split32, double half, double ec, double ethr,
-                      int &n0, double &fr, double &d)
+                      int &n0, double &fr, double &d, double &rd)
 {
     bool ordok = true;
     if (G.N >= 0) {
@@ -594,7 +618,7 @@ DEV bool image_eval_z(const ItemGeom &G, double rho2, int cord, int q, int w, do
     const double Z = zw + (2.0 * (double)q) * G.Lz;
     const double dz = Z - G.rz;
     const double d2 = rho2 + dz * dz;
-    d = sqrt_close(d2);
+    d = sqrt_close(d2, &rd);
     double tau = d * fsc;
     double fl = floor(tau + half);
     fr = tau - fl;
@@ -618,6 +642,7 @@ DEV bool image_eval_z(const ItemGeom &G, double rho2, int cord, int q, int w, do
 template <int KT, int VAR>
 __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__ P)
 {
+    constexpr bool LAG = VAR == VAR_LAG;  // the Lagrange filter (K = 4, taps -3..4 about floor(tau))
     const int lane = lane_id();
     const int K = KT > 0 ? KT : P->K;
     const int seg_max = P->seg_max;
@@ -696,12 +721,14 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
             n_defer += nd;
             if (lead) {
                 // taps of this record that land in [s0, s1): n0 + k with n0 = nr + rel
-                const int lo = max(nr + rel - K, s0), hi = min(nr + rel + K, s1 - 1);
+                const int lo = max(nr + rel - (LAG ? 3 : K), s0), hi = min(nr + rel + K, s1 - 1);
                 n_taps += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
                 ++n_rec;
                 long long *a64 = S.acc64 + (nr + K);  // acc index of tap k is nr + K + k
                 float *a32 = S.acc32 + (nr + K);
-                if (VAR == VAR_LUT) {
+                if (LAG) {
+                    taps_lagrange(a64, f, g * fscale);
+                } else if (VAR == VAR_LUT) {
                     taps_lut<KT>(a64, K, S.lut, f, g * fscale);
                 } else {
                     float a0, a1, a2;
@@ -766,15 +793,15 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
                     const int w = S.iw[c * 4 + iv];
                     int n0;
                     double fr, d;
-                    valid = image_eval(G, S.crho2[c], S.cord[c], q, w, order_mode, fs, cs, fsc, split32, 0.5, n0, fr,
-                                       d);
+                    valid = image_eval(G, S.crho2[c], S.cord[c], q, w, order_mode, fs, cs, fsc, split32,
+                                       LAG ? 0.0 : 0.5, n0, fr, d);
                     if (valid) {
                         const int ez0 = min(abs(q - w), G.pmax), ezL = min(abs(q), G.pmax);
                         const double B = (S.cbxy[c] * G.pz0[ez0]) * G.pzL[ezL];
                         // g = B / (4 pi d) to FP32 accuracy
                         rg = (float)B * (0.0795774715459477f * __builtin_amdgcn_rcpf((float)d));
                         rf = (float)fr;
-                        if (rf == 0.0f) rf = 0x1p-40f;  // integer delay: exact Kronecker limit
+                        if (!LAG && rf == 0.0f) rf = 0x1p-40f;  // integer delay: exact Kronecker limit
                         rn = n0 - rel;
                     }
                 }
@@ -1192,18 +1219,17 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                 for (int k = 0; k < n; ++k) {
                     if (k >= cnt) continue;
                     int n0;
-                    double fr, d;
+                    double fr, d, rd;
                     if (image_eval_z(G, mc.rho2, mc.cord, q, w, zw, order_mode, fs, cs, fsc, split32, half, ec,
-                                     ethr, n0, fr, d)) {
+                                     ethr, n0, fr, d, rd)) {
                         const double Bg = mc.bxy * S.pzz[pz];
                         ++rec_item;
                         {   // loss += |med3(n0, tlo, thi) - n0| (both non-negative)
                             const uint32_t a = (uint32_t)min(max(n0, tlo), thi);
                             asm("v_sad_u32 %0, %1, %2, %0" : "+v"(loss_item) : "v"(a), "v"(n0));
                         }
-                        // g 2^e = B 2^e / (4 pi d) in FP64 (reciprocal with one Newton step)
-                        double rd = __builtin_amdgcn_rcp(d);
-                        rd = fma(fma(-d, rd, 1.0), rd, rd);
+                        // g 2^e = B 2^e / (4 pi d) in FP64, 1/d from the square root's iteration
+                        // (relative error far below the 2^-30 fixed-point step)
                         const double gs = Bg * rd;
                         // Chebyshev variable: x = 2f for f in [-1/2, 1/2) (sinc), 2f - 1 for f in [0, 1)
                         const double xx = fma(2.0, fr, -xoff), x2 = xx + xx;
@@ -1427,6 +1453,7 @@ struct KernelEntry { LaunchFn fn; const void *sym; };
 
 KernelEntry select_segment_kernel(int K, int variant)
 {
+    if (variant == VAR_LAG) return {launch_t<4, VAR_LAG>, sym_t<4, VAR_LAG>()};
 #define ISM_CASE(KK)                                                                      \
     if (K == KK) {                                                                        \
         if (variant == VAR_LUT) return {launch_t<KK, VAR_LUT>, sym_t<KK, VAR_LUT>()};      \

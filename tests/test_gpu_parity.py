@@ -305,17 +305,47 @@ def test_paper_room_dataset_sources(H):
         assert cnt["taps"] == ntaps
 
 
-def test_long_rir_in_a_thin_room_uses_the_per_tap_kernel(H, torch_cuda):
+@pytest.mark.parametrize("fd_taps", [81, 8])
+def test_long_rir_in_a_thin_room_uses_the_per_tap_kernel(H, torch_cuda, fd_taps):
     # wall exponents up to about 130 (a 0.3 m room height, 3500 samples): the moment kernel
-    # holds at most 128 in LDS, so the windowed sinc falls back to the per-tap kernel and the
-    # Lagrange filter, which has no per-tap kernel, is refused
+    # holds at most 128 in LDS, so both the windowed sinc and the paper's Lagrange filter
+    # fall back to the per-tap kernel
     torch = torch_cuda
-    L, beta, s, m = [3.0, 3.0, 0.3], [0.6] * 6, [1.0, 1.2, 0.1], [[2.1, 1.7, 0.2]]
-    out = H.rir(L, beta, s, m, 16000.0, 343.0, -1, 3500, 81)
+    L, beta, s, m = [3.0, 3.0, 0.3], [0.6] * 6, [1.0, 1.2, 0.1], [[2.1, 1.7, 0.2], [0.4, 2.6, 0.15]]
+    out = H.rir(L, beta, s, m, 16000.0, 343.0, -1, 3500, fd_taps)
     torch.cuda.synchronize()
-    ref, st = oracle.rir(L, beta, s, m[0], 16000.0, 343.0, -1, 0, 3500, 81)
+    got = out.cpu().numpy()
+    taps = 0
+    for k in range(2):
+        ref, st = oracle.rir(L, beta, s, m[k], 16000.0, 343.0, -1, 0, 3500, fd_taps)
+        taps += st["taps"]
+        err = np.max(np.abs(got[k] - ref)) / np.max(np.abs(ref))
+        _say(f"thin room fd_taps {fd_taps} mic {k}: err {err:.2e}")
+        assert err <= TOL_FP32
+    assert H.last_counts()["taps"] == taps
+
+
+def test_lagrange_per_tap_kernel_tiny_rooms_and_kronecker(H, torch_cuda):
+    # the per-tap Lagrange path on thin tiny rooms (every tap of the image sum against the
+    # oracle) and an integer delay (the Kronecker impulse: one tap of weight g)
+    torch = torch_cuda
+    rng = np.random.default_rng(44)
+    for i in range(3):
+        L = [rng.uniform(1.0, 2.0), rng.uniform(1.0, 2.0), rng.uniform(0.12, 0.2)]
+        beta = list(rng.uniform(0.3, 0.9, 6))
+        s = [L[0] * 0.3, L[1] * 0.6, L[2] * 0.4]
+        m = [[L[0] * 0.7, L[1] * 0.2, L[2] * 0.7]]
+        n = 2600
+        out = H.rir(L, beta, s, m, 16000.0, 343.0, -1, n, 8)
+        torch.cuda.synchronize()
+        ref, st = oracle.rir(L, beta, s, m[0], 16000.0, 343.0, -1, 0, n, 8)
+        err = np.max(np.abs(out.cpu().numpy()[0] - ref)) / np.max(np.abs(ref))
+        _say(f"thin tiny room {i}: err {err:.2e}, taps {st['taps']}")
+        assert err <= TOL_FP32 and H.last_counts()["taps"] == st["taps"]
+    # Kronecker: beta 0, integer delay tau = 1 (s = (1,1,1), r = (1,1,3.5), c = 340, fs = 136),
+    # in a room thin enough in x for the per-tap kernel (the direct path is the only image)
+    out = H.rir([0.05, 2.0, 4.0], [0.0] * 6, [0.025, 1.0, 1.0], [[0.025, 1.0, 3.5]], 136.0, 340.0, -1, 4, 8)
+    torch.cuda.synchronize()
     got = out.cpu().numpy()[0]
-    assert np.max(np.abs(got - ref)) <= TOL_FP32 * np.max(np.abs(ref))
-    assert H.last_counts()["taps"] == st["taps"]
-    with pytest.raises(ism.IsmError):
-        H.rir(L, beta, s, m, 16000.0, 343.0, -1, 3500, 8)
+    g = 1.0 / (4.0 * math.pi * 2.5)
+    assert abs(got[1] - g) <= 1e-6 * g and np.max(np.abs(np.delete(got, 1))) <= 1e-6 * g
