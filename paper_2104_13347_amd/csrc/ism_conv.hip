@@ -414,34 +414,60 @@ DEV float room_sigma(const double *__restrict__ psum, int r, int n_parts, int64_
     return (float)sqrt(P * pow(10.0, -(double)snr_db / 10.0));
 }
 
-// grid (chunks, rooms): y += sigma_r z with z drawn here (one Philox call per 4 samples)
+// grid (chunks, rooms): y += sigma_r z with z drawn here (one Philox call per 4 samples).
+// Each thread takes kNoiseQ groups of 4 samples per pass: their loads are issued first, the
+// deviates computed while they are in flight, and the room's sigma (thread 0) is awaited
+// only before the stores.
+constexpr int kNoiseQ = 4;
 __global__ __launch_bounds__(256) void conv_noise_seeded(float *__restrict__ y, const double *__restrict__ psum,
                                                          const ConvRoom *__restrict__ rooms, int n_parts, int M,
                                                          int out_len, uint32_t k0, uint32_t k1)
 {
     const int r = blockIdx.y;
     __shared__ float sigma_s;
-    if (threadIdx.x == 0) sigma_s = room_sigma(psum, r, n_parts, (int64_t)M * out_len, rooms[r].snr_db);
-    __syncthreads();
-    const float sg = sigma_s;
     const int nq = (out_len + 3) >> 2;
+    const int64_t nall = (int64_t)M * nq;
     float *yr = y + (int64_t)r * M * out_len;
     const bool vec = (out_len & 3) == 0 && ((uintptr_t)y & 15) == 0;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)M * nq;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int m = (int)(t / nq), j = (int)(t - (int64_t)m * nq);
-        const float4 d = deviates4((uint32_t)j, (uint32_t)m, (uint32_t)r, k0, k1);
-        float *p = yr + (int64_t)m * out_len + 4 * j;
-        if (vec) {
-            float4 v = *(float4 *)p;
-            v.x = fmaf(sg, d.x, v.x);
-            v.y = fmaf(sg, d.y, v.y);
-            v.z = fmaf(sg, d.z, v.z);
-            v.w = fmaf(sg, d.w, v.w);
-            *(float4 *)p = v;
-        } else {
-            const float e[4] = {d.x, d.y, d.z, d.w};
-            for (int q = 0; q < 4 && 4 * j + q < out_len; ++q) p[q] = fmaf(sg, e[q], p[q]);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool have_sigma = false;
+    float sg = 0.0f;
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t0 - (int64_t)threadIdx.x < nall;
+         t0 += stride * kNoiseQ) {
+        float4 v[kNoiseQ], d[kNoiseQ];
+        float *pq[kNoiseQ];
+        int jq[kNoiseQ];
+#pragma unroll
+        for (int u = 0; u < kNoiseQ; ++u) {
+            const int64_t t = t0 + u * stride;
+            const int64_t tc = t < nall ? t : nall - 1;   // clamped: always a valid group
+            const int m = (int)(tc / nq), j = (int)(tc - (int64_t)m * nq);
+            jq[u] = t < nall ? j : -1;
+            pq[u] = yr + (int64_t)m * out_len + 4 * j;
+            if (vec) v[u] = *(const float4 *)pq[u];
+            d[u] = deviates4((uint32_t)j, (uint32_t)m, (uint32_t)r, k0, k1);
+        }
+        if (!have_sigma) {   // once per block, after its first loads are in flight
+            if (threadIdx.x == 0) sigma_s = room_sigma(psum, r, n_parts, (int64_t)M * out_len, rooms[r].snr_db);
+            __syncthreads();
+            sg = sigma_s;
+            have_sigma = true;
+        }
+#pragma unroll
+        for (int u = 0; u < kNoiseQ; ++u) {
+            if (jq[u] < 0) continue;
+            float *p = pq[u];
+            if (vec) {
+                float4 w = v[u];
+                w.x = fmaf(sg, d[u].x, w.x);
+                w.y = fmaf(sg, d[u].y, w.y);
+                w.z = fmaf(sg, d[u].z, w.z);
+                w.w = fmaf(sg, d[u].w, w.w);
+                *(float4 *)p = w;
+            } else {
+                const float e[4] = {d[u].x, d[u].y, d[u].z, d[u].w};
+                for (int q = 0; q < 4 && 4 * jq[u] + q < out_len; ++q) p[q] = fmaf(sg, e[q], p[q]);
+            }
         }
     }
 }
@@ -600,7 +626,7 @@ static int convolve_impl(ism_handle *h, int n_rooms, int M, const float *rirs, c
     }
     if (snr_db && seeded) {
         const int64_t quads = (int64_t)M * ((out_len + 3) / 4);
-        const int chunks = (int)std::min<int64_t>(256, (quads + 255) / 256);
+        const int chunks = (int)std::min<int64_t>(256, (quads + 256 * kNoiseQ - 1) / (256 * kNoiseQ));
         hipLaunchKernelGGL(conv_noise_seeded, dim3(chunks, n_rooms), dim3(256), 0, q, out, ps, rm, (int)n_parts, M,
                            out_len, (uint32_t)noise_seed, (uint32_t)(noise_seed >> 32));
         if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_noise_seeded launch");
