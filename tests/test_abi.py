@@ -139,6 +139,25 @@ def test_paper_room_scene_geometry():
     assert b["rir_len"][0] == 8000 and b["fd_taps"] == 8 and len(b["rir_len"]) == 2000
 
 
+def test_second_paper_room_scene_geometry():
+    # 5 x 5 x 4 m, the array centred at (2.5, 2.5, 1.5) m, the torus of radius 2 +- 0.5 m and
+    # +-7 degrees, positions at least 0.1 m from every wall (the torus reaches them on the axes)
+    b = scenes.paper_room2(n_sources=3000, seed=6)
+    L, c = np.array([5.0, 5.0, 4.0]), np.array([2.5, 2.5, 1.5])
+    src = b["src"]
+    assert len(src) == 3000 and np.allclose(b["L"], L)
+    assert np.all(src > 0.1) and np.all(src < L - 0.1)
+    r = np.linalg.norm(src - c, axis=1)
+    assert r.min() >= 1.5 and r.max() <= 2.5
+    elev = np.degrees(np.arcsin((src[:, 2] - c[2]) / r))
+    assert np.abs(elev).max() <= 7.0 + 1e-9
+    assert np.allclose(b["mics"][0], c) and b["n_mics"][0] == 7
+    assert b["rir_len"][0] == 8000 and b["fd_taps"] == 8
+    # Sabine's coefficient for RT 0.5 s unless a fitted one is passed
+    assert 0.8 < b["beta"][0][0] < 0.9
+    assert scenes.paper_room2(n_sources=1, beta=0.8)["beta"][0][0] == 0.8
+
+
 def test_room_too_small_for_its_rir_length_is_rejected(handle):
     # image columns past the kernels' 32-bit indexing: a 1 cm room with a 10 s RIR
     assert _call(handle, L=[0.01, 0.01, 0.01], src=[0.005, 0.005, 0.005], mics=[[0.002, 0.002, 0.002]],
