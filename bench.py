@@ -158,8 +158,12 @@ def bench_c3(H, torch, with_errors=True):
     if with_errors:
         import oracle
         ref = np.zeros(int(b["out_size"]))
-        oracle.rir_list(b, sample, out=ref)
+        t = time.perf_counter()
+        _, otaps = oracle.rir_list(b, sample, out=ref)
+        dt = time.perf_counter() - t
         res["error_sample"] = "all 16 mics of rooms 0 and 37 (32 RIRs), FP64 oracle"
+        res["cpu_oracle_on_sample"] = {"taps_per_s": otaps / dt, "rirs_per_s": len(sample) / dt, "s": dt,
+                                       "cores": os.cpu_count() or 1}
     bars = {"fp32": 1e-5, "fp32_direct": 1e-5, "fp16_lut": 2e-3, "fp32_split": None}
     for prec, name in [(ism.PREC_FP32, "fp32"), (ism.PREC_FP32_DIRECT, "fp32_direct"), (ism.PREC_FP16_LUT, "fp16_lut"),
                        (ism.PREC_FP32_SPLIT, "fp32_split")]:
@@ -196,9 +200,11 @@ def bench_paper(H, torch):
     return res
 
 
-def bench_c4(H, torch):
+def bench_c4(H, torch, with_errors=True):
     """256 rooms (1024-room distribution, seed 2108), 8 mics: RIR batch on the GPU, then convolution
-    with 1 s white-noise sources and sensor noise at SNR U[0,30] dB."""
+    with 1 s white-noise sources and sensor noise at SNR U[0,30] dB.  With errors: the noisy
+    recordings of rooms 0, 128 and 255 against the FP64 oracle's convolution of the same GPU RIRs
+    plus the oracle's own deviates for the same seed (relative RMS per room, both paths)."""
     from paper_2104_13347_amd import ism, scenes
     b = scenes.c4(with_z=False)
     rooms = ism.rooms_array(b)
@@ -225,6 +231,20 @@ def bench_c4(H, torch):
         res[name] = {"ms_with_noise": ms, "ms_convolution_only": ms_clean, "tflops": tf,
                      "peak_tflops": peak, "frac": tf / peak,
                      "path_tflops": flops / (ms / 1e3) / 1e12, "path_frac": flops / (ms / 1e3) / 1e12 / peak}
+        if with_errors:
+            import oracle
+            from oracle import noise
+            H.convolve_batch(rirs, offs, lens, 8, x, 16000, snr_db=b["snr_db"], noise_seed=seed, use_mfma=mfma, out=y)
+            got, hr = y.cpu().numpy(), rirs.cpu().numpy()
+            errs = []
+            for r in (0, 128, 255):
+                L = int(lens[r])
+                h = hr[offs[r]:offs[r] + 8 * L].reshape(8, L).astype(np.float64)
+                ref = oracle.conv_room(h, b["x"][r].astype(np.float64), 16000, snr_db=float(b["snr_db"][r]),
+                                       z=noise.deviates(seed, r, 8, 16000))
+                errs.append(float(np.sqrt(np.mean((got[r] - ref) ** 2) / np.mean(ref ** 2))))
+            res[name]["rel_rms_err"] = {"rooms": [0, 128, 255], "values": errs,
+                                        "bar": 1e-2 if mfma else None}
     res["noise_pass_ms"] = res["bf16_mfma"]["ms_with_noise"] - res["bf16_mfma"]["ms_convolution_only"]
 
     def pipeline():   # RIRs, convolution and device-drawn noise
@@ -590,13 +610,22 @@ def main():
     if lat:
         res["latency_ms_single_rir"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                                         "workload": "5x4x3 m room, index-L1 order 10, 1 mic, 4096 samples"}
+        if not args.no_cpu_baseline:   # the same RIR by the FP64 oracle on one host core, and its error
+            import oracle
+            t = time.perf_counter()
+            ref, st = oracle.rir(c0["L"][0], c0["beta"][0], c0["src"][0], c0["mics"][0], c0["fs"], c0["c"], 10, 0,
+                                 4096, 81)
+            dt = time.perf_counter() - t
+            o1h = o1.cpu().numpy()[0].astype(np.float64)
+            res["latency_ms_single_rir"]["cpu_oracle_ms_one_core"] = dt * 1e3
+            res["latency_ms_single_rir"]["max_err_over_peak"] = float(np.abs(o1h - ref).max() / np.abs(ref).max())
     extras = set() if args.no_extras else {e.strip() for e in args.extras.split(",") if e.strip()}
     if extras:
         res["extras"] = {}
         if "c3" in extras:
             res["extras"]["c3_precision"] = bench_c3(H, torch, with_errors=not args.no_cpu_baseline)
         if "c4" in extras:
-            res["extras"]["c4_convolution"] = bench_c4(H, torch)
+            res["extras"]["c4_convolution"] = bench_c4(H, torch, with_errors=not args.no_cpu_baseline)
         if "paper" in extras:
             res["extras"]["paper_room1_dataset"] = bench_paper(H, torch)
         if "c2" in extras:
