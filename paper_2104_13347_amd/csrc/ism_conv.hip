@@ -93,23 +93,25 @@ __global__ void conv_pack_h(const float *__restrict__ rirs, const ConvRoom *__re
 // grid (tiles, rooms), one wave.  LDS: a 128-sample source ring (BF16, reversed,
 // stored twice so that any 10-sample window is contiguous) and a 16-slot RIR ring.
 constexpr int XR = 128;   // source ring length (samples)
-constexpr int CRS = 40;   // RIR ring row stride (u16): 80 B rows keep the eight microphones' 16-B
-                          // reads of one step on eight different bank groups
+constexpr int kBufWord3 = 0x00020000;   // buffer descriptor word 3 (gfx9 family: raw 32-bit data)
+// RIR ring: two halves (taps 0-15 and 16-31 of a block), each 128 rows (16 slots x 8
+// microphones) of two 16-byte chunks.  Chunk c of the row of block b sits at position
+// c ^ ((b >> 2) & 1): the 16 rows that 16 lanes of a read instruction touch (blocks b and
+// b + 4, 8 microphones each) fill all 16 chunk positions of 256 bytes, so the reads have no
+// bank conflicts and the ring needs no padding.
+constexpr int CRH = 16 * CM * 16;   // one half (u16)
+DEV int ring_pos(int b, int m, int c) { return ((b & 15) * CM + m) * 16 + 8 * (c ^ ((b >> 2) & 1)); }
 
-#ifndef CONV_PD
-#define CONV_PD 4  // steps of global prefetch (a multiple of 4: the source-ring entries repeat every 4 steps)
-#endif
-#ifndef CONV_MIN_WAVES
-#define CONV_MIN_WAVES 4
-#endif
-__global__ __launch_bounds__(64, CONV_MIN_WAVES) void conv_mfma(const float *__restrict__ x, int src_len, int out_len,
+// Registers for 3 waves per SIMD (at most 168 VGPRs): the software pipeline keeps two steps'
+// operands live (accumulators 64, B operands 32 + 8, A operands 2 x 8, prefetch queue 12).
+__global__ __launch_bounds__(64, 3) void conv_mfma(const float *__restrict__ x, int src_len, int out_len,
                                                 const uint16_t *__restrict__ hb,
                                                 const ConvRoom *__restrict__ rooms,
                                                 float *__restrict__ y, double *__restrict__ psum,
                                                 int tiles_per_room)
 {
     __shared__ __attribute__((aligned(16))) uint16_t xring[2 * XR];
-    __shared__ __attribute__((aligned(16))) uint16_t ring[16 * CM * CRS];
+    __shared__ __attribute__((aligned(16))) uint16_t ring[2 * CRH];
     const int lane = threadIdx.x;
     // Workgroups are dealt to the 8 XCDs round-robin in launch order, and each XCD has
     // its own L2.  With the room count a multiple of 8, the k-th workgroup on XCD x takes
@@ -126,23 +128,28 @@ __global__ __launch_bounds__(64, CONV_MIN_WAVES) void conv_mfma(const float *__r
     const int t0 = tile * CG;
     const ConvRoom R = rooms[r];
     const int nb = R.nb;
-    const int s_start = max(0, t0 - nb + 1);
     const int s_end = t0 + CG - 1;
-    const float *xs = x + (int64_t)r * src_len;
-    const uint16_t *hr = hb + R.h_off;
-    // Global loads use clamped (always valid) addresses and keep the raw value; the zero
-    // outside the signal is applied when the value is written to LDS, so no load has to
-    // complete before the step that consumes it.
+    // Steps s_start .. s_end, with s_start moved down so that s_end - s_start is a multiple
+    // of 4 (whole groups below; up to 3 extra steps, whose source samples before 0 or RIR
+    // blocks past nb read as zeros).
+    const int s_start = s_end - 4 * ((s_end - max(0, t0 - nb + 1) + 3) / 4);
+    // The source and the RIR blocks of the room are read through buffer descriptors: a read
+    // outside the buffer returns zero, which is the zero padding of both signals (samples
+    // before 0 or past the end, blocks outside [0, nb)), with no clamp or select.
+    const __amdgpu_buffer_rsrc_t xrs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(x + (int64_t)r * src_len), (short)0, src_len * 4, kBufWord3);
+    const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(hb + R.h_off), (short)0, CM * nb * CB * 2, kBufWord3);
     auto load_x = [&](int sb) -> float {           // lane covers sample 32 sb + lane % 32
-        const int X = CB * sb + (lane & 31);
-        return xs[min(max(X, 0), src_len - 1)];
+        const int X = CB * sb + (lane & 31);    // X < 0: a byte offset of 2^32 - 4|X|, outside
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xrs, X * 4, 0, 0));
     };
     // source ring: sample X sits at (-X) mod 128 and again 128 entries later, so that any
     // 8 consecutive samples read downwards in time are contiguous
     auto store_x = [&](int sb, float v) {
         if (lane < 32) {
             const int X = CB * sb + lane;
-            const uint16_t bv = (X >= 0 && X < src_len) ? f2bf(v) : (uint16_t)0;
+            const uint16_t bv = f2bf(v);
             const int p = (-X) & (XR - 1);
             xring[p] = bv;
             xring[p + XR] = bv;
@@ -150,13 +157,15 @@ __global__ __launch_bounds__(64, CONV_MIN_WAVES) void conv_mfma(const float *__r
     };
     // RIR ring: slot (b & 15) holds block b of all microphones (zeros outside [0, nb));
     // lane covers 4 taps: mic = lane / 8, taps (lane % 8) * 4 .. + 3
+    const int hlane = ((lane >> 3) * nb * CB + (lane & 7) * 4) * 2;   // byte offset in block 0
     auto load_block = [&](int b) -> uint2 {
-        const int bc = min(max(b, 0), nb - 1);
-        return *(const uint2 *)(hr + (int64_t)(lane >> 3) * nb * CB + (int64_t)bc * CB + (lane & 7) * 4);
+        const int off = (b >= 0 && b < nb) ? b * CB * 2 : (1 << 30);   // (1 << 30): outside
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(hrs, hlane + off, 0, 0);
+        return make_uint2(v[0], v[1]);
     };
     auto store_block = [&](int b, uint2 v) {
-        if (b < 0 || b >= nb) v = make_uint2(0u, 0u);
-        *(uint2 *)(ring + ((b & 15) * CM + (lane >> 3)) * CRS + (lane & 7) * 4) = v;
+        const int k = (lane & 7) * 4;   // first tap
+        *(uint2 *)(ring + (k >> 4) * CRH + ring_pos(b, lane >> 3, (k >> 3) & 1) + (k & 7)) = v;
     };
     {
         float x0[3];
@@ -171,7 +180,7 @@ __global__ __launch_bounds__(64, CONV_MIN_WAVES) void conv_mfma(const float *__r
         for (int tl = 0; tl < CG; ++tl) store_block(t0 - s_start + tl, h0[tl]);
     }
     // prefetch queue: the blocks entering the rings at step u sit in slot (u - s_start - 1) % PD
-    constexpr int PD = CONV_PD;
+    constexpr int PD = 4;   // steps of global prefetch (one lap of the source ring)
     float xq[PD];
     uint2 hq[PD];
 #pragma unroll
@@ -193,8 +202,21 @@ __global__ __launch_bounds__(64, CONV_MIN_WAVES) void conv_mfma(const float *__r
     // fragments of T_s are x[X - e], X = 32 s + i - 16 ks - kk0, e = 0..7: ring entry
     // p = (-X) mod 128 for ks = 0 and p + 16 for ks = 1 (the ring is stored twice, so no
     // wrap); read as the dwords w = p / 2 .. w + 4 and realigned by 16 (p mod 2) bits.
-    auto step = [&](int s, int w, uint32_t sh) {
-        bf16x8_t a[2];
+    // B operand: column i of MFMA tile nt is output block tl = 4 (i / 8) + nt of microphone
+    // i % 8, so from one step to the next the operand of tile nt is the previous step's
+    // operand of tile nt - 1 (the same registers): each step reads only tile 0's operand,
+    // blocks t0 - s + 0, 4, 8, 12, from the ring.  bq slot (nt - ph) mod 4 holds tile nt's
+    // operand at phase ph = (s - s_start) mod 4 (a constant in the unrolled loop).
+    u32x4_t bq[2][4];
+    auto read_b = [&](int s, int nt, u32x4_t &b0, u32x4_t &b1) {
+        const int b = t0 + (i >> 3) * 4 + nt - s;
+        const uint16_t *bp = ring + ring_pos(b, i & 7, kk0 >> 3);
+        b0 = *(const u32x4_t *)bp;
+        b1 = *(const u32x4_t *)(bp + CRH);
+    };
+    // A operand of step s: the Toeplitz fragments read from the source ring at dword w,
+    // realigned by sh bits
+    auto read_a = [&](int w, uint32_t sh, bf16x8_t (&a)[2]) {
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
             uint32_t d[5];
@@ -205,22 +227,15 @@ __global__ __launch_bounds__(64, CONV_MIN_WAVES) void conv_mfma(const float *__r
             for (int k = 0; k < 4; ++k) v[k] = __builtin_amdgcn_alignbit(d[k + 1], d[k], sh);
             a[ks] = __builtin_bit_cast(bf16x8_t, v);
         }
-        u32x4_t bv[2][4];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int tl = nt * 4 + (i >> 3), m = i & 7;
-            const int b = t0 + tl - s;
-            const uint16_t *bp = ring + ((b & 15) * CM + m) * CRS + kk0;
-            bv[0][nt] = *(const u32x4_t *)bp;
-            bv[1][nt] = *(const u32x4_t *)(bp + 16);
-        }
-        // K step outermost: the four tiles' MFMAs are independent of each other
+    };
+    // the products of one step; K step outermost: the four tiles' MFMAs are independent
+    auto mma = [&](const bf16x8_t (&a)[2], int ph) {
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
-                acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], __builtin_bit_cast(bf16x8_t, bv[ks][nt]),
-                                                                   acc[nt], 0, 0, 0);
+                acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    a[ks], __builtin_bit_cast(bf16x8_t, bq[ks][(nt - ph) & 3]), acc[nt], 0, 0, 0);
     };
     auto ring_entry = [&](int s) { return (-(CB * s + i - kk0)) & (XR - 1); };
     // Step u = s_start + 1 + 4 k + j enters source block u at ring entry (-32 u - lane) mod 128
@@ -230,39 +245,49 @@ __global__ __launch_bounds__(64, CONV_MIN_WAVES) void conv_mfma(const float *__r
     int pj[PD];
 #pragma unroll
     for (int j = 0; j < PD; ++j) pj[j] = ring_entry(s_start + 1 + j);
+    // Software pipeline: step u's ring entries are written and its operands read before the
+    // products of step u - 1 are issued, so the LDS reads run under those products.
+    bf16x8_t a_cur[2];
     auto advance = [&](int u, int j) {
-        __syncthreads();   // the previous step's ring reads precede these writes
+        __syncthreads();   // the ring reads of step u - 1 precede these writes
         store_block(t0 - u, hq[j]);
         if (lane < 32) {
-            const int X = CB * u + lane;
-            const uint16_t bv = (X >= 0 && X < src_len) ? f2bf(xq[j]) : (uint16_t)0;
+            const uint16_t bv = f2bf(xq[j]);
             xring[pj[j]] = bv;
             xring[pj[j] + XR] = bv;
         }
         hq[j] = load_block(t0 - u - PD);
         xq[j] = load_x(u + PD);
         __syncthreads();
-        step(u, pj[j] >> 1, (uint32_t)(pj[j] & 1) * 16u);
+        bf16x8_t a_nx[2];
+        u32x4_t bn0, bn1;
+        read_a(pj[j] >> 1, (uint32_t)(pj[j] & 1) * 16u, a_nx);
+        read_b(u, 0, bn0, bn1);
+        mma(a_cur, j & 3);   // step u - 1: (u - 1 - s_start) mod 4 = j mod 4
+        const int sl = (-(1 + j)) & 3;   // tile 0's slot at step u
+        bq[0][sl] = bn0;
+        bq[1][sl] = bn1;
+        a_cur[0] = a_nx[0];
+        a_cur[1] = a_nx[1];
     };
     {
         const int p0 = ring_entry(s_start);
-        step(s_start, p0 >> 1, (uint32_t)(p0 & 1) * 16u);
+        read_a(p0 >> 1, (uint32_t)(p0 & 1) * 16u, a_cur);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) read_b(s_start, nt, bq[0][nt], bq[1][nt]);
     }
-    int u0 = s_start + 1;
-    for (; u0 + PD - 1 <= s_end; u0 += PD) {   // whole groups: no branch inside
+    for (int u0 = s_start + 1; u0 <= s_end; u0 += PD) {
 #pragma unroll
         for (int j = 0; j < PD; ++j) advance(u0 + j, j);
     }
-#pragma unroll
-    for (int j = 0; j < PD - 1; ++j)
-        if (u0 + j <= s_end) advance(u0 + j, j);
+    mma(a_cur, 0);   // step s_end: (s_end - s_start) mod 4 = 0
 
     // store: register q of tile nt holds row 8 (q / 4) + 4 (lane / 32) + (q % 4), column lane % 32
     double pw = 0.0;
     float *yr = y + (int64_t)r * CM * out_len;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        const int tl = nt * 4 + (i >> 3), m = i & 7;
+        const int tl = (i >> 3) * 4 + nt, m = i & 7;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int row = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
