@@ -243,8 +243,10 @@ int ism_get_launch_tuning(const ism_handle *h, int *seg_len, int *wg_per_cu, int
  *             (M must be 8); 0 = FP32 direct convolution on the vector units.
  *   Limits: 0 <= n_rooms <= 65535, 1 <= M <= 65535, rir_len in [1, 2^24],
  *   src_len and out_len in [1, 2^28]; otherwise ISM_EINVAL before any device work.
- *   Asynchronous on `stream`; the handle keeps a workspace (BF16 RIRs, tile power
- *   sums, room table) that a later call may reuse once this call's work has finished.
+ *   Asynchronous on `stream`.  The handle keeps two workspaces (BF16 RIRs, tile power
+ *   sums, room table) used by alternate calls: a call waits on the host only for the
+ *   work of the call before the previous one, so back-to-back calls overlap their host
+ *   work with the device work of the last.
  */
 int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float *rirs,
                        const int64_t *rir_offset, const int32_t *rir_len, const float *src,

@@ -49,20 +49,34 @@ struct alignas(16) ConvRoom {
     float snr_db;
     int32_t order;     // grid row j of the convolution kernels takes room rooms[j].order
                        // (rooms by decreasing RIR length, so the longest start first)
+    double nscale;     // 10^(-snr_db / 10), FP64, from the host
 };
 
-struct ConvState {
+// Two slots used in turn: a call waits only for the call before the previous one, so the
+// host work of a call (room table, upload, launches) overlaps the kernels of the last.
+struct ConvSlot {
     void *ws = nullptr;       // device: BF16 RIRs | tile power sums | room table
     size_t cap = 0;
     void *stage = nullptr;    // pinned staging for the room table
     size_t stage_cap = 0;
-    hipEvent_t ev = nullptr;  // end of the last launch that read the staging buffer
+    hipEvent_t ev = nullptr;  // end of the last call's kernels that used this slot
     bool used = false;
+};
+struct ConvState {
+    ConvSlot slot[2];
+    int next = 0;
 };
 
 constexpr int CB = 32;            // block length (samples / taps)
-constexpr int CG = 16;            // output blocks per MFMA workgroup
-constexpr int CTILE = CB * CG;    // 512 output samples per workgroup
+#ifndef CONV_CG
+#define CONV_CG 16
+#endif
+constexpr int CG = CONV_CG;       // output blocks per MFMA workgroup
+constexpr int CTILE = CB * CG;    // output samples per workgroup
+constexpr int NT = CG / 4;        // 32-column MFMA tiles per workgroup (4 blocks x 8 microphones)
+constexpr int LNT = NT == 2 ? 1 : NT == 4 ? 2 : 3;
+constexpr int UN = NT > 4 ? NT : 4;   // steps per loop group: a multiple of NT and of 4
+static_assert(NT == 2 || NT == 4 || NT == 8, "CG must be 8, 16 or 32");
 constexpr int CM = 8;             // microphones per room on the MFMA path
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
@@ -77,16 +91,27 @@ DEV uint16_t f2bf(float f)
 }
 
 // ------------------------------------------------------------------ RIRs -> padded BF16
-__global__ void conv_pack_h(const float *__restrict__ rirs, const ConvRoom *__restrict__ rooms, int M,
-                            uint16_t *__restrict__ hb)
+// grid (chunks, rooms, M), 256 threads of 4 consecutive taps each (one 8-byte store; a
+// microphone's padded row starts 64-byte aligned)
+__global__ __launch_bounds__(256) void conv_pack_h(const float *__restrict__ rirs,
+                                                   const ConvRoom *__restrict__ rooms, int M,
+                                                   uint16_t *__restrict__ hb)
 {
     const int r = blockIdx.y, m = blockIdx.z;
     const ConvRoom R = rooms[r];
     const int n = R.nb * CB;
     const float *src = rirs + R.rir_off + (int64_t)m * R.rir_len;
     uint16_t *dst = hb + R.h_off + (int64_t)m * n;
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
-        dst[j] = j < R.rir_len ? f2bf(src[j]) : (uint16_t)0;
+    for (int j = 4 * (blockIdx.x * blockDim.x + threadIdx.x); j < n; j += 4 * gridDim.x * blockDim.x) {
+        uint32_t w[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const uint32_t lo = j + 2 * q < R.rir_len ? f2bf(src[j + 2 * q]) : 0u;
+            const uint32_t hi = j + 2 * q + 1 < R.rir_len ? f2bf(src[j + 2 * q + 1]) : 0u;
+            w[q] = lo | (hi << 16);
+        }
+        *(uint2 *)(dst + j) = make_uint2(w[0], w[1]);
+    }
 }
 
 // ------------------------------------------------------------------ MFMA block-Toeplitz
@@ -96,15 +121,18 @@ constexpr int XR = 128;   // source ring length (samples)
 constexpr int kBufWord3 = 0x00020000;   // buffer descriptor word 3 (gfx9 family: raw 32-bit data)
 // RIR ring: two halves (taps 0-15 and 16-31 of a block), each 128 rows (16 slots x 8
 // microphones) of two 16-byte chunks.  Chunk c of the row of block b sits at position
-// c ^ ((b >> 2) & 1): the 16 rows that 16 lanes of a read instruction touch (blocks b and
-// b + 4, 8 microphones each) fill all 16 chunk positions of 256 bytes, so the reads have no
+// c ^ ((b / NT) & 1): the 16 rows that 16 lanes of a read instruction touch (blocks b and
+// b + NT, 8 microphones each) fill all 16 chunk positions of 256 bytes, so the reads have no
 // bank conflicts and the ring needs no padding.
-constexpr int CRH = 16 * CM * 16;   // one half (u16)
-DEV int ring_pos(int b, int m, int c) { return ((b & 15) * CM + m) * 16 + 8 * (c ^ ((b >> 2) & 1)); }
+constexpr int CRH = CG * CM * 16;   // one half (u16): CG slots
+DEV int ring_pos(int b, int m, int c) { return ((b & (CG - 1)) * CM + m) * 16 + 8 * (c ^ ((b >> LNT) & 1)); }
 
-// Registers for 3 waves per SIMD (at most 168 VGPRs): the software pipeline keeps two steps'
-// operands live (accumulators 64, B operands 32 + 8, A operands 2 x 8, prefetch queue 12).
-__global__ __launch_bounds__(64, 3) void conv_mfma(const float *__restrict__ x, int src_len, int out_len,
+// Registers: the software pipeline keeps two steps' operands live (accumulators 16 NT, B
+// operands 8 NT + 8, A operands 2 x 8, prefetch queue 12): 3 waves per SIMD for 16 blocks.
+#ifndef CONV_MW
+#define CONV_MW 3
+#endif
+__global__ __launch_bounds__(64, CONV_MW) void conv_mfma(const float *__restrict__ x, int src_len, int out_len,
                                                 const uint16_t *__restrict__ hb,
                                                 const ConvRoom *__restrict__ rooms,
                                                 float *__restrict__ y, double *__restrict__ psum,
@@ -130,9 +158,9 @@ __global__ __launch_bounds__(64, 3) void conv_mfma(const float *__restrict__ x, 
     const int nb = R.nb;
     const int s_end = t0 + CG - 1;
     // Steps s_start .. s_end, with s_start moved down so that s_end - s_start is a multiple
-    // of 4 (whole groups below; up to 3 extra steps, whose source samples before 0 or RIR
-    // blocks past nb read as zeros).
-    const int s_start = s_end - 4 * ((s_end - max(0, t0 - nb + 1) + 3) / 4);
+    // of UN (whole groups below; up to UN - 1 extra steps, whose source samples before 0 or
+    // RIR blocks past nb read as zeros).
+    const int s_start = s_end - UN * ((s_end - max(0, t0 - nb + 1) + UN - 1) / UN);
     // The source and the RIR blocks of the room are read through buffer descriptors: a read
     // outside the buffer returns zero, which is the zero padding of both signals (samples
     // before 0 or past the end, blocks outside [0, nb)), with no clamp or select.
@@ -155,7 +183,7 @@ __global__ __launch_bounds__(64, 3) void conv_mfma(const float *__restrict__ x, 
             xring[p + XR] = bv;
         }
     };
-    // RIR ring: slot (b & 15) holds block b of all microphones (zeros outside [0, nb));
+    // RIR ring: slot (b mod CG) holds block b of all microphones (zeros outside [0, nb));
     // lane covers 4 taps: mic = lane / 8, taps (lane % 8) * 4 .. + 3
     const int hlane = ((lane >> 3) * nb * CB + (lane & 7) * 4) * 2;   // byte offset in block 0
     auto load_block = [&](int b) -> uint2 {
@@ -169,18 +197,24 @@ __global__ __launch_bounds__(64, 3) void conv_mfma(const float *__restrict__ x, 
     };
     {
         float x0[3];
-        uint2 h0[CG];
 #pragma unroll
         for (int j = 0; j < 3; ++j) x0[j] = load_x(s_start - 2 + j);
 #pragma unroll
-        for (int tl = 0; tl < CG; ++tl) h0[tl] = load_block(t0 - s_start + tl);
-#pragma unroll
         for (int j = 0; j < 3; ++j) store_x(s_start - 2 + j, x0[j]);
 #pragma unroll
-        for (int tl = 0; tl < CG; ++tl) store_block(t0 - s_start + tl, h0[tl]);
+        for (int g = 0; g < CG; g += 8) {   // the first CG blocks, eight at a time
+            uint2 h0[8];
+#pragma unroll
+            for (int tl = 0; tl < 8; ++tl) h0[tl] = load_block(t0 - s_start + g + tl);
+#pragma unroll
+            for (int tl = 0; tl < 8; ++tl) store_block(t0 - s_start + g + tl, h0[tl]);
+        }
     }
     // prefetch queue: the blocks entering the rings at step u sit in slot (u - s_start - 1) % PD
-    constexpr int PD = 4;   // steps of global prefetch (one lap of the source ring)
+#ifndef CONV_PD
+#define CONV_PD 4
+#endif
+    constexpr int PD = CONV_PD;   // steps of global prefetch (2 or 4)
     float xq[PD];
     uint2 hq[PD];
 #pragma unroll
@@ -190,26 +224,26 @@ __global__ __launch_bounds__(64, 3) void conv_mfma(const float *__restrict__ x, 
     }
     __syncthreads();
 
-    f32x16_t acc[4];
+    f32x16_t acc[NT];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int nt = 0; nt < NT; ++nt)
         for (int q = 0; q < 16; ++q) acc[nt][q] = 0.0f;
 
     const int i = lane & 31;           // A row / B column within a tile
     const int kk0 = (lane >> 5) * 8;   // first K index of this lane's eight
     const uint32_t *xr32 = (const uint32_t *)xring;
-    // one step: Y_t += T_s H_{t - s} for the 16 output blocks t0 .. t0 + 15.  The A
+    // one step: Y_t += T_s H_{t - s} for the CG output blocks t0 .. t0 + CG - 1.  The A
     // fragments of T_s are x[X - e], X = 32 s + i - 16 ks - kk0, e = 0..7: ring entry
     // p = (-X) mod 128 for ks = 0 and p + 16 for ks = 1 (the ring is stored twice, so no
     // wrap); read as the dwords w = p / 2 .. w + 4 and realigned by 16 (p mod 2) bits.
-    // B operand: column i of MFMA tile nt is output block tl = 4 (i / 8) + nt of microphone
+    // B operand: column i of MFMA tile nt is output block tl = NT (i / 8) + nt of microphone
     // i % 8, so from one step to the next the operand of tile nt is the previous step's
     // operand of tile nt - 1 (the same registers): each step reads only tile 0's operand,
-    // blocks t0 - s + 0, 4, 8, 12, from the ring.  bq slot (nt - ph) mod 4 holds tile nt's
-    // operand at phase ph = (s - s_start) mod 4 (a constant in the unrolled loop).
-    u32x4_t bq[2][4];
+    // blocks t0 - s + NT k (k = 0..3), from the ring.  bq slot (nt - ph) mod NT holds tile
+    // nt's operand at phase ph = (s - s_start) mod NT (a constant in the unrolled loop).
+    u32x4_t bq[2][NT];
     auto read_b = [&](int s, int nt, u32x4_t &b0, u32x4_t &b1) {
-        const int b = t0 + (i >> 3) * 4 + nt - s;
+        const int b = t0 + (i >> 3) * NT + nt - s;
         const uint16_t *bp = ring + ring_pos(b, i & 7, kk0 >> 3);
         b0 = *(const u32x4_t *)bp;
         b1 = *(const u32x4_t *)(bp + CRH);
@@ -233,38 +267,38 @@ __global__ __launch_bounds__(64, 3) void conv_mfma(const float *__restrict__ x, 
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
+            for (int nt = 0; nt < NT; ++nt)
                 acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                    a[ks], __builtin_bit_cast(bf16x8_t, bq[ks][(nt - ph) & 3]), acc[nt], 0, 0, 0);
+                    a[ks], __builtin_bit_cast(bf16x8_t, bq[ks][(nt - ph) & (NT - 1)]), acc[nt], 0, 0, 0);
     };
     auto ring_entry = [&](int s) { return (-(CB * s + i - kk0)) & (XR - 1); };
     // Step u = s_start + 1 + 4 k + j enters source block u at ring entry (-32 u - lane) mod 128
-    // and reads T_u from entry (-(32 u + i - kk0)) mod 128: both depend on j only (four steps
-    // make one lap of the ring), so they are computed once.  Lanes below 32 store, and for
+    // and reads T_u from entry (-(32 u + i - kk0)) mod 128: both depend on j mod 4 only (four
+    // steps make one lap of the ring), so they are computed once.  Lanes below 32 store, and for
     // them the two entries coincide.
-    int pj[PD];
-#pragma unroll
-    for (int j = 0; j < PD; ++j) pj[j] = ring_entry(s_start + 1 + j);
+    const int p1 = ring_entry(s_start + 1);
     // Software pipeline: step u's ring entries are written and its operands read before the
     // products of step u - 1 are issued, so the LDS reads run under those products.
     bf16x8_t a_cur[2];
-    auto advance = [&](int u, int j) {
+    auto advance = [&](int u, int j) {   // u = s_start + 1 + UN k + j
+        const int q = j & (PD - 1);   // prefetch slot
+        const int pe = (p1 - CB * (j & 3)) & (XR - 1);   // ring entry of step u
         __syncthreads();   // the ring reads of step u - 1 precede these writes
-        store_block(t0 - u, hq[j]);
+        store_block(t0 - u, hq[q]);
         if (lane < 32) {
-            const uint16_t bv = f2bf(xq[j]);
-            xring[pj[j]] = bv;
-            xring[pj[j] + XR] = bv;
+            const uint16_t bv = f2bf(xq[q]);
+            xring[pe] = bv;
+            xring[pe + XR] = bv;
         }
-        hq[j] = load_block(t0 - u - PD);
-        xq[j] = load_x(u + PD);
+        hq[q] = load_block(t0 - u - PD);
+        xq[q] = load_x(u + PD);
         __syncthreads();
         bf16x8_t a_nx[2];
         u32x4_t bn0, bn1;
-        read_a(pj[j] >> 1, (uint32_t)(pj[j] & 1) * 16u, a_nx);
+        read_a(pe >> 1, (uint32_t)(pe & 1) * 16u, a_nx);
         read_b(u, 0, bn0, bn1);
-        mma(a_cur, j & 3);   // step u - 1: (u - 1 - s_start) mod 4 = j mod 4
-        const int sl = (-(1 + j)) & 3;   // tile 0's slot at step u
+        mma(a_cur, j & (NT - 1));   // step u - 1: (u - 1 - s_start) mod NT = j mod NT
+        const int sl = (-(1 + j)) & (NT - 1);   // tile 0's slot at step u
         bq[0][sl] = bn0;
         bq[1][sl] = bn1;
         a_cur[0] = a_nx[0];
@@ -274,20 +308,20 @@ __global__ __launch_bounds__(64, 3) void conv_mfma(const float *__restrict__ x, 
         const int p0 = ring_entry(s_start);
         read_a(p0 >> 1, (uint32_t)(p0 & 1) * 16u, a_cur);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) read_b(s_start, nt, bq[0][nt], bq[1][nt]);
+        for (int nt = 0; nt < NT; ++nt) read_b(s_start, nt, bq[0][nt], bq[1][nt]);
     }
-    for (int u0 = s_start + 1; u0 <= s_end; u0 += PD) {
+    for (int u0 = s_start + 1; u0 <= s_end; u0 += UN) {
 #pragma unroll
-        for (int j = 0; j < PD; ++j) advance(u0 + j, j);
+        for (int j = 0; j < UN; ++j) advance(u0 + j, j);
     }
-    mma(a_cur, 0);   // step s_end: (s_end - s_start) mod 4 = 0
+    mma(a_cur, 0);   // step s_end: (s_end - s_start) mod NT = 0
 
     // store: register q of tile nt holds row 8 (q / 4) + 4 (lane / 32) + (q % 4), column lane % 32
     double pw = 0.0;
     float *yr = y + (int64_t)r * CM * out_len;
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const int tl = (i >> 3) * 4 + nt, m = i & 7;
+    for (int nt = 0; nt < NT; ++nt) {
+        const int tl = (i >> 3) * NT + nt, m = i & 7;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int row = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
@@ -431,12 +465,18 @@ __global__ __launch_bounds__(256) void normal_deviates_kernel(float *__restrict_
 }
 
 // per-room noise scale from the convolution's partial power sums (fixed order)
-DEV float room_sigma(const double *__restrict__ psum, int r, int n_parts, int64_t per_room, float snr_db)
+// sigma_r = sqrt(mean of y^2 over the room x 10^(-snr/10)), by the first wave of a block (all
+// 64 lanes): lane k adds parts k, k + 64, ... in order, then a fixed shuffle reduction; lane
+// 0 writes the result.
+DEV void room_sigma(const double *__restrict__ psum, int r, int n_parts, int64_t per_room, double nscale,
+                    float *sigma)
 {
+    const int lane = threadIdx.x;
     double P = 0.0;
-    for (int k = 0; k < n_parts; ++k) P += psum[(int64_t)r * n_parts + k];
-    P /= (double)per_room;
-    return (float)sqrt(P * pow(10.0, -(double)snr_db / 10.0));
+    for (int k = lane; k < n_parts; k += 64) P += psum[(int64_t)r * n_parts + k];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) P += __shfl_xor(P, d, 64);
+    if (lane == 0) *sigma = (float)sqrt(P / (double)per_room * nscale);
 }
 
 // grid (chunks, rooms): y += sigma_r z with z drawn here (one Philox call per 4 samples).
@@ -473,7 +513,7 @@ __global__ __launch_bounds__(256) void conv_noise_seeded(float *__restrict__ y, 
             d[u] = deviates4((uint32_t)j, (uint32_t)m, (uint32_t)r, k0, k1);
         }
         if (!have_sigma) {   // once per block, after its first loads are in flight
-            if (threadIdx.x == 0) sigma_s = room_sigma(psum, r, n_parts, (int64_t)M * out_len, rooms[r].snr_db);
+            if (threadIdx.x < 64) room_sigma(psum, r, n_parts, (int64_t)M * out_len, rooms[r].nscale, &sigma_s);
             __syncthreads();
             sg = sigma_s;
             have_sigma = true;
@@ -504,7 +544,7 @@ __global__ void conv_noise(float *__restrict__ y, const float *__restrict__ z, c
 {
     const int r = blockIdx.y;
     __shared__ float sigma_s;
-    if (threadIdx.x == 0) sigma_s = room_sigma(psum, r, n_parts, per_room, rooms[r].snr_db);
+    if (threadIdx.x < 64) room_sigma(psum, r, n_parts, per_room, rooms[r].nscale, &sigma_s);
     __syncthreads();
     const float sg = sigma_s;
     float *yr = y + (int64_t)r * per_room;
@@ -521,12 +561,14 @@ void ism_conv_release(ism_handle *h)
 {
     if (!h || !h->conv) return;
     ConvState *c = h->conv;
-    if (c->ev) {
-        if (c->used) hipEventSynchronize(c->ev);
-        hipEventDestroy(c->ev);
+    for (ConvSlot &S : c->slot) {
+        if (S.ev) {
+            if (S.used) hipEventSynchronize(S.ev);
+            hipEventDestroy(S.ev);
+        }
+        if (S.ws) hipFree(S.ws);
+        if (S.stage) hipHostFree(S.stage);
     }
-    if (c->ws) hipFree(c->ws);
-    if (c->stage) hipHostFree(c->stage);
     delete c;
     h->conv = nullptr;
 }
@@ -580,6 +622,7 @@ static int convolve_impl(ism_handle *h, int n_rooms, int M, const float *rirs, c
         c.nb = (rir_len[r] + CB - 1) / CB;
         c.h_off = hb_total;
         c.snr_db = snr_db ? snr_db[r] : 0.0f;
+        c.nscale = std::pow(10.0, -(double)c.snr_db / 10.0);
         c.order = r;
         hb_total += (int64_t)M * c.nb * CB;
         nb_max = std::max(nb_max, c.nb);
@@ -593,7 +636,7 @@ static int convolve_impl(ism_handle *h, int n_rooms, int M, const float *rirs, c
     if (h->device < 0) { ism_set_error(h, "no HIP device"); return ISM_EDEVICE; }
     if (!h->conv) h->conv = new (std::nothrow) ConvState();
     if (!h->conv) return ISM_ENOMEM;
-    ConvState &C = *h->conv;
+    ConvSlot &C = h->conv->slot[h->conv->next];
     hipStream_t q = (hipStream_t)stream;
 
     const int mt_tiles = (out_len + CTILE - 1) / CTILE;
@@ -638,7 +681,7 @@ static int convolve_impl(ism_handle *h, int n_rooms, int M, const float *rirs, c
     hipError_t e = hipMemcpyAsync(rm, C.stage, rbytes, hipMemcpyHostToDevice, q);
     if (e != hipSuccess) return ism_hip_fail(h, e, "hipMemcpyAsync");
     if (use_mfma) {
-        hipLaunchKernelGGL(conv_pack_h, dim3(std::max(1, (nb_max * CB + 255) / 256), n_rooms, M), dim3(256), 0, q,
+        hipLaunchKernelGGL(conv_pack_h, dim3(std::max(1, (nb_max * CB + 1023) / 1024), n_rooms, M), dim3(256), 0, q,
                            rirs, rm, M, hb);
         if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_pack_h launch");
         hipLaunchKernelGGL(conv_mfma, dim3(mt_tiles, n_rooms), dim3(64), 0, q, src, src_len, out_len, hb, rm, out, ps,
@@ -663,6 +706,7 @@ static int convolve_impl(ism_handle *h, int n_rooms, int M, const float *rirs, c
     }
     if ((e = hipEventRecord(C.ev, q)) != hipSuccess) return ism_hip_fail(h, e, "hipEventRecord");
     C.used = true;
+    h->conv->next ^= 1;
     return ISM_OK;
 }
 

@@ -80,6 +80,40 @@ def test_conv_ragged_small(H, mfma):
         sys.stdout.write(f"room {r} len {lens[r]} mfma={mfma} err {e:.3e}\n")
 
 
+
+@pytest.mark.parametrize("mfma", [True, False])
+def test_back_to_back_calls_equal_separate_calls(H, mfma):
+    """Alternate calls use the handle's two workspaces and are not waited for by the next
+    call: three calls of different sizes issued back to back (the third reuses the first
+    workspace, grown) give the same bits as the same calls each followed by a wait, and
+    each is within the bar of the oracle."""
+    import torch
+    cases = []
+    for k, (lens, n_src, out_len) in enumerate([((120, 900, 33), 1200, 1000), ((2049, 7), 800, 2100),
+                                                 ((4000, 1, 64, 3000), 3000, 3500)]):
+        lens = np.array(lens)
+        rirs, offs = scenes.synthetic_rirs(lens, 8, seed=40 + k)
+        x = np.random.default_rng(50 + k).standard_normal((len(lens), n_src)).astype(np.float32)
+        snr = np.random.default_rng(60 + k).uniform(0, 30, len(lens)).astype(np.float32)
+        cases.append((lens, rirs, offs, x, out_len, snr, 70 + k))
+    alone = [_run(H, rirs, offs, lens, x, out_len, snr=snr, mfma=mfma, seed=sd)
+             for lens, rirs, offs, x, out_len, snr, sd in cases]
+    outs, keep = [], []
+    for lens, rirs, offs, x, out_len, snr, sd in cases:
+        d_rirs = torch.from_numpy(rirs).cuda()
+        d_x = torch.from_numpy(x).cuda()
+        keep += [d_rirs, d_x]
+        outs.append(H.convolve_batch(d_rirs, offs, lens, 8, d_x, out_len, snr_db=snr, noise_seed=sd,
+                                     use_mfma=mfma))
+    torch.cuda.synchronize()
+    from oracle import noise
+    for (lens, rirs, offs, x, out_len, snr, sd), a, y in zip(cases, alone, outs):
+        got = y.cpu().numpy().astype(np.float64)
+        assert np.array_equal(got, a)
+        for r in range(len(lens)):
+            ref = _oracle(rirs, offs, lens, x, out_len, r, snr=snr, zr=noise.deviates(sd, r, 8, out_len))
+            _check(got[r], ref, mfma)
+
 @pytest.mark.parametrize("mfma", [True, False])
 def test_conv_noise_hits_snr(H, mfma):
     lens = np.array([300, 800])
