@@ -410,9 +410,9 @@ DEV uint4 philox4x32_10(uint4 w, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t lo0 = w.x * 0xD2511F53u, hi0 = __umulhi(w.x, 0xD2511F53u);
-        const uint32_t lo2 = w.z * 0xCD9E8D57u, hi2 = __umulhi(w.z, 0xCD9E8D57u);
-        w = make_uint4(hi2 ^ w.y ^ k0, lo2, hi0 ^ w.w ^ k1, lo0);
+        // each 64-bit product (high and low words) is one v_mad_u64_u32
+        const uint64_t p0 = (uint64_t)w.x * 0xD2511F53u, p2 = (uint64_t)w.z * 0xCD9E8D57u;
+        w = make_uint4((uint32_t)(p2 >> 32) ^ w.y ^ k0, (uint32_t)p2, (uint32_t)(p0 >> 32) ^ w.w ^ k1, (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
