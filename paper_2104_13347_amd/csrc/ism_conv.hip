@@ -84,10 +84,8 @@ typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
 DEV uint16_t f2bf(float f)
-{   // round to nearest even (inputs are finite)
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+{   // round to nearest even: gfx950's v_cvt_pk_bf16_f32 (one instruction)
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
 // ------------------------------------------------------------------ RIRs -> padded BF16
