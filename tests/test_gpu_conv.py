@@ -142,6 +142,25 @@ def test_conv_full_size_sampled(H):
         sys.stdout.write(f"c4 room {r} len {lens[r]} rel rms {rms:.3e}\n")
 
 
+
+@pytest.mark.parametrize("mfma", [True, False])
+@pytest.mark.parametrize("src_len,out_len", [(1, 1), (5, 31), (40, 33), (3, 600), (700, 64)])
+def test_conv_tiny_signals(H, mfma, src_len, out_len):
+    """Outputs and sources shorter than a 32-sample block or a 512-sample tile, RIRs of 1,
+    2, 31, 32 and 33 taps: the MFMA path's zero steps before the first source block, its
+    one-block RIRs and its partial last tile, against the oracle."""
+    lens = np.array([1, 2, 31, 32, 33, 100])
+    rirs, offs = scenes.synthetic_rirs(lens, 8, seed=90 + src_len)
+    x = np.random.default_rng(91 + out_len).standard_normal((len(lens), src_len)).astype(np.float32)
+    got = _run(H, rirs, offs, lens, x, out_len, mfma=mfma)
+    assert got.shape == (len(lens), 8, out_len)
+    for r in range(len(lens)):
+        ref = _oracle(rirs, offs, lens, x, out_len, r)
+        if mfma:   # relative RMS of the room, as the other MFMA cases
+            _check(got[r], ref, True)
+        else:
+            assert np.max(np.abs(got[r] - ref)) <= TOL_FP32 * max(np.max(np.abs(ref)), 1e-30)
+
 @pytest.mark.parametrize("shape", [(3, 5, 1003), (2, 8, 16000), (1, 1, 1), (1, 2, 6)])
 def test_device_deviates_match_oracle(H, shape):
     # ragged (n % 4 != 0, scalar tail) and aligned (float4 stores) sample counts
