@@ -114,11 +114,11 @@ __global__ __launch_bounds__(256) void conv_pack_h(const float *__restrict__ rir
 
 // ------------------------------------------------------------------ MFMA block-Toeplitz
 // grid (tiles, rooms), one wave.  LDS: a 128-sample source ring (BF16, reversed,
-// stored twice so that any 10-sample window is contiguous) and a 16-slot RIR ring.
+// stored twice so that any 10-sample window is contiguous) and a CG-slot RIR ring.
 constexpr int XR = 128;   // source ring length (samples)
 constexpr int kBufWord3 = 0x00020000;   // buffer descriptor word 3 (gfx9 family: raw 32-bit data)
-// RIR ring: two halves (taps 0-15 and 16-31 of a block), each 128 rows (16 slots x 8
-// microphones) of two 16-byte chunks.  Chunk c of the row of block b sits at position
+// RIR ring: two halves (taps 0-15 and 16-31 of a block), each CG x 8 rows (a slot per block,
+// 8 microphones) of two 16-byte chunks.  Chunk c of the row of block b sits at position
 // c ^ ((b / NT) & 1): the 16 rows that 16 lanes of a read instruction touch (blocks b and
 // b + NT, 8 microphones each) fill all 16 chunk positions of 256 bytes, so the reads have no
 // bank conflicts and the ring needs no padding.
