@@ -264,6 +264,17 @@ int ism_convolve_batch_z(ism_handle *h, int n_rooms, int M, const float *rirs,
                          int use_mfma, float *out, ism_stream stream);
 
 /*
+ * Kernel timing of the convolution calls, for measurement.  With timing on, each
+ * ism_convolve_batch / ism_convolve_batch_z call records HIP events on its stream around
+ * its kernels; ism_conv_last_timing waits for the last call on this handle and writes
+ * the durations in ms of its RIR packing ([0], 0-length on the FP32 direct path), its
+ * convolution kernel ([1]) and its noise pass ([2], 0 without noise).  ISM_EINVAL when
+ * the last call was not timed.  Timing is off by default.
+ */
+int ism_conv_set_timing(ism_handle *h, int on);
+int ism_conv_last_timing(ism_handle *h, float ms[3]);
+
+/*
  * Seeded standard normal deviates (the sensor noise of paper section III.A), written
  * to the device FP32 array z[r][m][n], r < n_rooms, m < M, n < n_samples.  Generator:
  * Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011) with key

@@ -61,10 +61,15 @@ struct ConvSlot {
     size_t stage_cap = 0;
     hipEvent_t ev = nullptr;  // end of the last call's kernels that used this slot
     bool used = false;
+    hipEvent_t tev[4] = {};   // with kernel timing on: before pack, convolution, noise, and after
+    bool timed = false;       // the last call on this slot recorded tev
+    bool noise = false;       // ... and had a noise pass
 };
 struct ConvState {
     ConvSlot slot[2];
     int next = 0;
+    bool timing = false;
+    int last = -1;            // slot of the last call
 };
 
 constexpr int CB = 32;            // block length (samples / taps)
@@ -564,6 +569,8 @@ void ism_conv_release(ism_handle *h)
             if (S.used) hipEventSynchronize(S.ev);
             hipEventDestroy(S.ev);
         }
+        for (hipEvent_t &t : S.tev)
+            if (t) hipEventDestroy(t);
         if (S.ws) hipFree(S.ws);
         if (S.stage) hipHostFree(S.stage);
     }
@@ -678,18 +685,28 @@ static int convolve_impl(ism_handle *h, int n_rooms, int M, const float *rirs, c
     ConvRoom *rm = (ConvRoom *)(ws + off_rm);
     hipError_t e = hipMemcpyAsync(rm, C.stage, rbytes, hipMemcpyHostToDevice, q);
     if (e != hipSuccess) return ism_hip_fail(h, e, "hipMemcpyAsync");
+    const bool timed = h->conv->timing;
+    C.timed = false;
+    if (timed) {
+        for (hipEvent_t &t : C.tev)
+            if (!t && (e = hipEventCreate(&t)) != hipSuccess) return ism_hip_fail(h, e, "hipEventCreate");
+        if ((e = hipEventRecord(C.tev[0], q)) != hipSuccess) return ism_hip_fail(h, e, "hipEventRecord");
+    }
     if (use_mfma) {
         hipLaunchKernelGGL(conv_pack_h, dim3(std::max(1, (nb_max * CB + 1023) / 1024), n_rooms, M), dim3(256), 0, q,
                            rirs, rm, M, hb);
         if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_pack_h launch");
+        if (timed && (e = hipEventRecord(C.tev[1], q)) != hipSuccess) return ism_hip_fail(h, e, "hipEventRecord");
         hipLaunchKernelGGL(conv_mfma, dim3(mt_tiles, n_rooms), dim3(64), 0, q, src, src_len, out_len, hb, rm, out, ps,
                            mt_tiles);
         if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_mfma launch");
     } else {
+        if (timed && (e = hipEventRecord(C.tev[1], q)) != hipSuccess) return ism_hip_fail(h, e, "hipEventRecord");
         hipLaunchKernelGGL(conv_direct, dim3(dt_tiles, M, n_rooms), dim3(256), 0, q, rirs, rm, src, src_len, out_len, M,
                            out, ps, dt_tiles);
         if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_direct launch");
     }
+    if (timed && (e = hipEventRecord(C.tev[2], q)) != hipSuccess) return ism_hip_fail(h, e, "hipEventRecord");
     if (snr_db && seeded) {
         const int64_t quads = (int64_t)M * ((out_len + 3) / 4);
         const int chunks = (int)std::min<int64_t>(256, (quads + 256 * kNoiseQ - 1) / (256 * kNoiseQ));
@@ -702,8 +719,12 @@ static int convolve_impl(ism_handle *h, int n_rooms, int M, const float *rirs, c
         hipLaunchKernelGGL(conv_noise, dim3(chunks, n_rooms), dim3(256), 0, q, out, z, ps, rm, (int)n_parts, per_room);
         if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_noise launch");
     }
+    if (timed && (e = hipEventRecord(C.tev[3], q)) != hipSuccess) return ism_hip_fail(h, e, "hipEventRecord");
     if ((e = hipEventRecord(C.ev, q)) != hipSuccess) return ism_hip_fail(h, e, "hipEventRecord");
     C.used = true;
+    C.timed = timed;
+    C.noise = snr_db != nullptr;
+    h->conv->last = h->conv->next;
     h->conv->next ^= 1;
     return ISM_OK;
 }
@@ -723,6 +744,36 @@ extern "C" int ism_convolve_batch_z(ism_handle *h, int n_rooms, int M, const flo
 {
     return convolve_impl(h, n_rooms, M, rirs, rir_offset, rir_len, src, src_len, out_len, snr_db, z, false, 0,
                          use_mfma, out, stream);
+}
+
+extern "C" int ism_conv_set_timing(ism_handle *h, int on)
+{
+    if (!h) return ISM_EINVAL;
+    h->last_error.clear();
+    if (!h->conv) h->conv = new (std::nothrow) ConvState();
+    if (!h->conv) return ISM_ENOMEM;
+    h->conv->timing = on != 0;
+    return ISM_OK;
+}
+
+extern "C" int ism_conv_last_timing(ism_handle *h, float ms[3])
+{
+    if (!h) return ISM_EINVAL;
+    h->last_error.clear();
+    if (!ms) { ism_set_error(h, "NULL argument"); return ISM_EINVAL; }
+    if (!h->conv || h->conv->last < 0 || !h->conv->slot[h->conv->last].timed) {
+        ism_set_error(h, "no timed convolution call on this handle (ism_conv_set_timing first)");
+        return ISM_EINVAL;
+    }
+    ConvSlot &C = h->conv->slot[h->conv->last];
+    hipError_t e = hipEventSynchronize(C.tev[3]);
+    if (e != hipSuccess) return ism_hip_fail(h, e, "hipEventSynchronize");
+    for (int k = 0; k < 3; ++k) {
+        if ((e = hipEventElapsedTime(&ms[k], C.tev[k], C.tev[k + 1])) != hipSuccess)
+            return ism_hip_fail(h, e, "hipEventElapsedTime");
+    }
+    if (!C.noise) ms[2] = 0.0f;
+    return ISM_OK;
 }
 
 extern "C" int ism_normal_deviates(ism_handle *h, int n_rooms, int M, int n_samples, uint64_t seed, float *z,

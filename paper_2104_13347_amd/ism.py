@@ -23,7 +23,7 @@ PREC_FP32, PREC_FP16_LUT, PREC_FP32_SPLIT, PREC_FP32_ATOMIC, PREC_FP32_DIRECT = 
 EXPORTS = [
     "ism_create", "ism_destroy", "ism_strerror", "ism_last_error", "ism_version", "ism_rir",
     "ism_rir_batch", "ism_batch_plan_stats", "ism_last_counts", "ism_set_tuning", "ism_get_tuning",
-    "ism_autotune", "ism_set_autotune", "ism_get_launch_tuning", "ism_convolve_batch", "ism_convolve_batch_z", "ism_normal_deviates", "ism_server_create", "ism_server_destroy", "ism_server_submit",
+    "ism_autotune", "ism_set_autotune", "ism_get_launch_tuning", "ism_convolve_batch", "ism_convolve_batch_z", "ism_normal_deviates", "ism_conv_set_timing", "ism_conv_last_timing", "ism_server_create", "ism_server_destroy", "ism_server_submit",
     "ism_server_poll", "ism_server_copy_result", "ism_server_release", "ism_server_stats", "ism_server_counters", "ism_server_last_error", "ism_server_replay",
     "ism_rt_work_bytes", "ism_rir_t30", "ism_fit_beta", "ism_rt_mean_work_bytes", "ism_fit_beta_mean",
 ]
@@ -90,6 +90,10 @@ def load():
     L.ism_convolve_batch_z.restype = ci
     L.ism_normal_deviates.argtypes = [vp, ci, ci, ci, ctypes.c_uint64, vp, vp]
     L.ism_normal_deviates.restype = ci
+    L.ism_conv_set_timing.argtypes = [vp, ci]
+    L.ism_conv_set_timing.restype = ci
+    L.ism_conv_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+    L.ism_conv_last_timing.restype = ci
     L.ism_server_create.argtypes = [ci, ctypes.c_size_t, ci, ci, ctypes.POINTER(vp)]
     L.ism_server_create.restype = ci
     L.ism_server_destroy.argtypes = [vp]
@@ -342,6 +346,17 @@ class Handle:
                                                  int(seed) & 0xFFFFFFFFFFFFFFFF, ctypes.c_void_p(out.data_ptr()),
                                                  _stream_handle(stream)))
         return out
+
+    def set_conv_timing(self, on):
+        """Record HIP events around the kernels of each later convolve_batch call (off by default)."""
+        self._check(self.lib.ism_conv_set_timing(self.h, 1 if on else 0))
+
+    def conv_last_timing(self):
+        """(pack, convolution, noise) kernel durations in ms of the last timed convolve_batch call
+        (waits for it)."""
+        ms = (ctypes.c_float * 3)()
+        self._check(self.lib.ism_conv_last_timing(self.h, ms))
+        return float(ms[0]), float(ms[1]), float(ms[2])
 
     # -- reverberation time
     def rir_t30(self, rir, fs, stream=None):

@@ -143,6 +143,34 @@ def test_conv_full_size_sampled(H):
 
 
 
+
+@pytest.mark.parametrize("mfma", [True, False])
+def test_conv_kernel_timing(H, mfma):
+    """With kernel timing on, a call records its pack, convolution and noise durations and
+    gives the same bits as without; the FP32 path has no pack, a call without noise no
+    noise pass."""
+    import torch
+    b = scenes.c4()
+    lens = b["rir_len"][:16]
+    rirs, offs = scenes.synthetic_rirs(lens, 8, seed=8)
+    d_rirs = torch.from_numpy(rirs).cuda()
+    x = torch.from_numpy(b["x"][:16]).cuda()
+    snr = b["snr_db"][:16]
+    plain = H.convolve_batch(d_rirs, offs, lens, 8, x, 16000, snr_db=snr, noise_seed=5, use_mfma=mfma)
+    H.set_conv_timing(True)
+    try:
+        timed = H.convolve_batch(d_rirs, offs, lens, 8, x, 16000, snr_db=snr, noise_seed=5, use_mfma=mfma)
+        pk, cv, nz = H.conv_last_timing()
+        H.convolve_batch(d_rirs, offs, lens, 8, x, 16000, use_mfma=mfma)
+        pk2, cv2, nz2 = H.conv_last_timing()
+    finally:
+        H.set_conv_timing(False)
+    torch.cuda.synchronize()
+    assert torch.equal(plain, timed)
+    sys.stdout.write(f"mfma={mfma}: pack {pk:.4f} conv {cv:.4f} noise {nz:.4f} ms; clean {pk2:.4f} {cv2:.4f} {nz2:.4f}\n")
+    assert cv > 0 and nz > 0 and cv2 > 0 and nz2 == 0.0
+    assert pk >= 0 and pk2 >= 0 and (mfma or pk < 0.05)
+
 @pytest.mark.parametrize("mfma", [True, False])
 @pytest.mark.parametrize("src_len,out_len", [(1, 1), (5, 31), (40, 33), (3, 600), (700, 64)])
 def test_conv_tiny_signals(H, mfma, src_len, out_len):

@@ -64,3 +64,18 @@ def test_convolve_validation(handle, kw):
 @pytest.mark.skipif(_gpu(), reason="checks the no-device path")
 def test_convolve_without_device_fails_loudly(handle):
     assert _conv(handle) == ism.ISM_EDEVICE
+
+
+def test_conv_timing_needs_a_timed_call():
+    # a fresh handle: nothing timed yet; switching timing on touches no device
+    h = ism.Handle()
+    try:
+        ms = (ctypes.c_float * 3)()
+        assert h.lib.ism_conv_last_timing(h.h, ms) == ism.ISM_EINVAL
+        assert h.lib.ism_conv_last_timing(h.h, None) == ism.ISM_EINVAL
+        assert h.lib.ism_conv_set_timing(None, 1) == ism.ISM_EINVAL
+        assert h.lib.ism_conv_set_timing(h.h, 1) == ism.ISM_OK
+        assert h.lib.ism_conv_last_timing(h.h, ms) == ism.ISM_EINVAL
+        assert h.lib.ism_conv_set_timing(h.h, 0) == ism.ISM_OK
+    finally:
+        h.close()
