@@ -149,6 +149,19 @@ def rir_list(batch, rirs, nthreads=None, out=None):
     return out, int(taps)
 
 
+def conv_sample(h, x, n):
+    """One output sample of the clean source convolution (section III.A): y_m[n] = sum over
+    j <= n, j < len(h_m), n - j < len(x) of h_m[j] x[n - j], for every microphone m, in FP64
+    (a plain sum, for checking sampled outputs of launches too large for conv_room)."""
+    h = np.atleast_2d(np.asarray(h, dtype=np.float64))
+    x = np.asarray(x, dtype=np.float64)
+    n = int(n)
+    j = np.arange(h.shape[1])
+    ok = (j <= n) & (n - j < x.shape[0])
+    jj = j[ok]
+    return (h[:, jj] * x[n - jj][None, :]).sum(axis=1)
+
+
 def conv_room(h, x, out_len, snr_db=None, z=None):
     """Source convolution of one room's RIRs h [M, hlen] with x (direct FP64 sum), plus sensor
     noise sigma*z when z [M, out_len] is given, sigma^2 = mean(y^2) * 10^(-snr_db/10)

@@ -189,6 +189,37 @@ def test_conv_tiny_signals(H, mfma, src_len, out_len):
         else:
             assert np.max(np.abs(got[r] - ref)) <= TOL_FP32 * max(np.max(np.abs(ref)), 1e-30)
 
+
+@pytest.mark.parametrize("n_rooms", [1000, 1024])
+def test_conv_large_grid_sampled(H, n_rooms):
+    """Grids larger than the 256-room workload (ragged: 1000 rooms, no XCD mapping; 1024
+    rooms, XCD-mapped), RIRs up to 8000 taps, 20 000-sample sources and outputs: 400
+    sampled outputs against the oracle's one-output sum, within 3 % of the room's RMS (the
+    BF16 path's relative RMS error is about 2.3e-3; a sample's error is a sum of many
+    independent roundings)."""
+    import torch
+    rng = np.random.default_rng(100 + n_rooms)
+    lens = rng.integers(1, 8001, n_rooms)
+    rirs, offs = scenes.synthetic_rirs(lens, 8, seed=101)
+    x = rng.standard_normal((n_rooms, 20000)).astype(np.float32)
+    d_rirs = torch.from_numpy(rirs).cuda()
+    d_x = torch.from_numpy(x).cuda()
+    y = H.convolve_batch(d_rirs, offs, lens, 8, d_x, 20000, use_mfma=True)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    assert np.all(np.isfinite(got))
+    worst = 0.0
+    for r in rng.choice(n_rooms, 50, replace=False):
+        L = int(lens[r])
+        h = rirs[offs[r]:offs[r] + 8 * L].reshape(8, L)
+        scale = np.sqrt(np.mean(got[r].astype(np.float64) ** 2))
+        for n in rng.choice(20000, 8, replace=False):
+            ref = oracle.conv_sample(h, x[r], n)
+            err = np.max(np.abs(got[r, :, n] - ref)) / scale
+            worst = max(worst, err)
+            assert err <= 0.03, (r, n, err)
+    sys.stdout.write(f"{n_rooms} rooms: worst sampled error {worst:.3e} of the room RMS\n")
+
 @pytest.mark.parametrize("shape", [(3, 5, 1003), (2, 8, 16000), (1, 1, 1), (1, 2, 6)])
 def test_device_deviates_match_oracle(H, shape):
     # ragged (n % 4 != 0, scalar tail) and aligned (float4 stores) sample counts

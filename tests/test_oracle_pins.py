@@ -260,6 +260,21 @@ def test_convolution_matches_numpy_and_noise_hits_the_snr():
     assert snr == pytest.approx(12.5, abs=1e-9)
 
 
+
+def test_convolution_sample_matches_numpy_at_every_output():
+    # one output at a time, with RIRs longer and shorter than the source, and outputs past
+    # both ends of the full convolution (zeros there)
+    rng = np.random.default_rng(4)
+    for hlen, xlen, out_len in [(37, 120, 200), (300, 50, 400), (1, 9, 12)]:
+        h = rng.standard_normal((2, hlen))
+        x = rng.standard_normal(xlen)
+        full = np.zeros((2, out_len))
+        for m in range(2):
+            c = np.convolve(h[m], x)[:out_len]
+            full[m, :c.shape[0]] = c
+        got = np.stack([oracle.conv_sample(h, x, n) for n in range(out_len)], axis=1)
+        assert np.max(np.abs(got - full)) < 1e-12
+
 # ---------------------------------------------------------------- the paper's 7th-order Lagrange filter
 def _lagrange_basis_scipy(j, D):
     from scipy.interpolate import lagrange
