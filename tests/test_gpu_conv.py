@@ -190,6 +190,18 @@ def test_conv_tiny_signals(H, mfma, src_len, out_len):
             assert np.max(np.abs(got[r] - ref)) <= TOL_FP32 * max(np.max(np.abs(ref)), 1e-30)
 
 
+
+@pytest.mark.parametrize("mfma", [True, False])
+def test_silent_source_gets_no_noise(H, mfma):
+    """A silent source: zero power, so sigma = 0 and the output stays exactly zero with
+    seeded noise at any SNR (no NaN from 0 x 10^(-SNR/10))."""
+    lens = np.array([100, 2000, 1])
+    rirs, offs = scenes.synthetic_rirs(lens, 8, seed=12)
+    x = np.zeros((3, 1500), dtype=np.float32)
+    got = _run(H, rirs, offs, lens, x, 1500, snr=np.array([-20.0, 10.0, 300.0], dtype=np.float32), mfma=mfma,
+               seed=3)
+    assert np.all(got == 0.0)
+
 @pytest.mark.parametrize("n_rooms", [1000, 1024])
 def test_conv_large_grid_sampled(H, n_rooms):
     """Grids larger than the 256-room workload (ragged: 1000 rooms, no XCD mapping; 1024
