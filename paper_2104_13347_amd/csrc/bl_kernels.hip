@@ -917,7 +917,7 @@ extern "C" int bl_model_create(ism_handle *h, int c_in, int n_out, int mode, flo
     hipLaunchKernelGGL(bl_fold, dim3(NL + 1), dim3(256), 0, (hipStream_t)stream, F);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
-        hipFree(m->dev);
+        (void)hipFree(m->dev);
         delete m;
         return ism_hip_fail(h, e, "bl_fold launch");
     }
@@ -928,8 +928,8 @@ extern "C" int bl_model_create(ism_handle *h, int c_in, int n_out, int mode, flo
 extern "C" void bl_model_destroy(bl_model *m)
 {
     if (!m) return;
-    hipDeviceSynchronize();  // forward passes may still read the model
-    if (m->dev) hipFree(m->dev);
+    (void)hipDeviceSynchronize();  // forward passes may still read the model
+    if (m->dev) (void)hipFree(m->dev);
     delete m;
 }
 

@@ -49,11 +49,11 @@ int ism_hip_fail(ism_handle *h, hipError_t e, const char *what)
 
 static void free_slot(Slot &s)
 {
-    if (s.gexec) hipGraphExecDestroy(s.gexec);
-    if (s.graph) hipGraphDestroy(s.graph);
-    if (s.event) hipEventDestroy(s.event);
-    if (s.host) hipHostFree(s.host);
-    if (s.dev) hipFree(s.dev);
+    if (s.gexec) (void)hipGraphExecDestroy(s.gexec);
+    if (s.graph) (void)hipGraphDestroy(s.graph);
+    if (s.event) (void)hipEventDestroy(s.event);
+    if (s.host) (void)hipHostFree(s.host);
+    if (s.dev) (void)hipFree(s.dev);
     s = Slot();
 }
 
@@ -84,12 +84,12 @@ extern "C" void ism_destroy(ism_handle *h)
 {
     if (!h) return;
     for (auto &s : h->slots) {
-        if (s.event && s.used) hipEventSynchronize(s.event);
+        if (s.event && s.used) (void)hipEventSynchronize(s.event);
         free_slot(s);
     }
     ism_conv_release(h);
     ism_serve_release(h);
-    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
 }
 
@@ -407,7 +407,10 @@ static int ensure_slot(ism_handle *h, Slot &s, size_t bytes)
                       h->staging_fixed);
         return ISM_ENOMEM;
     }
-    if (s.event && s.used) hipEventSynchronize(s.event);
+    if (s.event && s.used) {   // the slot's last launch must be done before its buffers go
+        const hipError_t e = hipEventSynchronize(s.event);
+        if (e != hipSuccess) return ism_hip_fail(h, e, "hipEventSynchronize");
+    }
     free_slot(s);
     size_t cap = std::max<size_t>(bytes + bytes / 4, 1 << 20);
     hipError_t e = hipHostMalloc(&s.host, cap, hipHostMallocDefault);
@@ -425,7 +428,10 @@ int ism_reserve_staging(ism_handle *h, size_t bytes)
     if (!h || bytes < 4096) return ISM_EINVAL;
     if (h->device < 0) { ism_set_error(h, "no HIP device"); return ISM_EDEVICE; }
     for (Slot &s : h->slots) {
-        if (s.event && s.used) hipEventSynchronize(s.event);
+        if (s.event && s.used) {
+            const hipError_t e = hipEventSynchronize(s.event);
+            if (e != hipSuccess) return ism_hip_fail(h, e, "hipEventSynchronize");
+        }
         free_slot(s);
         hipError_t e = hipHostMalloc(&s.host, bytes, hipHostMallocDefault);
         if (e != hipSuccess) { s.host = nullptr; ism_set_error(h, "pinned allocation failed"); return ISM_ENOMEM; }
@@ -630,8 +636,8 @@ int ism_run_plan(ism_handle *h, const Plan &plan, const double *mics, double fs,
     if (h->graphs) {
         GraphKey key{(const void *)ke.fn, upload, grid, lds, n_rooms};
         if (!s.gexec || !(s.key == key)) {
-            if (s.gexec) { hipGraphExecDestroy(s.gexec); s.gexec = nullptr; }
-            if (s.graph) { hipGraphDestroy(s.graph); s.graph = nullptr; }
+            if (s.gexec) { (void)hipGraphExecDestroy(s.gexec); s.gexec = nullptr; }
+            if (s.graph) { (void)hipGraphDestroy(s.graph); s.graph = nullptr; }
             // capture on the handle's own stream (the caller's may be the legacy
             // default stream, which cannot be captured); replay on the caller's
             if (!h->cap_stream) {
@@ -788,7 +794,7 @@ static int tune_batch(ism_handle *h, int n_rooms, const ism_room *rooms, const d
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) { ism_set_error(h, "hipEventCreate failed"); return ISM_EDEVICE; }
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         ism_set_error(h, "hipEventCreate failed");
         return ISM_EDEVICE;
     }
@@ -808,7 +814,7 @@ static int tune_batch(ism_handle *h, int n_rooms, const ism_room *rooms, const d
                 return rc;
             if (hipEventRecord(e1, q) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return ISM_EDEVICE;
             float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return ISM_EDEVICE;
             t = std::min(t, ms);
         }
         if (t < best.ms) best = TuneVal{sl, wg, il, t};
@@ -829,8 +835,8 @@ static int tune_batch(ism_handle *h, int n_rooms, const ism_room *rooms, const d
         h->interleave = best.interleave;
         st = rir_batch_impl(h, n_rooms, rooms, mics, fs, c, fd_taps, order_mode, precision, out, q);
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st) {
         h->seg_len = s_seg;
         h->wg_per_cu = s_wg;

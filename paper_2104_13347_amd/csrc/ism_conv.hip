@@ -569,13 +569,13 @@ void ism_conv_release(ism_handle *h)
     ConvState *c = h->conv;
     for (ConvSlot &S : c->slot) {
         if (S.ev) {
-            if (S.used) hipEventSynchronize(S.ev);
-            hipEventDestroy(S.ev);
+            if (S.used) (void)hipEventSynchronize(S.ev);
+            (void)hipEventDestroy(S.ev);
         }
         for (hipEvent_t &t : S.tev)
-            if (t) hipEventDestroy(t);
-        if (S.ws) hipFree(S.ws);
-        if (S.stage) hipHostFree(S.stage);
+            if (t) (void)hipEventDestroy(t);
+        if (S.ws) (void)hipFree(S.ws);
+        if (S.stage) (void)hipHostFree(S.stage);
     }
     delete c;
     h->conv = nullptr;
@@ -660,7 +660,7 @@ static int convolve_impl(ism_handle *h, int n_rooms, int M, const float *rirs, c
         C.used = false;
     }
     if (C.cap < need) {
-        if (C.ws) hipFree(C.ws);
+        if (C.ws) (void)hipFree(C.ws);
         C.ws = nullptr;
         C.cap = 0;
         if (hipMalloc(&C.ws, need) != hipSuccess) { ism_set_error(h, "conv workspace allocation failed"); return ISM_ENOMEM; }
@@ -668,7 +668,7 @@ static int convolve_impl(ism_handle *h, int n_rooms, int M, const float *rirs, c
     }
     const size_t rbytes = sizeof(ConvRoom) * n_rooms;
     if (C.stage_cap < rbytes) {
-        if (C.stage) hipHostFree(C.stage);
+        if (C.stage) (void)hipHostFree(C.stage);
         C.stage = nullptr;
         C.stage_cap = 0;
         if (hipHostMalloc(&C.stage, rbytes, hipHostMallocDefault) != hipSuccess) {

@@ -335,13 +335,13 @@ extern "C" void ism_server_destroy(ism_server *s)
     s->cv.notify_all();
     if (s->worker.joinable()) s->worker.join();
     for (auto &L : s->lanes) {
-        if (L.stream) hipStreamSynchronize(L.stream);
-        if (L.done) hipEventDestroy(L.done);
-        if (L.stream) hipStreamDestroy(L.stream);
+        if (L.stream) (void)hipStreamSynchronize(L.stream);
+        if (L.done) (void)hipEventDestroy(L.done);
+        if (L.stream) (void)hipStreamDestroy(L.stream);
         if (L.h) ism_destroy(L.h);
-        if (L.counts) hipHostFree(L.counts);
+        if (L.counts) (void)hipHostFree(L.counts);
     }
-    if (s->base) hipFree(s->base);
+    if (s->base) (void)hipFree(s->base);
     delete s;
 }
 
