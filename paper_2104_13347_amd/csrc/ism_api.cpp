@@ -248,7 +248,7 @@ static void parallel_ranges(size_t n, int nt, F f)
     for (auto &x : th) x.join();
 }
 
-int ism_build_plan(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics, double fs,
+int ism_build_plan(ism_handle *h, int n_rooms, const ism_room *rooms, const double * /*mics: the plan needs none*/, double fs,
                    double c, int fd_taps, int seg_len, Plan &plan)
 {
     const int K = half_length(fd_taps);

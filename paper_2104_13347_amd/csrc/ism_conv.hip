@@ -100,7 +100,7 @@ DEV uint16_t f2bf(float f)
 // grid (chunks, rooms, M), 256 threads of 4 consecutive taps each (one 8-byte store; a
 // microphone's padded row starts 64-byte aligned)
 __global__ __launch_bounds__(256) void conv_pack_h(const float *__restrict__ rirs,
-                                                   const ConvRoom *__restrict__ rooms, int M,
+                                                   const ConvRoom *__restrict__ rooms,
                                                    uint16_t *__restrict__ hb)
 {
     const int r = blockIdx.y, m = blockIdx.z;
@@ -697,7 +697,7 @@ static int convolve_impl(ism_handle *h, int n_rooms, int M, const float *rirs, c
     }
     if (use_mfma) {
         hipLaunchKernelGGL(conv_pack_h, dim3(std::max(1, (nb_max * CB + 1023) / 1024), n_rooms, M), dim3(256), 0, q,
-                           rirs, rm, M, hb);
+                           rirs, rm, hb);
         if ((e = hipGetLastError()) != hipSuccess) return ism_hip_fail(h, e, "conv_pack_h launch");
         if (timed && (e = hipEventRecord(C.tev[1], q)) != hipSuccess) return ism_hip_fail(h, e, "hipEventRecord");
         hipLaunchKernelGGL(conv_mfma, dim3(mt_tiles, n_rooms), dim3(64), 0, q, src, src_len, out_len, hb, rm, out, ps,
