@@ -250,6 +250,19 @@ def test_device_deviates_match_oracle(H, shape):
     assert err <= TOL_DEV
 
 
+def test_device_deviates_many_against_oracle(H):
+    """16.8 M deviates (8.4 M Box-Muller pairs: each of the 2^23 possible radius and angle
+    uniforms drawn with probability 1 - 1/e) against the oracle's, under the same bar."""
+    import torch
+    from oracle import noise
+    seed = 0x0F1E_2D3C_4B5A_6978
+    got = H.normal_deviates(1, 64, 1 << 18, seed)
+    torch.cuda.synchronize()
+    err = float(np.abs(got[0].cpu().numpy().astype(np.float64) - noise.deviates(seed, 0, 64, 1 << 18)).max())
+    sys.stdout.write(f"16.8 M deviates: max|gpu - oracle| = {err:.2e} (bar {TOL_DEV:.2e})\n")
+    assert err <= TOL_DEV
+
+
 def test_device_deviates_moments():
     # 8 channels x 2^20 samples: mean 0, variance 1, kurtosis 3, and no correlation between
     # channels or between neighbouring samples (5-sigma bands of the sample statistics)
