@@ -491,7 +491,7 @@ DEV void room_sigma(const double *__restrict__ psum, int r, int n_parts, int64_t
 // Each thread takes kNoiseQ groups of 4 samples per pass: their loads are issued first, the
 // deviates computed while they are in flight, and the room's sigma (thread 0) is awaited
 // only before the stores.
-constexpr int kNoiseQ = 4;
+constexpr int kNoiseQ = 2;
 __global__ __launch_bounds__(256) void conv_noise_seeded(float *__restrict__ y, const double *__restrict__ psum,
                                                          const ConvRoom *__restrict__ rooms, int n_parts, int M,
                                                          int out_len, uint32_t k0, uint32_t k1)
