@@ -100,9 +100,11 @@ class Model:
     def _check_extent(self, x, n_t, batch, offsets, ex_stride, ch_stride):
         """Explicit frame layout: every element the kernels read, frame b < batch, channel
         c < c_in, sample n < n_t at off_b + c * ch_stride + n, must lie in x (contiguous).
-        Device offsets are read back to check them, once per offsets tensor object (held by a
-        weak reference, so a new tensor that reuses a freed one's memory is read again) and
-        torch's version counter of it; a tensor rewritten outside torch keeps its old check."""
+        Device offsets are read back to check them, once per offsets storage (its base tensor,
+        held by a weak reference, so a new tensor that reuses a freed one's memory is read
+        again), element offset into it, batch and torch's version counter (shared by a tensor
+        and its views, so a fresh slice of the same offsets, offsets[:b] on every call, keeps
+        the check); a tensor rewritten outside torch keeps its old check."""
         if n_t is None or batch is None or ch_stride is None:
             raise ValueError("n_t, batch and ch_stride are required with an explicit frame layout")
         if offsets is None and ex_stride is None:
@@ -122,12 +124,13 @@ class Model:
             return
         if offsets.numel() < batch:
             raise ValueError(f"offsets holds {offsets.numel()} entries for {batch} frames")
-        key = (offsets._version, batch)
+        base = offsets._base if offsets._base is not None else offsets
+        key = (offsets.storage_offset(), offsets._version, batch)
         cache = getattr(self, "_off_range", None)
-        if cache is None or cache[0]() is not offsets or cache[1] != key:
+        if cache is None or cache[0]() is not base or cache[1] != key:
             o = offsets[:batch]
             lo, hi = int(o.min().item()), int(o.max().item())
-            self._off_range = cache = (weakref.ref(offsets), key, lo, hi)
+            self._off_range = cache = (weakref.ref(base), key, lo, hi)
         lo, hi = cache[2], cache[3]
         if lo < 0 or hi + span > x.numel():
             raise ValueError(f"frame offsets in [{lo}, {hi}] reach past the {x.numel()} elements of x")

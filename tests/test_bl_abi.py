@@ -108,3 +108,26 @@ def test_offset_check_is_per_tensor_object():
     assert t2.data_ptr() == t1.data_ptr() and t2._version == t1._version
     with pytest.raises(ValueError):
         check(t2, n_t=500)
+
+
+def test_offset_check_reuses_its_read_for_slices_of_one_tensor():
+    # offsets[:b] is a new view object on every call; the check reads its values once per
+    # base tensor, element offset, batch and version, so a fresh slice of unchanged offsets
+    # costs no read, while another window of the base or an in-place change is read again
+    import types
+    import torch
+    fake = types.SimpleNamespace(c_in=3)
+    x = torch.zeros(3 * 1000)
+    check = lambda off, n_t=500: blm.Model._check_extent(fake, x, n_t, 1, off, None, 1000)
+    base = torch.tensor([0, -1, 0], dtype=torch.int64)
+    check(base[:1])
+    first = fake._off_range
+    check(base[:1])
+    assert fake._off_range is first                 # cache hit: nothing read back
+    with pytest.raises(ValueError):
+        check(base[1:])                             # another window of the same storage
+    check(base[2:])
+    assert fake._off_range is not first
+    base[:1].fill_(-1)                              # in place through a view: shared version moves
+    with pytest.raises(ValueError):
+        check(base[:1])
