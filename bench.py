@@ -241,13 +241,34 @@ def bench_c4(H, torch, with_errors=True):
         finally:
             H.set_conv_timing(False)
         kpk, kcv, knz = (float(np.median([t[i] for t in kt])) for i in range(3))
+        two = {}
+        if mfma:
+            # calls alternating between two streams and two outputs: one call's noise pass and
+            # the next call's pack run beside the other stream's convolution kernel
+            ss, y2 = [torch.cuda.Stream(), torch.cuda.Stream()], [y, torch.empty_like(y)]
+
+            def two_streams():
+                cur = torch.cuda.current_stream()
+                for s in ss:
+                    s.wait_stream(cur)
+                for i in range(n_two):
+                    H.convolve_batch(rirs, offs, lens, 8, x, 16000, snr_db=b["snr_db"], noise_seed=seed,
+                                     use_mfma=True, out=y2[i % 2], stream=ss[i % 2])
+                for s in ss:
+                    cur.wait_stream(s)
+            n_two = 16
+            ms2 = _time_it(torch, two_streams, reps=5) / n_two
+            del y2
+            two = {"ms_with_noise_two_streams": ms2, "timing_two_streams": f"per call, {n_two} calls in turn on two streams",
+                   "path_frac_two_streams": flops / (ms2 / 1e3) / 1e12 / peak}
         res[name] = {"ms_with_noise": ms, "ms_convolution_only": ms_clean, "timing": f"per call, {n_seq} calls back to back",
                      "ms_single_call_with_noise": _time_it(torch, noisy), "tflops": tf,
                      "peak_tflops": peak, "frac": tf / peak,
                      "path_tflops": flops / (ms / 1e3) / 1e12, "path_frac": flops / (ms / 1e3) / 1e12 / peak,
                      "kernel_ms": {"pack": kpk, "convolution": kcv, "noise": knz,
                                    "timing": "HIP events around each kernel, median of 5 calls"},
-                     "kernel_tflops": flops / (kcv / 1e3) / 1e12, "kernel_frac": flops / (kcv / 1e3) / 1e12 / peak}
+                     "kernel_tflops": flops / (kcv / 1e3) / 1e12, "kernel_frac": flops / (kcv / 1e3) / 1e12 / peak,
+                     **two}
         if with_errors:
             import oracle
             from oracle import noise

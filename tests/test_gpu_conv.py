@@ -116,6 +116,39 @@ def test_back_to_back_calls_equal_separate_calls(H, mfma):
             _check(got[r], ref, mfma)
 
 @pytest.mark.parametrize("mfma", [True, False])
+def test_calls_on_two_streams_equal_separate_calls(H, mfma):
+    """Calls issued in turn on two side streams (one call's noise pass may run beside the
+    next call's kernels; a workspace is reused only after the call that last used it ended)
+    give the same bits as the same calls each on the current stream followed by a wait."""
+    import torch
+    cases = []
+    for k, (lens, n_src, out_len) in enumerate([((3000, 900, 33), 4000, 3000), ((2049, 7), 800, 2100),
+                                                 ((4000, 1, 64, 3000), 3000, 3500), ((500,), 5000, 5200)]):
+        lens = np.array(lens)
+        rirs, offs = scenes.synthetic_rirs(lens, 8, seed=80 + k)
+        x = np.random.default_rng(90 + k).standard_normal((len(lens), n_src)).astype(np.float32)
+        snr = np.random.default_rng(100 + k).uniform(0, 30, len(lens)).astype(np.float32)
+        cases.append((lens, rirs, offs, x, out_len, snr, 110 + k))
+    alone = [_run(H, rirs, offs, lens, x, out_len, snr=snr, mfma=mfma, seed=sd)
+             for lens, rirs, offs, x, out_len, snr, sd in cases]
+    cur = torch.cuda.current_stream()
+    ss = [torch.cuda.Stream(), torch.cuda.Stream()]
+    dev = [(torch.from_numpy(rirs).cuda(), torch.from_numpy(x).cuda(),
+            torch.empty((len(lens), 8, out_len), dtype=torch.float32, device="cuda"))
+           for lens, rirs, offs, x, out_len, snr, sd in cases]
+    for s in ss:
+        s.wait_stream(cur)
+    for i, ((lens, rirs, offs, x, out_len, snr, sd), (d_rirs, d_x, y)) in enumerate(zip(cases, dev)):
+        H.convolve_batch(d_rirs, offs, lens, 8, d_x, out_len, snr_db=snr, noise_seed=sd, use_mfma=mfma, out=y,
+                         stream=ss[i % 2])
+    for s in ss:
+        cur.wait_stream(s)
+    torch.cuda.synchronize()
+    for i, (a, (_, _, y)) in enumerate(zip(alone, dev)):
+        assert np.array_equal(y.cpu().numpy().astype(np.float64), a), f"call {i}"
+
+
+@pytest.mark.parametrize("mfma", [True, False])
 def test_conv_noise_hits_snr(H, mfma):
     lens = np.array([300, 800])
     rirs, offs = scenes.synthetic_rirs(lens, 8, seed=5)
