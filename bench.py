@@ -178,6 +178,38 @@ def bench_c3(H, torch, with_errors=True):
     return res
 
 
+def bench_c0_replicated(H, torch, with_errors=True):
+    """The single-RIR room (5 x 4 x 3 m, beta 0.7, index-L1 order 10, 4096 samples, 81 taps)
+    as 4096 rooms of identical shape with sources moved by up to 0.25 m: the per-RIR work of
+    the latency workload at a batch size that fills the chip.  Errors against the FP64 oracle
+    on 8 of the rooms."""
+    from paper_2104_13347_amd import ism, scenes
+    b = scenes.c0_replicated()
+    rooms = ism.rooms_array(b)
+    out = torch.empty(int(b["out_size"]), dtype=torch.float32, device="cuda")
+    ms = _time_it(torch, lambda: H.rir_batch(b, out=out, rooms=rooms), reps=5)
+    taps = H.last_counts()["taps"]
+    tf = taps * FLOPS_PER_TAP / (ms / 1e3) / 1e12
+    res = {"workload": "4096 copies of the 5x4x3 m, beta 0.7, index-L1 order 10 room, 1 mic, 4096 samples, "
+                       "81 taps, sources moved by U[-0.25, 0.25] m per axis",
+           "ms": ms, "taps": taps, "taps_per_s": taps / (ms / 1e3), "rirs_per_s": 4096 / (ms / 1e3),
+           "nominal_tflops": tf, "nominal_frac": tf / FP32_VECTOR_PEAK_TFLOPS,
+           "note": "taps x 12 nominal flops of the direct method over the FP32 vector peak"}
+    if with_errors:
+        import oracle
+        sample = [(r, 0) for r in range(0, 4096, 512)]
+        ref = np.zeros(int(b["out_size"]))
+        t = time.perf_counter()
+        _, otaps = oracle.rir_list(b, sample, out=ref)
+        dt = time.perf_counter() - t
+        e = rir_errors(b, out.cpu().numpy(), ref, sample)
+        res["gpu_vs_oracle"] = {"rirs": len(sample), "max_err_over_peak": float(e.max()),
+                                "median_err_over_peak": float(np.median(e)), "bar": 1e-5}
+        res["cpu_oracle_on_sample"] = {"taps_per_s": otaps / dt, "s": dt, "cores": os.cpu_count() or 1}
+    del out
+    return res
+
+
 def bench_paper(H, torch):
     """The paper's room dataset: 7 x 10 x 3.7 m, RT 0.5 s, 48 000 torus source positions x the
     7-microphone array = 336 000 RIRs of 8000 samples (16 kHz), in one batched launch, with the
@@ -421,7 +453,38 @@ def bench_rt_fit(H, torch):
     return res
 
 
-def bench_c2(torch, n_requests, batched_taps_per_s=None):
+def cpu_oracle_c2(b, total_taps, budget_s=8.0, max_requests=256):
+    """The FP64 oracle on a seeded subset of the serving requests (at most 256, bounded to
+    about budget_s), threads over each request's RIRs; its rate extrapolated to every
+    request's taps (the device's exact count)."""
+    import oracle
+    from paper_2104_13347_amd import scenes
+    nthreads = os.cpu_count() or 1
+    idx = np.random.default_rng(2106).choice(len(b["rir_len"]), size=min(max_requests, len(b["rir_len"])),
+                                             replace=False)
+    sub = scenes.subset(b, idx)
+    ref = np.zeros(int(sub["out_size"]))
+    taps, done = 0, 0
+    t0 = time.perf_counter()
+    i = 0
+    while i < len(idx):   # requests in groups of at least one RIR per thread
+        lst = []
+        while i < len(idx) and len(lst) < nthreads:
+            lst += [(i, m) for m in range(int(sub["n_mics"][i]))]
+            i += 1
+        _, t = oracle.rir_list(sub, lst, nthreads=nthreads, out=ref)
+        taps += t
+        done = i
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"requests": done, "taps": taps, "s": dt, "taps_per_s": taps / dt, "requests_per_s": done / dt,
+            "cores": nthreads, "kind": "oracle",
+            "sample": f"{done} of a seeded subset of {len(idx)} requests, FP64 oracle, {nthreads} threads over RIRs",
+            "all_requests_s_extrapolated": total_taps / (taps / dt) if total_taps else None}
+
+
+def bench_c2(torch, n_requests, batched_taps_per_s=None, with_oracle=False):
     """Serving: Poisson arrivals of single-room requests (RT60 U[0.1,1.0] s, RIR RT60*fs, M in
     {4,8,16,32}).  A saturated run (all requests at t=0) on the 8 GB engine gives the sustainable
     rate; arrivals at 0.7 of it then run three times on each HBM budget (8 GB, 1 GB, and 32 MB,
@@ -433,7 +496,7 @@ def bench_c2(torch, n_requests, batched_taps_per_s=None):
     n_rirs = int(b["n_mics"].sum())
     res = {"workload": f"{n_requests} requests, Poisson arrivals, RT60 U[0.1,1.0] s, M in {{4,8,16,32}}, 16 kHz",
            "lanes": 4, "max_batch_rooms": 64, "replays_per_budget": 3}
-    lam = None
+    lam = total_taps = None
     for name, budget in [("budget_8GiB", 8 << 30), ("budget_1GiB", 1 << 30), ("budget_32MiB", 32 << 20)]:
         S = ism.Server(n_lanes=4, hbm_budget_bytes=budget, max_batch_rooms=64)
         try:
@@ -442,6 +505,8 @@ def bench_c2(torch, n_requests, batched_taps_per_s=None):
             c1 = S.counters()
             entry = {"saturated": {"requests_per_s": n_requests / wall0, "rirs_per_s": n_rirs / wall0,
                                    "taps_per_s": (c1["taps_done"] - c0["taps_done"]) / wall0, "wall_s": wall0}}
+            if total_taps is None:
+                total_taps = c1["taps_done"] - c0["taps_done"]
             if lam is None:
                 lam = 0.7 * n_requests / wall0
             reps = []
@@ -471,6 +536,8 @@ def bench_c2(torch, n_requests, batched_taps_per_s=None):
             res[name] = entry
         finally:
             S.close()
+    if with_oracle:
+        res["cpu_oracle"] = cpu_oracle_c2(b, total_taps)
     return res
 
 
@@ -490,8 +557,9 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the serving, precision and convolution sections")
-    ap.add_argument("--extras", default="c3,c4,paper,c2,beamlearning,rtfit",
-                    help="comma list of extra sections to run: c3 precision, c4 convolution, paper (the "
+    ap.add_argument("--extras", default="c0x,c3,c4,paper,c2,beamlearning,rtfit",
+                    help="comma list of extra sections to run: c0x (the single-RIR room as 4096 rooms), "
+                         "c3 precision, c4 convolution, paper (the "
                          "paper's 336 000-RIR room dataset), c2 serving, beamlearning (the paper's network "
                          "on frames of the convolution stage), rtfit (uniform-absorption fit for a target T30)")
     ap.add_argument("--serve-requests", type=int, default=20000)
@@ -662,12 +730,15 @@ def main():
         res["extras"] = {}
         if "c3" in extras:
             res["extras"]["c3_precision"] = bench_c3(H, torch, with_errors=not args.no_cpu_baseline)
+        if "c0x" in extras:
+            res["extras"]["c0_replicated"] = bench_c0_replicated(H, torch, with_errors=not args.no_cpu_baseline)
         if "c4" in extras:
             res["extras"]["c4_convolution"] = bench_c4(H, torch, with_errors=not args.no_cpu_baseline)
         if "paper" in extras:
             res["extras"]["paper_room1_dataset"] = bench_paper(H, torch)
         if "c2" in extras:
-            res["extras"]["c2_serving"] = bench_c2(torch, args.serve_requests, batched_taps_per_s=value)
+            res["extras"]["c2_serving"] = bench_c2(torch, args.serve_requests, batched_taps_per_s=value,
+                                                  with_oracle=not args.no_cpu_baseline)
         if "beamlearning" in extras:
             bl = bench_beamlearning(H, torch)
             if not args.no_cpu_baseline:

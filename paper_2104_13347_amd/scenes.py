@@ -11,6 +11,7 @@ III.A: RIRs convolved with source signals, Gaussian sensor noise at a drawn
 SNR), at the sizes of the five benchmark configurations:
 
 * ``c0``  one 5x4x3 m room, beta 0.7, index-L1 order 10, 4096 samples, 81 taps;
+          ``c0_replicated``: 4096 copies of it, sources moved by up to 0.25 m;
 * ``c1``  1024 rooms, dims U[3,10]xU[3,8]xU[2.5,4] m, RT60 U[0.2,0.8] s, Sabine
           beta, 8-mic circle r = 5 cm, len = round(0.8 RT60 fs), 81 taps;
 * ``c2``  serving requests, RT60 U[0.1,1.0] s, len = round(RT60 fs),
@@ -179,6 +180,18 @@ def c0():
     room = {"L": (5.0, 4.0, 3.0), "beta": (0.7,) * 6, "src": (1.3, 2.1, 1.5),
             "mics": [(3.6, 1.7, 1.2)], "max_order": 10, "rir_len": 4096}
     return pack([room], 16000.0, C_SOUND, 81, ORDER_INDEX_L1, "c0")
+
+
+def c0_replicated(n_rooms=4096, seed=2104, jitter=0.25):
+    """The single-RIR room repeated: n_rooms copies of c0's room, microphone, order bound and
+    length, each source moved by U[-jitter, jitter] m per axis (a batch of identical shape
+    whose per-RIR work is that of c0)."""
+    rng = np.random.default_rng(seed)
+    base = c0()
+    src0 = base["src"][0]
+    rooms = [{"L": (5.0, 4.0, 3.0), "beta": (0.7,) * 6, "src": src0 + rng.uniform(-jitter, jitter, 3),
+              "mics": [(3.6, 1.7, 1.2)], "max_order": 10, "rir_len": 4096} for _ in range(n_rooms)]
+    return pack(rooms, 16000.0, C_SOUND, 81, ORDER_INDEX_L1, "c0x")
 
 
 def _shoebox_room(rng, rt60_lo, rt60_hi, M, len_factor, fs, c):

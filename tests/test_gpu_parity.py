@@ -128,6 +128,22 @@ def test_c1_full_batch_sampled(H):
     assert cnt["taps"] > 0.9e11
 
 
+def test_c0_replicated_full_batch_sampled(H):
+    # the single-RIR room as 4096 rooms (the benchmark's launch): 16 RIRs against the oracle
+    # one by one, and the exact tap count of those 16 rooms run as a batch of their own
+    b = scenes.c0_replicated()
+    _say("c0 replicated full batch")
+    gpu, cnt = run(H, b)
+    rirs = [(r, 0) for r in range(0, 4096, 256)]
+    ref, taps, _ = oracle_batch(b, rirs)
+    err = rel_errors(b, gpu, ref, rirs)
+    _say(f"c0 replicated sampled max err {err.max():.3e}")
+    assert err.max() <= TOL_FP32
+    assert np.all(np.isfinite(gpu))
+    _, cnt16 = run(H, scenes.subset(b, [r for r, _ in rirs]))
+    assert cnt16["taps"] == taps
+
+
 def test_c3_precision_variants(H):
     b = scenes.subset(scenes.c3(), [0, 1])
     ref, taps, rirs = oracle_batch(b)
