@@ -203,7 +203,7 @@ int ism_get_tuning(const ism_handle *h, int *seg_len, int *wg_per_cu, int *graph
  * once untimed and twice timed with HIP events on `stream` (the faster run counts).
  * The winner is kept in the handle and in its cache under the batch's shape bucket
  * (precision, fd_taps, order_mode, fs, ceil(log2 longest RIR), ceil(log2 most
- * microphones)).  out receives the batch's result with the winning configuration.
+ * microphones), ceil(log2 RIRs in the batch)).  out receives the batch's result with the winning configuration.
  * cand / n_cand: segment lengths to try instead of the built-in list (n_cand = 0).
  * *best_seg_len (may be NULL): the chosen segment length.  Synchronises `stream`.
  */

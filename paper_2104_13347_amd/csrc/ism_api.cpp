@@ -690,12 +690,14 @@ static int tune_batch(ism_handle *h, int n_rooms, const ism_room *rooms, const d
 static TuneKey tune_key(int n_rooms, const ism_room *rooms, double fs, int fd_taps, int order_mode, int precision)
 {
     int len = 1, nm = 1;
+    int64_t nr = 0;
     for (int i = 0; i < n_rooms; ++i) {
         len = std::max(len, rooms[i].rir_len);
         nm = std::max(nm, rooms[i].n_mics);
+        nr += rooms[i].n_mics;
     }
-    auto clog2 = [](int v) { int b = 0; while ((1LL << b) < v) ++b; return b; };
-    return TuneKey{precision, fd_taps, order_mode, (long long)std::llround(fs * 1e3), clog2(len), clog2(nm)};
+    auto clog2 = [](int64_t v) { int b = 0; while ((1LL << b) < v) ++b; return b; };
+    return TuneKey{precision, fd_taps, order_mode, (long long)std::llround(fs * 1e3), clog2(len), clog2(nm), clog2(nr)};
 }
 
 static int rir_batch_impl(ism_handle *h, int n_rooms, const ism_room *rooms, const double *mics, double fs,

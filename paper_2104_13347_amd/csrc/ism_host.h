@@ -73,6 +73,8 @@ struct TuneKey {
     long long fs_mhz;   // sample rate in mHz
     int len_bucket;     // ceil(log2(longest RIR))
     int mic_bucket;     // ceil(log2(most microphones of a room))
+    int rir_bucket;     // ceil(log2(RIRs in the batch)): one RIR and thousands of RIRs of the
+                        // same shape fill the chip differently and tune differently
     bool operator<(const TuneKey &o) const
     {
         if (precision != o.precision) return precision < o.precision;
@@ -80,7 +82,8 @@ struct TuneKey {
         if (order_mode != o.order_mode) return order_mode < o.order_mode;
         if (fs_mhz != o.fs_mhz) return fs_mhz < o.fs_mhz;
         if (len_bucket != o.len_bucket) return len_bucket < o.len_bucket;
-        return mic_bucket < o.mic_bucket;
+        if (mic_bucket != o.mic_bucket) return mic_bucket < o.mic_bucket;
+        return rir_bucket < o.rir_bucket;
     }
 };
 struct TuneVal {

@@ -64,6 +64,34 @@ def test_autotune_on_first_use_of_a_bucket(torch_cuda):
         h.close()
 
 
+def test_batch_size_is_part_of_the_bucket(torch_cuda):
+    # one RIR and 4096 RIRs of the same room shape are tuned separately, and the large
+    # batch's tuned configuration is not slower than the small one's choice on it
+    torch = torch_cuda
+    h = ism.Handle()
+    try:
+        h.set_autotune(True)
+        big = scenes.c0_replicated()
+        one = scenes.subset(big, [0])
+        h.rir_batch(one)
+        torch.cuda.synchronize()
+        t1 = h.get_tuning()
+        out = torch.empty(int(big["out_size"]), dtype=torch.float32, device="cuda")
+        h.rir_batch(big, out=out)
+        torch.cuda.synchronize()
+        t2 = h.get_tuning()
+        _say(f"one RIR {t1}, 4096 RIRs {t2}")
+        assert t2["tuned_buckets"] == t1["tuned_buckets"] + 1
+        tuned = _time(torch, h, big, out)
+        h.set_autotune(False)
+        h.set_tuning(seg_len=t1["seg_len"])
+        small_choice = _time(torch, h, big, out)
+        _say(f"4096 RIRs: tuned {tuned:.3f} ms, with the one-RIR choice {small_choice:.3f} ms")
+        assert tuned <= small_choice * 1.05
+    finally:
+        h.close()
+
+
 def _time(torch, h, b, out, reps=3):
     ts = []
     for _ in range(reps + 1):
