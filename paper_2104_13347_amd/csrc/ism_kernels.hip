@@ -123,6 +123,19 @@ DEV int wave_incl_scan_dpp(int x)
     return x;
 }
 
+// The same pattern with max: lane 63 ends with the largest of the 64 values (x >= 0;
+// lanes with no source take 0).
+DEV uint32_t wave_incl_max_dpp(uint32_t x)
+{
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));
+    return x;
+}
+
 DEV void lds_add(float *p, float v)
 {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -357,6 +370,25 @@ DEV ItemDev load_item(const LaunchDev *P, int i)
 }
 
 DEV CRoomDev *room_ptr(const LaunchDev *P, int room) { return (CRoomDev *)P->rooms + room; }
+
+// Writes through generic pointers compile to flat instructions, which a wave counts among
+// its LDS operations as well: every later wait for LDS (each barrier) would also wait for
+// an output store or the item counter's atomic to complete.  The kernels write through
+// the global address space instead.
+typedef __attribute__((address_space(1))) float GFloat;
+DEV GFloat *global_out(float *p) { return (GFloat *)p; }
+
+// Next work item, fetched by one lane.  The counter's address goes through an empty asm
+// (a value the compiler cannot see to be uniform), so the atomic is not rewritten into a
+// wave-wide one, whose result the compiler would wait for at once: the wait comes where
+// the index is used.
+DEV int fetch_item(uint32_t *counter)
+{
+    uint64_t a = (uint64_t)counter;
+    asm volatile("" : "+v"(a));
+    return (int)__hip_atomic_fetch_add((__attribute__((address_space(1))) uint32_t *)a, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ---------------------------------------------------------------- item geometry
 // Everything about one work item (room, microphone, output segment [s0, s1)) that the
@@ -676,7 +708,7 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
 
     for (;;) {
         int item = 0;
-        if (lane == 0) item = (int)atomicAdd(P->counter, 1u);
+        if (lane == 0) item = fetch_item(P->counter);
         item = uniform(__shfl(item, 0, 64));
         if (item >= P->n_items) break;
 
@@ -819,7 +851,7 @@ __global__ __launch_bounds__(64) void ism_segments(const LaunchDev *__restrict__
 
         // ---- store the segment (coalesced), then clear the accumulator
         CRoomDev &R = *room_ptr(P, it.room);
-        float *o = P->out + R.out_offset + (long)(it.mic - R.mic_offset) * G.rir_len + s0;
+        GFloat *o = global_out(P->out) + R.out_offset + (long)(it.mic - R.mic_offset) * G.rir_len + s0;
         if (VAR == VAR_F32ATOM) {
             for (int i = lane; i < Sn; i += 64) o[i] = S.acc32[2 * K + i];
         } else {
@@ -1047,6 +1079,12 @@ DEV f16x8_t lds_f16x8_a4(const _Float16 *p)
     return __builtin_bit_cast(f16x8_t, v);
 }
 
+// Partial tiles of the filter: per wave 16 rows of 16 floats, kPartPitch floats apart, at
+// the start of the bins' area; kPartU4 16-byte units for all waves.
+constexpr int kPartPitch = 17;
+constexpr int kPartU4 = kMomWaves * 16 * kPartPitch * 4 / 16;
+static_assert(kMomWaves * 16 * kPartPitch * 4 % 16 == 0, "whole 16-byte units");
+
 // RED = true: the reduced-precision form (ISM_PREC_FP16_LUT on this kernel): kMomRed = 6
 // Chebyshev terms (truncation below 1.3e-4 of max|h|), FP16 bins and FP16 coefficients
 // without their low halves, one matrix-core product per step; delays, distances and the
@@ -1118,7 +1156,15 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             S.c16[((sh * 2 + 1) * kMom + m) * CL + idx] = lo;
         }
     }
-    if (tid == 0) S.item[0] = (int)atomicAdd(P->counter, 1u);
+    // The bins are cleared here for the first item; for later items their area beyond the
+    // partial tiles is cleared during the previous item's filter and the partial tiles'
+    // area at the item's start, once the store has read it.
+    typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+    u32x4_t *const zb = (u32x4_t *)S.U;
+    const u32x4_t zero4 = {0u, 0u, 0u, 0u};
+    static_assert(NM * mom_ustride(KT) / 2 >= kPartU4, "the bins cover the partial tiles");
+    for (int i = tid; i < nU / 2; i += kMomThreads) zb[i] = zero4;
+    if (tid == 0) S.item[0] = fetch_item(P->counter);
     __syncthreads();
     {
         const int first = uniform(S.item[0]);
@@ -1132,12 +1178,8 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
     for (int iter = 0;; ++iter) {
         const int item = uniform(S.item[iter & 1]);
         if (item >= P->n_items) break;
-        {   // zero the bins, 16 bytes per store (nU is even)
-            typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
-            u32x4_t *z = (u32x4_t *)S.U;
-            const u32x4_t zero = {0u, 0u, 0u, 0u};
-            for (int i = tid; i < nU / 2; i += kMomThreads) z[i] = zero;
-        }
+        // the partial tiles' area of the bins (the rest was cleared during the last filter)
+        for (int i = tid; i < kPartU4; i += kMomThreads) zb[i] = zero4;
         if (tid == 0) {
             S.bmax[0] = 0u;
             S.bmax[1] = 0u;
@@ -1156,7 +1198,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         // the next item's index, fetched now, published at the first batch barrier and first
         // used after the enumeration (every item has at least one column batch)
         int nxt_fetch = 0;
-        if (wave == kMomWaves - 1 && lane == 0) nxt_fetch = (int)atomicAdd(P->counter, 1u);
+        if (wave == kMomWaves - 1 && lane == 0) nxt_fetch = fetch_item(P->counter);
         __syncthreads();  // bins zeroed, tables of this item complete
 
         // ---- records: moments into the delay bins.  Each wave takes chunks of 64 columns
@@ -1302,16 +1344,13 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         {
             long long mx = 0;
             for (int i = tid; i < NB; i += kMomThreads) mx = max(mx, S.U[i]);
-            float fm = (float)mx;
-            uint32_t rc = rec_item;
-#pragma unroll
-            for (int dd = 32; dd >= 1; dd >>= 1) {
-                fm = fmaxf(fm, __shfl_xor(fm, dd, 64));
-                rc += __shfl_xor(rc, dd, 64);
-            }
-            if (lane == 0) {
-                if (fm > 0.0f) atomicMax(S.bmax, __float_as_uint(fm));
-                atomicAdd(S.bmax + 1, rc);
+            // the wave's largest bin and record total by DPP moves, in lane 63 (mx >= 0, so
+            // FP32 bit patterns order as the values)
+            const uint32_t fb = wave_incl_max_dpp(__float_as_uint((float)mx));
+            const int rc = wave_incl_scan_dpp((int)rec_item);
+            if (lane == 63) {
+                if (fb) atomicMax(S.bmax, fb);
+                atomicAdd(S.bmax + 1, (uint32_t)rc);
             }
         }
         __syncthreads();
@@ -1398,22 +1437,25 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                 }
             }
             if (fill) table_store(tid, tv);
-            // the int64 bins are no longer read: their area takes the partial tiles
-            float *part = (float *)S.U + wave * 256;  // D[i][b]: b = lane % 16, i = 4 (lane / 16) + v
+            // the int64 bins are no longer read: their area takes the partial tiles, rows
+            // kPartPitch floats apart (the store below reads down a column without bank
+            // conflicts), and the rest is cleared for the next item
+            float *part = (float *)S.U + wave * 16 * kPartPitch;  // D[i][b]: b = lane % 16, i = 4 (lane / 16) + v
 #pragma unroll
-            for (int v = 0; v < 4; ++v) part[(4 * kq + v) * 16 + r16] = acc[v];
+            for (int v = 0; v < 4; ++v) part[(4 * kq + v) * kPartPitch + r16] = acc[v];
+            for (int i = kPartU4 + tid; i < nU / 2; i += kMomThreads) zb[i] = zero4;
         }
         __syncthreads();
         {
             CRoomDev &R = *room_ptr(P, it.room);
-            float *o = P->out + R.out_offset + (long)(it.mic - R.mic_offset) * G.rir_len + G.s0;
+            GFloat *o = global_out(P->out) + R.out_offset + (long)(it.mic - R.mic_offset) * G.rir_len + G.s0;
             const double inv = ldexp(1.0, -G.escale - bexp - P->coef_exp);
             const float *part = (const float *)S.U;
             for (int i = tid; i < G.Sn; i += kMomThreads) {
                 const int blk = i >> 4, row = i & 15, tl = blk >> 4, col = blk & 15;
                 double v = 0.0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v += (double)part[(tl + 4 * q) * 256 + row * 16 + col];
+                for (int q = 0; q < 4; ++q) v += (double)part[(tl + 4 * q) * 16 * kPartPitch + row * kPartPitch + col];
                 o[i] = (float)(v * inv);
             }
         }
