@@ -96,11 +96,15 @@ constexpr int mom_cl(int K) { return mom_jp(K) + 32; }
 // records after them stay aligned.
 constexpr int mom_u_bytes(int K) { return (kMom * mom_ustride(K) * 8 + 127) & ~127; }
 
+// LDS bytes that hold one work item's geometry (the kernel checks its struct fits).
+constexpr int kMomGeomBytes = 256;
+
 inline int mom_lds_bytes(int K)
 {
     const int cols = 64 * kMomSetupWaves;
     int bytes = mom_u_bytes(K);
     bytes += cols * 48 + kMomSetupWaves * 4 + 32;                  // column records, slots
+    bytes += kMomGeomBytes;                                        // the next item's geometry
     bytes += 2 * 4 * kPowCap * 8;                                  // z and x/y wall powers
     bytes += 4 * kMom * mom_cl(K) * 2;                             // FP16 coefficient rows
     return bytes;

@@ -472,6 +472,21 @@ DEV ItemGeom item_geom(const LaunchDev *P, const ItemDev &it, int K)
     return G;
 }
 
+// An item's geometry as one wave wrote it to LDS, read back word by word into scalar
+// registers (every lane reads the same words).
+static_assert(sizeof(ItemGeom) <= kMomGeomBytes && sizeof(ItemGeom) % 4 == 0, "geometry fits its LDS area");
+DEV ItemGeom geom_from_lds(const ItemGeom *g)
+{
+    constexpr int NW = sizeof(ItemGeom) / 4;
+    const uint32_t *src = (const uint32_t *)g;
+    uint32_t w[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    ItemGeom G;
+    __builtin_memcpy(&G, w, sizeof G);
+    return G;
+}
+
 // One (x, y) image column: the z-index intervals whose images lie in the item's
 // distance shell (two parities w, each an interval with the inner hole cut out, so
 // at most four), the squared horizontal distance, the x/y wall-power product and the
@@ -1036,7 +1051,9 @@ struct MomLds {
     double *pxy;           // [4 kPowCap] x0, xL, y0, yL wall powers, kPowCap apart
     _Float16 *c16;         // [2 shifts][hi, lo][kMom][CL] FP16 coefficient rows (see the kernel)
     int32_t *item;         // [2] current and next item
-    uint32_t *bmax;        // [2] largest channel-0 bin of the item (FP32 bits), its records
+    uint32_t *bmax;        // [4] largest channel-0 bin of the item (FP32 bits), its records,
+                           // waves out of columns
+    ItemGeom *gnext;       // the next item's geometry
 };
 
 DEV MomLds mom_carve(char *base, int K)
@@ -1050,7 +1067,8 @@ DEV MomLds mom_carve(char *base, int K)
     s.c16 = (_Float16 *)p; p += (size_t)4 * kMom * mom_cl(K) * 2;
     s.chunk = (int32_t *)p; p += kMomSetupWaves * 4;
     s.item = (int32_t *)p; p += 16;
-    s.bmax = (uint32_t *)p;  // 2 words
+    s.bmax = (uint32_t *)p; p += 16;
+    s.gnext = (ItemGeom *)p;   // 16-byte aligned: every area above is a multiple of 16 bytes
     return s;
 }
 
@@ -1135,9 +1153,9 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         S.pzz[i] = v[0] * v[1];
         S.pxy[i] = v[2];
     };
-    // The index of the current item alternates between S.item[0] and S.item[1]: the last
-    // wave fetches the next item at the start of the current one; its tables are filled
-    // during the filter.
+    // The index of the current item alternates between S.item[0] and S.item[1]: the first
+    // wave to run out of columns fetches the next item and writes its geometry to LDS; its
+    // tables are filled during the filter.
     // FP16 coefficient rows of the filter (see there): row (sh, hl, m) holds at index i the
     // reversed tap t = i + sh - 16 of channel m, c[m][2K - t] (zero outside [0, 2K]),
     // scaled by 2^coef_exp, as hi = fp16(c) (hl = 0) and lo = fp16(c - hi) (hl = 1); the
@@ -1168,6 +1186,10 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
     __syncthreads();
     {
         const int first = uniform(S.item[0]);
+        if (first < P->n_items && wave == 0) {
+            const ItemGeom G0 = item_geom(P, load_item(P, first), K);
+            if (lane == 0) *S.gnext = G0;
+        }
         if (first < P->n_items && tid < kTab) {
             CItemDev &f = ((CItemDev *)P->items)[first];
             double tv[3];
@@ -1175,6 +1197,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             table_store(tid, tv);
         }
     }
+    __syncthreads();  // the first item's geometry
     for (int iter = 0;; ++iter) {
         const int item = uniform(S.item[iter & 1]);
         if (item >= P->n_items) break;
@@ -1183,10 +1206,13 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         if (tid == 0) {
             S.bmax[0] = 0u;
             S.bmax[1] = 0u;
+            S.bmax[2] = 0u;
             S.chunk[0] = 0;
         }
         const ItemDev it = load_item(P, item);
-        const ItemGeom G = item_geom(P, it, K);
+        // the geometry the first wave out of columns derived during the last item (the first
+        // item's, by wave 0 before the loop)
+        const ItemGeom G = geom_from_lds(S.gnext);
         const double gk = 0.07957747154594767 * ldexp(1.0, G.escale);  // 2^e / (4 pi), exact scaling
         // taps landing in [s0, s1) per record: W minus those cut at either end,
         // max(0, tL - n0) + max(0, n0 - tR) = |med3(n0, lo, hi) - n0| + max(0, tL - tR)
@@ -1195,10 +1221,6 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         uint32_t rec_item = 0, loss_item = 0;
         // rounding-boundary test of the delay split (image_eval_z)
         const double ec = half - 0.5, ethr = 0.5 - 1e-12 * ((double)G.nhi + 2.0);
-        // the next item's index, fetched now, published at the first batch barrier and first
-        // used after the enumeration (every item has at least one column batch)
-        int nxt_fetch = 0;
-        if (wave == kMomWaves - 1 && lane == 0) nxt_fetch = fetch_item(P->counter);
         __syncthreads();  // bins zeroed, tables of this item complete
 
         // ---- records: moments into the delay bins.  Each wave takes chunks of 64 columns
@@ -1210,7 +1232,24 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
             int ch = 0;
             if (lane == 0) ch = atomicAdd(S.chunk, 1);
             const int c0 = 64 * __builtin_amdgcn_readfirstlane(__shfl(ch, 0, 64));
-            if (c0 >= G.ncols) break;
+            if (c0 >= G.ncols) {
+                // The first wave out of columns fetches the next item and derives its
+                // geometry into LDS (while the other waves finish their chunks); the index
+                // is published for the table loads after the enumeration barrier.
+                uint32_t out = 0;
+                if (lane == 0) out = atomicAdd(S.bmax + 2, 1u);
+                if (__builtin_amdgcn_readfirstlane(out) == 0) {
+                    int nx = 0;
+                    if (lane == 0) nx = fetch_item(P->counter);
+                    nx = __builtin_amdgcn_readfirstlane(nx);
+                    if (nx < P->n_items) {
+                        const ItemGeom GN = item_geom(P, load_item(P, nx), K);
+                        if (lane == 0) *S.gnext = GN;
+                    }
+                    if (lane == 0) S.item[(iter + 1) & 1] = nx;
+                }
+                break;
+            }
             const MomColSetup C = mom_column(G, c0 + lane, order_mode, S.pxy, kPowCap);
             __builtin_amdgcn_s_setprio(0);
             const int ctot = C.ctot;
@@ -1315,8 +1354,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                 }
             }
         }
-        if (wave == kMomWaves - 1 && lane == 0) S.item[(iter + 1) & 1] = nxt_fetch;
-        __syncthreads();  // every chunk of the item is binned
+        __syncthreads();  // every chunk of the item is binned; the next item's index and geometry
 
         n_rec += rec_item;
         n_taps += (unsigned long long)rec_item * (unsigned)(kmax - kmin + 1 - max(0, tL - tR)) - loss_item;
