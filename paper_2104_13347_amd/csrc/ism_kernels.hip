@@ -392,13 +392,16 @@ DEV int fetch_item(uint32_t *counter)
 
 // ---------------------------------------------------------------- item geometry
 // Everything about one work item (room, microphone, output segment [s0, s1)) that the
-// enumeration needs, derived once per item.
+// enumeration needs, derived once per item.  Table pointers carry the global address space
+// (generic pointers would make their loads flat instructions, which waves count among
+// their LDS operations).
+typedef const __attribute__((address_space(1))) double GConstDouble;
 struct ItemGeom {
     double Lx, Ly, Lz, sx, sy, sz, rx, ry, rz;
     double dlo2, dhi2;            // squared distance shell of the item's records
     double zeps;                  // margin of the column intervals' z bounds (in z-index units)
     double inv2Lz;                // 1 / (2 Lz) (its rounding is inside the margin)
-    const double *px0, *pz0, *pzL;
+    GConstDouble *px0, *pz0, *pzL; // the room's wall-power tables (global memory)
     int alo, blo;                 // first (x, y) image column indices
     float inv_nb;                 // 1 / nb
     int pow_stride, pmax;
@@ -426,7 +429,7 @@ DEV ItemGeom item_geom(const LaunchDev *P, const ItemDev &it, int K)
     G.nlo = max(G.s0 - kmax, 0);
     G.nhi = min(G.s1 - 1 - kmin, G.rir_len - 1 - kmin);
     G.rel = G.s0 - K;
-    G.px0 = P->pow_tab + R.pow_offset;
+    G.px0 = (GConstDouble *)(P->pow_tab + R.pow_offset);
     G.pz0 = G.px0 + 4 * R.pow_stride;
     G.pzL = G.pz0 + R.pow_stride;
     G.pow_stride = R.pow_stride;
@@ -498,7 +501,7 @@ struct Column {
 };
 
 // px: x0, xL, y0, yL wall-power tables, `ps` apart (exponents 0 .. pmax)
-DEV Column column_setup(const ItemGeom &G, int ci, int order_mode, const double *px, int ps)
+DEV Column column_setup(const ItemGeom &G, int ci, int order_mode, GConstDouble *px, int ps)
 {
     Column C;
 #pragma unroll
