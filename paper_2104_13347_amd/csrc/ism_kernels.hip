@@ -1100,11 +1100,12 @@ DEV f16x8_t lds_f16x8_a4(const _Float16 *p)
     return __builtin_bit_cast(f16x8_t, v);
 }
 
-// Partial tiles of the filter: per wave 16 rows of 16 floats, kPartPitch floats apart, at
-// the start of the bins' area; kPartU4 16-byte units for all waves.
+// Partial tiles of the filter, one per (channel, tile of 256 output samples): 16 rows of 16
+// floats, kPartPitch floats apart, at the start of the bins' area; kPartU4 16-byte units.
 constexpr int kPartPitch = 17;
-constexpr int kPartU4 = kMomWaves * 16 * kPartPitch * 4 / 16;
-static_assert(kMomWaves * 16 * kPartPitch * 4 % 16 == 0, "whole 16-byte units");
+constexpr int kPartTiles = kMom * 4;
+constexpr int kPartU4 = kPartTiles * 16 * kPartPitch * 4 / 16;
+static_assert(kPartTiles * 16 * kPartPitch * 4 % 16 == 0, "whole 16-byte units");
 
 // RED = true: the reduced-precision form (ISM_PREC_FP16_LUT on this kernel): kMomRed = 6
 // Chebyshev terms (truncation below 1.3e-4 of max|h|), FP16 bins and FP16 coefficients
@@ -1448,42 +1449,77 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         //      A_m[r][j] = c_m[2K - (j - r)] (zero outside the band), B_m[j][b] = bin 16 b + j,
         //      j in [0, JP), 32 per step.  Lane l holds A[l % 16][8 (l / 16) + e] and
         //      B[8 (l / 16) + e][l % 16], e < 8, and D[4 (l / 16) + v][l % 16] in acc[v].
-        // Wave w takes the 16 output blocks of tile w % 4 (256 samples) and the channels
-        // w / 4, w / 4 + 4, ...; the 4 waves of a tile are summed after.
+        // Wave w < 8 takes channel w over the 4 tiles of 256 output samples (one accumulator
+        // per tile), so a step's coefficient fragments are read once for the four tiles; a
+        // ninth channel goes one tile each to waves 12..15 (one per SIMD).  The partial tile
+        // of each (channel, tile) is summed over the channels in the store.
         {
             constexpr int JP = mom_jp(K), NS = JP / 32;
-            const int tile = wave & 3, r16 = lane & 15, kq = lane >> 4;
-            f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            const int r16 = lane & 15, kq = lane >> 4;
             // the next item's wall-power table entries: loads issued before the tasks, stored
             // after them (this item no longer reads the tables)
             double tv[3];
             if (fill) table_load(nxt_pow_offset, nxt_pow_stride, tid, tv);
-            for (int m = wave >> 2; m < NM; m += 4) {
-                const int bb = m * NBP + 256 * tile + 16 * r16 + 8 * kq;  // this lane's bins, step 0
+            // A fragments of channel m, step s: taps j - r = 32 s + 8 kq + e - r, stored at
+            // index + 16; odd starts read the copy shifted by one
+            auto coef_row = [&](int m, int s) {
+                const int t0 = 32 * s + 8 * kq - r16 + 16, sh = t0 & 1;
+                return S.c16 + ((sh * 2) * kMom + m) * CL + (t0 - sh);
+            };
+            // the int64 bins are no longer read: their area takes the partial tiles, rows
+            // kPartPitch floats apart (the store below reads down a column without bank
+            // conflicts); D[i][b]: b = lane % 16, i = 4 (lane / 16) + v
+            auto put_part = [&](int m, int tile, const f32x4_t &acc) {
+                float *part = (float *)S.U + (m * 4 + tile) * 16 * kPartPitch;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) part[(4 * kq + v) * kPartPitch + r16] = acc[v];
+            };
+            if (wave < 8 && wave < NM) {
+                const int m = wave;
+                f32x4_t acc[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[t] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+                for (int s = 0; s < NS; ++s) {
+                    const _Float16 *crow = coef_row(m, s);
+                    const f16x8_t ah = lds_f16x8_a4(crow);
+                    f16x8_t al;
+                    if (!RED) al = lds_f16x8_a4(crow + kMom * CL);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int bb = m * NBP + 256 * t + 16 * r16 + 8 * kq + 32 * s;
+                        const f16x8_t bh = *(const f16x8_t *)(Uh + bb);
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, acc[t], 0, 0, 0);
+                        if (!RED) {
+                            const f16x8_t bl = *(const f16x8_t *)(Ul + bb);
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, acc[t], 0, 0, 0);
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, acc[t], 0, 0, 0);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) put_part(m, t, acc[t]);
+            } else if (NM > 8 && wave >= 12) {
+                const int m = 8, t = wave - 12;
+                f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    // taps j - r = 32 s + 8 kq + e - r, stored at index + 16; odd starts read the
-                    // copy shifted by one
-                    const int t0 = 32 * s + 8 * kq - r16 + 16, sh = t0 & 1;
-                    const _Float16 *crow = S.c16 + ((sh * 2) * kMom + m) * CL + (t0 - sh);
+                    const _Float16 *crow = coef_row(m, s);
+                    const int bb = m * NBP + 256 * t + 16 * r16 + 8 * kq + 32 * s;
                     const f16x8_t ah = lds_f16x8_a4(crow);
-                    const f16x8_t bh = *(const f16x8_t *)(Uh + bb + 32 * s);
+                    const f16x8_t bh = *(const f16x8_t *)(Uh + bb);
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, acc, 0, 0, 0);
                     if (!RED) {
                         const f16x8_t al = lds_f16x8_a4(crow + kMom * CL);
-                        const f16x8_t bl = *(const f16x8_t *)(Ul + bb + 32 * s);
+                        const f16x8_t bl = *(const f16x8_t *)(Ul + bb);
                         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, acc, 0, 0, 0);
                         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, acc, 0, 0, 0);
                     }
                 }
+                put_part(m, t, acc);
             }
             if (fill) table_store(tid, tv);
-            // the int64 bins are no longer read: their area takes the partial tiles, rows
-            // kPartPitch floats apart (the store below reads down a column without bank
-            // conflicts), and the rest is cleared for the next item
-            float *part = (float *)S.U + wave * 16 * kPartPitch;  // D[i][b]: b = lane % 16, i = 4 (lane / 16) + v
-#pragma unroll
-            for (int v = 0; v < 4; ++v) part[(4 * kq + v) * kPartPitch + r16] = acc[v];
+            // the rest of the bins' area is cleared for the next item
             for (int i = kPartU4 + tid; i < nU / 2; i += kMomThreads) zb[i] = zero4;
         }
         __syncthreads();
@@ -1496,7 +1532,7 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
                 const int blk = i >> 4, row = i & 15, tl = blk >> 4, col = blk & 15;
                 double v = 0.0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v += (double)part[(tl + 4 * q) * 16 * kPartPitch + row * kPartPitch + col];
+                for (int m = 0; m < NM; ++m) v += (double)part[(m * 4 + tl) * 16 * kPartPitch + row * kPartPitch + col];
                 o[i] = (float)(v * inv);
             }
         }
