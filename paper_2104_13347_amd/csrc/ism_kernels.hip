@@ -1405,32 +1405,38 @@ __global__ __launch_bounds__(kMomThreads) void ism_moments(const LaunchDev *__re
         }
         _Float16 *Uh = (_Float16 *)S.col, *Ul = Uh + kMom * NBP;
         {
-            // work units (bin i, group of 3 channels); the bin sums are below 2^53, so the
+            // work units (bins i, i + 1, group of 3 channels); the bin sums are below 2^53, so the
             // doubles are exact, and so is fma(U_m, 2^bexp, -U_0 2^bexp); one rounding to FP32
             const double bs = ldexp(1.0, bexp);
             auto u64d = [](long long v) {  // exact for 0 <= v < 2^53
                 const unsigned long long u = (unsigned long long)v;
                 return fma((double)(uint32_t)(u >> 32), 4294967296.0, (double)(uint32_t)u);
             };
-            auto put = [&](int e, float x) {
-                const _Float16 hi = (_Float16)x;
-                Uh[e] = hi;
-                if (!RED) Ul[e] = (_Float16)(x - (float)hi);
+            // two consecutive bins per work unit: 16-byte reads of the int64 pairs and 4-byte
+            // writes of the FP16 pairs (NB, NBP and the channel stride are even)
+            static_assert(NB % 2 == 0 && NBP % 2 == 0 && mom_ustride(KT) % 2 == 0, "bin pairs");
+            typedef long long i64x2_t __attribute__((ext_vector_type(2)));
+            typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+            auto put2 = [&](int e, float xa, float xb) {
+                const f16x2_t hi = {(_Float16)xa, (_Float16)xb};
+                *(f16x2_t *)(Uh + e) = hi;
+                if (!RED) *(f16x2_t *)(Ul + e) = f16x2_t{(_Float16)(xa - (float)hi[0]), (_Float16)(xb - (float)hi[1])};
             };
-            for (int w = tid; w < (NM / 3) * NB; w += kMomThreads) {
-                const int g = w / NB, i = w - g * NB;
+            constexpr int NB2 = NB / 2;
+            for (int w = tid; w < (NM / 3) * NB2; w += kMomThreads) {
+                const int g = w / NB2, i = 2 * (w - g * NB2);
                 // all four reads first (the stores below may alias them as far as the compiler
                 // knows, and would otherwise wait for each read in turn)
-                const long long v0 = S.U[i];
-                long long v[3];
+                const i64x2_t v0 = *(const i64x2_t *)(S.U + i);
+                i64x2_t v[3];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) v[k] = S.U[(3 * g + k) * ustride + i];
-                const double u0s = u64d(v0) * bs;
+                for (int k = 0; k < 3; ++k) v[k] = *(const i64x2_t *)(S.U + (3 * g + k) * ustride + i);
+                const double u0a = u64d(v0[0]) * bs, u0b = u64d(v0[1]) * bs;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const int m = 3 * g + k;
-                    const double d = fma(u64d(v[k]), bs, -u0s);
-                    put(m * NBP + i, (float)(m ? d : u0s));
+                    const double da = fma(u64d(v[k][0]), bs, -u0a), db = fma(u64d(v[k][1]), bs, -u0b);
+                    put2(m * NBP + i, (float)(m ? da : u0a), (float)(m ? db : u0b));
                 }
             }
             if constexpr (NBP > NB) {  // zeros past the last delay
