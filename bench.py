@@ -643,7 +643,9 @@ def main():
     res["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                        "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
                        "basis": "algorithmic: 12 flops per tap of the direct per-tap method (the work the "
-                                "output represents), not the instructions this kernel issues; see 'executed'",
+                                "output represents), not the instructions this kernel issues, so frac can pass 1: "
+                                "the moment kernel spends about 1/13 of those flops per tap (9 moments per "
+                                "record, one shared filter per output sample); see 'executed'",
                        "kernel": kernel, "launch_ms": k_ms, "launch_ms_min": float(np.min(launch_ms)),
                        "launch_ms_median": float(np.median(launch_ms)),
                        "flops_per_tap": FLOPS_PER_TAP, "taps_per_launch": taps}
