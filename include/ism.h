@@ -246,7 +246,11 @@ int ism_get_launch_tuning(const ism_handle *h, int *seg_len, int *wg_per_cu, int
  *   Asynchronous on `stream`.  The handle keeps two workspaces (BF16 RIRs, tile power
  *   sums, room table) used by alternate calls: a call waits on the host only for the
  *   work of the call before the previous one, so back-to-back calls overlap their host
- *   work with the device work of the last.
+ *   work with the device work of the last.  Calls may go to different streams (a
+ *   workspace is reused only after the host has waited for the call that last used it,
+ *   on whatever stream): calls in turn on two streams, with separate outputs, overlap
+ *   one call's noise pass with the next call's convolution.  Calls on one handle are
+ *   issued from one host thread at a time.
  */
 int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float *rirs,
                        const int64_t *rir_offset, const int32_t *rir_len, const float *src,
