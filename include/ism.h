@@ -249,8 +249,7 @@ int ism_get_launch_tuning(const ism_handle *h, int *seg_len, int *wg_per_cu, int
  *   work with the device work of the last.  Calls may go to different streams (a
  *   workspace is reused only after the host has waited for the call that last used it,
  *   on whatever stream): calls in turn on two streams, with separate outputs, overlap
- *   one call's noise pass with the next call's convolution.  Calls on one handle are
- *   issued from one host thread at a time.
+ *   one call's noise pass with the next call's convolution.
  */
 int ism_convolve_batch(ism_handle *h, int n_rooms, int M, const float *rirs,
                        const int64_t *rir_offset, const int32_t *rir_len, const float *src,
