@@ -11,8 +11,9 @@
 // T_s depends on s only, so one workgroup (one wave) keeps 16 output blocks x 8
 // microphones = 128 columns (four 32-column MFMA tiles sharing every A operand) and
 // walks s.  Per s: A = T_s from a 128-sample source ring in LDS (BF16, reversed and
-// stored twice, so each lane's eight K values are consecutive there; read as dwords
-// and realigned with v_alignbit), the ring gaining one 32-sample block per step;
+// stored twice, so each lane's eight K values are consecutive there, plus a copy one
+// entry later, so they start on a 4-byte boundary of one of the two: four dword reads),
+// the ring gaining one 32-sample block per step;
 // B = the RIR blocks b = t - s from a 16-slot LDS ring that gains one block per
 // step, of which three tiles' operands carry over from the previous step in
 // registers; eight v_mfma_f32_32x32x16_bf16, issued while the next step's operands
@@ -122,7 +123,8 @@ __global__ __launch_bounds__(256) void conv_pack_h(const float *__restrict__ rir
 
 // ------------------------------------------------------------------ MFMA block-Toeplitz
 // grid (tiles, rooms), one wave.  LDS: a 128-sample source ring (BF16, reversed,
-// stored twice so that any 10-sample window is contiguous) and a CG-slot RIR ring.
+// stored twice so that any 8-sample window is contiguous, and a copy shifted by one
+// entry) and a CG-slot RIR ring.
 constexpr int XR = 128;   // source ring length (samples)
 constexpr int kBufWord3 = 0x00020000;   // buffer descriptor word 3 (gfx9 family: raw 32-bit data)
 // RIR ring: two halves (taps 0-15 and 16-31 of a block), each CG x 8 rows (a slot per block,
@@ -144,7 +146,10 @@ __global__ __launch_bounds__(64, CONV_MW) void conv_mfma(const float *__restrict
                                                 float *__restrict__ y, double *__restrict__ psum,
                                                 int tiles_per_room)
 {
+    // source ring (below) and its copy one entry later, so that a fragment starting at an
+    // odd entry starts on a 4-byte boundary of the copy
     __shared__ __attribute__((aligned(16))) uint16_t xring[2 * XR];
+    __shared__ __attribute__((aligned(16))) uint16_t xring1[2 * XR + 8];
     __shared__ __attribute__((aligned(16))) uint16_t ring[2 * CRH];
     const int lane = threadIdx.x;
     // Workgroups are dealt to the 8 XCDs round-robin in launch order, and each XCD has
@@ -187,6 +192,8 @@ __global__ __launch_bounds__(64, CONV_MW) void conv_mfma(const float *__restrict
             const int p = (-X) & (XR - 1);
             xring[p] = bv;
             xring[p + XR] = bv;
+            xring1[p + 1] = bv;
+            xring1[p + 1 + XR] = bv;
         }
     };
     // RIR ring: slot (b mod CG) holds block b of all microphones (zeros outside [0, nb));
@@ -237,11 +244,11 @@ __global__ __launch_bounds__(64, CONV_MW) void conv_mfma(const float *__restrict
 
     const int i = lane & 31;           // A row / B column within a tile
     const int kk0 = (lane >> 5) * 8;   // first K index of this lane's eight
-    const uint32_t *xr32 = (const uint32_t *)xring;
+    const uint32_t *xr32 = (const uint32_t *)xring, *xr32s = (const uint32_t *)xring1;
     // one step: Y_t += T_s H_{t - s} for the CG output blocks t0 .. t0 + CG - 1.  The A
     // fragments of T_s are x[X - e], X = 32 s + i - 16 ks - kk0, e = 0..7: ring entry
     // p = (-X) mod 128 for ks = 0 and p + 16 for ks = 1 (the ring is stored twice, so no
-    // wrap); read as the dwords w = p / 2 .. w + 4 and realigned by 16 (p mod 2) bits.
+    // wrap); read as four dwords from the ring (p even) or its shifted copy (p odd).
     // B operand: column i of MFMA tile nt is output block tl = NT (i / 8) + nt of microphone
     // i % 8, so from one step to the next the operand of tile nt is the previous step's
     // operand of tile nt - 1 (the same registers): each step reads only tile 0's operand,
@@ -254,17 +261,15 @@ __global__ __launch_bounds__(64, CONV_MW) void conv_mfma(const float *__restrict
         b0 = *(const u32x4_t *)bp;
         b1 = *(const u32x4_t *)(bp + CRH);
     };
-    // A operand of step s: the Toeplitz fragments read from the source ring at dword w,
-    // realigned by sh bits
-    auto read_a = [&](int w, uint32_t sh, bf16x8_t (&a)[2]) {
+    // A operand of step s: the Toeplitz fragments starting at ring entry p, read as four
+    // dwords from the ring (p even) or from its copy one entry later (p odd)
+    auto read_a = [&](int p, bf16x8_t (&a)[2]) {
+        const uint32_t *src = (p & 1) ? xr32s + ((p + 1) >> 1) : xr32 + (p >> 1);
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-            uint32_t d[5];
-#pragma unroll
-            for (int k = 0; k < 5; ++k) d[k] = xr32[w + 8 * ks + k];
             u32x4_t v;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = __builtin_amdgcn_alignbit(d[k + 1], d[k], sh);
+            for (int k = 0; k < 4; ++k) v[k] = src[8 * ks + k];
             a[ks] = __builtin_bit_cast(bf16x8_t, v);
         }
     };
@@ -295,13 +300,15 @@ __global__ __launch_bounds__(64, CONV_MW) void conv_mfma(const float *__restrict
             const uint16_t bv = f2bf(xq[q]);
             xring[pe] = bv;
             xring[pe + XR] = bv;
+            xring1[pe + 1] = bv;
+            xring1[pe + 1 + XR] = bv;
         }
         hq[q] = load_block(t0 - u - PD);
         xq[q] = load_x(u + PD);
         __syncthreads();
         bf16x8_t a_nx[2];
         u32x4_t bn0, bn1;
-        read_a(pe >> 1, (uint32_t)(pe & 1) * 16u, a_nx);
+        read_a(pe, a_nx);
         read_b(u, 0, bn0, bn1);
         mma(a_cur, j & (NT - 1));   // step u - 1: (u - 1 - s_start) mod NT = j mod NT
         const int sl = (-(1 + j)) & (NT - 1);   // tile 0's slot at step u
@@ -312,7 +319,7 @@ __global__ __launch_bounds__(64, CONV_MW) void conv_mfma(const float *__restrict
     };
     {
         const int p0 = ring_entry(s_start);
-        read_a(p0 >> 1, (uint32_t)(p0 & 1) * 16u, a_cur);
+        read_a(p0, a_cur);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) read_b(s_start, nt, bq[0][nt], bq[1][nt]);
     }
