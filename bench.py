@@ -232,7 +232,7 @@ def bench_paper(H, torch):
     return res
 
 
-def bench_c4(H, torch, with_errors=True):
+def bench_c4(H, torch, with_errors=True, two_streams=True):
     """256 rooms (1024-room distribution, seed 2108), 8 mics: RIR batch on the GPU, then convolution
     with 1 s white-noise sources and sensor noise at SNR U[0,30] dB.  With errors: the noisy
     recordings of rooms 0, 128 and 255 against the FP64 oracle's convolution of the same GPU RIRs
@@ -274,7 +274,7 @@ def bench_c4(H, torch, with_errors=True):
             H.set_conv_timing(False)
         kpk, kcv, knz = (float(np.median([t[i] for t in kt])) for i in range(3))
         two = {}
-        if mfma:
+        if mfma and two_streams:
             # calls alternating between two streams and two outputs: one call's noise pass and
             # the next call's pack run beside the other stream's convolution kernel
             ss, y2 = [torch.cuda.Stream(), torch.cuda.Stream()], [y, torch.empty_like(y)]
@@ -563,6 +563,8 @@ def main():
                          "paper's 336 000-RIR room dataset), c2 serving, beamlearning (the paper's network "
                          "on frames of the convolution stage), rtfit (uniform-absorption fit for a target T30)")
     ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--no-two-streams", action="store_true",
+                    help="leave out the convolution calls on two streams (their kernels overlap)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="run only a plain device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -735,7 +737,8 @@ def main():
         if "c0x" in extras:
             res["extras"]["c0_replicated"] = bench_c0_replicated(H, torch, with_errors=not args.no_cpu_baseline)
         if "c4" in extras:
-            res["extras"]["c4_convolution"] = bench_c4(H, torch, with_errors=not args.no_cpu_baseline)
+            res["extras"]["c4_convolution"] = bench_c4(H, torch, with_errors=not args.no_cpu_baseline,
+                                                       two_streams=not args.no_two_streams)
         if "paper" in extras:
             res["extras"]["paper_room1_dataset"] = bench_paper(H, torch)
         if "c2" in extras:

@@ -147,9 +147,11 @@ __global__ __launch_bounds__(64, CONV_MW) void conv_mfma(const float *__restrict
                                                 int tiles_per_room)
 {
     // source ring (below) and its copy one entry later, so that a fragment starting at an
-    // odd entry starts on a 4-byte boundary of the copy
-    __shared__ __attribute__((aligned(16))) uint16_t xring[2 * XR];
-    __shared__ __attribute__((aligned(16))) uint16_t xring1[2 * XR + 8];
+    // odd entry starts on a 4-byte boundary of the copy; the copy starts 160 dwords after
+    // the ring, so dword d of either sits in banks d and d + 32 (mod 64): the two dword
+    // ranges a read instruction touches (about 20 dwords each) never share a bank
+    __shared__ __attribute__((aligned(16))) uint16_t xrings[2 * XR + 64 + 2 * XR + 8];
+    uint16_t *const xring = xrings, *const xring1 = xrings + 2 * XR + 64;
     __shared__ __attribute__((aligned(16))) uint16_t ring[2 * CRH];
     const int lane = threadIdx.x;
     // Workgroups are dealt to the 8 XCDs round-robin in launch order, and each XCD has
