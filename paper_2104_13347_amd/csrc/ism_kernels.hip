@@ -2,8 +2,17 @@
 // source in a shoebox room adds a fractional-delay filter, centred on its delay,
 // into the RIR of each microphone).
 //
-// Design (one wave64 per workgroup, persistent over a queue of work items; an
-// item is the output segment [s0, s1) of one microphone's RIR):
+// Two kernels compute the same sum over work items (an item is the output segment
+// [s0, s1) of one microphone's RIR; both are persistent over a queue of items):
+//  * ism_moments, the default for the compiled filter lengths and segments of at most
+//    1024 samples: 16 waves own an item; they enumerate its images in column chunks,
+//    add each image's 9 Chebyshev moments of its fractional delay (FP64, exact 64-bit
+//    fixed point) into LDS bins by integer delay, and then evaluate the filter once
+//    per output sample as a GEMM on the matrix cores (see the kernel's comments).
+//  * ism_segments, the per-tap kernel described next (the other filters, longer
+//    segments, rooms beyond the moment kernel's wall-power tables, and the ablations).
+//
+// Per-tap design (one wave64 per workgroup):
 //
 //  * Enumeration in registers.  Only images whose rounded delay n0 can put a tap
 //    into the segment are visited: they lie in a spherical shell around the
