@@ -144,6 +144,42 @@ def test_c0_replicated_full_batch_sampled(H):
     assert cnt16["taps"] == taps
 
 
+def _order_mix(mode, fd_taps, seed=31):
+    # 12 rooms of 2.5-4 m, random per-wall beta, 3 microphones, 1024 or 2048 samples at
+    # 16 kHz, image sets bounded by orders 0, 1, 2, 5 and 10 or by time (-1) in one batch
+    rng = np.random.default_rng(seed)
+    rooms = []
+    for i, order in enumerate([0, 1, 2, 5, 10, -1] * 2):
+        L = np.array([rng.uniform(2.5, 4.0), rng.uniform(2.5, 4.0), rng.uniform(2.5, 3.0)])
+        src = rng.uniform(0.3, 1.0, 3) * (L - 0.6) + 0.3
+        mics = np.array([rng.uniform(0.0, 1.0, 3) * (L - 0.6) + 0.3 for _ in range(3)])
+        rooms.append({"L": L, "beta": rng.uniform(0.4, 0.95, 6), "src": src, "mics": mics, "max_order": order,
+                      "rir_len": 1024 if i % 2 else 2048})
+    return scenes.pack(rooms, 16000.0, scenes.C_SOUND, fd_taps, mode, "order-mix")
+
+
+@pytest.mark.parametrize("precision", [ism.PREC_FP32, ism.PREC_FP32_DIRECT])
+@pytest.mark.parametrize("fd_taps", [81, 8])
+@pytest.mark.parametrize("mode", [ism.ORDER_INDEX_L1, ism.ORDER_REFLECTIONS])
+def test_order_bounded_batch(H, mode, fd_taps, precision):
+    # order bounds in both counting modes (index L1 and reflections), mixed with
+    # time-bounded rooms in one launch; every RIR against the oracle, exact tap count
+    b = _order_mix(mode, fd_taps)
+    _say(f"order mix mode={mode} fd_taps={fd_taps} precision={precision}")
+    if fd_taps == 8 and precision == ism.PREC_FP32_DIRECT:
+        # the Lagrange filter runs in the moment form (its per-tap form serves only rooms
+        # past the moment kernel's tables); the per-tap precision mode is refused for it
+        with pytest.raises(ism.IsmError):
+            run(H, b, precision=precision)
+        return
+    gpu, cnt = run(H, b, precision=precision)
+    ref, taps, rirs = oracle_batch(b)
+    err = rel_errors(b, gpu, ref, rirs)
+    _say(f"order mix max err {err.max():.3e}, taps {cnt['taps']} / {taps}")
+    assert err.max() <= TOL_FP32
+    assert cnt["taps"] == taps
+
+
 def test_c3_precision_variants(H):
     b = scenes.subset(scenes.c3(), [0, 1])
     ref, taps, rirs = oracle_batch(b)
