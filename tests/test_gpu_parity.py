@@ -180,6 +180,29 @@ def test_order_bounded_batch(H, mode, fd_taps, precision):
     assert cnt["taps"] == taps
 
 
+@pytest.mark.parametrize("fd_taps", [81, 8])
+def test_walls_of_zero_and_unit_reflection(H, fd_taps):
+    # walls that absorb everything (beta = 0: beta^0 = 1 for the images that never hit
+    # them) beside fully reflecting walls (beta = 1) and ordinary ones, time-bounded, in
+    # one launch; every RIR against the oracle, exact tap count
+    patterns = [[0.0, 1.0, 0.5, 0.0, 1.0, 0.7], [1.0] * 4 + [0.0, 0.0], [0.0, 0.0, 1.0, 1.0, 0.9, 0.9],
+                [1.0] * 6, [0.0] * 5 + [1.0], [0.3, 1.0, 0.0, 0.8, 1.0, 0.0]]
+    rng = np.random.default_rng(41)
+    rooms = []
+    for i, beta in enumerate(patterns):
+        L = np.array([rng.uniform(3.0, 5.0), rng.uniform(3.0, 4.0), rng.uniform(2.5, 3.0)])
+        src = rng.uniform(0.2, 0.8, 3) * L
+        mics = np.array([rng.uniform(0.2, 0.8, 3) * L for _ in range(2)])
+        rooms.append({"L": L, "beta": beta, "src": src, "mics": mics, "max_order": -1, "rir_len": 600 + 200 * i})
+    b = scenes.pack(rooms, 16000.0, scenes.C_SOUND, fd_taps, ism.ORDER_INDEX_L1, "walls")
+    gpu, cnt = run(H, b)
+    ref, taps, rirs = oracle_batch(b)
+    err = rel_errors(b, gpu, ref, rirs)
+    _say(f"zero/unit walls fd_taps={fd_taps}: max err {err.max():.3e}, taps {cnt['taps']} / {taps}")
+    assert err.max() <= TOL_FP32
+    assert cnt["taps"] == taps
+
+
 def test_c3_precision_variants(H):
     b = scenes.subset(scenes.c3(), [0, 1])
     ref, taps, rirs = oracle_batch(b)
