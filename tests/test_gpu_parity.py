@@ -203,6 +203,23 @@ def test_walls_of_zero_and_unit_reflection(H, fd_taps):
     assert cnt["taps"] == taps
 
 
+@pytest.mark.parametrize("fd_taps", [81, 8])
+def test_microphone_next_to_the_source(H, fd_taps):
+    # source-microphone distances of 1 mm, 1 cm and 10 cm: the direct path's gain (up to
+    # 80) sets the item's fixed-point scale far above every reflection; every RIR against
+    # the oracle, exact tap count
+    src = np.array([1.7, 2.2, 1.4])
+    rooms = [{"L": (4.0, 5.0, 3.0), "beta": (0.8,) * 6, "src": src, "max_order": -1, "rir_len": 1500,
+              "mics": [src + np.array([d, 0.0, 0.0]), src + np.array([0.0, -d, d])]} for d in (1e-3, 1e-2, 1e-1)]
+    b = scenes.pack(rooms, 16000.0, scenes.C_SOUND, fd_taps, ism.ORDER_INDEX_L1, "near")
+    gpu, cnt = run(H, b)
+    ref, taps, rirs = oracle_batch(b)
+    err = rel_errors(b, gpu, ref, rirs)
+    _say(f"near field fd_taps={fd_taps}: max err {err.max():.3e}, taps {cnt['taps']} / {taps}")
+    assert err.max() <= TOL_FP32
+    assert cnt["taps"] == taps
+
+
 def test_c3_precision_variants(H):
     b = scenes.subset(scenes.c3(), [0, 1])
     ref, taps, rirs = oracle_batch(b)
