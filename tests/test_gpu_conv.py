@@ -357,6 +357,34 @@ def test_conv_seeded_noise(H, mfma):
         assert abs(snr_hat - float(snr[r])) <= 3e-6
 
 
+@pytest.mark.parametrize("M", [1, 3, 13])
+def test_direct_path_other_microphone_counts(H, M):
+    # the FP32 direct path takes any microphone count (the MFMA path 8): M = 1, 3 and 13,
+    # ragged RIRs, with seeded noise, against the oracle given its own deviates
+    import torch
+    from oracle import noise
+    lens = np.array([1, 257, 900])
+    rirs, offs = scenes.synthetic_rirs(lens, M, seed=20 + M)
+    x = np.random.default_rng(30 + M).standard_normal((3, 1700)).astype(np.float32)
+    out_len = 1803
+    snr = np.array([5.0, 12.5, 28.0], dtype=np.float32)
+    seed = 4242 + M
+    y = H.convolve_batch(torch.from_numpy(rirs).cuda(), offs, lens, M, torch.from_numpy(x).cuda(), out_len,
+                         snr_db=snr, noise_seed=seed, use_mfma=False)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.float64)
+    assert got.shape == (3, M, out_len)
+    for r in range(3):
+        L = int(lens[r])
+        h = rirs[offs[r]:offs[r] + M * L].reshape(M, L).astype(np.float64)
+        ref = oracle.conv_room(h, x[r].astype(np.float64), out_len, snr_db=float(snr[r]),
+                               z=noise.deviates(seed, r, M, out_len))
+        _check(got[r], ref, False)
+    with pytest.raises(ism.IsmError):   # the MFMA path refuses M != 8
+        H.convolve_batch(torch.from_numpy(rirs).cuda(), offs, lens, M, torch.from_numpy(x).cuda(), out_len,
+                         use_mfma=True)
+
+
 def test_conv_seeded_full_size(H):
     # the 256-room workload with device noise: finite, four rooms against the oracle given
     # the oracle's deviates for the same seed
