@@ -205,6 +205,29 @@ def test_large_ragged_batch_equals_single_frames(handle):
     m.close()
 
 
+def test_slices_of_one_offsets_tensor(handle):
+    # windows of one device offsets tensor (offsets[:b], offsets[i:i+1], as a serving loop
+    # passes them on every call) give the frames a fresh tensor of the same values gives,
+    # and a window that reaches past x is still refused after the others passed
+    p, m = _model(handle, 51)
+    rng = np.random.default_rng(52)
+    rec = rng.standard_normal((2, 8, 3000)).astype(np.float32)
+    offs = np.array([0, 1500, 8 * 3000 + 700, 8 * 3000 + 1976], dtype=np.int64)
+    d = torch.from_numpy(rec).cuda()
+    od = torch.from_numpy(offs).cuda()
+    for lo, hi in [(0, 1), (0, 4), (2, 3), (0, 1), (1, 4)]:
+        f, o = m.forward(d, n_t=1024, batch=hi - lo, offsets=od[lo:hi], ch_stride=3000)
+        f2, o2 = m.forward(d, n_t=1024, batch=hi - lo, offsets=torch.from_numpy(offs[lo:hi].copy()).cuda(),
+                           ch_stride=3000)
+        torch.cuda.synchronize()
+        assert torch.equal(f, f2) and torch.equal(o, o2), (lo, hi)
+    # in place: frame 3 now ends at 29000 + 6 x 3000 + 1024 = 48024, past the 48000 of x
+    od[3:].fill_(29000)
+    with pytest.raises(ValueError):
+        m.forward(d, n_t=1024, batch=1, offsets=od[3:], ch_stride=3000)
+    m.close()
+
+
 def test_explicit_layout_is_checked_before_launch(handle):
     # an explicit frame layout that would read past x, or leaves a stride or the frame
     # count open, is refused on the host (the kernels cannot check device offsets)
