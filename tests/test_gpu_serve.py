@@ -73,6 +73,43 @@ def test_results_equal_alone_and_in_the_mix(torch_cuda):
         H.close()
 
 
+def test_uneven_requests_equal_alone(torch_cuda):
+    # requests of uneven shape in one mix: 1 and 32 microphones, RIRs of 1, 7 and 16000
+    # samples, order-bounded image sets in both counting modes, both filters; each result
+    # bitwise equal to the same room computed alone, and the smallest ones against the oracle
+    torch = torch_cuda
+    rng = np.random.default_rng(61)
+    L = np.array([4.0, 5.0, 3.0])
+    shapes = [(1, 1, -1, 0, 81), (32, 7, -1, 0, 81), (2, 16000, -1, 0, 8), (3, 2000, 3, 0, 81),
+              (3, 2000, 3, 1, 81), (1, 500, 0, 1, 8), (32, 300, -1, 0, 8), (5, 4096, 10, 0, 81)] * 2
+    reqs = []
+    for M, n, order, mode, taps in shapes:
+        src = rng.uniform(0.5, 1.0, 3) * (L - 1.0) + 0.5
+        mics = np.array([rng.uniform(0.2, 0.8, 3) * L for _ in range(M)])
+        reqs.append((src, mics, n, order, mode, taps, rng.uniform(0.5, 0.95, 6)))
+    S = ism.Server(n_lanes=4, hbm_budget_bytes=1 << 30, max_batch_rooms=4)
+    H = ism.Handle()
+    try:
+        tickets = [S.submit(L, beta, src, mics, n, 16000.0, 343.0, taps, max_order=order, order_mode=mode)
+                   for src, mics, n, order, mode, taps, beta in reqs]
+        _wait_all(S, tickets)
+        for t, (src, mics, n, order, mode, taps, beta) in zip(tickets, reqs):
+            mix = S.result(t, len(mics), n)
+            alone = H.rir(L, beta, src, mics, 16000.0, 343.0, order, n, taps, order_mode=mode)
+            torch.cuda.synchronize()
+            assert torch.equal(mix, alone), f"request {t} ({len(mics)} mics, {n} samples) differs"
+            if n <= 2000 and len(mics) <= 3:
+                got = mix.cpu().numpy()
+                for m in range(len(mics)):
+                    ref, _ = oracle.rir(L, beta, src, mics[m], 16000.0, 343.0, order, mode, n, taps)
+                    peak = max(np.max(np.abs(ref)), 1e-30)
+                    assert np.max(np.abs(got[m] - ref)) <= 1e-5 * peak
+            S.release(t)
+    finally:
+        S.close()
+        H.close()
+
+
 def test_budget_bounds_pool_and_everything_completes(torch_cuda):
     reqs, gaps, meta = scenes.c2(n_requests=60, seed=99)
     sizes = [4 * len(r["mics"]) * r["rir_len"] for r in reqs]
